@@ -1,0 +1,320 @@
+/*
+ * Skeleton oracle -- TEST INFRASTRUCTURE ONLY (see oracle.h).
+ *
+ * Every function is the plain definition of a skeleton from Section III of the
+ * paper (map, reduce, scan derived from higher-order functions; mapoverlap as a
+ * neighbourhood map), written out with no blocking, fusion or reordering.
+ * Floating point: binary64 from the stored binary32 values, sequential sums in
+ * index order.  Integers: unsigned modular arithmetic of the output width.
+ *
+ * Built with gcc -O2 -ffp-contract=off (no fast-math): no FMA contraction, no
+ * reassociation, IEEE round-to-nearest-even throughout.
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+static int g_threads = 1;
+
+void oracle_set_threads(int n) { g_threads = n < 1 ? 1 : n; }
+int oracle_get_threads(void) { return g_threads; }
+
+/* ---------------------------------------------------------------- Map ---- */
+
+/* The element function f(x, y; p0, p1) of a skeleton instance (Section III:
+ * a skeleton is parameterised by a user function). */
+static int elem_fn(int op, const double *p, int np, double x, double y,
+                   double *res)
+{
+    switch (op) {
+    case ORC_MAP_IDENTITY: *res = x; return 0;
+    case ORC_MAP_AXPY:
+        if (np < 1) return -1;
+        *res = p[0] * x + y; return 0;
+    case ORC_MAP_AFFINE:
+        if (np < 2) return -1;
+        *res = p[0] * x + p[1]; return 0;
+    case ORC_MAP_TANH: *res = tanh(x); return 0;
+    case ORC_MAP_AFFINE_TANH:
+        if (np < 2) return -1;
+        *res = tanh(p[0] * x + p[1]); return 0;
+    case ORC_MAP_MUL: *res = x * y; return 0;
+    case ORC_MAP_SQUARE: *res = x * x; return 0;
+    default: return -1;
+    }
+}
+
+static int needs_y(int op) { return op == ORC_MAP_AXPY || op == ORC_MAP_MUL; }
+
+/* map: out[i] = f(x[i], y[i]) for every i (Section III, "map") */
+int oracle_map_f32(int op, const double *params, int nparams, const float *x,
+                   const float *y, int64_t n, double *out)
+{
+    double probe;
+    if (elem_fn(op, params, nparams, 0.0, 0.0, &probe) != 0) return -1;
+    if (needs_y(op) && y == NULL) return -1;
+    if (n <= 0) return 0;
+    int64_t i;
+#pragma omp parallel for schedule(static) num_threads(g_threads)
+    for (i = 0; i < n; ++i) {
+        double yi = y ? (double)y[i] : 0.0;
+        elem_fn(op, params, nparams, (double)x[i], yi, &out[i]);
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------- Reduce ---- */
+
+/* reduce: x[0] op x[1] op ... op x[n-1] (Section III, "reduce"), sequential */
+double oracle_reduce_f32(int op, const float *x, int64_t n)
+{
+    double acc;
+    if (op == ORC_MIN) acc = INFINITY;
+    else if (op == ORC_MAX) acc = -INFINITY;
+    else acc = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double v = (double)x[i];
+        if (op == ORC_MIN) acc = v < acc ? v : acc;
+        else if (op == ORC_MAX) acc = v > acc ? v : acc;
+        else acc = acc + v;
+    }
+    return acc;
+}
+
+double oracle_abs_sum_f32(const float *x, int64_t n)
+{
+    double acc = 0.0;
+    for (int64_t i = 0; i < n; ++i) acc = acc + fabs((double)x[i]);
+    return acc;
+}
+
+int32_t oracle_reduce_i32_i32(int op, const int32_t *x, int64_t n)
+{
+    if (op == ORC_SUM) {
+        uint32_t acc = 0;
+        for (int64_t i = 0; i < n; ++i) acc = acc + (uint32_t)x[i];
+        return (int32_t)acc;
+    }
+    int32_t acc = op == ORC_MIN ? INT32_MAX : INT32_MIN;
+    for (int64_t i = 0; i < n; ++i) {
+        if (op == ORC_MIN) acc = x[i] < acc ? x[i] : acc;
+        else acc = x[i] > acc ? x[i] : acc;
+    }
+    return acc;
+}
+
+int64_t oracle_reduce_i32_i64(int op, const int32_t *x, int64_t n)
+{
+    if (op == ORC_SUM) {
+        uint64_t acc = 0;
+        for (int64_t i = 0; i < n; ++i) acc = acc + (uint64_t)(int64_t)x[i];
+        return (int64_t)acc;
+    }
+    int64_t acc = op == ORC_MIN ? INT64_MAX : INT64_MIN;
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t v = x[i];
+        if (op == ORC_MIN) acc = v < acc ? v : acc;
+        else acc = v > acc ? v : acc;
+    }
+    return acc;
+}
+
+int64_t oracle_reduce_i64_i64(int op, const int64_t *x, int64_t n)
+{
+    if (op == ORC_SUM) {
+        uint64_t acc = 0;
+        for (int64_t i = 0; i < n; ++i) acc = acc + (uint64_t)x[i];
+        return (int64_t)acc;
+    }
+    int64_t acc = op == ORC_MIN ? INT64_MAX : INT64_MIN;
+    for (int64_t i = 0; i < n; ++i) {
+        if (op == ORC_MIN) acc = x[i] < acc ? x[i] : acc;
+        else acc = x[i] > acc ? x[i] : acc;
+    }
+    return acc;
+}
+
+/* ---------------------------------------------------------- MapReduce ---- */
+
+/* map then reduce without a stored intermediate: op over i of f(x[i], y[i]) */
+double oracle_mapreduce_f32(int map_op, const double *params, int nparams,
+                            const float *x, const float *y, int64_t n,
+                            int reduce_op, double *abs_sum)
+{
+    double acc, mag = 0.0, v;
+    if (reduce_op == ORC_MIN) acc = INFINITY;
+    else if (reduce_op == ORC_MAX) acc = -INFINITY;
+    else acc = 0.0;
+    if (needs_y(map_op) && y == NULL) return NAN;
+    for (int64_t i = 0; i < n; ++i) {
+        double yi = y ? (double)y[i] : 0.0;
+        if (elem_fn(map_op, params, nparams, (double)x[i], yi, &v) != 0)
+            return NAN;
+        mag = mag + fabs(v);
+        if (reduce_op == ORC_MIN) acc = v < acc ? v : acc;
+        else if (reduce_op == ORC_MAX) acc = v > acc ? v : acc;
+        else acc = acc + v;
+    }
+    if (abs_sum) *abs_sum = mag;
+    return acc;
+}
+
+/* --------------------------------------------------------- MapOverlap ---- */
+
+/* border rule: index j of a length-n axis.  Returns 1 and sets *k to the index
+ * to read, or 0 when the element is the constant pad. */
+static int border_index(int64_t j, int64_t n, int edge, int64_t *k)
+{
+    if (j >= 0 && j < n) { *k = j; return 1; }
+    switch (edge) {
+    case ORC_EDGE_CLAMP: *k = j < 0 ? 0 : n - 1; return 1;
+    case ORC_EDGE_CYCLIC: {
+        int64_t m = j % n;
+        *k = m < 0 ? m + n : m;
+        return 1;
+    }
+    default: return 0; /* ORC_EDGE_CONST */
+    }
+}
+
+int oracle_mapoverlap1d_f32(const float *x, int64_t n, const float *w, int r,
+                            int edge, float pad, double *out, double *mag)
+{
+    if (r < 0 || w == NULL) return -1;
+    if (edge != ORC_EDGE_CLAMP && edge != ORC_EDGE_CONST &&
+        edge != ORC_EDGE_CYCLIC)
+        return -1;
+    if (n <= 0) return 0;
+    int64_t i;
+#pragma omp parallel for schedule(static) num_threads(g_threads)
+    for (i = 0; i < n; ++i) {
+        double acc = 0.0, m = 0.0;
+        for (int k = 0; k <= 2 * r; ++k) {
+            int64_t src;
+            double v = border_index(i + k - r, n, edge, &src) ? (double)x[src]
+                                                               : (double)pad;
+            double t = (double)w[k] * v;
+            acc = acc + t;
+            m = m + fabs(t);
+        }
+        out[i] = acc;
+        if (mag) mag[i] = m;
+    }
+    return 0;
+}
+
+/* W[a][b]: the given 2D weights, or the exact binary64 outer product of the
+ * separable factors (a 24-bit by 24-bit product fits the 53-bit significand) */
+static double weight2d(const float *w2d, const float *wy, const float *wx,
+                       int rx, int a, int b)
+{
+    if (w2d) return (double)w2d[(int64_t)a * (2 * rx + 1) + b];
+    return (double)wy[a] * (double)wx[b];
+}
+
+double oracle_mapoverlap2d_at_f32(const float *x, int64_t rows, int64_t cols,
+                                  const float *w2d, const float *wy,
+                                  const float *wx, int ry, int rx, int edge,
+                                  float pad, int64_t i, int64_t j, double *mag)
+{
+    double acc = 0.0, m = 0.0;
+    for (int a = 0; a <= 2 * ry; ++a) {
+        for (int b = 0; b <= 2 * rx; ++b) {
+            int64_t si, sj;
+            int in_r = border_index(i + a - ry, rows, edge, &si);
+            int in_c = border_index(j + b - rx, cols, edge, &sj);
+            double v = (in_r && in_c) ? (double)x[si * cols + sj] : (double)pad;
+            double t = weight2d(w2d, wy, wx, rx, a, b) * v;
+            acc = acc + t;
+            m = m + fabs(t);
+        }
+    }
+    if (mag) *mag = m;
+    return acc;
+}
+
+int oracle_mapoverlap2d_f32(const float *x, int64_t rows, int64_t cols,
+                            const float *w2d, const float *wy, const float *wx,
+                            int ry, int rx, int edge, float pad, double *out,
+                            double *mag)
+{
+    if (ry < 0 || rx < 0) return -1;
+    if (w2d == NULL && (wy == NULL || wx == NULL)) return -1;
+    if (edge != ORC_EDGE_CLAMP && edge != ORC_EDGE_CONST &&
+        edge != ORC_EDGE_CYCLIC)
+        return -1;
+    if (rows <= 0 || cols <= 0) return 0;
+    int64_t i;
+#pragma omp parallel for schedule(static) num_threads(g_threads)
+    for (i = 0; i < rows; ++i) {
+        for (int64_t j = 0; j < cols; ++j) {
+            double m;
+            out[i * cols + j] = oracle_mapoverlap2d_at_f32(
+                x, rows, cols, w2d, wy, wx, ry, rx, edge, pad, i, j, &m);
+            if (mag) mag[i * cols + j] = m;
+        }
+    }
+    return 0;
+}
+
+/* --------------------------------------------------------------- Scan ---- */
+
+/* scan: running combination in index order (Section III, "scan").  The
+ * exclusive form starts from the operator's identity. */
+#define ORC_SCAN_INT(NAME, TIN, TOUT, UACC, TMIN, TMAX)                       \
+    int NAME(const TIN *x, int64_t n, int kind, int op, TOUT *out)             \
+    {                                                                          \
+        if (kind != ORC_INCLUSIVE && kind != ORC_EXCLUSIVE) return -1;         \
+        if (op != ORC_SUM && op != ORC_MIN && op != ORC_MAX) return -1;        \
+        UACC sacc = 0;                                                         \
+        TOUT macc = op == ORC_MIN ? TMAX : TMIN;                               \
+        for (int64_t i = 0; i < n; ++i) {                                      \
+            if (kind == ORC_EXCLUSIVE)                                         \
+                out[i] = op == ORC_SUM ? (TOUT)sacc : macc;                    \
+            TOUT v = (TOUT)x[i];                                               \
+            if (op == ORC_SUM) sacc = sacc + (UACC)v;                          \
+            else if (op == ORC_MIN) macc = v < macc ? v : macc;                \
+            else macc = v > macc ? v : macc;                                   \
+            if (kind == ORC_INCLUSIVE)                                         \
+                out[i] = op == ORC_SUM ? (TOUT)sacc : macc;                    \
+        }                                                                      \
+        return 0;                                                              \
+    }
+
+ORC_SCAN_INT(oracle_scan_i32_i32, int32_t, int32_t, uint32_t, INT32_MIN,
+             INT32_MAX)
+ORC_SCAN_INT(oracle_scan_i32_i64, int32_t, int64_t, uint64_t, INT64_MIN,
+             INT64_MAX)
+ORC_SCAN_INT(oracle_scan_i64_i64, int64_t, int64_t, uint64_t, INT64_MIN,
+             INT64_MAX)
+
+int oracle_scan_f32(const float *x, int64_t n, int kind, int op, double *out,
+                    double *mag)
+{
+    if (kind != ORC_INCLUSIVE && kind != ORC_EXCLUSIVE) return -1;
+    if (op != ORC_SUM && op != ORC_MIN && op != ORC_MAX) return -1;
+    double acc = op == ORC_MIN ? INFINITY : (op == ORC_MAX ? -INFINITY : 0.0);
+    double m = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (kind == ORC_EXCLUSIVE) {
+            out[i] = acc;
+            if (mag) mag[i] = m;
+        }
+        double v = (double)x[i];
+        if (op == ORC_SUM) acc = acc + v;
+        else if (op == ORC_MIN) acc = v < acc ? v : acc;
+        else acc = v > acc ? v : acc;
+        m = m + fabs(v);
+        if (kind == ORC_INCLUSIVE) {
+            out[i] = acc;
+            if (mag) mag[i] = m;
+        }
+    }
+    return 0;
+}

@@ -1,0 +1,114 @@
+/*
+ * Skeleton oracle: a plain, slow, obviously correct CPU definition of what the
+ * data-parallel skeletons compute.  TEST INFRASTRUCTURE ONLY -- the product
+ * library never includes, links or calls this code; only the test suite, the
+ * smoke check and the CPU-baseline leg of the benchmark load it.
+ *
+ * Paper: Kessler, Dastgeer, Li, "Optimized Composition: Generating Efficient
+ * Code for Heterogeneous Systems from Multi-Variant Components, Skeletons and
+ * Containers" (arXiv:1405.2915).  Section III names the skeletons (map, scan,
+ * reduce, derived from higher-order functions; mapoverlap among SkePU's
+ * data-parallel skeletons) but gives no formulas.  Each function below states
+ * the textbook higher-order-function definition it implements.
+ *
+ * Arithmetic: floating point is evaluated in IEEE binary64 from the stored
+ * binary32 inputs, summed sequentially in index order (no blocking, no
+ * reordering); integer arithmetic is modular in the unsigned type of the
+ * output width (two's-complement wrap, no signed-overflow UB).
+ *
+ * Operation codes are this file's own; callers pass them by value.
+ */
+#ifndef SKEL_ORACLE_H
+#define SKEL_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* element functions of Map / MapReduce (the "user function" of a skeleton
+ * instance, Section III): f(x, y; p0, p1) */
+enum {
+    ORC_MAP_IDENTITY = 0,    /* x                 */
+    ORC_MAP_AXPY = 1,        /* p0*x + y          */
+    ORC_MAP_AFFINE = 2,      /* p0*x + p1         */
+    ORC_MAP_TANH = 3,        /* tanh(x)           */
+    ORC_MAP_AFFINE_TANH = 4, /* tanh(p0*x + p1)   */
+    ORC_MAP_MUL = 5,         /* x*y               */
+    ORC_MAP_SQUARE = 6       /* x*x               */
+};
+
+/* combining operator of Reduce / Scan */
+enum { ORC_SUM = 0, ORC_MIN = 1, ORC_MAX = 2 };
+enum { ORC_INCLUSIVE = 0, ORC_EXCLUSIVE = 1 };
+/* border handling of MapOverlap */
+enum { ORC_EDGE_CLAMP = 0, ORC_EDGE_CONST = 1, ORC_EDGE_CYCLIC = 2 };
+
+/* number of OpenMP threads used by the element-parallel loops (map, stencil);
+ * reductions and scans are always sequential */
+void oracle_set_threads(int n);
+int oracle_get_threads(void);
+
+/* Map: out[i] = f(x[i], y[i]).  y may be NULL for one-input functions.
+ * Returns 0, or -1 for an unknown op / missing operand. */
+int oracle_map_f32(int op, const double *params, int nparams, const float *x,
+                   const float *y, int64_t n, double *out);
+
+/* Reduce over binary32 input, evaluated in binary64.  SUM of n = 0 is 0,
+ * MIN is +inf, MAX is -inf. */
+double oracle_reduce_f32(int op, const float *x, int64_t n);
+/* sum of |x[i]| in binary64: the magnitude scale of a floating-point sum */
+double oracle_abs_sum_f32(const float *x, int64_t n);
+
+/* integer Reduce, wrapping in the output width */
+int32_t oracle_reduce_i32_i32(int op, const int32_t *x, int64_t n);
+int64_t oracle_reduce_i32_i64(int op, const int32_t *x, int64_t n);
+int64_t oracle_reduce_i64_i64(int op, const int64_t *x, int64_t n);
+
+/* MapReduce: r = reduce_op over i of f(x[i], y[i]).  *abs_sum (may be NULL)
+ * receives sum of |f(x[i], y[i])|. */
+double oracle_mapreduce_f32(int map_op, const double *params, int nparams,
+                            const float *x, const float *y, int64_t n,
+                            int reduce_op, double *abs_sum);
+
+/* MapOverlap 1D (a weighted neighbourhood, correlation orientation):
+ *   out[i] = sum_{k=0}^{2r} w[k] * x[e(i + k - r)]
+ * e() is the border rule (clamp, constant pad, cyclic).  mag[i] (may be NULL)
+ * receives sum_k |w[k] * x[e(i+k-r)]|.  Returns 0 or -1 on bad arguments. */
+int oracle_mapoverlap1d_f32(const float *x, int64_t n, const float *w, int r,
+                            int edge, float pad, double *out, double *mag);
+
+/* MapOverlap 2D on a rows x cols row-major image:
+ *   out[i][j] = sum_{a=0}^{2ry} sum_{b=0}^{2rx} W[a][b] * x[e(i+a-ry)][e(j+b-rx)]
+ * W is w2d ((2ry+1) x (2rx+1) row-major) if w2d != NULL, else the outer
+ * product wy[a]*wx[b] formed exactly in binary64. */
+int oracle_mapoverlap2d_f32(const float *x, int64_t rows, int64_t cols,
+                            const float *w2d, const float *wy, const float *wx,
+                            int ry, int rx, int edge, float pad, double *out,
+                            double *mag);
+/* the same definition for the single output (i, j) */
+double oracle_mapoverlap2d_at_f32(const float *x, int64_t rows, int64_t cols,
+                                  const float *w2d, const float *wy,
+                                  const float *wx, int ry, int rx, int edge,
+                                  float pad, int64_t i, int64_t j, double *mag);
+
+/* Scan (prefix combination):
+ *   inclusive out[i] = x[0] op ... op x[i]
+ *   exclusive out[0] = identity, out[i] = x[0] op ... op x[i-1]
+ * Return 0, or -1 for a bad op / kind. */
+int oracle_scan_i32_i32(const int32_t *x, int64_t n, int kind, int op,
+                        int32_t *out);
+int oracle_scan_i32_i64(const int32_t *x, int64_t n, int kind, int op,
+                        int64_t *out);
+int oracle_scan_i64_i64(const int64_t *x, int64_t n, int kind, int op,
+                        int64_t *out);
+/* floating-point Scan in binary64; mag[i] (may be NULL) is the sum of |x[j]|
+ * over the terms of out[i] */
+int oracle_scan_f32(const float *x, int64_t n, int kind, int op, double *out,
+                    double *mag);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,435 @@
+"""Pins of the CPU oracle against facts fixed by the mathematics.
+
+Each skeleton definition (Section III of arXiv:1405.2915: map, reduce, scan as
+higher-order functions, mapoverlap as a neighbourhood map) is checked against
+hand-worked examples (tests/golden/hand_examples.json), closed forms,
+invariants, library routines it reduces to (math.fsum, numpy.cumsum,
+scipy.ndimage.correlate*), and exact rational brute force on tiny inputs.  The
+checks are chosen so that a dropped term, a wrong sign or index, a swapped
+operand or an off-by-one in inclusive/exclusive fails at least one of them.
+"""
+import json
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import scipy.ndimage as ndi
+
+import synth_inputs as si
+
+pytestmark = pytest.mark.filterwarnings("ignore::DeprecationWarning")
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                   "hand_examples.json")))
+
+
+# ------------------------------------------------------------------ golden --
+
+def test_golden_map(oracle_mod):
+    g = GOLD["map_axpy"]
+    out = oracle_mod.map_f32("axpy", [g["p0"]], np.array(g["x"], np.float32),
+                             np.array(g["y"], np.float32))
+    assert out.tolist() == g["out"]
+    g = GOLD["map_affine"]
+    out = oracle_mod.map_f32("affine", [g["p0"], g["p1"]],
+                             np.array(g["x"], np.float32))
+    assert out.tolist() == g["out"]
+
+
+def test_golden_reduce(oracle_mod):
+    g = GOLD["reduce_sum_i32"]
+    assert oracle_mod.reduce("sum", np.array(g["x"], np.int32)) == g["out"]
+    assert oracle_mod.reduce("sum", np.array(g["x"], np.float32)) == g["out"]
+    g = GOLD["reduce_min_max_i32"]
+    x = np.array(g["x"], np.int32)
+    assert oracle_mod.reduce("min", x) == g["min"]
+    assert oracle_mod.reduce("max", x) == g["max"]
+    assert oracle_mod.reduce("min", x, np.int64) == g["min"]
+    assert oracle_mod.reduce("max", x.astype(np.int64)) == g["max"]
+    assert oracle_mod.reduce("min", x.astype(np.float32)) == g["min"]
+    g = GOLD["reduce_wrap_i32"]
+    x = np.array(g["x"], np.int32)
+    assert oracle_mod.reduce("sum", x) == g["out_i32"]
+    assert oracle_mod.reduce("sum", x, np.int64) == g["out_i64"]
+
+
+def test_golden_mapreduce(oracle_mod):
+    g = GOLD["mapreduce_dot"]
+    r, mag = oracle_mod.mapreduce("mul", None, np.array(g["x"], np.float32),
+                                  np.array(g["y"], np.float32))
+    assert r == g["out"]
+    assert mag == 16.0  # 4 + 2 + 6 + 4
+
+
+@pytest.mark.parametrize("name,op", [("scan_sum_i32", "sum"),
+                                     ("scan_max_i32", "max")])
+def test_golden_scan(oracle_mod, name, op):
+    g = GOLD[name]
+    x = np.array(g["x"], np.int32)
+    for kind in ("inclusive", "exclusive"):
+        assert oracle_mod.scan(x, kind, op).tolist() == g[kind]
+        if op == "sum":
+            assert oracle_mod.scan(x, kind, op, np.int64).tolist() == g[kind]
+            assert oracle_mod.scan(x.astype(np.int64), kind, op).tolist() == g[kind]
+            out, _ = oracle_mod.scan(x.astype(np.float32), kind, op)
+            assert out.tolist() == g[kind]
+
+
+@pytest.mark.parametrize("name,edge", [("mapoverlap1d_clamp", "clamp"),
+                                       ("mapoverlap1d_const", "const"),
+                                       ("mapoverlap1d_cyclic", "cyclic")])
+def test_golden_mapoverlap1d(oracle_mod, name, edge):
+    g = GOLD[name]
+    out, _ = oracle_mod.mapoverlap1d(np.array(g["x"], np.float32),
+                                     np.array(g["w"], np.float32), g["r"],
+                                     edge, g.get("pad", 0.0))
+    assert out.tolist() == g["out"]
+
+
+def test_golden_mapoverlap2d(oracle_mod):
+    g = GOLD["mapoverlap2d_clamp"]
+    out, _ = oracle_mod.mapoverlap2d(np.array(g["x"], np.float32), 1, 1,
+                                     w2d=np.array(g["w"], np.float32))
+    assert out.tolist() == g["out"]
+
+
+# --------------------------------------------------------------------- Map --
+
+def test_map_saxpy_exact_on_grid(oracle_mod):
+    # x, y = 2U - 1 with U on the 2^-24 grid: x, y on the 2^-23 grid, so
+    # 2.5 x + y is exact in binary64 and equal to the exact rational value.
+    x = si.uniform_f32(4096, -1.0, 1.0, 0, 0)
+    y = si.uniform_f32(4096, -1.0, 1.0, 0, 1)
+    assert np.all((x.astype(np.float64) * 2 ** 23) % 1 == 0)
+    out = oracle_mod.map_f32("axpy", [2.5], x, y)
+    for i in range(0, 4096, 37):
+        exact = Fraction(5, 2) * Fraction(float(x[i])) + Fraction(float(y[i]))
+        assert Fraction(float(out[i])) == exact
+
+
+def test_map_properties(oracle_mod):
+    x = si.uniform_f32(1000, -1.0, 1.0, 0, 2)
+    y = si.uniform_f32(1000, -1.0, 1.0, 0, 3)
+    z = np.zeros_like(x)
+    # x = 0 leaves y unchanged; y = 0 gives p0 * x (operand roles fixed)
+    assert np.array_equal(oracle_mod.map_f32("axpy", [2.5], z, y), y)
+    assert np.array_equal(oracle_mod.map_f32("axpy", [3.0], x, z),
+                          3.0 * x.astype(np.float64))
+    # affine with p0 = 0 is the constant p1; identity copies
+    assert np.all(oracle_mod.map_f32("affine", [0.0, 1.25], x) == 1.25)
+    assert np.array_equal(oracle_mod.map_f32("identity", None, x), x)
+    # mul commutes, square = mul(x, x), x * 1 = x
+    assert np.array_equal(oracle_mod.map_f32("mul", None, x, y),
+                          oracle_mod.map_f32("mul", None, y, x))
+    assert np.array_equal(oracle_mod.map_f32("square", None, x),
+                          oracle_mod.map_f32("mul", None, x, x))
+    assert np.array_equal(oracle_mod.map_f32("mul", None, x, np.ones_like(x)), x)
+
+
+def test_map_tanh_library(oracle_mod):
+    x = si.normal_f32(500, 0, 4) * np.float32(3)
+    t = oracle_mod.map_f32("tanh", None, x)
+    ref = np.array([math.tanh(float(v)) for v in x])
+    assert np.array_equal(t, ref)
+    # affine_tanh(p0, p1) = tanh(p0 x + p1); p0 = 1, p1 = 0 reduces to tanh
+    assert np.array_equal(oracle_mod.map_f32("affine_tanh", [1.0, 0.0], x), t)
+    at = oracle_mod.map_f32("affine_tanh", [0.5, -0.25], x)
+    ref = np.array([math.tanh(0.5 * float(v) - 0.25) for v in x])
+    assert np.array_equal(at, ref)
+    # odd symmetry, tanh(0) = 0
+    assert np.array_equal(oracle_mod.map_f32("tanh", None, -x), -t)
+    assert oracle_mod.map_f32("tanh", None, np.zeros(1, np.float32))[0] == 0.0
+
+
+def test_map_rejects_bad_ops(oracle_mod):
+    with pytest.raises(ValueError):
+        oracle_mod.map_f32("axpy", [], np.ones(3, np.float32), np.ones(3, np.float32))
+    with pytest.raises(ValueError):
+        oracle_mod.map_f32("mul", None, np.ones(3, np.float32))
+
+
+# ------------------------------------------------------------------ Reduce --
+
+@pytest.mark.parametrize("n", [0, 1, 2, 3, 1000, 65536, 1 << 20])
+def test_reduce_sum_of_indices(oracle_mod, n):
+    # sum_{i<n} i = n (n - 1) / 2; binary32 holds i exactly for n <= 2^24
+    i32 = np.arange(n, dtype=np.int32)
+    exact = n * (n - 1) // 2
+    assert oracle_mod.reduce("sum", i32.astype(np.float32)) == float(exact)
+    assert oracle_mod.reduce("sum", i32, np.int64) == exact
+    assert oracle_mod.reduce("sum", i32.astype(np.int64)) == exact
+    wrapped = ((exact + 2 ** 31) % 2 ** 32) - 2 ** 31
+    assert oracle_mod.reduce("sum", i32) == wrapped
+    if n <= 65536:
+        assert oracle_mod.reduce("sum", i32) == exact
+
+
+def test_reduce_special_cases(oracle_mod):
+    ones = np.ones(12345, np.float32)
+    assert oracle_mod.reduce("sum", ones) == 12345.0
+    alt = np.where(np.arange(1001) % 2 == 0, 1, -1).astype(np.float32)
+    assert oracle_mod.reduce("sum", alt) == 1.0
+    empty = np.zeros(0, np.float32)
+    assert oracle_mod.reduce("sum", empty) == 0.0
+    assert oracle_mod.reduce("min", empty) == math.inf
+    assert oracle_mod.reduce("max", empty) == -math.inf
+    ei = np.zeros(0, np.int32)
+    assert oracle_mod.reduce("min", ei) == 2 ** 31 - 1
+    assert oracle_mod.reduce("max", ei, np.int64) == -2 ** 63
+
+
+def test_reduce_fsum_and_bruteforce(oracle_mod):
+    x = si.normal_f32(1 << 16, 0, 5)
+    s = oracle_mod.reduce("sum", x)
+    exact = math.fsum(float(v) for v in x)
+    # sequential binary64 error bound n * 2^-53 * sum |x|
+    assert abs(s - exact) <= x.size * 2.0 ** -53 * oracle_mod.abs_sum(x)
+    assert oracle_mod.abs_sum(x) == pytest.approx(float(np.abs(x.astype(np.float64)).sum()),
+                                                  rel=1e-12)
+    assert oracle_mod.reduce("min", x) == float(x.min())
+    assert oracle_mod.reduce("max", x) == float(x.max())
+    rng = si.rng(9, 0)
+    for n in range(0, 65):
+        xi = rng.integers(-2 ** 31, 2 ** 31, n, dtype=np.int64).astype(np.int32)
+        tot = sum(int(v) for v in xi)
+        assert oracle_mod.reduce("sum", xi, np.int64) == tot
+        assert oracle_mod.reduce("sum", xi) == ((tot + 2 ** 31) % 2 ** 32) - 2 ** 31
+        if n:
+            assert oracle_mod.reduce("min", xi) == min(int(v) for v in xi)
+            assert oracle_mod.reduce("max", xi) == max(int(v) for v in xi)
+        xl = rng.integers(-2 ** 62, 2 ** 62, n, dtype=np.int64)
+        t = sum(int(v) for v in xl)
+        assert oracle_mod.reduce("sum", xl) == ((t + 2 ** 63) % 2 ** 64) - 2 ** 63
+
+
+# --------------------------------------------------------------- MapReduce --
+
+def test_mapreduce_identities(oracle_mod):
+    x = si.normal_f32(4097, 1, 0)
+    y = si.normal_f32(4097, 1, 1)
+    ones = np.ones_like(x)
+    # dot(x, 1) performs exactly the additions of reduce(x)
+    r, _ = oracle_mod.mapreduce("mul", None, x, ones)
+    assert r == oracle_mod.reduce("sum", x)
+    # dot(e_k, y) = y_k
+    for k in (0, 17, 4096):
+        e = np.zeros_like(x)
+        e[k] = 1
+        assert oracle_mod.mapreduce("mul", None, e, y)[0] == float(y[k])
+    # dot(x, x) = sum of squares >= 0, and equals mapreduce(square)
+    rxx, mag = oracle_mod.mapreduce("mul", None, x, x)
+    assert rxx >= 0 and rxx == mag
+    assert rxx == oracle_mod.mapreduce("square", None, x)[0]
+    # numpy binary64 dot agrees to rounding
+    ref = float(np.dot(x.astype(np.float64), y.astype(np.float64)))
+    r, mag = oracle_mod.mapreduce("mul", None, x, y)
+    assert abs(r - ref) <= 4097 * 2.0 ** -52 * mag
+    # min / max of the mapped values
+    prods = x.astype(np.float64) * y.astype(np.float64)
+    assert oracle_mod.mapreduce("mul", None, x, y, "max")[0] == prods.max()
+    assert oracle_mod.mapreduce("mul", None, x, y, "min")[0] == prods.min()
+
+
+def test_mapreduce_exact_bruteforce(oracle_mod):
+    # products of binary32 values are exact in binary64; the binary64 sum of a
+    # few terms stays within n ulps of the exact rational sum
+    for seed in range(8):
+        x = si.normal_f32(13, 7, seed)
+        y = si.normal_f32(13, 8, seed)
+        exact = sum(Fraction(float(a)) * Fraction(float(b)) for a, b in zip(x, y))
+        r, mag = oracle_mod.mapreduce("mul", None, x, y)
+        assert abs(Fraction(r) - exact) <= Fraction(13 * 2.0 ** -53) * Fraction(mag)
+        r, _ = oracle_mod.mapreduce("axpy", [2.5], x, y)
+        exact = sum(Fraction(5, 2) * Fraction(float(a)) + Fraction(float(b))
+                    for a, b in zip(x, y))
+        assert abs(Fraction(r) - exact) < Fraction(1, 2 ** 40)
+
+
+# -------------------------------------------------------------- MapOverlap --
+
+def test_mapoverlap1d_constant_field(oracle_mod):
+    # clamp keeps a constant field constant, so out = c * sum(w), borders too
+    for w in (si.binomial5_weights(), si.gaussian_weights(4, 2.0),
+              np.array([0.1, -0.7, 0.3], np.float32)):
+        r = (w.size - 1) // 2
+        c = np.float32(0.75)
+        out, _ = oracle_mod.mapoverlap1d(np.full(300, c, np.float32), w, r)
+        sw = math.fsum(float(v) for v in w)
+        assert np.all(np.abs(out - float(c) * sw) <= 1e-15)
+    # the binomial weights sum to 1 exactly; the 9-tap Gaussian to 1.000000011...
+    assert math.fsum(float(v) for v in si.binomial5_weights()) == 1.0
+    assert math.fsum(float(v) for v in si.gaussian_weights()) == pytest.approx(
+        1.000000011175871, abs=1e-15)
+
+
+def test_mapoverlap1d_impulse_orientation(oracle_mod):
+    # correlation orientation: an impulse at m yields out[m + j] = w[r - j]
+    w = np.array([1, 2, 3, 4, 5], np.float32)
+    x = np.zeros(21, np.float32)
+    x[10] = 1
+    out, _ = oracle_mod.mapoverlap1d(x, w, 2)
+    assert out[8:13].tolist() == [5, 4, 3, 2, 1]
+    assert np.count_nonzero(out) == 5
+
+
+@pytest.mark.parametrize("edge,mode", [("clamp", "nearest"), ("const", "constant"),
+                                       ("cyclic", "wrap")])
+@pytest.mark.parametrize("n,r", [(1, 2), (3, 2), (64, 1), (1000, 5), (7, 4)])
+def test_mapoverlap1d_scipy(oracle_mod, edge, mode, n, r):
+    x = si.uniform_f32(n, -1.0, 1.0, 3, n)
+    w = si.uniform_f32(2 * r + 1, -1.0, 1.0, 3, 100 + r)
+    pad = 0.375
+    out, mag = oracle_mod.mapoverlap1d(x, w, r, edge, pad)
+    ref = ndi.correlate1d(x.astype(np.float64), w.astype(np.float64), mode=mode,
+                          cval=pad)
+    assert np.all(np.abs(out - ref) <= 1e-14 * (mag + 1e-300))
+    assert np.all(mag >= np.abs(out) - 1e-15)
+
+
+def test_mapoverlap1d_ramp(oracle_mod):
+    # symmetric weights summing to 1 reproduce a linear ramp in the interior
+    x = np.arange(200, dtype=np.float32) * np.float32(0.5)
+    out, _ = oracle_mod.mapoverlap1d(x, si.binomial5_weights(), 2)
+    assert np.array_equal(out[2:-2], x[2:-2].astype(np.float64))
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (1, 17), (13, 1), (40, 33), (5, 3)])
+@pytest.mark.parametrize("edge,mode", [("clamp", "nearest"), ("const", "constant"),
+                                       ("cyclic", "wrap")])
+def test_mapoverlap2d_scipy(oracle_mod, shape, edge, mode):
+    x = si.uniform_f32(shape[0] * shape[1], 0.0, 1.0, 3, 7).reshape(shape)
+    w = si.uniform_f32(5 * 7, -1.0, 1.0, 3, 8).reshape(5, 7)  # ry = 2, rx = 3
+    out, mag = oracle_mod.mapoverlap2d(x, 2, 3, w2d=w, edge=edge, pad=-0.5)
+    ref = ndi.correlate(x.astype(np.float64), w.astype(np.float64), mode=mode,
+                        cval=-0.5)
+    assert np.all(np.abs(out - ref) <= 1e-14 * mag)
+
+
+def test_mapoverlap2d_impulse_and_transpose(oracle_mod):
+    # W not symmetric: the impulse response is W flipped in both axes, which
+    # exposes a transposed or mirrored weight index
+    w = np.arange(1, 16, dtype=np.float32).reshape(3, 5)  # ry = 1, rx = 2
+    x = np.zeros((9, 11), np.float32)
+    x[4, 5] = 1
+    out, _ = oracle_mod.mapoverlap2d(x, 1, 2, w2d=w)
+    assert np.array_equal(out[3:6, 3:8], w[::-1, ::-1].astype(np.float64))
+    assert np.count_nonzero(out) == 15
+
+
+def test_mapoverlap2d_separable_and_constant(oracle_mod):
+    g = si.gaussian_weights(4, 2.0)
+    x = si.uniform_f32(37 * 29, 0.0, 1.0, 1, 0).reshape(37, 29)
+    sep, mag = oracle_mod.mapoverlap2d(x, 4, 4, wy=g, wx=g)
+    full = np.outer(g.astype(np.float64), g.astype(np.float64))
+    # the 2D weights as binary32 products would round; the separable form uses
+    # the exact binary64 outer product, equal to correlate with that W
+    ref = ndi.correlate(x.astype(np.float64), full, mode="nearest")
+    assert np.all(np.abs(sep - ref) <= 1e-14 * mag)
+    # separable identity: rows(wx) then columns(wy) in binary64
+    rows = ndi.correlate1d(x.astype(np.float64), g.astype(np.float64), axis=1,
+                           mode="nearest")
+    both = ndi.correlate1d(rows, g.astype(np.float64), axis=0, mode="nearest")
+    assert np.all(np.abs(sep - both) <= 1e-14 * mag)
+    # constant field -> c * (sum w)^2 everywhere, corners included
+    c = np.float32(0.3)
+    out, _ = oracle_mod.mapoverlap2d(np.full((20, 20), c, np.float32), 4, 4,
+                                     wy=g, wx=g)
+    sw = math.fsum(float(v) for v in g)
+    assert np.all(np.abs(out - float(c) * sw * sw) <= 1e-15)
+    assert sw * sw == pytest.approx(1.0000000223517418, abs=1e-15)
+    # separable factors that differ: W[a][b] = wy[a] * wx[b], not wy[b] * wx[a]
+    wy = np.array([0.25, 0.5, -1.0], np.float32)
+    wx = np.array([2.0, -0.125, 0.75, 1.5, 3.0], np.float32)
+    s2, m2 = oracle_mod.mapoverlap2d(x, 1, 2, wy=wy, wx=wx)
+    ref = ndi.correlate(x.astype(np.float64),
+                        np.outer(wy.astype(np.float64), wx.astype(np.float64)),
+                        mode="nearest")
+    assert np.all(np.abs(s2 - ref) <= 1e-14 * m2)
+    # single-output form agrees with the full form
+    for (i, j) in ((0, 0), (36, 28), (18, 3)):
+        v, m = oracle_mod.mapoverlap2d_at(x, 4, 4, i, j, wy=g, wx=g)
+        assert v == sep[i, j] and m == mag[i, j]
+
+
+# -------------------------------------------------------------------- Scan --
+
+def test_scan_closed_forms(oracle_mod):
+    n = 100000
+    ones = np.ones(n, np.int32)
+    assert np.array_equal(oracle_mod.scan(ones, "inclusive"), np.arange(1, n + 1))
+    assert np.array_equal(oracle_mod.scan(ones, "exclusive"), np.arange(n))
+    x = si.int_uniform_i32(n, 1000, 1, 0)
+    inc = oracle_mod.scan(x, "inclusive", "sum", np.int64)
+    exc = oracle_mod.scan(x, "exclusive", "sum", np.int64)
+    assert inc[-1] == oracle_mod.reduce("sum", x, np.int64)
+    assert exc[0] == 0
+    assert np.array_equal(np.diff(exc), x[:-1].astype(np.int64))
+    assert exc[-1] + x[-1] == inc[-1]
+    assert np.array_equal(inc, np.cumsum(x, dtype=np.int64))
+
+
+def test_scan_wrap_and_library(oracle_mod):
+    x = si.rng(2, 3).integers(-2 ** 31, 2 ** 31, 5000, dtype=np.int64).astype(np.int32)
+    inc32 = oracle_mod.scan(x, "inclusive")
+    inc64 = oracle_mod.scan(x, "inclusive", "sum", np.int64)
+    assert np.array_equal(inc64, np.cumsum(x.astype(np.int64)))
+    assert np.array_equal(inc32, inc64.astype(np.int32))  # mod 2^32
+    assert np.array_equal(oracle_mod.scan(x, "inclusive", "min"),
+                          np.minimum.accumulate(x))
+    assert np.array_equal(oracle_mod.scan(x, "inclusive", "max", np.int64),
+                          np.maximum.accumulate(x.astype(np.int64)))
+    exc = oracle_mod.scan(x, "exclusive", "min")
+    assert exc[0] == 2 ** 31 - 1
+    assert np.array_equal(exc[1:], np.minimum.accumulate(x)[:-1])
+    xl = si.rng(2, 4).integers(-2 ** 62, 2 ** 62, 3000, dtype=np.int64)
+    with np.errstate(over="ignore"):
+        assert np.array_equal(oracle_mod.scan(xl, "inclusive"), np.cumsum(xl))
+
+
+def test_scan_f32(oracle_mod):
+    x = si.normal_f32(3000, 0, 11)
+    out, mag = oracle_mod.scan(x, "inclusive")
+    assert np.array_equal(out, np.cumsum(x.astype(np.float64)))
+    assert np.array_equal(mag, np.cumsum(np.abs(x.astype(np.float64))))
+    exc, emag = oracle_mod.scan(x, "exclusive")
+    assert exc[0] == 0.0 and emag[0] == 0.0
+    assert np.array_equal(exc[1:], out[:-1])
+    assert out[-1] == oracle_mod.reduce("sum", x)
+    mx, _ = oracle_mod.scan(x, "inclusive", "max")
+    assert np.array_equal(mx, np.maximum.accumulate(x.astype(np.float64)))
+
+
+def test_scan_bruteforce_tiny(oracle_mod):
+    rng = si.rng(5, 5)
+    for n in range(0, 65):
+        x = rng.integers(-50, 51, n, dtype=np.int32)
+        for op, fn in (("sum", lambda a, b: a + b), ("min", min), ("max", max)):
+            acc = None
+            inc, exc = [], []
+            ident = {"sum": 0, "min": 2 ** 31 - 1, "max": -2 ** 31}[op]
+            for v in x:
+                exc.append(ident if acc is None else acc)
+                acc = int(v) if acc is None else fn(acc, int(v))
+                inc.append(acc)
+            assert oracle_mod.scan(x, "inclusive", op).tolist() == inc
+            assert oracle_mod.scan(x, "exclusive", op).tolist() == exc
+
+
+# ------------------------------------------------------------ generators --
+
+def test_generators_reproducible_and_on_grid():
+    a = si.uniform_f32(1000, -1.0, 1.0, 0, 0)
+    b = si.uniform_f32(1000, -1.0, 1.0, 0, 0)
+    assert np.array_equal(a, b) and a.dtype == np.float32
+    assert a.min() >= -1 and a.max() < 1
+    assert np.all((a.astype(np.float64) * 2 ** 23) % 1 == 0)
+    g = si.gaussian_weights()
+    assert g.dtype == np.float32 and g.size == 9
+    assert g[4] == np.float32(0.20416368544101715)
+    assert g[0] == g[8] == np.float32(0.027630550786852837)
+    lens = si.log_uniform_lengths(4096, 32, 1 << 20)
+    assert lens.min() >= 32 and lens.max() <= 1 << 20
+    h = si.bf16_bits_from_f32(np.array([1.0, -2.5, 3.0e-3, 1.00390625], np.float32))
+    assert h.tolist() == [0x3F80, 0xC020, 0x3B45, 0x3F80]  # last: tie to even
