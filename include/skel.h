@@ -1,0 +1,274 @@
+/*
+ * skel.h -- C ABI of libskel, a library of data-parallel skeletons over smart
+ * containers for one AMD Instinct MI355X (gfx950) GPU.
+ *
+ * Source of the concepts: Kessler, Dastgeer, Li, "Optimized Composition:
+ * Generating Efficient Code for Heterogeneous Systems from Multi-Variant
+ * Components, Skeletons and Containers" (arXiv:1405.2915).
+ *   - Section III: skeletons are generic components derived from higher-order
+ *     functions (map, scan, reduce, ...; mapoverlap among the data-parallel
+ *     ones), parameterised by a user function; every skeleton has several
+ *     implementation variants, and an execution plan picks one per call
+ *     context (problem size, ...).
+ *   - Section II: conditional composition (selectability constraints per
+ *     variant) and static / off-line-tuned selection.
+ *   - Section IV: smart containers own the operand data, track where valid
+ *     copies live (a software coherence protocol), copy lazily, and never let a
+ *     stale copy be read.
+ *   - Section V: calls are asynchronous; containers carry the dependences.
+ *
+ * The paper defines none of these operations by formula.  The definitions
+ * stated with each call below are the textbook ones and are the contract.
+ *
+ * General conventions
+ *   - Every call returns a skel_status and never aborts or throws.  On an
+ *     error, skel_last_error() returns a message (thread-local, valid until
+ *     the next call on the same thread).  Arguments are validated before any
+ *     work is enqueued: a call that fails validation has no side effect.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Skeleton calls are asynchronous on it; results stay in device memory
+ *     until a host acquire asks for them (Section V).
+ *   - Element counts and sizes are int64_t; containers may hold up to 2^31
+ *     elements per axis and more than 2^32 bytes.
+ *   - Thread compatibility: distinct containers may be used from distinct
+ *     threads; calls on one container must not overlap.
+ *   - `variant` selects an implementation variant by index (see
+ *     skel_variant_name), or SKEL_VARIANT_AUTO to let the library's execution
+ *     plan choose from the call context.  Forcing a variant whose
+ *     selectability constraint does not hold returns SKEL_E_UNSUPPORTED.
+ */
+#ifndef SKEL_H
+#define SKEL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum skel_status {
+    SKEL_OK = 0,
+    SKEL_E_INVAL = 1,       /* null pointer, unknown enum, bad count/radius  */
+    SKEL_E_DTYPE = 2,       /* element type combination not supported        */
+    SKEL_E_SHAPE = 3,       /* operand sizes do not match                    */
+    SKEL_E_NOMEM = 4,       /* host or device allocation failed              */
+    SKEL_E_STATE = 5,       /* container access conflict or uninitialised read */
+    SKEL_E_UNSUPPORTED = 6, /* forced variant not selectable for this call   */
+    SKEL_E_HIP = 7,         /* HIP runtime error (message has the HIP text)  */
+    SKEL_E_NOINIT = 8,      /* skel_init has not been called                 */
+    SKEL_E_TIMEOUT = 9      /* a kernel's bounded inter-workgroup wait expired */
+} skel_status;
+
+typedef enum skel_dtype {
+    SKEL_F32 = 0,  /* IEEE binary32                          */
+    SKEL_BF16 = 1, /* bfloat16 (storage only, computed in f32) */
+    SKEL_I32 = 2,  /* two's-complement 32-bit                */
+    SKEL_I64 = 3   /* two's-complement 64-bit                */
+} skel_dtype;
+
+typedef enum skel_place { SKEL_HOST = 0, SKEL_DEVICE = 1 } skel_place;
+typedef enum skel_access { SKEL_READ = 1, SKEL_WRITE = 2, SKEL_RW = 3 } skel_access;
+
+/* border rule of MapOverlap: replicate the edge element, read a constant
+ * pad value, or wrap around (periodic) */
+typedef enum skel_edge {
+    SKEL_EDGE_CLAMP = 0,
+    SKEL_EDGE_CONST = 1,
+    SKEL_EDGE_CYCLIC = 2
+} skel_edge;
+
+typedef enum skel_scan_kind { SKEL_INCLUSIVE = 0, SKEL_EXCLUSIVE = 1 } skel_scan_kind;
+
+/* associative and commutative combining operator of Reduce / Scan */
+typedef enum skel_reduce_op { SKEL_SUM = 0, SKEL_MIN = 1, SKEL_MAX = 2 } skel_reduce_op;
+
+/* Built-in user functions f(x, y; p0, p1) of Map / MapReduce (a skeleton
+ * instance is a skeleton plus its user function, Section III).  Parameters
+ * are rounded to binary32, the type the kernels compute in. */
+typedef enum skel_map_op {
+    SKEL_MAP_IDENTITY = 0,    /* x               (1 input,  0 params) */
+    SKEL_MAP_AXPY = 1,        /* p0*x + y        (2 inputs, 1 param, fused multiply-add) */
+    SKEL_MAP_AFFINE = 2,      /* p0*x + p1       (1 input,  2 params) */
+    SKEL_MAP_TANH = 3,        /* tanh(x)         (1 input,  0 params) */
+    SKEL_MAP_AFFINE_TANH = 4, /* tanh(p0*x + p1) (1 input,  2 params) */
+    SKEL_MAP_MUL = 5,         /* x*y             (2 inputs, 0 params) */
+    SKEL_MAP_SQUARE = 6       /* x*x             (1 input,  0 params) */
+} skel_map_op;
+
+/* skeleton ids for the variant registry */
+typedef enum skel_skeleton {
+    SKEL_SK_MAP = 0,
+    SKEL_SK_REDUCE = 1,
+    SKEL_SK_MAPREDUCE = 2,
+    SKEL_SK_MAPOVERLAP1D = 3,
+    SKEL_SK_MAPOVERLAP2D = 4,
+    SKEL_SK_SCAN = 5,
+    SKEL_SK_COUNT = 6
+} skel_skeleton;
+
+#define SKEL_VARIANT_AUTO (-1)
+#define SKEL_MAX_RADIUS_1D 64
+#define SKEL_MAX_RADIUS_2D 8
+
+/* Opaque smart container (Section IV): a Vector (rows = 1) or a row-major
+ * Matrix, owned by the library. */
+typedef struct skel_container skel_container;
+
+/* Device-memory provider.  alloc returns a device pointer aligned to at least
+ * 256 bytes (NULL on failure); free releases it, stream-ordered on `stream`.
+ * Both are called from the thread that makes the library call. */
+typedef struct skel_allocator {
+    void *(*alloc)(size_t bytes, void *stream, void *ctx);
+    void (*free)(void *ptr, void *stream, void *ctx);
+    void *ctx;
+} skel_allocator;
+
+/* Transfer accounting of one container (Section IV, lazy copying).
+ *   h2d / d2h          copies the coherence protocol actually issued
+ *   h2d_bytes/d2h_bytes their sizes
+ *   eager_equiv        copies an eager scheme would have issued: one host-to-
+ *                      device copy per skeleton call that reads the container
+ *                      and one device-to-host copy per call that writes it
+ *   acquires           successful acquire calls (host or device)          */
+typedef struct skel_xfer_stats {
+    uint64_t h2d, d2h, h2d_bytes, d2h_bytes, eager_equiv, acquires;
+} skel_xfer_stats;
+
+/* ------------------------------------------------------------ runtime --- */
+
+/* Bind the library to HIP device `device` (it becomes the current device of
+ * the calling thread) and set the device-memory provider (NULL = hipMalloc /
+ * hipFree).  May be called again with the same device to change the
+ * provider; containers keep the provider they were created under. */
+skel_status skel_init(int device, const skel_allocator *alloc);
+
+/* Release the library's per-stream workspaces (not containers).  Blocks until
+ * the device is idle.  skel_init may be called again afterwards. */
+skel_status skel_finalize(void);
+
+/* Wait for all work on `stream`, then report any error a kernel flagged (a
+ * bounded wait that expired gives SKEL_E_TIMEOUT). */
+skel_status skel_sync(void *stream);
+
+const char *skel_last_error(void);
+
+/* ---------------------------------------------------------- containers --- */
+
+/* Create a rows x cols container of `dtype` (rows >= 1, cols >= 0).  If
+ * host_src is non-NULL, rows*cols elements are copied from it (the caller may
+ * free it on return) and the host copy is the valid one; otherwise the
+ * container is uninitialised and must be written before it is read. */
+skel_status skel_container_create(skel_dtype dtype, int64_t rows, int64_t cols,
+                                  const void *host_src, skel_container **out);
+
+/* Destroy a container with no outstanding acquire; device memory is released
+ * stream-ordered after the last device access. */
+skel_status skel_container_destroy(skel_container *c);
+
+/* Section IV coherence protocol.  Make the copy at `place` usable for
+ * `access` and return its address in *ptr_out (valid until release):
+ *   READ  copies from the other place iff this copy is stale;
+ *   WRITE copies nothing and invalidates the other copy (whole overwrite);
+ *   RW    both.
+ * A device acquire enqueues its copy on `stream` and orders it after the
+ * container's last device access on any other stream.  A host acquire waits
+ * for the container's device work to finish.  Errors: SKEL_E_STATE when a
+ * WRITE/RW acquire is outstanding, when WRITE/RW meets outstanding readers,
+ * or when READ/RW finds no valid copy. */
+skel_status skel_container_acquire(skel_container *c, skel_place place,
+                                   skel_access access, void *stream,
+                                   void **ptr_out);
+
+/* End the access begun by the matching acquire at `place`; a device release
+ * records the container's last-access event on `stream`. */
+skel_status skel_container_release(skel_container *c, skel_place place,
+                                   void *stream);
+
+skel_status skel_container_stats(const skel_container *c, skel_xfer_stats *out);
+
+/* rows, cols and dtype of a container (any output pointer may be NULL) */
+skel_status skel_container_info(const skel_container *c, skel_dtype *dtype,
+                                int64_t *rows, int64_t *cols);
+
+/* ----------------------------------------------------------- skeletons --- */
+
+/* Map (Section III): out[i] = f(in[0][i], in[1][i]) for every element i.
+ * nin is 1 or 2 as the op requires; all containers are F32 with the same
+ * element count.  `out` may be one of the inputs (in-place). */
+skel_status skel_map(skel_map_op op, const double *params, int nparams,
+                     skel_container *const *in, int nin, skel_container *out,
+                     int variant, void *stream);
+
+/* Reduce (Section III): out1[0] = in[0] op in[1] op ... op in[n-1].
+ * Type pairs (in -> out1): F32 -> F32 (binary32 accumulation),
+ * BF16 -> F32, I32 -> I32 (wraps mod 2^32), I32 -> I64, I64 -> I64.  out1
+ * holds one element.  n = 0 gives the identity (0, +inf / INT_MAX,
+ * -inf / INT_MIN). */
+skel_status skel_reduce(skel_reduce_op op, skel_container *in,
+                        skel_container *out1, int variant, void *stream);
+
+/* MapReduce: out1[0] = op over i of f(in[0][i], in[1][i]) with no stored
+ * intermediate.  Inputs F32 (or BF16 for IDENTITY/MUL/SQUARE), out1 F32. */
+skel_status skel_mapreduce(skel_map_op map_op, const double *params,
+                           int nparams, skel_container *const *in, int nin,
+                           skel_reduce_op op, skel_container *out1,
+                           int variant, void *stream);
+
+/* MapOverlap 1D: out[i] = sum_{k=0}^{2r} w[k] * in[e(i + k - r)] over a
+ * vector of n F32 elements (correlation orientation: w[0] weighs the lowest
+ * index).  e() applies `edge` (pad is the CONST value).  w holds 2r+1 floats
+ * (copied at call time); 0 <= r <= SKEL_MAX_RADIUS_1D.  out != in. */
+skel_status skel_mapoverlap1d(skel_container *in, skel_container *out,
+                              const float *w, int radius, skel_edge edge,
+                              float pad, int variant, void *stream);
+
+/* MapOverlap 2D on a rows x cols F32 matrix:
+ *   out[i][j] = sum_{a=0}^{2ry} sum_{b=0}^{2rx} W[a][b] * in[e(i+a-ry)][e(j+b-rx)]
+ * W is w2d ((2ry+1) x (2rx+1) row-major) when non-NULL, else the separable
+ * outer product wy[a] * wx[b].  0 <= ry, rx <= SKEL_MAX_RADIUS_2D.  Weights
+ * are copied at call time.  out != in. */
+skel_status skel_mapoverlap2d(skel_container *in, skel_container *out,
+                              const float *w2d, const float *wy,
+                              const float *wx, int ry, int rx, skel_edge edge,
+                              float pad, int variant, void *stream);
+
+/* Scan (Section III): inclusive out[i] = in[0] op ... op in[i]; exclusive
+ * out[0] = identity, out[i] = in[0] op ... op in[i-1].  Type pairs: I32 ->
+ * I32 (wraps), I32 -> I64, I64 -> I64 (exact, wrapping), F32 -> F32.  out may
+ * equal in when the types agree. */
+skel_status skel_scan(skel_container *in, skel_container *out,
+                      skel_scan_kind kind, skel_reduce_op op, int variant,
+                      void *stream);
+
+/* ------------------------------------------- variants and selection ---- */
+
+int skel_variant_count(int skeleton);
+const char *skel_variant_name(int skeleton, int variant); /* NULL if out of range */
+
+/* The execution plan's choice (Section III) for a call context, without
+ * running anything: returns the variant index, or -1 if none is selectable.
+ * n is the element count (rows*cols for 2D); `separable` is 1 when the 2D
+ * weights are given as factors; dtype is the input element type. */
+int skel_select_variant(int skeleton, skel_dtype dtype, int64_t n,
+                        int64_t rows, int64_t cols, int separable);
+
+/* Load a size-keyed dispatch table produced by off-line tuning (Section II:
+ * a precomputed dispatch structure for fast run-time lookup; Section III:
+ * execution plans built off-line per target system).  Text, one entry per
+ * line, '#' starts a comment:
+ *     <SKELETON> <dtype> <log2 n> <variant name or index>
+ * e.g. "REDUCE f32 20 R2_ticket".  A call of size n uses the entry with the
+ * largest log2 n <= ceil(log2 n) for its skeleton and input dtype (sizes
+ * beyond the table extrapolate from its last entry, sizes below use its
+ * first).  An entry that is not selectable for a call falls back to the
+ * static rules.  The whole file is validated before it replaces the current
+ * table; on error the old table stays.  SKEL_VARIANT_<SKELETON>=<name> in the
+ * environment overrides both. */
+skel_status skel_load_plan(const char *path);
+skel_status skel_clear_plan(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SKEL_H */

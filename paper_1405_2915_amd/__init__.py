@@ -1,0 +1,459 @@
+"""Python binding of libskel: data-parallel skeletons over smart containers on
+one MI355X (gfx950).
+
+Each ``skel_*`` function below marshals its arguments and calls the C entry
+point of the same name in ``libskel.so`` (declared in ``include/skel.h``);
+every step of the computation runs in the library's HIP kernels.  PyTorch is
+used only as plumbing: its caching allocator provides device memory and its
+current stream orders the calls.  If ``libskel.so`` has not been built, import
+of the library fails loudly -- there is no fallback.
+
+Concepts (Kessler, Dastgeer, Li, arXiv:1405.2915): skeletons with several
+implementation variants and an execution plan (Section III), smart containers
+with lazy host/device coherence (Section IV), asynchronous calls ordered by
+container dependences (Section V).
+"""
+from __future__ import annotations
+
+import atexit
+import ctypes as C
+import os
+import weakref
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libskel.so")
+
+# ------------------------------------------------------------- skel.h enums
+OK, E_INVAL, E_DTYPE, E_SHAPE, E_NOMEM, E_STATE, E_UNSUPPORTED, E_HIP, E_NOINIT, \
+    E_TIMEOUT = range(10)
+STATUS_NAMES = {0: "SKEL_OK", 1: "SKEL_E_INVAL", 2: "SKEL_E_DTYPE", 3: "SKEL_E_SHAPE",
+                4: "SKEL_E_NOMEM", 5: "SKEL_E_STATE", 6: "SKEL_E_UNSUPPORTED",
+                7: "SKEL_E_HIP", 8: "SKEL_E_NOINIT", 9: "SKEL_E_TIMEOUT"}
+F32, BF16, I32, I64 = 0, 1, 2, 3
+HOST, DEVICE = 0, 1
+READ, WRITE, RW = 1, 2, 3
+EDGE_CLAMP, EDGE_CONST, EDGE_CYCLIC = 0, 1, 2
+INCLUSIVE, EXCLUSIVE = 0, 1
+SUM, MIN, MAX = 0, 1, 2
+MAP_IDENTITY, MAP_AXPY, MAP_AFFINE, MAP_TANH, MAP_AFFINE_TANH, MAP_MUL, MAP_SQUARE = range(7)
+SK_MAP, SK_REDUCE, SK_MAPREDUCE, SK_MAPOVERLAP1D, SK_MAPOVERLAP2D, SK_SCAN = range(6)
+VARIANT_AUTO = -1
+MAX_RADIUS_1D, MAX_RADIUS_2D = 64, 8
+
+NP_DTYPE = {F32: np.dtype(np.float32), BF16: np.dtype(np.uint16), I32: np.dtype(np.int32),
+            I64: np.dtype(np.int64)}
+DTYPE_OF_NP = {np.dtype(np.float32): F32, np.dtype(np.int32): I32,
+               np.dtype(np.int64): I64}
+
+
+class SkelError(RuntimeError):
+    def __init__(self, status: int, where: str, message: str):
+        self.status = status
+        super().__init__(f"{where}: {STATUS_NAMES.get(status, status)}: {message}")
+
+
+class _XferStats(C.Structure):
+    _fields_ = [(k, C.c_uint64) for k in
+                ("h2d", "d2h", "h2d_bytes", "d2h_bytes", "eager_equiv", "acquires")]
+
+
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+
+
+class _Allocator(C.Structure):
+    _fields_ = [("alloc", _ALLOC_FN), ("free", _FREE_FN), ("ctx", C.c_void_p)]
+
+
+_lib = None
+_live = weakref.WeakSet()
+_keepalive = []
+_shutting_down = False
+_device = 0
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libskel.so and declare its C signatures.  Raises ImportError with
+    the build command when the library is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built; run `python -m paper_1405_2915_amd.build_lib`"
+                          " (the HIP library is required, there is no fallback)")
+    lib = C.CDLL(path)
+    st, vp, i64, i = C.c_int, C.c_void_p, C.c_int64, C.c_int
+    dp = C.POINTER(C.c_double)
+    fp = C.POINTER(C.c_float)
+    sig = {
+        "skel_init": (st, [i, C.POINTER(_Allocator)]),
+        "skel_finalize": (st, []),
+        "skel_sync": (st, [vp]),
+        "skel_last_error": (C.c_char_p, []),
+        "skel_container_create": (st, [i, i64, i64, vp, C.POINTER(vp)]),
+        "skel_container_destroy": (st, [vp]),
+        "skel_container_acquire": (st, [vp, i, i, vp, C.POINTER(vp)]),
+        "skel_container_release": (st, [vp, i, vp]),
+        "skel_container_stats": (st, [vp, C.POINTER(_XferStats)]),
+        "skel_container_info": (st, [vp, C.POINTER(i), C.POINTER(i64), C.POINTER(i64)]),
+        "skel_map": (st, [i, dp, i, C.POINTER(vp), i, vp, i, vp]),
+        "skel_reduce": (st, [i, vp, vp, i, vp]),
+        "skel_mapreduce": (st, [i, dp, i, C.POINTER(vp), i, i, vp, i, vp]),
+        "skel_mapoverlap1d": (st, [vp, vp, fp, i, i, C.c_float, i, vp]),
+        "skel_mapoverlap2d": (st, [vp, vp, fp, fp, fp, i, i, i, C.c_float, i, vp]),
+        "skel_scan": (st, [vp, vp, i, i, i, vp]),
+        "skel_variant_count": (i, [i]),
+        "skel_variant_name": (C.c_char_p, [i, i]),
+        "skel_select_variant": (i, [i, i, i64, i64, i64, i]),
+        "skel_load_plan": (st, [C.c_char_p]),
+        "skel_clear_plan": (st, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _L():
+    return _lib if _lib is not None else load_library()
+
+
+def _check(status: int, where: str) -> None:
+    if status != OK:
+        msg = _lib.skel_last_error()
+        raise SkelError(status, where, msg.decode() if msg else "")
+
+
+def _current_stream() -> int:
+    try:
+        import torch
+        if torch.cuda.is_initialized():
+            return torch.cuda.current_stream().cuda_stream
+    except ImportError:
+        pass
+    return 0
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        return _current_stream()
+    if hasattr(stream, "cuda_stream"):
+        return stream.cuda_stream
+    return int(stream)
+
+
+# ----------------------------------------------------------------- runtime
+def skel_init(device: int = 0, allocator: str = "torch") -> None:
+    """Bind the library to `device`.  allocator="torch" routes device memory
+    through torch's caching allocator; "hip" uses hipMalloc/hipFree."""
+    global _device
+    lib = load_library()
+    _device = device
+    if allocator == "torch":
+        import torch
+        torch.cuda.init()
+        torch.cuda.set_device(device)
+
+        def _alloc(nbytes, stream, ctx):
+            try:
+                return torch.cuda.caching_allocator_alloc(int(nbytes), device, int(stream or 0))
+            except Exception:  # out of memory: report NULL to the library
+                return None
+
+        def _free(ptr, stream, ctx):
+            if not _shutting_down:
+                torch.cuda.caching_allocator_delete(ptr)
+
+        a = _Allocator(_ALLOC_FN(_alloc), _FREE_FN(_free), None)
+        _keepalive[:] = [a]
+        _check(lib.skel_init(device, C.byref(a)), "skel_init")
+    elif allocator == "hip":
+        _check(lib.skel_init(device, None), "skel_init")
+    else:
+        raise ValueError(f"unknown allocator {allocator!r}")
+
+
+def skel_finalize() -> None:
+    _check(load_library().skel_finalize(), "skel_finalize")
+
+
+def skel_sync(stream=None) -> None:
+    _check(load_library().skel_sync(C.c_void_p(_stream(stream))), "skel_sync")
+
+
+def skel_last_error() -> str:
+    m = load_library().skel_last_error()
+    return m.decode() if m else ""
+
+
+# -------------------------------------------------------------- containers
+class Container:
+    """A smart container (Section IV): library-owned host and device copies
+    with lazy coherence.  Wraps the opaque skel_container handle."""
+
+    def __init__(self, handle: int, dtype: int, rows: int, cols: int):
+        self.handle = handle
+        self.dtype = dtype
+        self.rows = rows
+        self.cols = cols
+        _live.add(self)
+
+    @property
+    def shape(self):
+        return (self.rows, self.cols)
+
+    @property
+    def n(self) -> int:
+        return self.rows * self.cols
+
+    @classmethod
+    def from_numpy(cls, arr: np.ndarray, dtype: int | None = None) -> "Container":
+        arr = np.ascontiguousarray(arr)
+        if dtype is None:
+            dtype = DTYPE_OF_NP[arr.dtype]
+        if arr.dtype != NP_DTYPE[dtype]:
+            raise TypeError(f"array dtype {arr.dtype} does not store skel dtype {dtype}")
+        rows, cols = (1, arr.size) if arr.ndim <= 1 else (arr.shape[0], arr.size // arr.shape[0])
+        return skel_container_create(dtype, rows, cols, arr)
+
+    @classmethod
+    def empty(cls, dtype: int, rows: int, cols: int | None = None) -> "Container":
+        if cols is None:
+            rows, cols = 1, rows
+        return skel_container_create(dtype, rows, cols, None)
+
+    def to_numpy(self) -> np.ndarray:
+        """Host acquire for READ (copies from the device only if the host copy
+        is stale), copy out, release."""
+        ptr = skel_container_acquire(self, HOST, READ)
+        try:
+            dt = NP_DTYPE[self.dtype]
+            out = np.empty(self.n, dtype=dt)
+            if self.n:
+                C.memmove(out.ctypes.data, ptr, self.n * dt.itemsize)
+        finally:
+            skel_container_release(self, HOST)
+        return out.reshape(self.shape) if self.rows > 1 else out
+
+    def write_numpy(self, arr: np.ndarray) -> None:
+        """Host acquire for WRITE (invalidates the device copy), fill, release."""
+        dt = NP_DTYPE[self.dtype]
+        arr = np.ascontiguousarray(arr, dtype=dt).reshape(-1)
+        if arr.size != self.n:
+            raise ValueError("size mismatch")
+        ptr = skel_container_acquire(self, HOST, WRITE)
+        try:
+            if self.n:
+                C.memmove(ptr, arr.ctypes.data, self.n * dt.itemsize)
+        finally:
+            skel_container_release(self, HOST)
+
+    def stats(self) -> dict:
+        return skel_container_stats(self)
+
+    def destroy(self) -> None:
+        if self.handle:
+            h, self.handle = self.handle, None
+            _check(_L().skel_container_destroy(C.c_void_p(h)), "skel_container_destroy")
+
+    def __del__(self):
+        if self.handle and not _shutting_down and _lib is not None:
+            try:
+                self.destroy()
+            except Exception:
+                pass
+
+
+def _h(c):
+    if c is None:
+        return None
+    if not isinstance(c, Container) or not c.handle:
+        raise TypeError("expected a live Container")
+    return C.c_void_p(c.handle)
+
+
+def skel_container_create(dtype: int, rows: int, cols: int, host_src=None) -> Container:
+    lib = load_library()
+    out = C.c_void_p()
+    src = None
+    if host_src is not None:
+        host_src = np.ascontiguousarray(host_src)
+        if host_src.size != rows * cols:
+            raise ValueError("host_src size does not match rows*cols")
+        src = C.c_void_p(host_src.ctypes.data)
+    _check(lib.skel_container_create(dtype, rows, cols, src, C.byref(out)),
+           "skel_container_create")
+    return Container(out.value, dtype, rows, cols)
+
+
+def skel_container_destroy(c: Container) -> None:
+    c.destroy()
+
+
+def skel_container_acquire(c: Container, place: int, access: int, stream=None) -> int:
+    ptr = C.c_void_p()
+    _check(_L().skel_container_acquire(_h(c), place, access, C.c_void_p(_stream(stream)),
+                                       C.byref(ptr)), "skel_container_acquire")
+    return ptr.value or 0
+
+
+def skel_container_release(c: Container, place: int, stream=None) -> None:
+    _check(_L().skel_container_release(_h(c), place, C.c_void_p(_stream(stream))),
+           "skel_container_release")
+
+
+def skel_container_stats(c: Container) -> dict:
+    s = _XferStats()
+    _check(_L().skel_container_stats(_h(c), C.byref(s)), "skel_container_stats")
+    return {k: int(getattr(s, k)) for k, _ in _XferStats._fields_}
+
+
+def skel_container_info(c: Container):
+    dt, r, cc = C.c_int(), C.c_int64(), C.c_int64()
+    _check(_L().skel_container_info(_h(c), C.byref(dt), C.byref(r), C.byref(cc)),
+           "skel_container_info")
+    return dt.value, r.value, cc.value
+
+
+# --------------------------------------------------------------- skeletons
+def _params(params):
+    p = np.ascontiguousarray(np.asarray(params if params is not None else [],
+                                        dtype=np.float64))
+    return p, (p.ctypes.data_as(C.POINTER(C.c_double)) if p.size else None), p.size
+
+
+def _handles(cs):
+    arr = (C.c_void_p * len(cs))(*[c.handle for c in cs])
+    return arr, len(cs)
+
+
+def _floats(w):
+    if w is None:
+        return None, None
+    a = np.ascontiguousarray(np.asarray(w, dtype=np.float32)).reshape(-1)
+    return a, a.ctypes.data_as(C.POINTER(C.c_float))
+
+
+def skel_map(op: int, params, ins, out: Container, variant: int = VARIANT_AUTO,
+             stream=None) -> None:
+    """Map: out[i] = f(ins[0][i], ins[1][i])."""
+    for c in ins:
+        _h(c)
+    _h(out)
+    p, pp, np_ = _params(params)
+    arr, nin = _handles(ins)
+    _check(_L().skel_map(op, pp, np_, arr, nin, _h(out), variant,
+                         C.c_void_p(_stream(stream))), "skel_map")
+
+
+def skel_reduce(op: int, inp: Container, out1: Container, variant: int = VARIANT_AUTO,
+                stream=None) -> None:
+    _check(_L().skel_reduce(op, _h(inp), _h(out1), variant, C.c_void_p(_stream(stream))),
+           "skel_reduce")
+
+
+def skel_mapreduce(map_op: int, params, ins, op: int, out1: Container,
+                   variant: int = VARIANT_AUTO, stream=None) -> None:
+    for c in ins:
+        _h(c)
+    p, pp, np_ = _params(params)
+    arr, nin = _handles(ins)
+    _check(_L().skel_mapreduce(map_op, pp, np_, arr, nin, op, _h(out1), variant,
+                               C.c_void_p(_stream(stream))), "skel_mapreduce")
+
+
+def skel_mapoverlap1d(inp: Container, out: Container, w, radius: int,
+                      edge: int = EDGE_CLAMP, pad: float = 0.0,
+                      variant: int = VARIANT_AUTO, stream=None) -> None:
+    wa, wp = _floats(w)
+    if wa is None or wa.size != 2 * radius + 1:
+        raise ValueError("w must hold 2*radius+1 weights")
+    _check(_L().skel_mapoverlap1d(_h(inp), _h(out), wp, radius, edge, pad, variant,
+                                  C.c_void_p(_stream(stream))), "skel_mapoverlap1d")
+
+
+def skel_mapoverlap2d(inp: Container, out: Container, w2d=None, wy=None, wx=None,
+                      ry: int | None = None, rx: int | None = None,
+                      edge: int = EDGE_CLAMP, pad: float = 0.0,
+                      variant: int = VARIANT_AUTO, stream=None) -> None:
+    a2, p2 = _floats(w2d)
+    ay, py = _floats(wy)
+    ax, px = _floats(wx)
+    if w2d is not None:
+        shp = np.shape(w2d)
+        ry = (shp[0] - 1) // 2 if ry is None else ry
+        rx = (shp[1] - 1) // 2 if rx is None else rx
+        if a2.size != (2 * ry + 1) * (2 * rx + 1):
+            raise ValueError("w2d must be (2ry+1) x (2rx+1)")
+    else:
+        if ay is None or ax is None:
+            raise ValueError("need w2d or both wy and wx")
+        ry = (ay.size - 1) // 2 if ry is None else ry
+        rx = (ax.size - 1) // 2 if rx is None else rx
+        if ay.size != 2 * ry + 1 or ax.size != 2 * rx + 1:
+            raise ValueError("wy / wx sizes must be 2r+1")
+    _check(_L().skel_mapoverlap2d(_h(inp), _h(out), p2, py, px, ry, rx, edge, pad, variant,
+                                  C.c_void_p(_stream(stream))), "skel_mapoverlap2d")
+
+
+def skel_scan(inp: Container, out: Container, kind: int = INCLUSIVE, op: int = SUM,
+              variant: int = VARIANT_AUTO, stream=None) -> None:
+    _check(_L().skel_scan(_h(inp), _h(out), kind, op, variant, C.c_void_p(_stream(stream))),
+           "skel_scan")
+
+
+def skel_variant_count(skeleton: int) -> int:
+    return load_library().skel_variant_count(skeleton)
+
+
+def skel_variant_name(skeleton: int, variant: int):
+    n = load_library().skel_variant_name(skeleton, variant)
+    return n.decode() if n else None
+
+
+def skel_select_variant(skeleton: int, dtype: int, n: int, rows: int = 1, cols: int | None = None,
+                        separable: int = 0) -> int:
+    return load_library().skel_select_variant(skeleton, dtype, n, rows,
+                                              n if cols is None else cols, separable)
+
+
+def skel_load_plan(path: str) -> None:
+    _check(load_library().skel_load_plan(path.encode()), "skel_load_plan")
+
+
+def skel_clear_plan() -> None:
+    _check(load_library().skel_clear_plan(), "skel_clear_plan")
+
+
+def variant_index(skeleton: int, name: str) -> int:
+    for v in range(skel_variant_count(skeleton)):
+        if skel_variant_name(skeleton, v) == name:
+            return v
+    raise KeyError(name)
+
+
+@atexit.register
+def _shutdown():
+    global _shutting_down
+    if _lib is None:
+        return
+    for c in list(_live):
+        try:
+            c.destroy()
+        except Exception:
+            pass
+    try:
+        _L().skel_finalize()
+    except Exception:
+        pass
+    _shutting_down = True
+
+
+# Load eagerly when built, so a broken library fails at import; when it is not
+# built yet (e.g. while running build_lib), every call raises ImportError.
+if os.path.exists(LIB_PATH):
+    load_library()

@@ -1,0 +1,85 @@
+"""Build libskel.so (HIP, gfx950) in-tree, and the CPU-only host-logic test
+library used by the container-protocol tests.
+
+    python -m paper_1405_2915_amd.build_lib [-v]
+
+Every HIP source is compiled by hipcc for gfx950 only, with packed-FP32
+instruction generation disabled.  The container protocol, the execution plan
+and error reporting are plain C++ and are also compiled by g++, together with
+a host-memory fake of the copy backend, into libskel_hosttest.so.
+"""
+from __future__ import annotations
+
+import concurrent.futures as cf
+import os
+import subprocess
+import sys
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+CSRC = os.path.join(PKG, "csrc")
+INC = os.path.join(ROOT, "include")
+BUILD = os.path.join(PKG, "_build")
+LIB = os.path.join(PKG, "libskel.so")
+HOSTTEST_LIB = os.path.join(PKG, "libskel_hosttest.so")
+
+HIP_SOURCES = ["common.cpp", "container.cpp", "dispatch.cpp", "runtime.cpp",
+               "skeletons.cpp", "k_map.hip", "k_reduce.hip", "k_scan.hip",
+               "k_overlap.hip"]
+HOST_SOURCES = ["common.cpp", "container.cpp", "dispatch.cpp"]
+
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
+             "-Wall", "-Wno-unused-function",
+             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+             f"-I{INC}", f"-I{CSRC}"]
+
+
+def _run(cmd, verbose):
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"command failed ({r.returncode}): {' '.join(cmd)}\n"
+                           f"{r.stdout}\n{r.stderr}")
+    if verbose and r.stderr.strip():
+        print(r.stderr, flush=True)
+
+
+def build_hip(verbose: bool = False, jobs: int = 8) -> str:
+    os.makedirs(BUILD, exist_ok=True)
+    objs = []
+    cmds = []
+    for src in HIP_SOURCES:
+        obj = os.path.join(BUILD, src + ".o")
+        objs.append(obj)
+        lang = ["-x", "hip"] if src.endswith(".hip") else []
+        cmds.append([HIPCC] + HIP_FLAGS + lang + ["-c", os.path.join(CSRC, src),
+                                                  "-o", obj])
+    with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
+        list(ex.map(lambda c: _run(c, verbose), cmds))
+    tmp = LIB + ".tmp"
+    _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs,
+         verbose)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+def build_hosttest(verbose: bool = False) -> str:
+    srcs = [os.path.join(CSRC, s) for s in HOST_SOURCES]
+    srcs.append(os.path.join(ROOT, "tests", "host", "fake_backend.cpp"))
+    tmp = HOSTTEST_LIB + ".tmp"
+    _run(["g++", "-std=c++17", "-O1", "-g", "-fPIC", "-shared", "-Wall",
+          f"-I{INC}", f"-I{CSRC}", "-o", tmp] + srcs, verbose)
+    os.replace(tmp, HOSTTEST_LIB)
+    return HOSTTEST_LIB
+
+
+def build(verbose: bool = False) -> None:
+    build_hip(verbose)
+    build_hosttest(verbose)
+
+
+if __name__ == "__main__":
+    build(verbose="-v" in sys.argv)
+    print(LIB)

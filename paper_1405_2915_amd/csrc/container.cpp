@@ -1,0 +1,260 @@
+// Smart-container coherence protocol (Section IV) and its C ABI.
+//
+// Each container has a host copy and a device copy with one validity bit
+// each.  Reading a copy that is stale triggers exactly one transfer from the
+// other (the only other holder on a one-GPU system); writing a copy makes the
+// other stale.  Nothing is ever copied eagerly: results stay on the device
+// until the host asks for them, which is what removes the redundant transfers
+// of call sequences (lazy memory copying).
+#include "container.hpp"
+
+#include <cstring>
+#include <new>
+
+namespace skel {
+
+namespace {
+
+bool has_read(skel_access a) { return (a & SKEL_READ) != 0; }
+bool has_write(skel_access a) { return (a & SKEL_WRITE) != 0; }
+
+skel_container::StreamEvent* event_for(skel_container* c, void* stream,
+                                       skel_status* st) {
+    for (auto& e : c->events)
+        if (e.stream == stream) return &e;
+    void* ev = nullptr;
+    *st = rt().backend->event_create(&ev);
+    if (*st != SKEL_OK) return nullptr;
+    c->events.push_back({stream, ev, false, 0, {}});
+    return &c->events.back();
+}
+
+// Make `stream` wait for the last recorded device access of every other
+// stream, skipping events whose current generation it already waited on.
+skel_status order_after_other_streams(skel_container* c, void* stream) {
+    skel_status st = SKEL_OK;
+    if (!event_for(c, stream, &st)) return st;  // entry for `stream` exists now
+    size_t me = 0;
+    while (c->events[me].stream != stream) ++me;
+    for (size_t k = 0; k < c->events.size(); ++k) {
+        const auto& e = c->events[k];
+        if (k == me || !e.recorded) continue;
+        auto& seen = c->events[me].seen;
+        auto it = seen.begin();
+        while (it != seen.end() && it->first != e.stream) ++it;
+        if (it != seen.end() && it->second == e.gen) continue;
+        st = rt().backend->stream_wait_event(stream, e.event);
+        if (st != SKEL_OK) return st;
+        if (it != seen.end()) it->second = e.gen;
+        else seen.emplace_back(e.stream, e.gen);
+    }
+    return SKEL_OK;
+}
+
+// Block until every recorded device access of the container has finished.
+skel_status wait_device_idle(skel_container* c) {
+    for (auto& e : c->events) {
+        if (!e.recorded) continue;
+        skel_status st = rt().backend->event_sync(e.event);
+        if (st != SKEL_OK) return st;
+    }
+    return SKEL_OK;
+}
+
+skel_status ensure_host(skel_container* c) {
+    if (c->host || c->bytes == 0) return SKEL_OK;
+    return rt().backend->host_alloc(&c->host, c->bytes);
+}
+
+}  // namespace
+
+skel_status check_acquire(const skel_container* c, skel_place place,
+                          skel_access access) {
+    if (!c) return fail(SKEL_E_INVAL, "null container");
+    if (place != SKEL_HOST && place != SKEL_DEVICE)
+        return fail(SKEL_E_INVAL, "bad place %d", (int)place);
+    if (access != SKEL_READ && access != SKEL_WRITE && access != SKEL_RW)
+        return fail(SKEL_E_INVAL, "bad access mode %d", (int)access);
+    if (c->writer != -1)
+        return fail(SKEL_E_STATE, "container has an outstanding %s write access",
+                    c->writer == SKEL_HOST ? "host" : "device");
+    if (has_write(access) && (c->host_readers + c->dev_readers) > 0)
+        return fail(SKEL_E_STATE,
+                    "write access requested while %d read access(es) are outstanding",
+                    c->host_readers + c->dev_readers);
+    if (has_read(access) && !c->host_valid && !c->dev_valid)
+        return fail(SKEL_E_STATE, "read of an uninitialised container");
+    return SKEL_OK;
+}
+
+skel_status acquire(skel_container* c, skel_place place, skel_access access,
+                    void* stream, void** ptr) {
+    skel_status st = check_acquire(c, place, access);
+    if (st != SKEL_OK) return st;
+    Backend* be = rt().backend;
+
+    if (place == SKEL_DEVICE) {
+        if (c->bytes > 0) {
+            if (!c->dev) {
+                st = be->dev_alloc(c->allocator, &c->dev, c->bytes, stream);
+                if (st != SKEL_OK) return st;
+            }
+            // order after device work on other streams (Section V dependences)
+            st = order_after_other_streams(c, stream);
+            if (st != SKEL_OK) return st;
+            if (has_read(access) && !c->dev_valid) {
+                st = be->copy_h2d(c->dev, c->host, c->bytes, stream);
+                if (st != SKEL_OK) return st;
+                c->stats.h2d += 1;
+                c->stats.h2d_bytes += c->bytes;
+            }
+        }
+        c->dev_valid = true;
+        if (has_write(access)) c->host_valid = false;
+        c->last_stream = stream;
+        if (has_write(access)) c->writer = SKEL_DEVICE;
+        else c->dev_readers += 1;
+        *ptr = c->dev;
+    } else {
+        st = wait_device_idle(c);
+        if (st != SKEL_OK) return st;
+        if (c->bytes > 0) {
+            st = ensure_host(c);
+            if (st != SKEL_OK) return st;
+            if (has_read(access) && !c->host_valid) {
+                st = be->copy_d2h(c->host, c->dev, c->bytes, c->last_stream);
+                if (st != SKEL_OK) return st;
+                skel_container::StreamEvent* e = event_for(c, c->last_stream, &st);
+                if (!e) return st;
+                st = be->event_record(e->event, c->last_stream);
+                if (st == SKEL_OK) st = be->event_sync(e->event);
+                if (st != SKEL_OK) return st;
+                e->recorded = true;
+                e->gen += 1;
+                c->stats.d2h += 1;
+                c->stats.d2h_bytes += c->bytes;
+            }
+        }
+        c->host_valid = true;
+        if (has_write(access)) c->dev_valid = false;
+        if (has_write(access)) c->writer = SKEL_HOST;
+        else c->host_readers += 1;
+        *ptr = c->host;
+    }
+    c->stats.acquires += 1;
+    return SKEL_OK;
+}
+
+skel_status release(skel_container* c, skel_place place, void* stream) {
+    if (!c) return fail(SKEL_E_INVAL, "null container");
+    if (place != SKEL_HOST && place != SKEL_DEVICE)
+        return fail(SKEL_E_INVAL, "bad place %d", (int)place);
+    if (place == SKEL_DEVICE) {
+        if (c->writer != SKEL_DEVICE && c->dev_readers == 0)
+            return fail(SKEL_E_STATE, "device release without a device acquire");
+        if (c->bytes > 0) {
+            skel_status st;
+            skel_container::StreamEvent* e = event_for(c, stream, &st);
+            if (!e) return st;
+            st = rt().backend->event_record(e->event, stream);
+            if (st != SKEL_OK) return st;
+            e->recorded = true;
+            e->gen += 1;
+            c->last_stream = stream;
+        }
+        if (c->writer == SKEL_DEVICE) c->writer = -1;
+        else c->dev_readers -= 1;
+    } else {
+        if (c->writer != SKEL_HOST && c->host_readers == 0)
+            return fail(SKEL_E_STATE, "host release without a host acquire");
+        if (c->writer == SKEL_HOST) c->writer = -1;
+        else c->host_readers -= 1;
+    }
+    return SKEL_OK;
+}
+
+}  // namespace skel
+
+using namespace skel;
+
+extern "C" {
+
+skel_status skel_container_create(skel_dtype dtype, int64_t rows, int64_t cols,
+                                  const void* host_src, skel_container** out) {
+    if (!rt().initialized) return fail(SKEL_E_NOINIT, "skel_init has not been called");
+    if (!out) return fail(SKEL_E_INVAL, "null output pointer");
+    if (!dtype_valid(dtype)) return fail(SKEL_E_DTYPE, "unknown dtype %d", (int)dtype);
+    if (rows < 1 || cols < 0)
+        return fail(SKEL_E_SHAPE, "bad shape %lld x %lld", (long long)rows,
+                    (long long)cols);
+    const int64_t lim = INT64_C(1) << 31;
+    if (rows > lim || cols > lim || (cols > 0 && rows > (INT64_C(1) << 40) / cols))
+        return fail(SKEL_E_SHAPE, "shape %lld x %lld too large", (long long)rows,
+                    (long long)cols);
+    auto* c = new (std::nothrow) skel_container();
+    if (!c) return fail(SKEL_E_NOMEM, "out of host memory");
+    c->dtype = dtype;
+    c->rows = rows;
+    c->cols = cols;
+    c->n = rows * cols;
+    c->bytes = (size_t)c->n * dtype_size(dtype);
+    c->allocator = rt().allocator;
+    if (c->bytes == 0) {
+        c->host_valid = c->dev_valid = true;  // nothing to hold
+    } else if (host_src) {
+        skel_status st = rt().backend->host_alloc(&c->host, c->bytes);
+        if (st != SKEL_OK) {
+            delete c;
+            return st;
+        }
+        std::memcpy(c->host, host_src, c->bytes);
+        c->host_valid = true;
+    }
+    *out = c;
+    return SKEL_OK;
+}
+
+skel_status skel_container_destroy(skel_container* c) {
+    if (!c) return fail(SKEL_E_INVAL, "null container");
+    if (c->writer != -1 || c->host_readers || c->dev_readers)
+        return fail(SKEL_E_STATE, "destroy with an outstanding acquire");
+    Backend* be = rt().backend;
+    skel_status st = wait_device_idle(c);
+    if (st != SKEL_OK) return st;
+    if (c->dev) be->dev_free(c->allocator, c->dev, c->last_stream);
+    if (c->host) be->host_free(c->host);
+    for (auto& e : c->events) be->event_destroy(e.event);
+    delete c;
+    return SKEL_OK;
+}
+
+skel_status skel_container_acquire(skel_container* c, skel_place place,
+                                   skel_access access, void* stream,
+                                   void** ptr_out) {
+    if (!rt().initialized) return fail(SKEL_E_NOINIT, "skel_init has not been called");
+    if (!ptr_out) return fail(SKEL_E_INVAL, "null ptr_out");
+    return acquire(c, place, access, stream, ptr_out);
+}
+
+skel_status skel_container_release(skel_container* c, skel_place place,
+                                   void* stream) {
+    if (!rt().initialized) return fail(SKEL_E_NOINIT, "skel_init has not been called");
+    return release(c, place, stream);
+}
+
+skel_status skel_container_stats(const skel_container* c, skel_xfer_stats* out) {
+    if (!c || !out) return fail(SKEL_E_INVAL, "null argument");
+    *out = c->stats;
+    return SKEL_OK;
+}
+
+skel_status skel_container_info(const skel_container* c, skel_dtype* dtype,
+                                int64_t* rows, int64_t* cols) {
+    if (!c) return fail(SKEL_E_INVAL, "null container");
+    if (dtype) *dtype = c->dtype;
+    if (rows) *rows = c->rows;
+    if (cols) *cols = c->cols;
+    return SKEL_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,54 @@
+// Smart containers (Section IV of the paper): a host copy and a device copy
+// of one operand, each with a validity bit, plus the bookkeeping that lets a
+// skeleton call find a valid copy close to the device, copy lazily, and never
+// read a stale one.  Dependences between asynchronous calls (Section V) are
+// carried by a per-container event recorded after the last device access.
+#pragma once
+
+#include <vector>
+
+#include "common.hpp"
+
+struct skel_container {
+    skel_dtype dtype;
+    int64_t rows, cols, n;
+    size_t bytes;
+    skel_allocator allocator;  // device-memory provider captured at creation
+
+    void* host = nullptr;  // pinned host copy, allocated on first need
+    void* dev = nullptr;   // device copy, allocated on first device acquire
+    bool host_valid = false;
+    bool dev_valid = false;
+
+    // One event per stream that has accessed the device copy, recorded at each
+    // device release on that stream.  A device access on another stream waits
+    // on all of them; a host access waits for all of them.
+    struct StreamEvent {
+        void* stream;
+        void* event;
+        bool recorded;
+        uint64_t gen;  // number of records so far
+        // (other stream, generation of its event this stream already waited on)
+        std::vector<std::pair<void*, uint64_t>> seen;
+    };
+    std::vector<StreamEvent> events;
+    void* last_stream = nullptr;  // stream of the most recent device access
+
+    int host_readers = 0, dev_readers = 0;
+    int writer = -1;  // place holding an outstanding WRITE/RW acquire, or -1
+
+    skel_xfer_stats stats{};
+};
+
+namespace skel {
+
+// Check, without side effects, that `access` at `place` would succeed.
+skel_status check_acquire(const skel_container* c, skel_place place,
+                          skel_access access);
+
+// The coherence protocol proper (see skel_container_acquire in skel.h).
+skel_status acquire(skel_container* c, skel_place place, skel_access access,
+                    void* stream, void** ptr);
+skel_status release(skel_container* c, skel_place place, void* stream);
+
+}  // namespace skel

@@ -1,0 +1,57 @@
+// Variant registry and execution plan.
+//
+// Section III: each skeleton has several implementation variants, and an
+// execution plan attached to the skeleton gives the expected best one for the
+// current call context (problem size, ...).  Section II: conditional
+// composition restricts which variants are selectable for a context, and the
+// plan may come from static rules or from off-line tuning (a precomputed,
+// size-keyed dispatch structure looked up at run time).
+#pragma once
+
+#include "common.hpp"
+
+namespace skel {
+
+// variant indices (stable: they are the values of the `variant` argument)
+enum MapVariant { M0_SCALAR = 0, M1_VEC4 = 1, M2_VEC4X4_NT = 2, MAP_NVAR };
+enum ReduceVariant { R0_SINGLE_WG = 0, R1_TWO_PASS = 1, R2_TICKET = 2, R3_ATOMIC = 3,
+                     REDUCE_NVAR };
+enum MapReduceVariant { MR0_UNFUSED = 0, MR1_FUSED_TWO_PASS = 1, MR2_FUSED_TICKET = 2,
+                        MR3_FUSED_SINGLE_WG = 3, MAPREDUCE_NVAR };
+enum Overlap1DVariant { O1A_DIRECT = 0, O1B_LDS_TILE = 1, OVERLAP1D_NVAR };
+enum Overlap2DVariant { O2A_DIRECT = 0, O2B_LDS_TILE = 1, O2C_LDS_SEPARABLE = 2,
+                        OVERLAP2D_NVAR };
+enum ScanVariant { S0_SINGLE_WG = 0, S1_REDUCE_THEN_SCAN = 1, S2_LOOKBACK = 2,
+                   SCAN_NVAR };
+
+// What the plan may look at for one call.
+struct CallContext {
+    int skeleton = 0;
+    skel_dtype din = SKEL_F32, dout = SKEL_F32;
+    int64_t n = 0, rows = 0, cols = 0;
+    int op = 0;         // reduce op (Reduce/MapReduce/Scan) or map op (Map)
+    int map_op = 0;     // MapReduce's element function
+    int separable = 0;  // MapOverlap2D: weights given as factors
+};
+
+int variant_count(int skeleton);
+const char* variant_name(int skeleton, int variant);
+
+// Selectability constraint of one variant for a context (conditional
+// composition).  Returns true, or false and sets *why to a reason.
+bool selectable(int variant, const CallContext& ctx, const char** why);
+
+// The execution plan: forced variant (checked), an environment override
+// SKEL_VARIANT_<SKELETON>=<name or index>, a loaded size-keyed table, or the
+// static rules, in that order.  Returns the variant or a negative status.
+int choose_variant(int requested, const CallContext& ctx, skel_status* st);
+
+// Size-keyed dispatch table (off-line tuning result).  Text format, one entry
+// per line:  <skeleton> <dtype> <log2 n> <variant name>
+// Lookup takes the entry with the largest log2 n not above ceil(log2(n)) for
+// the skeleton and dtype; sizes beyond the table extrapolate from the last.
+skel_status load_plan_table(const char* path);
+void clear_plan_table();
+int plan_table_size();
+
+}  // namespace skel

@@ -1,0 +1,393 @@
+// MapOverlap skeleton kernels: a map whose element function sees a
+// neighbourhood (Section III lists mapoverlap among the data-parallel
+// skeletons).  Here the neighbourhood function is a linear weighting in
+// correlation orientation:
+//   1D  out[i]    = sum_k w[k] * x[e(i + k - r)]
+//   2D  out[i][j] = sum_a sum_b W[a][b] * x[e(i + a - ry)][e(j + b - rx)]
+// with e() the border rule (clamp, constant pad, cyclic).
+//
+// Variants:
+//   O1a  1D direct: one output per lane, taps read through the caches
+//   O1b  1D LDS tile: a workgroup stages 1024 + 2r inputs once, each lane
+//        computes four outputs from registers
+//   O2a  2D direct: one output per lane, (2ry+1)(2rx+1) taps from global
+//   O2b  2D LDS tile: a 64x64 output tile plus halo staged in LDS with 16-byte
+//        loads; each lane computes a 4x4 output block, reusing every loaded
+//        row segment for up to four output rows
+//   O2c  2D separable (W = wy (x) wx): the staged tile is filtered along rows
+//        into a second LDS buffer, then along columns; 2(2r+1) instead of
+//        (2r+1)^2 multiply-adds per output
+// 2D tiles are visited in an XCD-aware order: consecutive workgroups go to
+// different XCDs round-robin, so tile ids are remapped to give each XCD a
+// contiguous band of tiles whose shared halo rows stay in that XCD's L2.
+#include "kcommon.hpp"
+#include "dispatch.hpp"
+#include "launch.hpp"
+
+namespace skel {
+namespace {
+
+using dev::f32x4;
+
+struct W1 {
+    float w[2 * SKEL_MAX_RADIUS_1D + 1];
+};
+struct W2 {
+    float w[(2 * SKEL_MAX_RADIUS_2D + 1) * (2 * SKEL_MAX_RADIUS_2D + 1)];
+    float wy[2 * SKEL_MAX_RADIUS_2D + 1];
+    float wx[2 * SKEL_MAX_RADIUS_2D + 1];
+};
+
+// border rule: true and the index to read, or false for the constant pad
+__device__ __forceinline__ bool border(int64_t j, int64_t n, int edge, int64_t& k) {
+    if (j >= 0 && j < n) {
+        k = j;
+        return true;
+    }
+    if (edge == SKEL_EDGE_CLAMP) {
+        k = j < 0 ? 0 : n - 1;
+        return true;
+    }
+    if (edge == SKEL_EDGE_CYCLIC) {
+        int64_t m = j % n;
+        k = m < 0 ? m + n : m;
+        return true;
+    }
+    return false;
+}
+
+__device__ __forceinline__ float fetch1(const float* x, int64_t n, int64_t j, int edge,
+                                        float pad) {
+    int64_t k;
+    return border(j, n, edge, k) ? x[k] : pad;
+}
+
+__device__ __forceinline__ float fetch2(const float* x, int64_t rows, int64_t cols, int64_t i,
+                                        int64_t j, int edge, float pad) {
+    int64_t a, b;
+    if (!border(i, rows, edge, a) || !border(j, cols, edge, b)) return pad;
+    return x[a * cols + b];
+}
+
+constexpr int kBlock = 256;
+
+// ------------------------------------------------------------------- 1D
+template <int RT>
+__global__ __launch_bounds__(kBlock) void ov1_direct(const float* x, float* out, int64_t n,
+                                                     W1 w, int r_, int edge, float pad) {
+    const int r = RT >= 0 ? RT : r_;
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    float acc = 0.0f;
+    if (i - r >= 0 && i + r < n) {
+#pragma unroll
+        for (int k = 0; k <= 2 * (RT >= 0 ? RT : SKEL_MAX_RADIUS_1D); ++k) {
+            if (k > 2 * r) break;
+            acc = __builtin_fmaf(w.w[k], x[i + k - r], acc);
+        }
+    } else {
+        for (int k = 0; k <= 2 * r; ++k)
+            acc = __builtin_fmaf(w.w[k], fetch1(x, n, i + k - r, edge, pad), acc);
+    }
+    out[i] = acc;
+}
+
+constexpr int kT1 = kBlock * 4;  // outputs per workgroup
+
+template <int RT>
+__global__ __launch_bounds__(kBlock) void ov1_lds(const float* x, float* out, int64_t n, W1 w,
+                                                  int r_, int edge, float pad) {
+    constexpr int MR = RT >= 0 ? RT : SKEL_MAX_RADIUS_1D;
+    const int r = RT >= 0 ? RT : r_;
+    __shared__ float s[kT1 + 2 * MR];
+    const int64_t base = (int64_t)blockIdx.x * kT1;
+    for (int k = threadIdx.x; k < kT1 + 2 * r; k += kBlock) {
+        const int64_t j = base - r + k;
+        s[k] = (j >= 0 && j < n) ? x[j] : fetch1(x, n, j, edge, pad);
+    }
+    __syncthreads();
+    const int o = threadIdx.x * 4;
+    float win[4 + 2 * MR];
+#pragma unroll
+    for (int k = 0; k < 4 + 2 * MR; ++k)
+        if (k < 4 + 2 * r) win[k] = s[o + k];
+    float acc[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int k = 0; k <= 2 * MR; ++k) {
+        if (k > 2 * r) break;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[c] = __builtin_fmaf(w.w[k], win[c + k], acc[c]);
+    }
+    const int64_t i = base + o;
+    if (i + 4 <= n && (n & 3) == 0) {
+        *reinterpret_cast<f32x4*>(out + i) = f32x4{acc[0], acc[1], acc[2], acc[3]};
+    } else {
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            if (i + c < n) out[i + c] = acc[c];
+    }
+}
+
+// ------------------------------------------------------------------- 2D
+constexpr int kTX = 64, kTY = 64;  // output tile of the LDS variants
+
+// compile-time radii, or (-1, -1) for any radius up to the maximum
+template <int RY, int RX>
+struct Rad {
+    static constexpr bool dyn = RY < 0;
+    static constexpr int MY = dyn ? SKEL_MAX_RADIUS_2D : RY;
+    static constexpr int MX = dyn ? SKEL_MAX_RADIUS_2D : RX;
+    static constexpr int HX = (MX + 3) / 4 * 4;  // column halo rounded to 16 bytes
+    static constexpr int LW = kTX + 2 * HX;      // LDS row width of the input tile
+    static constexpr int LH = kTY + 2 * MY;      // LDS rows of the input tile
+};
+
+// tile id -> (tile x, tile y) with an XCD-contiguous order
+__device__ __forceinline__ void tile_coords(int64_t nbx, int64_t nb, int64_t& bx, int64_t& by) {
+    int64_t b = blockIdx.x, L = b;
+    if ((nb & 7) == 0) L = (b & 7) * (nb >> 3) + (b >> 3);
+    bx = L % nbx;
+    by = L / nbx;
+}
+
+// Stage rows [y0 - ry, y0 + kTY + ry) and columns [x0 - HX, x0 + kTX + HX) of
+// the input into LDS (row stride Rad::LW).
+template <class RD>
+__device__ __forceinline__ void stage_tile(const float* x, int64_t rows, int64_t cols,
+                                           int64_t y0, int64_t x0, int ry, int edge, float pad,
+                                           float* tin) {
+    constexpr int LW = RD::LW, HX = RD::HX, V = LW / 4;
+    const int nrows = kTY + 2 * ry;
+    const bool interior = y0 - ry >= 0 && y0 + kTY + ry <= rows && x0 - HX >= 0 &&
+                          x0 + kTX + HX <= cols && (cols & 3) == 0;
+    if (interior) {
+        const float* src = x + (y0 - ry) * cols + (x0 - HX);
+        for (int k = threadIdx.x; k < nrows * V; k += kBlock) {
+            const int rr = k / V, cc = k - rr * V;
+            f32x4 v = *reinterpret_cast<const f32x4*>(src + (int64_t)rr * cols + 4 * cc);
+            *reinterpret_cast<f32x4*>(tin + rr * LW + 4 * cc) = v;
+        }
+    } else {
+        for (int k = threadIdx.x; k < nrows * LW; k += kBlock) {
+            const int rr = k / LW, cc = k - rr * LW;
+            tin[rr * LW + cc] = fetch2(x, rows, cols, y0 - ry + rr, x0 - HX + cc, edge, pad);
+        }
+    }
+}
+
+template <int RY, int RX>
+__global__ __launch_bounds__(kBlock) void ov2_direct(const float* x, float* out, int64_t rows,
+                                                     int64_t cols, W2 w, int ry_, int rx_,
+                                                     int edge, float pad, int64_t nbx) {
+    using RD = Rad<RY, RX>;
+    const int ry = RD::dyn ? ry_ : RY, rx = RD::dyn ? rx_ : RX;
+    const int wx = 2 * rx + 1;
+    const int64_t j = (blockIdx.x % nbx) * 64 + threadIdx.x % 64;
+    const int64_t i = (blockIdx.x / nbx) * 4 + threadIdx.x / 64;
+    if (i >= rows || j >= cols) return;
+    float acc = 0.0f;
+    const bool interior = i - ry >= 0 && i + ry < rows && j - rx >= 0 && j + rx < cols;
+#pragma unroll
+    for (int a = 0; a <= 2 * RD::MY; ++a) {
+        if (a > 2 * ry) break;
+#pragma unroll
+        for (int b = 0; b <= 2 * RD::MX; ++b) {
+            if (b > 2 * rx) break;
+            const float v = interior ? x[(i + a - ry) * cols + (j + b - rx)]
+                                     : fetch2(x, rows, cols, i + a - ry, j + b - rx, edge, pad);
+            acc = __builtin_fmaf(w.w[a * wx + b], v, acc);
+        }
+    }
+    out[i * cols + j] = acc;
+}
+
+// store one 4-wide output segment of row i starting at column j
+__device__ __forceinline__ void store4(float* out, int64_t rows, int64_t cols, int64_t i,
+                                       int64_t j, const float (&v)[4]) {
+    if (i >= rows) return;
+    if (j + 4 <= cols && (cols & 3) == 0) {
+        __builtin_nontemporal_store(f32x4{v[0], v[1], v[2], v[3]},
+                                    reinterpret_cast<f32x4*>(out + i * cols + j));
+    } else {
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            if (j + c < cols) out[i * cols + j + c] = v[c];
+    }
+}
+
+template <int RY, int RX>
+__global__ __launch_bounds__(kBlock) void ov2_lds(const float* x, float* out, int64_t rows,
+                                                  int64_t cols, W2 w, int ry_, int rx_, int edge,
+                                                  float pad, int64_t nbx, int64_t nb) {
+    using RD = Rad<RY, RX>;
+    constexpr int LW = RD::LW, HX = RD::HX, MY = RD::MY, MX = RD::MX;
+    const int ry = RD::dyn ? ry_ : RY, rx = RD::dyn ? rx_ : RX;
+    const int wx = 2 * rx + 1;
+    __shared__ __attribute__((aligned(16))) float tin[RD::LH * LW];
+    int64_t bx, by;
+    tile_coords(nbx, nb, bx, by);
+    const int64_t y0 = by * kTY, x0 = bx * kTX;
+    stage_tile<RD>(x, rows, cols, y0, x0, ry, edge, pad, tin);
+    __syncthreads();
+    const int cg = threadIdx.x % 16, rg = threadIdx.x / 16;
+    float acc[4][4];
+#pragma unroll
+    for (int o = 0; o < 4; ++o)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[o][c] = 0.0f;
+    const int c0 = 4 * cg + HX - rx;  // LDS column of tap b = 0 for output column 0
+    // input row k of the block's window contributes to output row o with a = k - o
+#pragma unroll
+    for (int k = 0; k < 4 + 2 * MY; ++k) {
+        if (k >= 4 + 2 * ry) break;
+        float seg[4 + 2 * MX];
+        const float* row = tin + (4 * rg + k) * LW + c0;
+#pragma unroll
+        for (int t = 0; t < 4 + 2 * MX; ++t)
+            if (t < 4 + 2 * rx) seg[t] = row[t];
+#pragma unroll
+        for (int o = 0; o < 4; ++o) {
+            const int a = k - o;
+            if (a < 0 || a > 2 * ry) continue;
+#pragma unroll
+            for (int b = 0; b <= 2 * MX; ++b) {
+                if (b > 2 * rx) break;
+                const float wab = w.w[a * wx + b];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) acc[o][c] = __builtin_fmaf(wab, seg[c + b], acc[o][c]);
+            }
+        }
+    }
+#pragma unroll
+    for (int o = 0; o < 4; ++o) store4(out, rows, cols, y0 + 4 * rg + o, x0 + 4 * cg, acc[o]);
+}
+
+template <int RY, int RX>
+__global__ __launch_bounds__(kBlock) void ov2_sep(const float* x, float* out, int64_t rows,
+                                                  int64_t cols, W2 w, int ry_, int rx_, int edge,
+                                                  float pad, int64_t nbx, int64_t nb) {
+    using RD = Rad<RY, RX>;
+    constexpr int LW = RD::LW, HX = RD::HX, MY = RD::MY, MX = RD::MX;
+    constexpr int HW = kTX + 4;  // row-pass buffer stride (padded)
+    const int ry = RD::dyn ? ry_ : RY, rx = RD::dyn ? rx_ : RX;
+    __shared__ __attribute__((aligned(16))) float tin[RD::LH * LW];
+    __shared__ __attribute__((aligned(16))) float th[RD::LH * HW];
+    int64_t bx, by;
+    tile_coords(nbx, nb, bx, by);
+    const int64_t y0 = by * kTY, x0 = bx * kTX;
+    stage_tile<RD>(x, rows, cols, y0, x0, ry, edge, pad, tin);
+    __syncthreads();
+    const int cg = threadIdx.x % 16, rg = threadIdx.x / 16;
+    // row pass: th[y][x] = sum_b wx[b] * in[y][x + b - rx] for all staged rows
+    const int nrows = kTY + 2 * ry;
+    for (int y = rg; y < nrows; y += 16) {
+        const float* row = tin + y * LW + 4 * cg + HX - rx;
+        float seg[4 + 2 * MX];
+#pragma unroll
+        for (int t = 0; t < 4 + 2 * MX; ++t)
+            if (t < 4 + 2 * rx) seg[t] = row[t];
+        float h[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int b = 0; b <= 2 * MX; ++b) {
+            if (b > 2 * rx) break;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) h[c] = __builtin_fmaf(w.wx[b], seg[c + b], h[c]);
+        }
+        *reinterpret_cast<f32x4*>(th + y * HW + 4 * cg) = f32x4{h[0], h[1], h[2], h[3]};
+    }
+    __syncthreads();
+    // column pass: out[y][x] = sum_a wy[a] * th[y + a][x]
+    float acc[4][4];
+#pragma unroll
+    for (int o = 0; o < 4; ++o)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[o][c] = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 4 + 2 * MY; ++k) {
+        if (k >= 4 + 2 * ry) break;
+        const f32x4 v = *reinterpret_cast<const f32x4*>(th + (4 * rg + k) * HW + 4 * cg);
+#pragma unroll
+        for (int o = 0; o < 4; ++o) {
+            const int a = k - o;
+            if (a < 0 || a > 2 * ry) continue;
+            const float wa = w.wy[a];
+            acc[o][0] = __builtin_fmaf(wa, v.x, acc[o][0]);
+            acc[o][1] = __builtin_fmaf(wa, v.y, acc[o][1]);
+            acc[o][2] = __builtin_fmaf(wa, v.z, acc[o][2]);
+            acc[o][3] = __builtin_fmaf(wa, v.w, acc[o][3]);
+        }
+    }
+#pragma unroll
+    for (int o = 0; o < 4; ++o) store4(out, rows, cols, y0 + 4 * rg + o, x0 + 4 * cg, acc[o]);
+}
+
+// --------------------------------------------------------------- launchers
+int64_t div_up(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+template <int RT>
+skel_status run1d(int v, const float* x, float* out, int64_t n, const W1& w, int r, int edge,
+                  float pad, hipStream_t st) {
+    if (v == O1A_DIRECT) {
+        ov1_direct<RT><<<(unsigned)div_up(n, kBlock), kBlock, 0, st>>>(x, out, n, w, r, edge, pad);
+        return launch_check("overlap1d_direct");
+    }
+    ov1_lds<RT><<<(unsigned)div_up(n, kT1), kBlock, 0, st>>>(x, out, n, w, r, edge, pad);
+    return launch_check("overlap1d_lds");
+}
+
+template <int RY, int RX>
+skel_status run2d(int v, const float* x, float* out, int64_t rows, int64_t cols, const W2& w,
+                  int ry, int rx, int edge, float pad, hipStream_t st) {
+    if (v == O2A_DIRECT) {
+        const int64_t nbx = div_up(cols, 64), nby = div_up(rows, 4);
+        ov2_direct<RY, RX><<<(unsigned)(nbx * nby), kBlock, 0, st>>>(x, out, rows, cols, w, ry,
+                                                                      rx, edge, pad, nbx);
+        return launch_check("overlap2d_direct");
+    }
+    const int64_t nbx = div_up(cols, kTX), nby = div_up(rows, kTY), nb = nbx * nby;
+    if (v == O2B_LDS_TILE) {
+        ov2_lds<RY, RX><<<(unsigned)nb, kBlock, 0, st>>>(x, out, rows, cols, w, ry, rx, edge,
+                                                         pad, nbx, nb);
+        return launch_check("overlap2d_lds");
+    }
+    ov2_sep<RY, RX><<<(unsigned)nb, kBlock, 0, st>>>(x, out, rows, cols, w, ry, rx, edge, pad,
+                                                     nbx, nb);
+    return launch_check("overlap2d_separable");
+}
+
+}  // namespace
+
+skel_status launch_overlap1d(int v, const float* x, float* out, int64_t n, const float* w,
+                             int r, int edge, float pad, LaunchCtx& lc) {
+    W1 wk{};
+    for (int k = 0; k <= 2 * r; ++k) wk.w[k] = w[k];
+    switch (r) {
+    case 1: return run1d<1>(v, x, out, n, wk, r, edge, pad, lc.stream);
+    case 2: return run1d<2>(v, x, out, n, wk, r, edge, pad, lc.stream);
+    case 4: return run1d<4>(v, x, out, n, wk, r, edge, pad, lc.stream);
+    default: return run1d<-1>(v, x, out, n, wk, r, edge, pad, lc.stream);
+    }
+}
+
+skel_status launch_overlap2d(int v, const float* x, float* out, int64_t rows, int64_t cols,
+                             const float* w2d, const float* wy, const float* wx, int ry, int rx,
+                             int edge, float pad, LaunchCtx& lc) {
+    W2 wk{};
+    const int ny = 2 * ry + 1, nx = 2 * rx + 1;
+    for (int a = 0; a < ny; ++a)
+        for (int b = 0; b < nx; ++b)
+            wk.w[a * nx + b] = w2d ? w2d[a * nx + b] : wy[a] * wx[b];
+    if (!w2d) {
+        for (int a = 0; a < ny; ++a) wk.wy[a] = wy[a];
+        for (int b = 0; b < nx; ++b) wk.wx[b] = wx[b];
+    }
+    if (ry == 4 && rx == 4)
+        return run2d<4, 4>(v, x, out, rows, cols, wk, ry, rx, edge, pad, lc.stream);
+    if (ry == 1 && rx == 1)
+        return run2d<1, 1>(v, x, out, rows, cols, wk, ry, rx, edge, pad, lc.stream);
+    if (ry == 2 && rx == 2)
+        return run2d<2, 2>(v, x, out, rows, cols, wk, ry, rx, edge, pad, lc.stream);
+    return run2d<-1, -1>(v, x, out, rows, cols, wk, ry, rx, edge, pad, lc.stream);
+}
+
+}  // namespace skel

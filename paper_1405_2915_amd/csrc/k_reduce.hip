@@ -1,0 +1,401 @@
+// Reduce and MapReduce skeleton kernels.
+//
+// Reduce (Section III): r = x[0] op x[1] op ... op x[n-1].  MapReduce: the
+// same over f(x[i], y[i]) with no stored intermediate.  Variants:
+//   R0 / MR3  one workgroup of 1024 lanes (small n: one launch, no partials)
+//   R1 / MR1  two passes: a grid of workgroups writes partials, one
+//             workgroup combines them (the plain form; R1 runs at a fixed
+//             launch shape)
+//   R2 / MR2  one pass: each workgroup publishes its partial and takes a
+//             ticket; the workgroup that draws the last ticket combines all
+//             partials in index order, so the result is deterministic
+//   R3        one pass with a hardware atomic finish (order-dependent for
+//             floating point)
+//   MR0       the composed plain form: Map into a temporary, then R1
+// Every lane streams 16-byte vectors with four loads in flight and keeps four
+// independent accumulators; partials are combined by 64-lane butterflies and
+// one LDS step.  Integer sums wrap in the output width (unsigned arithmetic).
+#include <type_traits>
+
+#include "kcommon.hpp"
+#include "dispatch.hpp"
+#include "launch.hpp"
+
+namespace skel {
+namespace {
+
+using namespace dev;
+
+constexpr int kBlock = 256;
+constexpr int kSingleBlock = 1024;
+constexpr int kUnroll = 4;
+
+template <int DIN, int DOUT, int OP>
+struct RP {
+    using in_t = typename Stored<DIN>::type;
+    using out_t = typename Stored<DOUT>::type;
+    using acc_t = typename Acc<DIN, DOUT, OP>::type;
+    using C = Comb<acc_t, OP>;
+    static constexpr int E = 16 / sizeof(in_t);
+    static constexpr int kOp = OP;
+};
+
+// ----------------------------------------------------------- element sources
+template <class P>
+struct PlainSrc {
+    using acc_t = typename P::acc_t;
+    using in_t = typename P::in_t;
+    static constexpr int E = P::E;
+    struct Vec {
+        in_t a[E];
+    };
+    const in_t* x;
+    __device__ __forceinline__ void load(int64_t vi, Vec& v) const { load16(x + vi * E, v.a); }
+    __device__ __forceinline__ void accum(const Vec& v, acc_t& acc) const {
+#pragma unroll
+        for (int e = 0; e < E; ++e) acc = P::C::op(acc, widen<acc_t>(v.a[e]));
+    }
+    __device__ __forceinline__ acc_t at(int64_t i) const { return widen<acc_t>(x[i]); }
+};
+
+template <int MOP>
+__device__ __forceinline__ float fmap(float x, float y, float p0, float p1) {
+    if constexpr (MOP == SKEL_MAP_IDENTITY) return x;
+    else if constexpr (MOP == SKEL_MAP_AXPY) return __builtin_fmaf(p0, x, y);
+    else if constexpr (MOP == SKEL_MAP_AFFINE) return __builtin_fmaf(p0, x, p1);
+    else if constexpr (MOP == SKEL_MAP_TANH) return tanhf(x);
+    else if constexpr (MOP == SKEL_MAP_AFFINE_TANH) return tanhf(__builtin_fmaf(p0, x, p1));
+    else if constexpr (MOP == SKEL_MAP_MUL) return x * y;
+    else return x * x;
+}
+template <int MOP>
+constexpr bool two_inputs() { return MOP == SKEL_MAP_AXPY || MOP == SKEL_MAP_MUL; }
+
+// f(x[i], y[i]) accumulated in binary32; inputs f32 or bf16 bit patterns
+template <class P, int MOP>
+struct MapSrc {
+    using acc_t = float;
+    using in_t = typename P::in_t;
+    static constexpr int E = P::E;
+    struct Vec {
+        in_t a[E], b[E];
+    };
+    const in_t* x;
+    const in_t* y;
+    float p0, p1;
+    __device__ __forceinline__ void load(int64_t vi, Vec& v) const {
+        load16(x + vi * E, v.a);
+        if constexpr (two_inputs<MOP>()) load16(y + vi * E, v.b);
+    }
+    __device__ __forceinline__ void accum(const Vec& v, float& acc) const {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            float xv = widen<float>(v.a[e]);
+            float yv = two_inputs<MOP>() ? widen<float>(v.b[e]) : 0.0f;
+            acc = P::C::op(acc, fmap<MOP>(xv, yv, p0, p1));
+        }
+    }
+    __device__ __forceinline__ float at(int64_t i) const {
+        float xv = widen<float>(x[i]);
+        float yv = two_inputs<MOP>() ? widen<float>(y[i]) : 0.0f;
+        return fmap<MOP>(xv, yv, p0, p1);
+    }
+};
+
+// One lane's share: 16-byte vectors gtid, gtid + gstride, ... with kUnroll
+// loads in flight, then the n % E tail elements (one per low lane).
+template <class P, class Src>
+__device__ __forceinline__ typename P::acc_t thread_acc(const Src& s, int64_t n, int64_t gtid,
+                                                        int64_t gstride) {
+    using acc_t = typename P::acc_t;
+    constexpr int E = P::E;
+    acc_t a[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) a[u] = P::C::id();
+    const int64_t nv = n / E;
+    int64_t i = gtid;
+    for (; i + (kUnroll - 1) * gstride < nv; i += kUnroll * gstride) {
+        typename Src::Vec v[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) s.load(i + u * gstride, v[u]);
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) s.accum(v[u], a[u]);
+    }
+    for (; i < nv; i += gstride) {
+        typename Src::Vec v;
+        s.load(i, v);
+        s.accum(v, a[0]);
+    }
+    const int64_t t = nv * E + gtid;
+    if (t < n) a[0] = P::C::op(a[0], s.at(t));
+#pragma unroll
+    for (int u = 1; u < kUnroll; ++u) a[0] = P::C::op(a[0], a[u]);
+    return a[0];
+}
+
+// device-scope coherent access to partials written by other XCDs
+template <class T>
+__device__ __forceinline__ void store_coherent(T* p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class T>
+__device__ __forceinline__ T load_coherent(const T* p) {
+    return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ------------------------------------------------------------------ kernels
+template <class P, class Src>
+__global__ __launch_bounds__(kSingleBlock) void k_single(Src s, int64_t n,
+                                                         typename P::out_t* out) {
+    __shared__ typename P::acc_t lds[kSingleBlock / kWave];
+    auto a = thread_acc<P>(s, n, threadIdx.x, kSingleBlock);
+    a = block_reduce<typename P::C>(a, lds);
+    if (threadIdx.x == 0) *out = (typename P::out_t)a;
+}
+
+template <class P, class Src>
+__global__ __launch_bounds__(kBlock) void k_partials(Src s, int64_t n,
+                                                     typename P::acc_t* partials) {
+    __shared__ typename P::acc_t lds[kBlock / kWave];
+    auto a = thread_acc<P>(s, n, (int64_t)blockIdx.x * kBlock + threadIdx.x,
+                           (int64_t)gridDim.x * kBlock);
+    a = block_reduce<typename P::C>(a, lds);
+    if (threadIdx.x == 0) partials[blockIdx.x] = a;
+}
+
+template <class P>
+__global__ __launch_bounds__(kSingleBlock) void k_finish(const typename P::acc_t* partials,
+                                                         int g, typename P::out_t* out) {
+    __shared__ typename P::acc_t lds[kSingleBlock / kWave];
+    auto a = P::C::id();
+    for (int i = threadIdx.x; i < g; i += kSingleBlock) a = P::C::op(a, partials[i]);
+    a = block_reduce<typename P::C>(a, lds);
+    if (threadIdx.x == 0) *out = (typename P::out_t)a;
+}
+
+template <class P, class Src>
+__global__ __launch_bounds__(kBlock) void k_ticket(Src s, int64_t n,
+                                                   typename P::acc_t* partials,
+                                                   unsigned long long* ticket,
+                                                   typename P::out_t* out) {
+    using acc_t = typename P::acc_t;
+    __shared__ acc_t lds[kBlock / kWave];
+    __shared__ int is_last;
+    acc_t a = thread_acc<P>(s, n, (int64_t)blockIdx.x * kBlock + threadIdx.x,
+                            (int64_t)gridDim.x * kBlock);
+    a = block_reduce<typename P::C>(a, lds);
+    if (threadIdx.x == 0) {
+        store_coherent(&partials[blockIdx.x], a);
+        __threadfence();
+        unsigned long long t = atomicAdd(ticket, 1ull);
+        is_last = (t == gridDim.x - 1) ? 1 : 0;
+    }
+    __syncthreads();
+    if (!is_last) return;
+    __threadfence();
+    acc_t b = P::C::id();
+    for (unsigned i = threadIdx.x; i < gridDim.x; i += kBlock)
+        b = P::C::op(b, load_coherent(&partials[i]));
+    b = block_reduce<typename P::C>(b, lds);
+    if (threadIdx.x == 0) {
+        *out = (typename P::out_t)b;
+        __hip_atomic_store(ticket, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+template <class P>
+__global__ void k_set_identity(typename P::out_t* out) {
+    *out = (typename P::out_t)P::C::id();
+}
+
+template <class P>
+__device__ __forceinline__ void atomic_combine(typename P::out_t* out, typename P::acc_t v);
+
+template <class P, class Src>
+__global__ __launch_bounds__(kBlock) void k_atomic(Src s, int64_t n, typename P::out_t* out) {
+    __shared__ typename P::acc_t lds[kBlock / kWave];
+    auto a = thread_acc<P>(s, n, (int64_t)blockIdx.x * kBlock + threadIdx.x,
+                           (int64_t)gridDim.x * kBlock);
+    a = block_reduce<typename P::C>(a, lds);
+    if (threadIdx.x == 0) atomic_combine<P>(out, a);
+}
+
+template <class P>
+__device__ __forceinline__ void atomic_combine(typename P::out_t* out, typename P::acc_t v) {
+    using acc_t = typename P::acc_t;
+    if constexpr (std::is_same<acc_t, float>::value) {
+        unsafeAtomicAdd(out, v);  // SUM only (selectability constraint)
+    } else if constexpr (std::is_same<acc_t, uint32_t>::value) {
+        atomicAdd(reinterpret_cast<unsigned int*>(out), (unsigned int)v);
+    } else if constexpr (std::is_same<acc_t, uint64_t>::value) {
+        atomicAdd(reinterpret_cast<unsigned long long*>(out), (unsigned long long)v);
+    } else if constexpr (std::is_same<acc_t, int32_t>::value) {
+        if (P::kOp == SKEL_MIN) atomicMin(reinterpret_cast<int*>(out), (int)v);
+        else atomicMax(reinterpret_cast<int*>(out), (int)v);
+    } else {
+        if (P::kOp == SKEL_MIN) atomicMin(reinterpret_cast<long long*>(out), (long long)v);
+        else atomicMax(reinterpret_cast<long long*>(out), (long long)v);
+    }
+}
+
+// --------------------------------------------------------------- launchers
+int64_t div_up(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// grid of the streaming passes: enough 16-byte vectors per lane for kUnroll
+// loads in flight, at most 8 workgroups per CU
+template <class P>
+int grid_for(int64_t n, const DevInfo& d) {
+    int64_t g = div_up(n / P::E, (int64_t)kBlock * kUnroll);
+    if (g < 1) g = 1;
+    int64_t cap = (int64_t)d.cus * 8;
+    return (int)(g < cap ? g : cap);
+}
+
+// partial buffer bytes for the grid variants: at most 8 groups per CU, 8-byte
+// accumulators, rounded to 256 bytes
+size_t partial_bytes(const DevInfo& d) { return ((size_t)d.cus * 8 * 8 + 255) & ~size_t(255); }
+
+template <class P, class Src>
+skel_status run_variant(int v, const Src& s, int64_t n, typename P::out_t* out,
+                        LaunchCtx& lc, void* partial_mem) {
+    using acc_t = typename P::acc_t;
+    hipStream_t st = lc.stream;
+    switch (v) {
+    case R0_SINGLE_WG:
+        k_single<P, Src><<<1, kSingleBlock, 0, st>>>(s, n, out);
+        return launch_check("reduce_single");
+    case R1_TWO_PASS: {
+        // fixed plain launch: 256 lanes, min(ceil(n / 2048), 4 * CUs) groups
+        int64_t g = div_up(n, 2048);
+        if (g < 1) g = 1;
+        if (g > (int64_t)lc.dev->cus * 4) g = (int64_t)lc.dev->cus * 4;
+        acc_t* part = static_cast<acc_t*>(partial_mem);
+        k_partials<P, Src><<<(unsigned)g, kBlock, 0, st>>>(s, n, part);
+        skel_status e = launch_check("reduce_partials");
+        if (e != SKEL_OK) return e;
+        k_finish<P><<<1, kSingleBlock, 0, st>>>(part, (int)g, out);
+        return launch_check("reduce_finish");
+    }
+    case R2_TICKET: {
+        int g = grid_for<P>(n, *lc.dev);
+        k_ticket<P, Src><<<(unsigned)g, kBlock, 0, st>>>(
+            s, n, static_cast<acc_t*>(partial_mem), lc.ws->sync + SYNC_TICKET, out);
+        return launch_check("reduce_ticket");
+    }
+    default: {  // R3_ATOMIC
+        int g = grid_for<P>(n, *lc.dev);
+        k_set_identity<P><<<1, 1, 0, st>>>(out);
+        skel_status e = launch_check("reduce_set_identity");
+        if (e != SKEL_OK) return e;
+        k_atomic<P, Src><<<(unsigned)g, kBlock, 0, st>>>(s, n, out);
+        return launch_check("reduce_atomic");
+    }
+    }
+}
+
+template <int DIN, int DOUT, int OP>
+skel_status reduce_typed(int v, const void* x, int64_t n, void* out, LaunchCtx& lc) {
+    using P = RP<DIN, DOUT, OP>;
+    void* part = nullptr;
+    skel_status e = ws_scratch(lc, partial_bytes(*lc.dev), &part);
+    if (e != SKEL_OK) return e;
+    PlainSrc<P> s{static_cast<const typename P::in_t*>(x)};
+    return run_variant<P>(v, s, n, static_cast<typename P::out_t*>(out), lc, part);
+}
+
+template <int DIN, int DOUT>
+skel_status reduce_op(int v, int op, const void* x, int64_t n, void* out, LaunchCtx& lc) {
+    switch (op) {
+    case SKEL_SUM: return reduce_typed<DIN, DOUT, SKEL_SUM>(v, x, n, out, lc);
+    case SKEL_MIN: return reduce_typed<DIN, DOUT, SKEL_MIN>(v, x, n, out, lc);
+    default: return reduce_typed<DIN, DOUT, SKEL_MAX>(v, x, n, out, lc);
+    }
+}
+
+template <int DIN, int MOP, int OP>
+skel_status mapreduce_typed(int v, float p0, float p1, const void* x, const void* y,
+                            int64_t n, float* out, LaunchCtx& lc) {
+    using P = RP<DIN, SKEL_F32, OP>;
+    using in_t = typename P::in_t;
+    MapSrc<P, MOP> s{static_cast<const in_t*>(x), static_cast<const in_t*>(y), p0, p1};
+    if constexpr (DIN == SKEL_F32) if (v == MR0_UNFUSED) {
+        // Map into a temporary with the Map skeleton's vector kernel, then the
+        // plain two-pass Reduce over the temporary
+        size_t tbytes = ((size_t)n * 4 + 255) & ~size_t(255);
+        void* mem = nullptr;
+        skel_status e = ws_scratch(lc, tbytes + partial_bytes(*lc.dev), &mem);
+        if (e != SKEL_OK) return e;
+        float* tmp = static_cast<float*>(mem);
+        if (n > 0) {
+            e = launch_map(M1_VEC4, MOP, p0, p1, static_cast<const float*>(x),
+                           static_cast<const float*>(y), tmp, n, lc);
+            if (e != SKEL_OK) return e;
+        }
+        using PF = RP<SKEL_F32, SKEL_F32, OP>;
+        PlainSrc<PF> ps{tmp};
+        return run_variant<PF>(R1_TWO_PASS, ps, n, out, lc,
+                               static_cast<char*>(mem) + tbytes);
+    }
+    void* part = nullptr;
+    skel_status e = ws_scratch(lc, partial_bytes(*lc.dev), &part);
+    if (e != SKEL_OK) return e;
+    int rv = v == MR1_FUSED_TWO_PASS ? R1_TWO_PASS
+             : v == MR2_FUSED_TICKET ? R2_TICKET
+                                     : R0_SINGLE_WG;
+    return run_variant<P>(rv, s, n, out, lc, part);
+}
+
+template <int DIN, int MOP>
+skel_status mapreduce_op(int v, int op, float p0, float p1, const void* x, const void* y,
+                         int64_t n, float* out, LaunchCtx& lc) {
+    switch (op) {
+    case SKEL_SUM: return mapreduce_typed<DIN, MOP, SKEL_SUM>(v, p0, p1, x, y, n, out, lc);
+    case SKEL_MIN: return mapreduce_typed<DIN, MOP, SKEL_MIN>(v, p0, p1, x, y, n, out, lc);
+    default: return mapreduce_typed<DIN, MOP, SKEL_MAX>(v, p0, p1, x, y, n, out, lc);
+    }
+}
+
+}  // namespace
+
+skel_status launch_reduce(int v, int op, skel_dtype din, skel_dtype dout, const void* x,
+                          int64_t n, void* out, LaunchCtx& lc) {
+    if (din == SKEL_F32) return reduce_op<SKEL_F32, SKEL_F32>(v, op, x, n, out, lc);
+    if (din == SKEL_BF16) return reduce_op<SKEL_BF16, SKEL_F32>(v, op, x, n, out, lc);
+    if (din == SKEL_I32 && dout == SKEL_I32)
+        return reduce_op<SKEL_I32, SKEL_I32>(v, op, x, n, out, lc);
+    if (din == SKEL_I32) return reduce_op<SKEL_I32, SKEL_I64>(v, op, x, n, out, lc);
+    return reduce_op<SKEL_I64, SKEL_I64>(v, op, x, n, out, lc);
+}
+
+skel_status launch_mapreduce(int v, int map_op, float p0, float p1, skel_dtype din,
+                             const void* x, const void* y, int64_t n, int op, float* out,
+                             LaunchCtx& lc) {
+    if (din == SKEL_BF16) {
+        switch (map_op) {
+        case SKEL_MAP_IDENTITY:
+            return mapreduce_op<SKEL_BF16, SKEL_MAP_IDENTITY>(v, op, p0, p1, x, y, n, out, lc);
+        case SKEL_MAP_MUL:
+            return mapreduce_op<SKEL_BF16, SKEL_MAP_MUL>(v, op, p0, p1, x, y, n, out, lc);
+        default:
+            return mapreduce_op<SKEL_BF16, SKEL_MAP_SQUARE>(v, op, p0, p1, x, y, n, out, lc);
+        }
+    }
+    switch (map_op) {
+    case SKEL_MAP_IDENTITY:
+        return mapreduce_op<SKEL_F32, SKEL_MAP_IDENTITY>(v, op, p0, p1, x, y, n, out, lc);
+    case SKEL_MAP_AXPY:
+        return mapreduce_op<SKEL_F32, SKEL_MAP_AXPY>(v, op, p0, p1, x, y, n, out, lc);
+    case SKEL_MAP_AFFINE:
+        return mapreduce_op<SKEL_F32, SKEL_MAP_AFFINE>(v, op, p0, p1, x, y, n, out, lc);
+    case SKEL_MAP_TANH:
+        return mapreduce_op<SKEL_F32, SKEL_MAP_TANH>(v, op, p0, p1, x, y, n, out, lc);
+    case SKEL_MAP_AFFINE_TANH:
+        return mapreduce_op<SKEL_F32, SKEL_MAP_AFFINE_TANH>(v, op, p0, p1, x, y, n, out, lc);
+    case SKEL_MAP_MUL:
+        return mapreduce_op<SKEL_F32, SKEL_MAP_MUL>(v, op, p0, p1, x, y, n, out, lc);
+    default:
+        return mapreduce_op<SKEL_F32, SKEL_MAP_SQUARE>(v, op, p0, p1, x, y, n, out, lc);
+    }
+}
+
+}  // namespace skel

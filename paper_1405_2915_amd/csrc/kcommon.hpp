@@ -1,0 +1,159 @@
+// Device-side building blocks shared by the skeleton kernels: combining
+// operators, element-type policies, 64-lane wavefront reductions and scans,
+// and 16-byte vector access.  gfx950 only: wavefronts are 64 lanes wide.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "skel.h"
+
+namespace skel {
+namespace dev {
+
+constexpr int kWave = 64;
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ int lane() { return (int)__lane_id(); }
+
+// ------------------------------------------------------------ operators --
+
+template <class T, int OP>
+struct Comb;
+
+template <class T>
+struct Comb<T, SKEL_SUM> {
+    static __device__ __forceinline__ T id() { return T(0); }
+    static __device__ __forceinline__ T op(T a, T b) { return a + b; }
+};
+
+template <class T>
+struct Lim;
+template <>
+struct Lim<float> {
+    static __device__ __forceinline__ float hi() { return __builtin_inff(); }
+    static __device__ __forceinline__ float lo() { return -__builtin_inff(); }
+};
+template <>
+struct Lim<int32_t> {
+    static __device__ __forceinline__ int32_t hi() { return INT32_MAX; }
+    static __device__ __forceinline__ int32_t lo() { return INT32_MIN; }
+};
+template <>
+struct Lim<int64_t> {
+    static __device__ __forceinline__ int64_t hi() { return INT64_MAX; }
+    static __device__ __forceinline__ int64_t lo() { return INT64_MIN; }
+};
+
+template <class T>
+struct Comb<T, SKEL_MIN> {
+    static __device__ __forceinline__ T id() { return Lim<T>::hi(); }
+    static __device__ __forceinline__ T op(T a, T b) { return b < a ? b : a; }
+};
+template <class T>
+struct Comb<T, SKEL_MAX> {
+    static __device__ __forceinline__ T id() { return Lim<T>::lo(); }
+    static __device__ __forceinline__ T op(T a, T b) { return b > a ? b : a; }
+};
+
+// --------------------------------------------------------- element types --
+// Storage types by dtype; bf16 is stored as its 16-bit pattern.
+template <int DT>
+struct Stored;
+template <> struct Stored<SKEL_F32> { using type = float; };
+template <> struct Stored<SKEL_BF16> { using type = uint16_t; };
+template <> struct Stored<SKEL_I32> { using type = int32_t; };
+template <> struct Stored<SKEL_I64> { using type = int64_t; };
+
+// Accumulator of a (input, output, op) triple.  Integer sums use unsigned
+// arithmetic of the output width, which is the two's-complement wrap the
+// contract asks for without signed-overflow undefined behaviour.
+template <int DIN, int DOUT, int OP>
+struct Acc {
+    using type = typename Stored<DOUT>::type;
+};
+template <int DIN>
+struct Acc<DIN, SKEL_F32, SKEL_SUM> { using type = float; };
+template <>
+struct Acc<SKEL_I32, SKEL_I32, SKEL_SUM> { using type = uint32_t; };
+template <int DIN>
+struct Acc<DIN, SKEL_I64, SKEL_SUM> { using type = uint64_t; };
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) {
+    return __uint_as_float((uint32_t)h << 16);
+}
+
+// Widen a stored input element to the accumulator type.
+template <class A, class S>
+__device__ __forceinline__ A widen(S v) {
+    return (A)v;  // int32 -> uint64 / int64 sign-extends; float -> float
+}
+template <>
+__device__ __forceinline__ float widen<float, uint16_t>(uint16_t v) {
+    return bf16_to_f32(v);
+}
+template <>
+__device__ __forceinline__ uint64_t widen<uint64_t, int32_t>(int32_t v) {
+    return (uint64_t)(int64_t)v;
+}
+
+// ------------------------------------------------------- wave primitives --
+// 64-lane butterfly reduction: every lane ends with the full result, combined
+// in a fixed order (deterministic for a fixed launch shape).
+template <class C, class T>
+__device__ __forceinline__ T wave_reduce(T v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = C::op(v, __shfl_xor(v, o));
+    return v;
+}
+
+// Inclusive scan over the 64 lanes (Hillis-Steele with lane shifts).
+template <class C, class T>
+__device__ __forceinline__ T wave_inclusive_scan(T v) {
+    const int l = lane();
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        T u = __shfl_up(v, d);
+        if (l >= d) v = C::op(u, v);
+    }
+    return v;
+}
+
+// Block reduction for blocks of up to 1024 threads.  `lds` holds one T per
+// wavefront.  The result is valid in every lane of wavefront 0.
+template <class C, class T>
+__device__ __forceinline__ T block_reduce(T v, T* lds) {
+    const int w = threadIdx.x / kWave, nw = blockDim.x / kWave;
+    v = wave_reduce<C>(v);
+    if (lane() == 0) lds[w] = v;
+    __syncthreads();
+    if (w == 0) {
+        v = lane() < nw ? lds[lane()] : C::id();
+        v = wave_reduce<C>(v);
+    }
+    return v;
+}
+
+// ---------------------------------------------------------- vector access --
+template <class T>
+__device__ __forceinline__ void load16(const T* p, T (&v)[16 / sizeof(T)]) {
+    u32x4 raw = *reinterpret_cast<const u32x4*>(p);
+    __builtin_memcpy(&v, &raw, 16);
+}
+
+template <class T, int E>
+__device__ __forceinline__ void store_nt(T* p, const T (&v)[E]) {
+    static_assert((sizeof(T) * E) % 16 == 0, "whole 16-byte vectors only");
+#pragma unroll
+    for (int k = 0; k < (int)(sizeof(T) * E / 16); ++k) {
+        u32x4 raw;
+        __builtin_memcpy(&raw, reinterpret_cast<const char*>(&v) + 16 * k, 16);
+        __builtin_nontemporal_store(raw, reinterpret_cast<u32x4*>(p) + k);
+    }
+}
+
+}  // namespace dev
+}  // namespace skel

@@ -1,0 +1,77 @@
+// Host-side launch interface between the skeleton entry points and the HIP
+// kernels.  Every launcher takes device pointers that the container protocol
+// has made valid, plain sizes, and a LaunchCtx naming the stream, the device
+// limits and the per-stream workspace.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "common.hpp"
+
+namespace skel {
+
+struct DevInfo {
+    int cus = 256;            // compute units
+    int lds_bytes = 65536;    // LDS per workgroup
+    int wave = 64;            // wavefront width
+    int max_threads = 1024;   // per workgroup
+};
+
+// Per-stream device scratch.  `sync` is a small persistent area that is zero
+// when allocated and that kernels keep zero between calls (each ticket or tile
+// counter is reset by the workgroup that takes its last value); `status` holds
+// the decoupled look-back tile descriptors, tagged with `epoch` so they never
+// need clearing between calls.
+struct Workspace {
+    void* stream = nullptr;
+    void* scratch = nullptr;
+    size_t scratch_bytes = 0;
+    unsigned long long* sync = nullptr;
+    void* status = nullptr;
+    size_t status_bytes = 0;
+    uint32_t epoch = 0;
+};
+
+// slots of the sync area (64-bit words)
+enum SyncSlot {
+    SYNC_TICKET = 0,      // reduce / mapreduce "last workgroup" ticket
+    SYNC_TILE_COUNTER = 1,  // scan dynamic tile id counter
+    SYNC_ERROR = 2,       // nonzero: a kernel's bounded wait expired
+    SYNC_SLOTS = 64
+};
+
+struct LaunchCtx {
+    hipStream_t stream;
+    const DevInfo* dev;
+    Workspace* ws;
+};
+
+// runtime.cpp
+const DevInfo& device_info();
+skel_status workspace_for(void* stream, Workspace** out);
+skel_status ws_scratch(LaunchCtx& lc, size_t bytes, void** p);
+// status array of at least `bytes`, and a fresh nonzero epoch for one call
+skel_status ws_status(LaunchCtx& lc, size_t bytes, void** p, uint32_t* epoch);
+skel_status hip_check(hipError_t e, const char* what);
+skel_status launch_check(const char* kernel);
+
+// kernels (k_*.hip); all return SKEL_OK or SKEL_E_HIP
+skel_status launch_map(int variant, int op, float p0, float p1, const float* x,
+                       const float* y, float* out, int64_t n, LaunchCtx& lc);
+skel_status launch_reduce(int variant, int op, skel_dtype din, skel_dtype dout,
+                          const void* x, int64_t n, void* out, LaunchCtx& lc);
+skel_status launch_mapreduce(int variant, int map_op, float p0, float p1,
+                             skel_dtype din, const void* x, const void* y,
+                             int64_t n, int op, float* out, LaunchCtx& lc);
+skel_status launch_overlap1d(int variant, const float* x, float* out, int64_t n,
+                             const float* w, int r, int edge, float pad,
+                             LaunchCtx& lc);
+skel_status launch_overlap2d(int variant, const float* x, float* out,
+                             int64_t rows, int64_t cols, const float* w2d,
+                             const float* wy, const float* wx, int ry, int rx,
+                             int edge, float pad, LaunchCtx& lc);
+skel_status launch_scan(int variant, int kind, int op, skel_dtype din,
+                        skel_dtype dout, const void* x, void* out, int64_t n,
+                        LaunchCtx& lc);
+
+}  // namespace skel

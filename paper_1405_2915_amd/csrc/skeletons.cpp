@@ -1,0 +1,358 @@
+// Skeleton entry points of the C ABI.  Each call: validate the arguments and
+// the operands' container states (no side effect on failure), let the
+// execution plan pick a variant (Section III), acquire every operand on the
+// device through the coherence protocol (Section IV: this is where lazy
+// copies happen), enqueue the kernels on the caller's stream, and release the
+// operands, which records their dependence events (Section V).  Nothing
+// waits: results stay on the device until a host acquire.
+#include <cmath>
+#include <cstring>
+
+#include "container.hpp"
+#include "dispatch.hpp"
+#include "launch.hpp"
+
+namespace skel {
+
+namespace {
+
+// The operands of one call.  A container named twice is acquired once with
+// the union of the access modes (e.g. in-place Map: READ + WRITE = RW).
+class Operands {
+  public:
+    skel_status add(skel_container* c, skel_access a) {
+        if (!c) return fail(SKEL_E_INVAL, "null container operand");
+        for (int i = 0; i < n_; ++i)
+            if (ops_[i].c == c) {
+                ops_[i].access = (skel_access)(ops_[i].access | a);
+                count_eager(c, a);
+                return SKEL_OK;
+            }
+        ops_[n_++] = {c, a, nullptr, false};
+        count_eager(c, a);
+        return SKEL_OK;
+    }
+    skel_status check() const {
+        for (int i = 0; i < n_; ++i) {
+            skel_status st = check_acquire(ops_[i].c, SKEL_DEVICE, ops_[i].access);
+            if (st != SKEL_OK) return st;
+        }
+        return SKEL_OK;
+    }
+    skel_status acquire_all(void* stream) {
+        for (int i = 0; i < n_; ++i) {
+            skel_status st = acquire(ops_[i].c, SKEL_DEVICE, ops_[i].access, stream,
+                                     &ops_[i].ptr);
+            if (st != SKEL_OK) {
+                release_all(stream);
+                return st;
+            }
+            ops_[i].held = true;
+        }
+        return SKEL_OK;
+    }
+    void release_all(void* stream) {
+        for (int i = 0; i < n_; ++i)
+            if (ops_[i].held) {
+                release(ops_[i].c, SKEL_DEVICE, stream);
+                ops_[i].held = false;
+            }
+    }
+    // Eager-equivalent accounting (Section IV comparison point): an eager
+    // scheme copies every input in and every output out at every call.
+    void commit_eager() {
+        for (int i = 0; i < pending_n_; ++i) pending_[i].c->stats.eager_equiv += pending_[i].k;
+    }
+    void* ptr(const skel_container* c) const {
+        for (int i = 0; i < n_; ++i)
+            if (ops_[i].c == c) return ops_[i].ptr;
+        return nullptr;
+    }
+
+  private:
+    struct Op {
+        skel_container* c;
+        skel_access access;
+        void* ptr;
+        bool held;
+    };
+    struct Pending {
+        skel_container* c;
+        uint64_t k;
+    };
+    void count_eager(skel_container* c, skel_access a) {
+        uint64_t k = ((a & SKEL_READ) ? 1 : 0) + ((a & SKEL_WRITE) ? 1 : 0);
+        pending_[pending_n_++] = {c, k};
+    }
+    Op ops_[4];
+    int n_ = 0;
+    Pending pending_[8];
+    int pending_n_ = 0;
+};
+
+skel_status begin(void* stream, LaunchCtx* lc) {
+    if (!rt().initialized) return fail(SKEL_E_NOINIT, "skel_init has not been called");
+    lc->stream = reinterpret_cast<hipStream_t>(stream);
+    lc->dev = &device_info();
+    return SKEL_OK;
+}
+
+// Run `launch` between acquire and release of the operands.
+template <class F>
+skel_status run(Operands& ops, void* stream, LaunchCtx& lc, F&& launch) {
+    skel_status st = ops.check();
+    if (st != SKEL_OK) return st;
+    st = workspace_for(stream, &lc.ws);
+    if (st != SKEL_OK) return st;
+    st = ops.acquire_all(stream);
+    if (st != SKEL_OK) return st;
+    st = launch();
+    ops.release_all(stream);
+    if (st == SKEL_OK) ops.commit_eager();
+    return st;
+}
+
+bool map_op_valid(int op) { return op >= SKEL_MAP_IDENTITY && op <= SKEL_MAP_SQUARE; }
+int map_inputs(int op) { return (op == SKEL_MAP_AXPY || op == SKEL_MAP_MUL) ? 2 : 1; }
+int map_params(int op) {
+    switch (op) {
+    case SKEL_MAP_AXPY: return 1;
+    case SKEL_MAP_AFFINE:
+    case SKEL_MAP_AFFINE_TANH: return 2;
+    default: return 0;
+    }
+}
+bool reduce_op_valid(int op) { return op >= SKEL_SUM && op <= SKEL_MAX; }
+
+skel_status check_map_args(int op, const double* params, int nparams,
+                           skel_container* const* in, int nin, float* p0, float* p1) {
+    if (!map_op_valid(op)) return fail(SKEL_E_INVAL, "unknown map op %d", op);
+    if (nin != map_inputs(op))
+        return fail(SKEL_E_INVAL, "map op %d takes %d input(s), got %d", op,
+                    map_inputs(op), nin);
+    if (!in) return fail(SKEL_E_INVAL, "null input array");
+    if (nparams < map_params(op) || (nparams > 0 && !params))
+        return fail(SKEL_E_INVAL, "map op %d needs %d parameter(s)", op, map_params(op));
+    *p0 = nparams > 0 ? (float)params[0] : 0.0f;
+    *p1 = nparams > 1 ? (float)params[1] : 0.0f;
+    for (int i = 0; i < nin; ++i)
+        if (!in[i]) return fail(SKEL_E_INVAL, "null input container %d", i);
+    return SKEL_OK;
+}
+
+}  // namespace
+}  // namespace skel
+
+using namespace skel;
+
+extern "C" {
+
+skel_status skel_map(skel_map_op op, const double* params, int nparams,
+                     skel_container* const* in, int nin, skel_container* out,
+                     int variant, void* stream) {
+    LaunchCtx lc;
+    skel_status st = begin(stream, &lc);
+    if (st != SKEL_OK) return st;
+    float p0, p1;
+    st = check_map_args(op, params, nparams, in, nin, &p0, &p1);
+    if (st != SKEL_OK) return st;
+    if (!out) return fail(SKEL_E_INVAL, "null output container");
+    for (int i = 0; i < nin; ++i) {
+        if (in[i]->dtype != SKEL_F32) return fail(SKEL_E_DTYPE, "Map inputs must be f32");
+        if (in[i]->n != out->n) return fail(SKEL_E_SHAPE, "Map operand sizes differ");
+    }
+    if (out->dtype != SKEL_F32) return fail(SKEL_E_DTYPE, "Map output must be f32");
+    CallContext cc;
+    cc.skeleton = SKEL_SK_MAP;
+    cc.n = out->n;
+    cc.op = op;
+    int v = choose_variant(variant, cc, &st);
+    if (v < 0) return st;
+    Operands ops;
+    for (int i = 0; i < nin; ++i) ops.add(in[i], SKEL_READ);
+    ops.add(out, SKEL_WRITE);
+    return run(ops, stream, lc, [&]() -> skel_status {
+        if (out->n == 0) return SKEL_OK;
+        const float* x = (const float*)ops.ptr(in[0]);
+        const float* y = nin > 1 ? (const float*)ops.ptr(in[1]) : nullptr;
+        return launch_map(v, op, p0, p1, x, y, (float*)ops.ptr(out), out->n, lc);
+    });
+}
+
+skel_status skel_reduce(skel_reduce_op op, skel_container* in, skel_container* out1,
+                        int variant, void* stream) {
+    LaunchCtx lc;
+    skel_status st = begin(stream, &lc);
+    if (st != SKEL_OK) return st;
+    if (!reduce_op_valid(op)) return fail(SKEL_E_INVAL, "unknown reduce op %d", (int)op);
+    if (!in || !out1) return fail(SKEL_E_INVAL, "null container");
+    if (in == out1) return fail(SKEL_E_INVAL, "Reduce output must differ from its input");
+    if (out1->n != 1) return fail(SKEL_E_SHAPE, "Reduce output must hold one element");
+    const skel_dtype a = in->dtype, b = out1->dtype;
+    bool ok = (a == SKEL_F32 && b == SKEL_F32) || (a == SKEL_BF16 && b == SKEL_F32) ||
+              (a == SKEL_I32 && (b == SKEL_I32 || b == SKEL_I64)) ||
+              (a == SKEL_I64 && b == SKEL_I64);
+    if (!ok)
+        return fail(SKEL_E_DTYPE, "Reduce %s -> %s not supported", dtype_name(a),
+                    dtype_name(b));
+    CallContext cc;
+    cc.skeleton = SKEL_SK_REDUCE;
+    cc.din = a;
+    cc.dout = b;
+    cc.n = in->n;
+    cc.op = op;
+    int v = choose_variant(variant, cc, &st);
+    if (v < 0) return st;
+    Operands ops;
+    ops.add(in, SKEL_READ);
+    ops.add(out1, SKEL_WRITE);
+    return run(ops, stream, lc, [&]() -> skel_status {
+        return launch_reduce(v, op, a, b, ops.ptr(in), in->n, ops.ptr(out1), lc);
+    });
+}
+
+skel_status skel_mapreduce(skel_map_op map_op, const double* params, int nparams,
+                           skel_container* const* in, int nin, skel_reduce_op op,
+                           skel_container* out1, int variant, void* stream) {
+    LaunchCtx lc;
+    skel_status st = begin(stream, &lc);
+    if (st != SKEL_OK) return st;
+    float p0, p1;
+    st = check_map_args(map_op, params, nparams, in, nin, &p0, &p1);
+    if (st != SKEL_OK) return st;
+    if (!reduce_op_valid(op)) return fail(SKEL_E_INVAL, "unknown reduce op %d", (int)op);
+    if (!out1) return fail(SKEL_E_INVAL, "null output container");
+    if (out1->n != 1 || out1->dtype != SKEL_F32)
+        return fail(SKEL_E_SHAPE, "MapReduce output must be one f32 element");
+    const skel_dtype a = in[0]->dtype;
+    for (int i = 0; i < nin; ++i) {
+        if (in[i] == out1) return fail(SKEL_E_INVAL, "MapReduce output aliases an input");
+        if (in[i]->dtype != a) return fail(SKEL_E_DTYPE, "MapReduce inputs differ in dtype");
+        if (in[i]->n != in[0]->n) return fail(SKEL_E_SHAPE, "MapReduce input sizes differ");
+    }
+    bool bf16_ok = map_op == SKEL_MAP_IDENTITY || map_op == SKEL_MAP_MUL ||
+                   map_op == SKEL_MAP_SQUARE;
+    if (!(a == SKEL_F32 || (a == SKEL_BF16 && bf16_ok)))
+        return fail(SKEL_E_DTYPE, "MapReduce over %s with map op %d not supported",
+                    dtype_name(a), (int)map_op);
+    CallContext cc;
+    cc.skeleton = SKEL_SK_MAPREDUCE;
+    cc.din = a;
+    cc.n = in[0]->n;
+    cc.op = op;
+    cc.map_op = map_op;
+    int v = choose_variant(variant, cc, &st);
+    if (v < 0) return st;
+    Operands ops;
+    for (int i = 0; i < nin; ++i) ops.add(in[i], SKEL_READ);
+    ops.add(out1, SKEL_WRITE);
+    return run(ops, stream, lc, [&]() -> skel_status {
+        const void* x = ops.ptr(in[0]);
+        const void* y = nin > 1 ? ops.ptr(in[1]) : nullptr;
+        return launch_mapreduce(v, map_op, p0, p1, a, x, y, in[0]->n, op,
+                                (float*)ops.ptr(out1), lc);
+    });
+}
+
+skel_status skel_mapoverlap1d(skel_container* in, skel_container* out, const float* w,
+                              int radius, skel_edge edge, float pad, int variant,
+                              void* stream) {
+    LaunchCtx lc;
+    skel_status st = begin(stream, &lc);
+    if (st != SKEL_OK) return st;
+    if (!in || !out || !w) return fail(SKEL_E_INVAL, "null argument");
+    if (in == out) return fail(SKEL_E_INVAL, "MapOverlap cannot run in place");
+    if (radius < 0 || radius > SKEL_MAX_RADIUS_1D)
+        return fail(SKEL_E_INVAL, "radius %d outside 0..%d", radius, SKEL_MAX_RADIUS_1D);
+    if (edge < SKEL_EDGE_CLAMP || edge > SKEL_EDGE_CYCLIC)
+        return fail(SKEL_E_INVAL, "unknown edge rule %d", (int)edge);
+    if (in->dtype != SKEL_F32 || out->dtype != SKEL_F32)
+        return fail(SKEL_E_DTYPE, "MapOverlap operands must be f32");
+    if (in->n != out->n) return fail(SKEL_E_SHAPE, "MapOverlap operand sizes differ");
+    CallContext cc;
+    cc.skeleton = SKEL_SK_MAPOVERLAP1D;
+    cc.n = in->n;
+    int v = choose_variant(variant, cc, &st);
+    if (v < 0) return st;
+    Operands ops;
+    ops.add(in, SKEL_READ);
+    ops.add(out, SKEL_WRITE);
+    return run(ops, stream, lc, [&]() -> skel_status {
+        if (in->n == 0) return SKEL_OK;
+        return launch_overlap1d(v, (const float*)ops.ptr(in), (float*)ops.ptr(out), in->n,
+                                w, radius, edge, pad, lc);
+    });
+}
+
+skel_status skel_mapoverlap2d(skel_container* in, skel_container* out, const float* w2d,
+                              const float* wy, const float* wx, int ry, int rx,
+                              skel_edge edge, float pad, int variant, void* stream) {
+    LaunchCtx lc;
+    skel_status st = begin(stream, &lc);
+    if (st != SKEL_OK) return st;
+    if (!in || !out) return fail(SKEL_E_INVAL, "null container");
+    if (in == out) return fail(SKEL_E_INVAL, "MapOverlap cannot run in place");
+    if (!w2d && (!wy || !wx))
+        return fail(SKEL_E_INVAL, "need w2d or both separable factors wy, wx");
+    if (ry < 0 || rx < 0 || ry > SKEL_MAX_RADIUS_2D || rx > SKEL_MAX_RADIUS_2D)
+        return fail(SKEL_E_INVAL, "radii (%d, %d) outside 0..%d", ry, rx,
+                    SKEL_MAX_RADIUS_2D);
+    if (edge < SKEL_EDGE_CLAMP || edge > SKEL_EDGE_CYCLIC)
+        return fail(SKEL_E_INVAL, "unknown edge rule %d", (int)edge);
+    if (in->dtype != SKEL_F32 || out->dtype != SKEL_F32)
+        return fail(SKEL_E_DTYPE, "MapOverlap operands must be f32");
+    if (in->rows != out->rows || in->cols != out->cols)
+        return fail(SKEL_E_SHAPE, "MapOverlap operand shapes differ");
+    CallContext cc;
+    cc.skeleton = SKEL_SK_MAPOVERLAP2D;
+    cc.n = in->n;
+    cc.rows = in->rows;
+    cc.cols = in->cols;
+    cc.separable = w2d ? 0 : 1;
+    int v = choose_variant(variant, cc, &st);
+    if (v < 0) return st;
+    Operands ops;
+    ops.add(in, SKEL_READ);
+    ops.add(out, SKEL_WRITE);
+    return run(ops, stream, lc, [&]() -> skel_status {
+        if (in->n == 0) return SKEL_OK;
+        return launch_overlap2d(v, (const float*)ops.ptr(in), (float*)ops.ptr(out),
+                                in->rows, in->cols, w2d, w2d ? nullptr : wy,
+                                w2d ? nullptr : wx, ry, rx, edge, pad, lc);
+    });
+}
+
+skel_status skel_scan(skel_container* in, skel_container* out, skel_scan_kind kind,
+                      skel_reduce_op op, int variant, void* stream) {
+    LaunchCtx lc;
+    skel_status st = begin(stream, &lc);
+    if (st != SKEL_OK) return st;
+    if (!in || !out) return fail(SKEL_E_INVAL, "null container");
+    if (kind != SKEL_INCLUSIVE && kind != SKEL_EXCLUSIVE)
+        return fail(SKEL_E_INVAL, "unknown scan kind %d", (int)kind);
+    if (!reduce_op_valid(op)) return fail(SKEL_E_INVAL, "unknown scan op %d", (int)op);
+    const skel_dtype a = in->dtype, b = out->dtype;
+    bool ok = (a == SKEL_I32 && (b == SKEL_I32 || b == SKEL_I64)) ||
+              (a == SKEL_I64 && b == SKEL_I64) || (a == SKEL_F32 && b == SKEL_F32);
+    if (!ok)
+        return fail(SKEL_E_DTYPE, "Scan %s -> %s not supported", dtype_name(a),
+                    dtype_name(b));
+    if (in->n != out->n) return fail(SKEL_E_SHAPE, "Scan operand sizes differ");
+    CallContext cc;
+    cc.skeleton = SKEL_SK_SCAN;
+    cc.din = a;
+    cc.dout = b;
+    cc.n = in->n;
+    cc.op = op;
+    int v = choose_variant(variant, cc, &st);
+    if (v < 0) return st;
+    Operands ops;
+    ops.add(in, SKEL_READ);
+    ops.add(out, SKEL_WRITE);
+    return run(ops, stream, lc, [&]() -> skel_status {
+        if (in->n == 0) return SKEL_OK;
+        return launch_scan(v, kind, op, a, b, ops.ptr(in), ops.ptr(out), in->n, lc);
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,126 @@
+// Host-memory stand-in for the device runtime, linked with the library's
+// container protocol and execution plan into libskel_hosttest.so (g++ only, no
+// HIP).  "Device" memory is malloc'd, copies are memcpy, streams are opaque
+// tokens, and every operation is counted so tests can check exactly which
+// transfers and synchronisations the protocol issued.  Failures of device
+// allocation and of copies can be injected.
+#include <cstdlib>
+#include <cstring>
+#include <vector>
+
+#include "common.hpp"
+
+namespace {
+
+struct Counts {
+    unsigned long long host_allocs, host_frees, dev_allocs, dev_frees, h2d, d2h,
+        event_creates, event_records, stream_waits, event_syncs, stream_syncs;
+};
+Counts g_counts;
+int g_fail_dev_alloc = 0;
+int g_fail_copy = 0;
+// (stream, event) of every stream_wait_event, for ordering checks
+std::vector<std::pair<void*, void*>> g_waits;
+
+class FakeBackend final : public skel::Backend {
+  public:
+    skel_status host_alloc(void** p, size_t bytes) override {
+        *p = std::malloc(bytes);
+        if (!*p) return skel::fail(SKEL_E_NOMEM, "fake host alloc failed");
+        g_counts.host_allocs++;
+        return SKEL_OK;
+    }
+    void host_free(void* p) override {
+        g_counts.host_frees++;
+        std::free(p);
+    }
+    skel_status dev_alloc(const skel_allocator&, void** p, size_t bytes, void*) override {
+        if (g_fail_dev_alloc > 0) {
+            g_fail_dev_alloc--;
+            return skel::fail(SKEL_E_NOMEM, "injected device allocation failure");
+        }
+        *p = std::aligned_alloc(256, (bytes + 255) & ~size_t(255));
+        g_counts.dev_allocs++;
+        return SKEL_OK;
+    }
+    void dev_free(const skel_allocator&, void* p, void*) override {
+        g_counts.dev_frees++;
+        std::free(p);
+    }
+    skel_status copy_h2d(void* dst, const void* src, size_t bytes, void*) override {
+        if (g_fail_copy > 0) {
+            g_fail_copy--;
+            return skel::fail(SKEL_E_HIP, "injected copy failure");
+        }
+        std::memcpy(dst, src, bytes);
+        g_counts.h2d++;
+        return SKEL_OK;
+    }
+    skel_status copy_d2h(void* dst, const void* src, size_t bytes, void*) override {
+        if (g_fail_copy > 0) {
+            g_fail_copy--;
+            return skel::fail(SKEL_E_HIP, "injected copy failure");
+        }
+        std::memcpy(dst, src, bytes);
+        g_counts.d2h++;
+        return SKEL_OK;
+    }
+    skel_status event_create(void** ev) override {
+        *ev = new int(0);
+        g_counts.event_creates++;
+        return SKEL_OK;
+    }
+    void event_destroy(void* ev) override { delete static_cast<int*>(ev); }
+    skel_status event_record(void* ev, void*) override {
+        ++*static_cast<int*>(ev);
+        g_counts.event_records++;
+        return SKEL_OK;
+    }
+    skel_status stream_wait_event(void* s, void* ev) override {
+        g_counts.stream_waits++;
+        g_waits.emplace_back(s, ev);
+        return SKEL_OK;
+    }
+    skel_status event_sync(void*) override {
+        g_counts.event_syncs++;
+        return SKEL_OK;
+    }
+    skel_status stream_sync(void*) override {
+        g_counts.stream_syncs++;
+        return SKEL_OK;
+    }
+};
+
+FakeBackend g_fake;
+
+}  // namespace
+
+extern "C" {
+
+skel_status skel_hosttest_init(void) {
+    skel::rt().backend = &g_fake;
+    skel::rt().device = 0;
+    skel::rt().initialized = true;
+    std::memset(&g_counts, 0, sizeof g_counts);
+    g_fail_dev_alloc = g_fail_copy = 0;
+    g_waits.clear();
+    return SKEL_OK;
+}
+
+void skel_hosttest_fail_dev_alloc(int k) { g_fail_dev_alloc = k; }
+void skel_hosttest_fail_copy(int k) { g_fail_copy = k; }
+
+// host_allocs, host_frees, dev_allocs, dev_frees, h2d, d2h, event_creates,
+// event_records, stream_waits, event_syncs, stream_syncs
+void skel_hosttest_counts(unsigned long long* out11) {
+    std::memcpy(out11, &g_counts, sizeof g_counts);
+}
+
+int skel_hosttest_wait_count_on(void* stream) {
+    int k = 0;
+    for (auto& w : g_waits)
+        if (w.first == stream) ++k;
+    return k;
+}
+
+}  // extern "C"

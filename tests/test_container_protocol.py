@@ -1,0 +1,369 @@
+"""Smart-container coherence protocol (Section IV of arXiv:1405.2915) and the
+execution plan (Sections II-III), tested on the CPU.
+
+libskel_hosttest.so links the library's own container, plan and error code
+(compiled by g++) with a host-memory fake of the device runtime, so every
+transfer the protocol issues is counted exactly.  A small Python model of the
+validity state machine replays the same acquire/release traces and predicts
+status codes and transfer counts.
+"""
+import ctypes as C
+import os
+import random
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_1405_2915_amd", "libskel_hosttest.so")
+
+OK, E_INVAL, E_DTYPE, E_SHAPE, E_NOMEM, E_STATE, E_UNSUP, E_HIP = range(8)
+F32, BF16, I32, I64 = range(4)
+HOST, DEVICE = 0, 1
+READ, WRITE, RW = 1, 2, 3
+
+
+class Stats(C.Structure):
+    _fields_ = [(k, C.c_uint64) for k in
+                ("h2d", "d2h", "h2d_bytes", "d2h_bytes", "eager_equiv", "acquires")]
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("libskel_hosttest.so not built (paper_1405_2915_amd/build_lib.py)")
+    L = C.CDLL(LIB)
+    vp = C.c_void_p
+    L.skel_container_create.argtypes = [C.c_int, C.c_int64, C.c_int64, vp, C.POINTER(vp)]
+    L.skel_container_destroy.argtypes = [vp]
+    L.skel_container_acquire.argtypes = [vp, C.c_int, C.c_int, vp, C.POINTER(vp)]
+    L.skel_container_release.argtypes = [vp, C.c_int, vp]
+    L.skel_container_stats.argtypes = [vp, C.POINTER(Stats)]
+    L.skel_last_error.restype = C.c_char_p
+    L.skel_hosttest_counts.argtypes = [C.POINTER(C.c_ulonglong)]
+    L.skel_hosttest_wait_count_on.argtypes = [vp]
+    L.skel_select_variant.argtypes = [C.c_int, C.c_int, C.c_int64, C.c_int64, C.c_int64,
+                                      C.c_int]
+    L.skel_variant_name.restype = C.c_char_p
+    L.skel_load_plan.argtypes = [C.c_char_p]
+    return L
+
+
+@pytest.fixture()
+def rt(lib):
+    lib.skel_hosttest_init()
+    lib.skel_clear_plan()
+    return lib
+
+
+def counts(lib):
+    a = (C.c_ulonglong * 11)()
+    lib.skel_hosttest_counts(a)
+    keys = ("host_allocs", "host_frees", "dev_allocs", "dev_frees", "h2d", "d2h",
+            "event_creates", "event_records", "stream_waits", "event_syncs", "stream_syncs")
+    return dict(zip(keys, a))
+
+
+def create(lib, n, data=None, dtype=F32):
+    h = C.c_void_p()
+    src = None if data is None else C.c_void_p(data.ctypes.data)
+    assert lib.skel_container_create(dtype, 1, n, src, C.byref(h)) == OK
+    return h
+
+
+def acquire(lib, h, place, access, stream=1):
+    p = C.c_void_p()
+    st = lib.skel_container_acquire(h, place, access, C.c_void_p(stream), C.byref(p))
+    return st, p.value
+
+
+def stats(lib, h):
+    s = Stats()
+    assert lib.skel_container_stats(h, C.byref(s)) == OK
+    return {k: getattr(s, k) for k, _ in Stats._fields_}
+
+
+class Model:
+    """Validity bits and outstanding accesses of one container."""
+
+    def __init__(self, initialised):
+        self.valid = {HOST: initialised, DEVICE: False}
+        self.readers = {HOST: 0, DEVICE: 0}
+        self.writer = None
+        self.h2d = self.d2h = 0
+
+    def acquire(self, place, access):
+        if self.writer is not None:
+            return E_STATE
+        if access & WRITE and (self.readers[HOST] + self.readers[DEVICE]):
+            return E_STATE
+        if access & READ and not (self.valid[HOST] or self.valid[DEVICE]):
+            return E_STATE
+        other = HOST if place == DEVICE else DEVICE
+        if access & READ and not self.valid[place]:
+            if place == DEVICE:
+                self.h2d += 1
+            else:
+                self.d2h += 1
+        self.valid[place] = True
+        if access & WRITE:
+            self.valid[other] = False
+            self.writer = place
+        else:
+            self.readers[place] += 1
+        return OK
+
+    def release(self, place):
+        if self.writer == place:
+            self.writer = None
+            return OK
+        if self.readers[place] == 0:
+            return E_STATE
+        self.readers[place] -= 1
+        return OK
+
+
+def test_lazy_copies_and_data_flow(rt):
+    x = np.arange(16, dtype=np.float32)
+    h = create(rt, 16, x)
+    # device read: one H2D
+    st, dp = acquire(rt, h, DEVICE, READ)
+    assert st == OK and dp
+    got = np.frombuffer((C.c_float * 16).from_address(dp), dtype=np.float32)
+    assert np.array_equal(got, x)
+    assert rt.skel_container_release(h, DEVICE, C.c_void_p(1)) == OK
+    # second device read: copy still valid, no transfer
+    st, _ = acquire(rt, h, DEVICE, READ)
+    assert st == OK and rt.skel_container_release(h, DEVICE, C.c_void_p(1)) == OK
+    assert stats(rt, h)["h2d"] == 1
+    # a "kernel" writes the device copy in place
+    st, dp = acquire(rt, h, DEVICE, RW)
+    assert st == OK
+    C.memmove(dp, (np.full(16, 7.0, np.float32)).ctypes.data, 64)
+    assert rt.skel_container_release(h, DEVICE, C.c_void_p(1)) == OK
+    # host read sees the device write: exactly one D2H, and it waited first
+    before = counts(rt)["event_syncs"]
+    st, hp = acquire(rt, h, HOST, READ)
+    assert st == OK
+    host = np.frombuffer((C.c_float * 16).from_address(hp), dtype=np.float32)
+    assert np.all(host == 7.0)
+    assert counts(rt)["event_syncs"] > before
+    assert rt.skel_container_release(h, HOST, None) == OK
+    s = stats(rt, h)
+    assert (s["h2d"], s["d2h"], s["h2d_bytes"], s["d2h_bytes"]) == (1, 1, 64, 64)
+    # host read again: no transfer
+    st, _ = acquire(rt, h, HOST, READ)
+    assert st == OK and rt.skel_container_release(h, HOST, None) == OK
+    assert stats(rt, h)["d2h"] == 1
+    assert rt.skel_container_destroy(h) == OK
+
+
+def test_chain_of_twenty_device_calls(rt):
+    # Section IV: lazy copying removes the redundant transfers of a call loop.
+    # 20 dependent device calls over one in/out container move data twice.
+    x = np.ones(1024, np.float32)
+    h = create(rt, 1024, x)
+    for _ in range(20):
+        st, _ = acquire(rt, h, DEVICE, RW)
+        assert st == OK
+        assert rt.skel_container_release(h, DEVICE, C.c_void_p(1)) == OK
+    st, _ = acquire(rt, h, HOST, READ)
+    assert st == OK and rt.skel_container_release(h, HOST, None) == OK
+    s = stats(rt, h)
+    assert (s["h2d"], s["d2h"]) == (1, 1)
+    c = counts(rt)
+    assert (c["h2d"], c["d2h"], c["dev_allocs"]) == (1, 1, 1)
+    assert rt.skel_container_destroy(h) == OK
+
+
+def test_write_only_acquire_copies_nothing(rt):
+    h = create(rt, 64)  # uninitialised
+    st, _ = acquire(rt, h, DEVICE, READ)
+    assert st == E_STATE and b"uninitialised" in rt.skel_last_error()
+    st, _ = acquire(rt, h, DEVICE, WRITE)
+    assert st == OK
+    assert rt.skel_container_release(h, DEVICE, C.c_void_p(1)) == OK
+    assert counts(rt)["h2d"] == 0 and counts(rt)["host_allocs"] == 0
+    st, _ = acquire(rt, h, HOST, READ)
+    assert st == OK and rt.skel_container_release(h, HOST, None) == OK
+    assert counts(rt)["d2h"] == 1
+    # host WRITE invalidates the device copy; next device read copies again
+    st, _ = acquire(rt, h, HOST, WRITE)
+    assert st == OK and rt.skel_container_release(h, HOST, None) == OK
+    st, _ = acquire(rt, h, DEVICE, READ)
+    assert st == OK and rt.skel_container_release(h, DEVICE, C.c_void_p(1)) == OK
+    assert stats(rt, h)["h2d"] == 1
+    assert rt.skel_container_destroy(h) == OK
+
+
+def test_conflicts_and_release_errors(rt):
+    h = create(rt, 8, np.zeros(8, np.float32))
+    assert rt.skel_container_release(h, DEVICE, C.c_void_p(1)) == E_STATE
+    st, _ = acquire(rt, h, DEVICE, READ)
+    assert st == OK
+    st, _ = acquire(rt, h, HOST, READ)  # two readers are fine
+    assert st == OK
+    st, _ = acquire(rt, h, HOST, WRITE)  # writer while readers are out
+    assert st == E_STATE
+    assert rt.skel_container_destroy(h) == E_STATE
+    assert rt.skel_container_release(h, HOST, None) == OK
+    assert rt.skel_container_release(h, DEVICE, C.c_void_p(1)) == OK
+    st, _ = acquire(rt, h, DEVICE, WRITE)
+    assert st == OK
+    st, _ = acquire(rt, h, DEVICE, READ)  # anything while a writer is out
+    assert st == E_STATE
+    assert rt.skel_container_release(h, DEVICE, C.c_void_p(1)) == OK
+    assert rt.skel_container_acquire(h, 7, READ, None, C.byref(C.c_void_p())) == E_INVAL
+    assert rt.skel_container_acquire(h, HOST, 0, None, C.byref(C.c_void_p())) == E_INVAL
+    assert rt.skel_container_destroy(h) == OK
+
+
+def test_cross_stream_dependence(rt):
+    # Section V: containers carry dependences between asynchronous calls; an
+    # access on another stream must wait for the last access's event
+    h = create(rt, 32, np.zeros(32, np.float32))
+    st, _ = acquire(rt, h, DEVICE, RW, stream=11)
+    assert st == OK and rt.skel_container_release(h, DEVICE, C.c_void_p(11)) == OK
+    assert rt.skel_hosttest_wait_count_on(C.c_void_p(22)) == 0
+    st, _ = acquire(rt, h, DEVICE, READ, stream=22)
+    assert st == OK and rt.skel_container_release(h, DEVICE, C.c_void_p(22)) == OK
+    assert rt.skel_hosttest_wait_count_on(C.c_void_p(22)) == 1
+    # same stream: stream order suffices, no wait
+    st, _ = acquire(rt, h, DEVICE, READ, stream=22)
+    assert st == OK and rt.skel_container_release(h, DEVICE, C.c_void_p(22)) == OK
+    assert rt.skel_hosttest_wait_count_on(C.c_void_p(22)) == 1
+    # a writer on a third stream waits for both earlier streams
+    st, _ = acquire(rt, h, DEVICE, WRITE, stream=33)
+    assert st == OK and rt.skel_container_release(h, DEVICE, C.c_void_p(33)) == OK
+    assert rt.skel_hosttest_wait_count_on(C.c_void_p(33)) == 2
+    assert rt.skel_container_destroy(h) == OK
+
+
+def test_injected_failures_leave_state_unchanged(rt):
+    x = np.arange(8, dtype=np.float32)
+    h = create(rt, 8, x)
+    rt.skel_hosttest_fail_dev_alloc(1)
+    st, _ = acquire(rt, h, DEVICE, READ)
+    assert st == E_NOMEM
+    rt.skel_hosttest_fail_copy(1)
+    st, _ = acquire(rt, h, DEVICE, READ)
+    assert st == E_HIP
+    s = stats(rt, h)
+    assert (s["h2d"], s["acquires"]) == (0, 0)
+    st, _ = acquire(rt, h, DEVICE, READ)  # recovers
+    assert st == OK and rt.skel_container_release(h, DEVICE, C.c_void_p(1)) == OK
+    assert stats(rt, h)["h2d"] == 1
+    assert rt.skel_container_destroy(h) == OK
+    c = counts(rt)
+    assert c["dev_allocs"] == c["dev_frees"] == 1
+    assert c["host_allocs"] == c["host_frees"] == 1
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_traces_match_model(rt, seed):
+    rnd = random.Random(seed)
+    init = rnd.random() < 0.7
+    h = create(rt, 4, np.zeros(4, np.int32) if init else None, dtype=I32)
+    m = Model(init)
+    held = []
+    for _ in range(300):
+        if held and rnd.random() < 0.45:
+            place = held.pop(rnd.randrange(len(held)))
+            assert rt.skel_container_release(h, place, C.c_void_p(1)) == m.release(place)
+            continue
+        place = rnd.choice((HOST, DEVICE))
+        access = rnd.choice((READ, WRITE, RW))
+        expect = m.acquire(place, access)
+        st, _ = acquire(rt, h, place, access)
+        assert st == expect, (place, access, rt.skel_last_error())
+        if st == OK:
+            held.append(place)
+        s = stats(rt, h)
+        assert (s["h2d"], s["d2h"]) == (m.h2d, m.d2h)
+    for place in held:
+        assert rt.skel_container_release(h, place, C.c_void_p(1)) == OK
+    assert rt.skel_container_destroy(h) == OK
+
+
+def test_create_validation(rt):
+    h = C.c_void_p()
+    assert rt.skel_container_create(9, 1, 4, None, C.byref(h)) == E_DTYPE
+    assert rt.skel_container_create(F32, 0, 4, None, C.byref(h)) == E_SHAPE
+    assert rt.skel_container_create(F32, 1, -1, None, C.byref(h)) == E_SHAPE
+    assert rt.skel_container_create(F32, 1 << 33, 4, None, C.byref(h)) == E_SHAPE
+    # empty containers are valid everywhere and never allocate
+    assert rt.skel_container_create(F32, 1, 0, None, C.byref(h)) == OK
+    st, p = acquire(rt, h, DEVICE, READ)
+    assert st == OK and not p
+    assert rt.skel_container_release(h, DEVICE, C.c_void_p(1)) == OK
+    assert rt.skel_container_destroy(h) == OK
+    assert counts(rt)["dev_allocs"] == 0
+
+
+# ------------------------------------------------------------ execution plan
+
+SK_MAP, SK_REDUCE, SK_MAPREDUCE, SK_OV1, SK_OV2, SK_SCAN = range(6)
+
+
+def name_of(lib, sk, v):
+    n = lib.skel_variant_name(sk, v)
+    return n.decode() if n else None
+
+
+def test_variant_registry(rt):
+    want = {SK_MAP: 3, SK_REDUCE: 4, SK_MAPREDUCE: 4, SK_OV1: 2, SK_OV2: 3, SK_SCAN: 3}
+    for sk, k in want.items():
+        assert rt.skel_variant_count(sk) == k
+        names = [name_of(rt, sk, v) for v in range(k)]
+        assert len(set(names)) == k and all(names)
+        assert rt.skel_variant_name(sk, k) is None
+    assert rt.skel_variant_count(99) == 0
+
+
+def test_static_plan(rt):
+    sel = lambda sk, n, dt=F32, sep=0: name_of(
+        rt, sk, rt.skel_select_variant(sk, dt, n, 1, n, sep))
+    assert sel(SK_REDUCE, 1000) == "R0_single_wg"
+    assert sel(SK_REDUCE, 1 << 26) == "R2_ticket"
+    assert sel(SK_SCAN, 100, I32) == "S0_single_wg"
+    assert sel(SK_SCAN, 1 << 27, I32) == "S2_decoupled_lookback"
+    assert sel(SK_OV2, 1 << 24, F32, 1) == "O2c_lds_separable"
+    assert sel(SK_OV2, 1 << 24, F32, 0) == "O2b_lds_tile"  # separable not selectable
+    assert sel(SK_MAP, 1 << 20) == "M2_vec4x4_nt"
+    assert rt.skel_select_variant(17, F32, 10, 1, 10, 0) == -1
+
+
+def test_plan_table(rt, tmp_path):
+    p = tmp_path / "plan.txt"
+    p.write_text("# tuned\nREDUCE f32 10 R1_two_pass\nREDUCE f32 20 R3_atomic\n"
+                 "SCAN i32 12 S1_reduce_then_scan\nMAPOVERLAP2D f32 10 O2c_lds_separable\n")
+    assert rt.skel_load_plan(str(p).encode()) == OK
+    sel = lambda sk, n, dt=F32, sep=0: name_of(
+        rt, sk, rt.skel_select_variant(sk, dt, n, 1, n, sep))
+    assert sel(SK_REDUCE, 1 << 15) == "R1_two_pass"
+    assert sel(SK_REDUCE, (1 << 20) - 5) == "R3_atomic"   # ceil(log2) = 20
+    assert sel(SK_REDUCE, 1 << 28) == "R3_atomic"          # extrapolate beyond
+    assert sel(SK_REDUCE, 16) == "R1_two_pass"             # below the table
+    assert sel(SK_SCAN, 1 << 20, I32) == "S1_reduce_then_scan"
+    assert sel(SK_SCAN, 1 << 20, I64) == "S2_decoupled_lookback"  # no entry: static
+    # table entry not selectable for this call: static rule instead
+    assert sel(SK_OV2, 1 << 20, F32, 0) == "O2b_lds_tile"
+    # a bad file is rejected whole and the old table stays
+    bad = tmp_path / "bad.txt"
+    bad.write_text("REDUCE f32 10 R1_two_pass\nREDUCE f99 4 nope\n")
+    assert rt.skel_load_plan(str(bad).encode()) == E_INVAL
+    assert sel(SK_REDUCE, 1 << 15) == "R1_two_pass"
+    assert rt.skel_clear_plan() == OK
+    assert sel(SK_REDUCE, 1 << 15) == "R0_single_wg"
+
+
+def test_environment_override(rt, monkeypatch):
+    monkeypatch.setenv("SKEL_VARIANT_REDUCE", "R1_two_pass")
+    assert name_of(rt, SK_REDUCE, rt.skel_select_variant(SK_REDUCE, F32, 100, 1, 100, 0)) \
+        == "R1_two_pass"
+    monkeypatch.setenv("SKEL_VARIANT_REDUCE", "3")
+    assert rt.skel_select_variant(SK_REDUCE, F32, 100, 1, 100, 0) == 3
+    monkeypatch.setenv("SKEL_VARIANT_MAPOVERLAP2D", "O2c_lds_separable")
+    # override not selectable (weights not separable): falls through
+    assert name_of(rt, SK_OV2, rt.skel_select_variant(SK_OV2, F32, 100, 10, 10, 0)) \
+        == "O2b_lds_tile"

@@ -1,0 +1,128 @@
+"""The C ABI on the GPU: argument validation (no side effects on failure),
+selectability of forced variants, transfer accounting of the smart containers
+over a chain of dependent skeleton calls (Section IV), and cross-stream
+ordering through container events (Section V)."""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+import synth_inputs as si
+
+pytestmark = pytest.mark.gpu
+
+
+def status_of(fn, *a, **k):
+    import paper_1405_2915_amd as skel
+    try:
+        fn(*a, **k)
+    except skel.SkelError as e:
+        return e.status
+    return skel.OK
+
+
+def test_validation_statuses(skel):
+    x = skel.Container.from_numpy(np.ones(100, np.float32))
+    xi = skel.Container.from_numpy(np.ones(100, np.int32))
+    y = skel.Container.from_numpy(np.ones(50, np.float32))
+    r = skel.Container.empty(skel.F32, 1)
+    r2 = skel.Container.empty(skel.F32, 2)
+    assert status_of(skel.skel_map, 99, [], [x], x) == skel.E_INVAL
+    assert status_of(skel.skel_map, skel.MAP_AXPY, [2.5], [x], x) == skel.E_INVAL  # 1 input
+    assert status_of(skel.skel_map, skel.MAP_AXPY, [], [x, x], x) == skel.E_INVAL  # no p0
+    assert status_of(skel.skel_map, skel.MAP_MUL, [], [x, y], x) == skel.E_SHAPE
+    assert status_of(skel.skel_map, skel.MAP_SQUARE, [], [xi], x) == skel.E_DTYPE
+    assert status_of(skel.skel_reduce, skel.SUM, x, r2) == skel.E_SHAPE
+    assert status_of(skel.skel_reduce, skel.SUM, x, x) == skel.E_INVAL
+    assert status_of(skel.skel_reduce, skel.SUM, xi, r) == skel.E_DTYPE  # i32 -> f32
+    assert status_of(skel.skel_reduce, 7, x, r) == skel.E_INVAL
+    assert status_of(skel.skel_reduce, skel.SUM, x, r, variant=17) == skel.E_UNSUPPORTED
+    assert status_of(skel.skel_reduce, skel.MAX, x, r, variant=3) == skel.E_UNSUPPORTED
+    assert status_of(skel.skel_scan, x, x, 5, skel.SUM) == skel.E_INVAL
+    assert status_of(skel.skel_scan, xi, y, skel.INCLUSIVE, skel.SUM) == skel.E_DTYPE
+    assert status_of(skel.skel_mapoverlap1d, x, x, [1, 1, 1], 1) == skel.E_INVAL
+    big = np.ones(2 * 65 + 1, np.float32)
+    o = skel.Container.empty(skel.F32, 100)
+    assert status_of(skel.skel_mapoverlap1d, x, o, big, 65) == skel.E_INVAL
+    img = skel.Container.from_numpy(np.ones((8, 8), np.float32))
+    img2 = skel.Container.empty(skel.F32, 8, 9)
+    assert status_of(skel.skel_mapoverlap2d, img, img2, wy=[1, 1, 1], wx=[1, 1, 1]) \
+        == skel.E_SHAPE
+    img3 = skel.Container.empty(skel.F32, 8, 8)
+    assert status_of(skel.skel_mapoverlap2d, img, img3, w2d=np.ones((3, 3)), variant=2) \
+        == skel.E_UNSUPPORTED
+    # failed calls moved nothing and counted nothing
+    for c in (x, xi, y, r, r2):
+        s = c.stats()
+        assert s["h2d"] == 0 and s["eager_equiv"] == 0, s
+    # an uninitialised container cannot be read
+    u = skel.Container.empty(skel.F32, 100)
+    assert status_of(skel.skel_reduce, skel.SUM, u, r) == skel.E_STATE
+    assert "uninitialised" in skel.skel_last_error()
+
+
+def test_chain_of_twenty_calls_counts_copies(skel):
+    # Section IV: in a loop of calls, lazy copying moves each operand once.
+    n = (1 << 20) + 3
+    x = si.uniform_f32(n, -1.0, 1.0, 0, 0)
+    y = si.uniform_f32(n, -1.0, 1.0, 0, 1)
+    cx, cy = skel.Container.from_numpy(x), skel.Container.from_numpy(y)
+    want = y.copy()
+    for _ in range(20):
+        skel.skel_map(skel.MAP_AXPY, [2.5], [cx, cy], cy)
+        # exact binary64 value rounded once = the fused multiply-add result
+        want = (2.5 * x.astype(np.float64) + want.astype(np.float64)).astype(np.float32)
+    assert np.array_equal(cy.to_numpy(), want)
+    sx, sy = cx.stats(), cy.stats()
+    assert (sx["h2d"], sx["d2h"], sx["eager_equiv"]) == (1, 0, 20)
+    assert (sy["h2d"], sy["d2h"], sy["eager_equiv"]) == (1, 1, 40)
+    # the lazy scheme moved 3 copies where an eager one moves 60
+    assert sx["h2d"] + sx["d2h"] + sy["h2d"] + sy["d2h"] == 3
+    assert sy["d2h_bytes"] == 4 * n
+
+
+def test_device_pointer_and_host_write(skel):
+    import torch
+    n = 4096
+    c = skel.Container.from_numpy(np.arange(n, dtype=np.float32))
+    ptr = skel.skel_container_acquire(c, skel.DEVICE, skel.READ)
+    assert ptr % 256 == 0
+    skel.skel_container_release(c, skel.DEVICE)
+    c.write_numpy(np.full(n, 3.0, np.float32))  # host write invalidates device copy
+    r = skel.Container.empty(skel.F32, 1)
+    skel.skel_reduce(skel.SUM, c, r)
+    assert r.to_numpy()[0] == 3.0 * n
+    assert c.stats()["h2d"] == 2
+    torch.cuda.synchronize()
+
+
+def test_cross_stream_dependence(skel):
+    import torch
+    n = 1 << 22
+    x = si.uniform_f32(n, -1.0, 1.0, 0, 5)
+    cx = skel.Container.from_numpy(x)
+    cy = skel.Container.empty(skel.F32, n)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    for _ in range(3):
+        skel.skel_map(skel.MAP_AFFINE, [2.0, 1.0], [cx], cy, stream=s1)
+        r = skel.Container.empty(skel.F32, 1)
+        # reads cy on another stream: must wait for the write on s1
+        skel.skel_reduce(skel.SUM, cy, r, stream=s2)
+        got = float(r.to_numpy()[0])
+        ref = float(np.sum(2.0 * x.astype(np.float64) + 1.0))
+        assert abs(got - ref) <= 1e-5 * float(np.sum(np.abs(2.0 * x.astype(np.float64) + 1.0)))
+    skel.skel_sync(s1)
+    skel.skel_sync(s2)
+
+
+def test_variant_names_and_plan(skel):
+    names = {sk: [skel.skel_variant_name(sk, v) for v in range(skel.skel_variant_count(sk))]
+             for sk in range(6)}
+    assert names[skel.SK_REDUCE] == ["R0_single_wg", "R1_two_pass", "R2_ticket", "R3_atomic"]
+    assert names[skel.SK_SCAN][2] == "S2_decoupled_lookback"
+    assert skel.skel_select_variant(skel.SK_SCAN, skel.I32, 1 << 27) == 2
+
+
+def test_sync_reports_no_error(skel):
+    skel.skel_sync()
+    skel.skel_sync(0)
