@@ -1,0 +1,315 @@
+"""Benchmark of the skeleton hot path on one MI355X.
+
+One step = one pass over every skeleton on a fixed, HBM-resident synthetic
+workload (the large configuration; every call goes through the execution
+plan, and every operand through the container protocol, which copies nothing
+once the device copies are valid):
+
+  Map        saxpy y <- 2.5 x + y, in place          x, y  f32[2^26]
+  MapOverlap 1D 5-point binomial, clamp             z     f32[2^26]
+  Scan       exclusive, int32 -> int64               s     i32[2^27]
+  MapReduce  dot(x, y)                               x, y  f32[2^26]
+  MapOverlap 2D 9x9 separable Gaussian (sigma 2)     img   f32[4096][4096]
+  Reduce     sum of the 1D stencil's output          f32[2^26]
+
+The order keeps consecutive calls on different data, so no call finds its
+inputs in the 256 MiB Infinity Cache.  Reported: whole-step throughput in
+algorithmic GB/s (inputs read once + outputs written once), each skeleton's
+kernel time from HIP events on the launch stream, the roofline of the
+dominant kernel (the scan), a measured copy-kernel ceiling, the speedup over
+the fixed plain variants, and the CPU oracle timed on a sample.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import platform
+import re
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+N_VEC = 1 << 26
+N_SCAN = 1 << 27
+IMG = 4096
+
+# algorithmic bytes per call
+BYTES = {
+    "map_saxpy": 12 * N_VEC,
+    "mapoverlap1d_5pt": 8 * N_VEC,
+    "scan_excl_i32_i64": 12 * N_SCAN,
+    "mapreduce_dot": 8 * N_VEC,
+    "mapoverlap2d_9x9": 8 * IMG * IMG,
+    "reduce_sum": 4 * N_VEC,
+}
+ORDER = list(BYTES)
+PLAIN = {"map_saxpy": "M0_scalar", "mapoverlap1d_5pt": "O1a_direct",
+         "scan_excl_i32_i64": "S1_reduce_then_scan", "mapreduce_dot": "MR0_unfused",
+         "mapoverlap2d_9x9": "O2a_direct", "reduce_sum": "R1_two_pass"}
+DOMINANT = "scan_excl_i32_i64"
+KERNEL_SRC = {"scan_excl_i32_i64": "k_scan.hip"}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def host_info():
+    model = platform.processor() or "?"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return model, len(os.sched_getaffinity(0))
+
+
+class Workload:
+    def __init__(self, skel):
+        import synth_inputs as si
+        self.skel = skel
+        log("generating inputs")
+        self.x_h = si.normal_f32(N_VEC, 1, 0)
+        self.y_h = si.normal_f32(N_VEC, 1, 1)
+        self.z_h = si.uniform_f32(N_VEC, -1.0, 1.0, 0, 3)
+        self.s_h = si.int_uniform_i32(N_SCAN, 1000, 1, 2)
+        self.img_h = si.uniform_f32(IMG * IMG, 0.0, 1.0, 1, 0).reshape(IMG, IMG)
+        self.w5 = si.binomial5_weights()
+        self.g9 = si.gaussian_weights(4, 2.0)
+        C = skel.Container
+        self.x, self.y = C.from_numpy(self.x_h), C.from_numpy(self.y_h)
+        self.z = C.from_numpy(self.z_h)
+        self.o1 = C.empty(skel.F32, N_VEC)
+        self.s = C.from_numpy(self.s_h)
+        self.so = C.empty(skel.I64, N_SCAN)
+        self.img = C.from_numpy(self.img_h)
+        self.imo = C.empty(skel.F32, IMG, IMG)
+        self.r_dot = C.empty(skel.F32, 1)
+        self.r_sum = C.empty(skel.F32, 1)
+
+    def calls(self, variants=None):
+        """(name, thunk) for one step; variants maps name -> forced variant."""
+        sk = self.skel
+        v = lambda name: -1 if variants is None else variants[name]
+        return [
+            ("map_saxpy", lambda: sk.skel_map(sk.MAP_AXPY, [2.5], [self.x, self.y], self.y,
+                                              variant=v("map_saxpy"))),
+            ("mapoverlap1d_5pt", lambda: sk.skel_mapoverlap1d(
+                self.z, self.o1, self.w5, 2, sk.EDGE_CLAMP, variant=v("mapoverlap1d_5pt"))),
+            ("scan_excl_i32_i64", lambda: sk.skel_scan(self.s, self.so, sk.EXCLUSIVE, sk.SUM,
+                                                       variant=v("scan_excl_i32_i64"))),
+            ("mapreduce_dot", lambda: sk.skel_mapreduce(sk.MAP_MUL, None, [self.x, self.y],
+                                                        sk.SUM, self.r_dot,
+                                                        variant=v("mapreduce_dot"))),
+            ("mapoverlap2d_9x9", lambda: sk.skel_mapoverlap2d(
+                self.img, self.imo, wy=self.g9, wx=self.g9, edge=sk.EDGE_CLAMP,
+                variant=v("mapoverlap2d_9x9"))),
+            ("reduce_sum", lambda: sk.skel_reduce(sk.SUM, self.o1, self.r_sum,
+                                                  variant=v("reduce_sum"))),
+        ]
+
+    def selected(self):
+        sk = self.skel
+        return {
+            "map_saxpy": sk.skel_select_variant(sk.SK_MAP, sk.F32, N_VEC),
+            "mapoverlap1d_5pt": sk.skel_select_variant(sk.SK_MAPOVERLAP1D, sk.F32, N_VEC),
+            "scan_excl_i32_i64": sk.skel_select_variant(sk.SK_SCAN, sk.I32, N_SCAN),
+            "mapreduce_dot": sk.skel_select_variant(sk.SK_MAPREDUCE, sk.F32, N_VEC),
+            "mapoverlap2d_9x9": sk.skel_select_variant(sk.SK_MAPOVERLAP2D, sk.F32, IMG * IMG,
+                                                       IMG, IMG, 1),
+            "reduce_sum": sk.skel_select_variant(sk.SK_REDUCE, sk.F32, N_VEC),
+        }
+
+
+def run_steps(torch, calls, steps, with_events):
+    """Run `steps` steps; return (elapsed seconds, {name: [kernel ms, ...]})."""
+    stream = torch.cuda.current_stream()
+    ev = {name: [] for name, _ in calls}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for name, fn in calls:
+            if with_events:
+                a = torch.cuda.Event(enable_timing=True)
+                b = torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+                fn()
+                b.record(stream)
+                ev[name].append((a, b))
+            else:
+                fn()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ms = {k: [a.elapsed_time(b) for a, b in v] for k, v in ev.items()}
+    return el, ms
+
+
+def copy_ceiling(skel, torch, reps=10):
+    """Plain device copy (Map identity, 16-byte vectors) of 2^27 floats."""
+    n = 1 << 27
+    a = skel.Container.from_numpy(np.ones(n, np.float32))
+    b = skel.Container.empty(skel.F32, n)
+    v = skel.variant_index(skel.SK_MAP, "M2_vec4x4_nt")
+    skel.skel_map(skel.MAP_IDENTITY, None, [a], b, variant=v)
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    times = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        skel.skel_map(skel.MAP_IDENTITY, None, [a], b, variant=v)
+        e1.record(st)
+        times.append((e0, e1))
+    torch.cuda.synchronize()
+    ms = float(np.median([x.elapsed_time(y) for x, y in times]))
+    a.destroy()
+    b.destroy()
+    return 8 * n / (ms * 1e-3) / 1e9, ms
+
+
+def traffic_from_profile(name, per_launch_bytes):
+    """HBM bytes per launch measured by rocprofv3 counters, from the committed
+    summary in profiles/, or None when the kernel source changed since."""
+    src = KERNEL_SRC.get(name)
+    path = os.path.join(ROOT, "profiles", f"{name}_traffic.txt")
+    if not src or not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m_hash = re.search(r"source_sha256:\s*([0-9a-f]{64})", text)
+    m_bytes = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not m_hash or not m_bytes:
+        return None
+    cur = hashlib.sha256(open(os.path.join(ROOT, "paper_1405_2915_amd", "csrc", src),
+                              "rb").read()).hexdigest()
+    if cur != m_hash.group(1):
+        return None
+    return float(m_bytes.group(1))
+
+
+def cpu_baseline(wl):
+    """The oracle (as it is, not tuned) over one full step on the host."""
+    import oracle
+    model, ncpu = host_info()
+    threads = min(ncpu, 64)
+    oracle.set_threads(threads)
+    t0 = time.perf_counter()
+    oracle.map_f32("axpy", [2.5], wl.x_h, wl.y_h)
+    o1, _ = oracle.mapoverlap1d(wl.z_h, wl.w5, 2)
+    oracle.scan(wl.s_h, "exclusive", "sum", np.int64)
+    oracle.mapreduce("mul", None, wl.x_h, wl.y_h)
+    oracle.mapoverlap2d(wl.img_h, 4, 4, wy=wl.g9, wx=wl.g9)
+    oracle.reduce("sum", o1.astype(np.float32))
+    el = time.perf_counter() - t0
+    total = sum(BYTES.values())
+    return {"value": round(total / el / 1e9, 3), "unit": "GB/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"one full step (all six skeletons, same sizes) in {el:.2f} s; "
+                      f"binary64/exact C oracle, OpenMP over independent outputs "
+                      f"(map, stencils), sequential reductions and scans; host {model}"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain-variant pass")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(how the skeletons would shard is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_1405_2915_amd as skel
+
+    skel.skel_init(0, "torch")
+    wl = Workload(skel)
+    calls = wl.calls()
+    log(f"warmup {args.warmup} (first call copies every operand to HBM once)")
+    run_steps(torch, calls, max(args.warmup, 1), with_events=False)
+    skel.skel_sync()
+    xfer_before = {k: getattr(wl, k).stats() for k in ("x", "y", "z", "s", "img")}
+    log(f"timing {args.steps} steps")
+    el, ms = run_steps(torch, calls, args.steps, with_events=True)
+    skel.skel_sync()
+    for k, before in xfer_before.items():
+        after = getattr(wl, k).stats()
+        assert after["h2d"] == before["h2d"], "no host-device copy inside the timed region"
+    ms_step = el / args.steps * 1e3
+    total_bytes = sum(BYTES.values())
+    value = total_bytes / (el / args.steps) / 1e9
+
+    sel = wl.selected()
+    per = {}
+    for name in ORDER:
+        avg = float(np.mean(ms[name]))
+        gbs = BYTES[name] / (avg * 1e-3) / 1e9
+        sk_id = {"map_saxpy": skel.SK_MAP, "mapoverlap1d_5pt": skel.SK_MAPOVERLAP1D,
+                 "scan_excl_i32_i64": skel.SK_SCAN, "mapreduce_dot": skel.SK_MAPREDUCE,
+                 "mapoverlap2d_9x9": skel.SK_MAPOVERLAP2D, "reduce_sum": skel.SK_REDUCE}[name]
+        per[name] = {"variant": skel.skel_variant_name(sk_id, sel[name]),
+                     "bytes": BYTES[name], "us": round(avg * 1e3, 2),
+                     "GBps": round(gbs, 1), "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)}
+
+    speedup = None
+    if not args.no_plain:
+        log("timing the fixed plain variants")
+        ids = {"map_saxpy": skel.SK_MAP, "mapoverlap1d_5pt": skel.SK_MAPOVERLAP1D,
+               "scan_excl_i32_i64": skel.SK_SCAN, "mapreduce_dot": skel.SK_MAPREDUCE,
+               "mapoverlap2d_9x9": skel.SK_MAPOVERLAP2D, "reduce_sum": skel.SK_REDUCE}
+        pv = {k: skel.variant_index(ids[k], PLAIN[k]) for k in ORDER}
+        pcalls = wl.calls(pv)
+        run_steps(torch, pcalls, 1, with_events=False)
+        pel, pms = run_steps(torch, pcalls, max(3, args.steps // 4), with_events=True)
+        skel.skel_sync()
+        speedup = {"step": round((pel / max(3, args.steps // 4)) / (el / args.steps), 3)}
+        for name in ORDER:
+            p = float(np.mean(pms[name]))
+            speedup[name] = round(p / (per[name]["us"] * 1e-3), 3)
+            per[name]["plain_variant"] = PLAIN[name]
+            per[name]["plain_us"] = round(p * 1e3, 2)
+
+    ceil_gbs, ceil_ms = copy_ceiling(skel, torch)
+    dom = per[DOMINANT]
+    achieved = BYTES[DOMINANT] / (dom["us"] * 1e-6) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic_from_profile(DOMINANT, BYTES[DOMINANT]),
+                "kernel": "scan_lookback<int32 -> int64, exclusive sum>",
+                "algorithmic_bytes_per_launch": BYTES[DOMINANT]}
+    out = {
+        "metric": "skeleton GB/s & % of HBM peak; autotuned/fused vs fixed-variant speedup",
+        "value": round(value, 1), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32/i64", "data": "synthetic",
+        "config": {"workload": "plain skeleton step on the large configuration: 9x9 "
+                               "separable Gaussian MapOverlap2D 4096x4096 f32, dot "
+                               "MapReduce 2^26 f32, exclusive Scan 2^27 i32->i64, plus "
+                               "saxpy Map, 5-pt MapOverlap1D and sum Reduce on 2^26 f32",
+                   "bytes_per_step": total_bytes, "parallelism": "single GPU"},
+        "frac_hbm_step": round(value / HBM_PEAK_GBS, 4),
+        "roofline": roofline,
+        "copy_ceiling_GBps": round(ceil_gbs, 1),
+        "per_skeleton": per,
+        "speedup_vs_plain": speedup,
+    }
+    if not args.no_cpu:
+        log("timing the CPU oracle on one step")
+        out["cpu_baseline"] = cpu_baseline(wl)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
