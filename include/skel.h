@@ -248,10 +248,12 @@ const char *skel_variant_name(int skeleton, int variant); /* NULL if out of rang
 
 /* The execution plan's choice (Section III) for a call context, without
  * running anything: returns the variant index, or -1 if none is selectable.
- * n is the element count (rows*cols for 2D); `separable` is 1 when the 2D
- * weights are given as factors; dtype is the input element type. */
+ * n is the element count (rows*cols for 2D); dtype is the input element type;
+ * `aux` is the radius for SKEL_SK_MAPOVERLAP1D, 1 when the 2D weights are
+ * given as separable factors for SKEL_SK_MAPOVERLAP2D, and ignored
+ * otherwise. */
 int skel_select_variant(int skeleton, skel_dtype dtype, int64_t n,
-                        int64_t rows, int64_t cols, int separable);
+                        int64_t rows, int64_t cols, int aux);
 
 /* Load a size-keyed dispatch table produced by off-line tuning (Section II:
  * a precomputed dispatch structure for fast run-time lookup; Section III:

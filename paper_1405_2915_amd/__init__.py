@@ -416,9 +416,10 @@ def skel_variant_name(skeleton: int, variant: int):
 
 
 def skel_select_variant(skeleton: int, dtype: int, n: int, rows: int = 1, cols: int | None = None,
-                        separable: int = 0) -> int:
+                        aux: int = 0) -> int:
+    """aux: the radius for MapOverlap1D, 1 for separable MapOverlap2D weights."""
     return load_library().skel_select_variant(skeleton, dtype, n, rows,
-                                              n if cols is None else cols, separable)
+                                              n if cols is None else cols, aux)
 
 
 def skel_load_plan(path: str) -> None:

@@ -25,20 +25,34 @@ skel_container::StreamEvent* event_for(skel_container* c, void* stream,
     void* ev = nullptr;
     *st = rt().backend->event_create(&ev);
     if (*st != SKEL_OK) return nullptr;
-    c->events.push_back({stream, ev, false, 0, {}});
+    c->events.push_back({stream, ev, false, false, 0, {}});
     return &c->events.back();
 }
 
-// Make `stream` wait for the last recorded device access of every other
-// stream, skipping events whose current generation it already waited on.
+// Record the stream's event now if work was enqueued since its last record.
+skel_status flush_pending(skel_container::StreamEvent& e) {
+    if (!e.pending) return SKEL_OK;
+    skel_status st = rt().backend->event_record(e.event, e.stream);
+    if (st != SKEL_OK) return st;
+    e.recorded = true;
+    e.pending = false;
+    e.gen += 1;
+    return SKEL_OK;
+}
+
+// Make `stream` wait for the last device access of every other stream,
+// skipping events whose current generation it already waited on.
 skel_status order_after_other_streams(skel_container* c, void* stream) {
     skel_status st = SKEL_OK;
     if (!event_for(c, stream, &st)) return st;  // entry for `stream` exists now
     size_t me = 0;
     while (c->events[me].stream != stream) ++me;
     for (size_t k = 0; k < c->events.size(); ++k) {
+        if (k == me) continue;
+        st = flush_pending(c->events[k]);
+        if (st != SKEL_OK) return st;
         const auto& e = c->events[k];
-        if (k == me || !e.recorded) continue;
+        if (!e.recorded) continue;
         auto& seen = c->events[me].seen;
         auto it = seen.begin();
         while (it != seen.end() && it->first != e.stream) ++it;
@@ -51,11 +65,13 @@ skel_status order_after_other_streams(skel_container* c, void* stream) {
     return SKEL_OK;
 }
 
-// Block until every recorded device access of the container has finished.
+// Block until every device access of the container has finished.
 skel_status wait_device_idle(skel_container* c) {
     for (auto& e : c->events) {
+        skel_status st = flush_pending(e);
+        if (st != SKEL_OK) return st;
         if (!e.recorded) continue;
-        skel_status st = rt().backend->event_sync(e.event);
+        st = rt().backend->event_sync(e.event);
         if (st != SKEL_OK) return st;
     }
     return SKEL_OK;
@@ -130,6 +146,7 @@ skel_status acquire(skel_container* c, skel_place place, skel_access access,
                 if (st == SKEL_OK) st = be->event_sync(e->event);
                 if (st != SKEL_OK) return st;
                 e->recorded = true;
+                e->pending = false;
                 e->gen += 1;
                 c->stats.d2h += 1;
                 c->stats.d2h_bytes += c->bytes;
@@ -156,10 +173,7 @@ skel_status release(skel_container* c, skel_place place, void* stream) {
             skel_status st;
             skel_container::StreamEvent* e = event_for(c, stream, &st);
             if (!e) return st;
-            st = rt().backend->event_record(e->event, stream);
-            if (st != SKEL_OK) return st;
-            e->recorded = true;
-            e->gen += 1;
+            e->pending = true;  // recorded lazily, when someone must order after it
             c->last_stream = stream;
         }
         if (c->writer == SKEL_DEVICE) c->writer = -1;

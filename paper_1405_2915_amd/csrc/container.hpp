@@ -20,14 +20,18 @@ struct skel_container {
     bool host_valid = false;
     bool dev_valid = false;
 
-    // One event per stream that has accessed the device copy, recorded at each
-    // device release on that stream.  A device access on another stream waits
-    // on all of them; a host access waits for all of them.
+    // One event per stream that has accessed the device copy.  A device release
+    // only marks the stream `pending`; the event is recorded when someone must
+    // order after that work -- a device access on another stream, a host
+    // access, or destroy.  Recording later on the same stream is conservative
+    // (it also covers later work on that stream) and keeps event markers off
+    // the single-stream fast path.
     struct StreamEvent {
         void* stream;
         void* event;
-        bool recorded;
-        uint64_t gen;  // number of records so far
+        bool recorded;  // the event holds a record
+        bool pending;   // work enqueued on the stream since the last record
+        uint64_t gen;   // number of records so far
         // (other stream, generation of its event this stream already waited on)
         std::vector<std::pair<void*, uint64_t>> seen;
     };

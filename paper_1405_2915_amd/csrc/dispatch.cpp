@@ -16,9 +16,9 @@ const char* const kReduce[] = {"R0_single_wg", "R1_two_pass", "R2_ticket",
                                "R3_atomic"};
 const char* const kMapReduce[] = {"MR0_unfused", "MR1_fused_two_pass",
                                   "MR2_fused_ticket", "MR3_fused_single_wg"};
-const char* const kOverlap1D[] = {"O1a_direct", "O1b_lds_tile"};
-const char* const kOverlap2D[] = {"O2a_direct", "O2b_lds_tile",
-                                  "O2c_lds_separable"};
+const char* const kOverlap1D[] = {"O1a_direct", "O1b_lds_tile", "O1c_shuffle"};
+const char* const kOverlap2D[] = {"O2a_direct", "O2b_lds_tile", "O2c_lds_separable",
+                                  "O2d_separable_l1"};
 const char* const kScan[] = {"S0_single_wg", "S1_reduce_then_scan",
                              "S2_decoupled_lookback"};
 
@@ -56,8 +56,8 @@ int static_rule(const CallContext& c) {
     case SKEL_SK_REDUCE: return c.n <= (INT64_C(1) << 15) ? R0_SINGLE_WG : R2_TICKET;
     case SKEL_SK_MAPREDUCE:
         return c.n <= (INT64_C(1) << 15) ? MR3_FUSED_SINGLE_WG : MR2_FUSED_TICKET;
-    case SKEL_SK_MAPOVERLAP1D: return O1B_LDS_TILE;
-    case SKEL_SK_MAPOVERLAP2D: return c.separable ? O2C_LDS_SEPARABLE : O2B_LDS_TILE;
+    case SKEL_SK_MAPOVERLAP1D: return c.radius <= 4 ? O1C_SHUFFLE : O1B_LDS_TILE;
+    case SKEL_SK_MAPOVERLAP2D: return c.separable ? O2D_SEPARABLE_L1 : O2B_LDS_TILE;
     case SKEL_SK_SCAN: return c.n <= (INT64_C(1) << 15) ? S0_SINGLE_WG : S2_LOOKBACK;
     }
     return -1;
@@ -139,9 +139,15 @@ bool selectable(int v, const CallContext& c, const char** why) {
             return false;
         }
         return true;
+    case SKEL_SK_MAPOVERLAP1D:
+        if (v == O1C_SHUFFLE && c.radius > 4) {
+            *why = "cross-lane variant reaches at most 4 neighbours per side";
+            return false;
+        }
+        return true;
     case SKEL_SK_MAPOVERLAP2D:
-        if (v == O2C_LDS_SEPARABLE && !c.separable) {
-            *why = "separable variant needs the weights as factors wy, wx";
+        if ((v == O2C_LDS_SEPARABLE || v == O2D_SEPARABLE_L1) && !c.separable) {
+            *why = "separable variants need the weights as factors wy, wx";
             return false;
         }
         return true;
@@ -255,7 +261,7 @@ const char* skel_variant_name(int skeleton, int variant) {
 }
 
 int skel_select_variant(int skeleton, skel_dtype dtype, int64_t n, int64_t rows,
-                        int64_t cols, int separable) {
+                        int64_t cols, int aux) {
     if (skeleton < 0 || skeleton >= SKEL_SK_COUNT || !skel::dtype_valid(dtype)) return -1;
     skel::CallContext c;
     c.skeleton = skeleton;
@@ -264,7 +270,8 @@ int skel_select_variant(int skeleton, skel_dtype dtype, int64_t n, int64_t rows,
     c.n = n;
     c.rows = rows;
     c.cols = cols;
-    c.separable = separable;
+    if (skeleton == SKEL_SK_MAPOVERLAP1D) c.radius = aux;
+    else c.separable = aux;
     skel_status st;
     return skel::choose_variant(SKEL_VARIANT_AUTO, c, &st);
 }

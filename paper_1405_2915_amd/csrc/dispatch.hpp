@@ -18,9 +18,9 @@ enum ReduceVariant { R0_SINGLE_WG = 0, R1_TWO_PASS = 1, R2_TICKET = 2, R3_ATOMIC
                      REDUCE_NVAR };
 enum MapReduceVariant { MR0_UNFUSED = 0, MR1_FUSED_TWO_PASS = 1, MR2_FUSED_TICKET = 2,
                         MR3_FUSED_SINGLE_WG = 3, MAPREDUCE_NVAR };
-enum Overlap1DVariant { O1A_DIRECT = 0, O1B_LDS_TILE = 1, OVERLAP1D_NVAR };
+enum Overlap1DVariant { O1A_DIRECT = 0, O1B_LDS_TILE = 1, O1C_SHUFFLE = 2, OVERLAP1D_NVAR };
 enum Overlap2DVariant { O2A_DIRECT = 0, O2B_LDS_TILE = 1, O2C_LDS_SEPARABLE = 2,
-                        OVERLAP2D_NVAR };
+                        O2D_SEPARABLE_L1 = 3, OVERLAP2D_NVAR };
 enum ScanVariant { S0_SINGLE_WG = 0, S1_REDUCE_THEN_SCAN = 1, S2_LOOKBACK = 2,
                    SCAN_NVAR };
 
@@ -32,6 +32,7 @@ struct CallContext {
     int op = 0;         // reduce op (Reduce/MapReduce/Scan) or map op (Map)
     int map_op = 0;     // MapReduce's element function
     int separable = 0;  // MapOverlap2D: weights given as factors
+    int radius = 0;     // MapOverlap1D radius
 };
 
 int variant_count(int skeleton);

@@ -10,6 +10,8 @@
 //   O1a  1D direct: one output per lane, taps read through the caches
 //   O1b  1D LDS tile: a workgroup stages 1024 + 2r inputs once, each lane
 //        computes four outputs from registers
+//   O1c  1D cross-lane: r <= 4 neighbours come from adjacent lanes by
+//        shuffles; no LDS, no barrier
 //   O2a  2D direct: one output per lane, (2ry+1)(2rx+1) taps from global
 //   O2b  2D LDS tile: a 64x64 output tile plus halo staged in LDS with 16-byte
 //        loads; each lane computes a 4x4 output block, reusing every loaded
@@ -17,6 +19,8 @@
 //   O2c  2D separable (W = wy (x) wx): the staged tile is filtered along rows
 //        into a second LDS buffer, then along columns; 2(2r+1) instead of
 //        (2r+1)^2 multiply-adds per output
+//   O2d  2D separable with the row pass read from global memory through L1
+//        and only its result staged in LDS (64x32 tiles, full occupancy)
 // 2D tiles are visited in an XCD-aware order: consecutive workgroups go to
 // different XCDs round-robin, so tile ids are remapped to give each XCD a
 // contiguous band of tiles whose shared halo rows stay in that XCD's L2.
@@ -125,6 +129,58 @@ __global__ __launch_bounds__(kBlock) void ov1_lds(const float* x, float* out, in
 #pragma unroll
         for (int c = 0; c < 4; ++c)
             if (i + c < n) out[i + c] = acc[c];
+    }
+}
+
+// O1c: no LDS and no barrier.  Each wavefront owns 256 consecutive outputs
+// (one 16-byte vector per lane); the r <= 4 neighbours on either side of a
+// lane's vector come from the adjacent lanes by cross-lane shuffles, and the
+// two lanes at the wavefront's ends read one extra vector each (from cache).
+// Wavefront rows that touch the array ends take the scalar path.
+template <int RT>
+__global__ __launch_bounds__(kBlock) void ov1_shfl(const float* x, float* out, int64_t n, W1 w,
+                                                   int r_, int edge, float pad) {
+    constexpr int MR = RT >= 0 ? RT : 4;
+    const int r = RT >= 0 ? RT : r_;
+    const int l = dev::lane();
+    const int64_t wb = ((int64_t)blockIdx.x * kBlock + threadIdx.x - l) * 4;  // row start
+    if (wb >= n) return;
+    const bool interior = wb - 4 >= 0 && wb + 4 * dev::kWave + 4 <= n;
+    if (interior) {
+        const f32x4* xv = reinterpret_cast<const f32x4*>(x + wb);
+        const f32x4 c = xv[l];
+        f32x4 lt, rt;
+        lt.x = __shfl_up(c.x, 1);
+        lt.y = __shfl_up(c.y, 1);
+        lt.z = __shfl_up(c.z, 1);
+        lt.w = __shfl_up(c.w, 1);
+        rt.x = __shfl_down(c.x, 1);
+        rt.y = __shfl_down(c.y, 1);
+        rt.z = __shfl_down(c.z, 1);
+        rt.w = __shfl_down(c.w, 1);
+        if (l == 0) lt = xv[-1];
+        if (l == dev::kWave - 1) rt = xv[dev::kWave];
+        const float v[12] = {lt.x, lt.y, lt.z, lt.w, c.x, c.y, c.z, c.w,
+                             rt.x, rt.y, rt.z, rt.w};
+        float acc[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int k = 0; k <= 2 * MR; ++k) {
+            if (k > 2 * r) break;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[q] = __builtin_fmaf(w.w[k], v[4 + q + k - r], acc[q]);
+        }
+        __builtin_nontemporal_store(f32x4{acc[0], acc[1], acc[2], acc[3]},
+                                    reinterpret_cast<f32x4*>(out + wb) + l);
+    } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t i = wb + 4 * l + q;
+            if (i >= n) break;
+            float acc = 0.0f;
+            for (int k = 0; k <= 2 * r; ++k)
+                acc = __builtin_fmaf(w.w[k], fetch1(x, n, i + k - r, edge, pad), acc);
+            out[i] = acc;
+        }
     }
 }
 
@@ -321,6 +377,87 @@ __global__ __launch_bounds__(kBlock) void ov2_sep(const float* x, float* out, in
     for (int o = 0; o < 4; ++o) store4(out, rows, cols, y0 + 4 * rg + o, x0 + 4 * cg, acc[o]);
 }
 
+// O2d: separable, with the row pass read straight from global memory through
+// the L1 cache (each lane loads its 4 + 2*HX aligned inputs as 16-byte
+// vectors; neighbouring lanes' overlaps hit L1), so LDS holds only the
+// row-pass result of a 64 x 32 tile.  The small LDS footprint allows full
+// occupancy, and the 32-row tile keeps 4x more workgroups in flight than the
+// 64 x 64 tile.
+constexpr int kTY2 = 32;
+
+template <int RY, int RX>
+__global__ __launch_bounds__(kBlock) void ov2_sep_l1(const float* x, float* out, int64_t rows,
+                                                     int64_t cols, W2 w, int ry_, int rx_,
+                                                     int edge, float pad, int64_t nbx,
+                                                     int64_t nb) {
+    using RD = Rad<RY, RX>;
+    constexpr int MY = RD::MY, MX = RD::MX, HX = RD::HX;
+    constexpr int HW = kTX + 4;              // row-pass buffer stride (padded)
+    constexpr int LH = kTY2 + 2 * MY;        // row-pass rows
+    constexpr int NV = (4 + 2 * HX) / 4;     // 16-byte vectors per lane and row
+    constexpr int RO = kTY2 / 16;            // output rows per lane
+    const int ry = RD::dyn ? ry_ : RY, rx = RD::dyn ? rx_ : RX;
+    __shared__ __attribute__((aligned(16))) float th[LH * HW];
+    int64_t bx, by;
+    tile_coords(nbx, nb, bx, by);
+    const int64_t y0 = by * kTY2, x0 = bx * kTX;
+    const bool interior = y0 - ry >= 0 && y0 + kTY2 + ry <= rows && x0 - HX >= 0 &&
+                          x0 + kTX + HX <= cols && (cols & 3) == 0;
+    const int cg = threadIdx.x % 16, rg = threadIdx.x / 16;
+    const int nrows = kTY2 + 2 * ry;
+    for (int y = rg; y < nrows; y += 16) {
+        const int64_t gy = y0 - ry + y;
+        float seg[4 + 2 * HX];
+        if (interior) {
+            const float* src = x + gy * cols + (x0 - HX + 4 * cg);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                const f32x4 t = *reinterpret_cast<const f32x4*>(src + 4 * v);
+                seg[4 * v] = t.x;
+                seg[4 * v + 1] = t.y;
+                seg[4 * v + 2] = t.z;
+                seg[4 * v + 3] = t.w;
+            }
+        } else {
+#pragma unroll
+            for (int t = 0; t < 4 + 2 * HX; ++t)
+                seg[t] = fetch2(x, rows, cols, gy, x0 - HX + 4 * cg + t, edge, pad);
+        }
+        float h[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int b = 0; b <= 2 * MX; ++b) {
+            if (b > 2 * rx) break;
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                h[c] = __builtin_fmaf(w.wx[b], seg[c + b + HX - rx], h[c]);
+        }
+        *reinterpret_cast<f32x4*>(th + y * HW + 4 * cg) = f32x4{h[0], h[1], h[2], h[3]};
+    }
+    __syncthreads();
+    float acc[RO][4];
+#pragma unroll
+    for (int o = 0; o < RO; ++o)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[o][c] = 0.0f;
+#pragma unroll
+    for (int k = 0; k < RO + 2 * MY; ++k) {
+        if (k >= RO + 2 * ry) break;
+        const f32x4 v = *reinterpret_cast<const f32x4*>(th + (RO * rg + k) * HW + 4 * cg);
+#pragma unroll
+        for (int o = 0; o < RO; ++o) {
+            const int a = k - o;
+            if (a < 0 || a > 2 * ry) continue;
+            const float wa = w.wy[a];
+            acc[o][0] = __builtin_fmaf(wa, v.x, acc[o][0]);
+            acc[o][1] = __builtin_fmaf(wa, v.y, acc[o][1]);
+            acc[o][2] = __builtin_fmaf(wa, v.z, acc[o][2]);
+            acc[o][3] = __builtin_fmaf(wa, v.w, acc[o][3]);
+        }
+    }
+#pragma unroll
+    for (int o = 0; o < RO; ++o) store4(out, rows, cols, y0 + RO * rg + o, x0 + 4 * cg, acc[o]);
+}
+
 // --------------------------------------------------------------- launchers
 int64_t div_up(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
@@ -330,6 +467,11 @@ skel_status run1d(int v, const float* x, float* out, int64_t n, const W1& w, int
     if (v == O1A_DIRECT) {
         ov1_direct<RT><<<(unsigned)div_up(n, kBlock), kBlock, 0, st>>>(x, out, n, w, r, edge, pad);
         return launch_check("overlap1d_direct");
+    }
+    if (v == O1C_SHUFFLE) {  // selectable for r <= 4 only
+        ov1_shfl<RT><<<(unsigned)div_up(n, 4 * kBlock), kBlock, 0, st>>>(x, out, n, w, r, edge,
+                                                                           pad);
+        return launch_check("overlap1d_shuffle");
     }
     ov1_lds<RT><<<(unsigned)div_up(n, kT1), kBlock, 0, st>>>(x, out, n, w, r, edge, pad);
     return launch_check("overlap1d_lds");
@@ -343,6 +485,12 @@ skel_status run2d(int v, const float* x, float* out, int64_t rows, int64_t cols,
         ov2_direct<RY, RX><<<(unsigned)(nbx * nby), kBlock, 0, st>>>(x, out, rows, cols, w, ry,
                                                                       rx, edge, pad, nbx);
         return launch_check("overlap2d_direct");
+    }
+    if (v == O2D_SEPARABLE_L1) {
+        const int64_t nbx = div_up(cols, kTX), nb = nbx * div_up(rows, kTY2);
+        ov2_sep_l1<RY, RX><<<(unsigned)nb, kBlock, 0, st>>>(x, out, rows, cols, w, ry, rx, edge,
+                                                            pad, nbx, nb);
+        return launch_check("overlap2d_separable_l1");
     }
     const int64_t nbx = div_up(cols, kTX), nby = div_up(rows, kTY), nb = nbx * nby;
     if (v == O2B_LDS_TILE) {

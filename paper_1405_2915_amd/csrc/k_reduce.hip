@@ -50,7 +50,7 @@ struct PlainSrc {
         in_t a[E];
     };
     const in_t* x;
-    __device__ __forceinline__ void load(int64_t vi, Vec& v) const { load16(x + vi * E, v.a); }
+    __device__ __forceinline__ void load(int64_t vi, Vec& v) const { load16_nt(x + vi * E, v.a); }
     __device__ __forceinline__ void accum(const Vec& v, acc_t& acc) const {
 #pragma unroll
         for (int e = 0; e < E; ++e) acc = P::C::op(acc, widen<acc_t>(v.a[e]));
@@ -84,8 +84,8 @@ struct MapSrc {
     const in_t* y;
     float p0, p1;
     __device__ __forceinline__ void load(int64_t vi, Vec& v) const {
-        load16(x + vi * E, v.a);
-        if constexpr (two_inputs<MOP>()) load16(y + vi * E, v.b);
+        load16_nt(x + vi * E, v.a);
+        if constexpr (two_inputs<MOP>()) load16_nt(y + vi * E, v.b);
     }
     __device__ __forceinline__ void accum(const Vec& v, float& acc) const {
 #pragma unroll
@@ -102,53 +102,52 @@ struct MapSrc {
     }
 };
 
-// One lane's share: 16-byte vectors gtid, gtid + gstride, ... with kUnroll
-// loads in flight, then the n % E tail elements (one per low lane).
-template <class P, class Src>
-__device__ __forceinline__ typename P::acc_t thread_acc(const Src& s, int64_t n, int64_t gtid,
-                                                        int64_t gstride) {
+// One lane's share of workgroup `blk` of `nblk`: the workgroup walks chunks of
+// NT * kUnroll consecutive 16-byte vectors (chunk blk, blk + nblk, ...), every
+// lane with kUnroll loads in flight; then the vectors after the last whole
+// chunk, then the n % E tail elements (one per low lane of workgroup 0).
+// Consecutive workgroups read consecutive chunks, so the whole grid sweeps one
+// narrow window of memory.
+template <class P, int NT, class Src>
+__device__ __forceinline__ typename P::acc_t thread_acc(const Src& s, int64_t n, int64_t blk,
+                                                        int64_t nblk) {
     using acc_t = typename P::acc_t;
     constexpr int E = P::E;
+    constexpr int64_t CH = (int64_t)NT * kUnroll;
     acc_t a[kUnroll];
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) a[u] = P::C::id();
     const int64_t nv = n / E;
-    int64_t i = gtid;
-    for (; i + (kUnroll - 1) * gstride < nv; i += kUnroll * gstride) {
+    const int64_t nch = nv / CH;
+    for (int64_t c = blk; c < nch; c += nblk) {
+        const int64_t b = c * CH + threadIdx.x;
         typename Src::Vec v[kUnroll];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) s.load(i + u * gstride, v[u]);
+        for (int u = 0; u < kUnroll; ++u) s.load(b + u * NT, v[u]);
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) s.accum(v[u], a[u]);
     }
-    for (; i < nv; i += gstride) {
+    for (int64_t i = nch * CH + blk * NT + threadIdx.x; i < nv; i += nblk * NT) {
         typename Src::Vec v;
         s.load(i, v);
         s.accum(v, a[0]);
     }
-    const int64_t t = nv * E + gtid;
+    const int64_t t = nv * E + blk * NT + threadIdx.x;
     if (t < n) a[0] = P::C::op(a[0], s.at(t));
 #pragma unroll
     for (int u = 1; u < kUnroll; ++u) a[0] = P::C::op(a[0], a[u]);
     return a[0];
 }
 
-// device-scope coherent access to partials written by other XCDs
-template <class T>
-__device__ __forceinline__ void store_coherent(T* p, T v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-template <class T>
-__device__ __forceinline__ T load_coherent(const T* p) {
-    return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
+constexpr uint32_t kSpinLimit = 1u << 22;
+constexpr int kSlotReady = 1;  // state of a published partial
 
 // ------------------------------------------------------------------ kernels
 template <class P, class Src>
 __global__ __launch_bounds__(kSingleBlock) void k_single(Src s, int64_t n,
                                                          typename P::out_t* out) {
     __shared__ typename P::acc_t lds[kSingleBlock / kWave];
-    auto a = thread_acc<P>(s, n, threadIdx.x, kSingleBlock);
+    auto a = thread_acc<P, kSingleBlock>(s, n, 0, 1);
     a = block_reduce<typename P::C>(a, lds);
     if (threadIdx.x == 0) *out = (typename P::out_t)a;
 }
@@ -157,8 +156,7 @@ template <class P, class Src>
 __global__ __launch_bounds__(kBlock) void k_partials(Src s, int64_t n,
                                                      typename P::acc_t* partials) {
     __shared__ typename P::acc_t lds[kBlock / kWave];
-    auto a = thread_acc<P>(s, n, (int64_t)blockIdx.x * kBlock + threadIdx.x,
-                           (int64_t)gridDim.x * kBlock);
+    auto a = thread_acc<P, kBlock>(s, n, blockIdx.x, gridDim.x);
     a = block_reduce<typename P::C>(a, lds);
     if (threadIdx.x == 0) partials[blockIdx.x] = a;
 }
@@ -173,29 +171,58 @@ __global__ __launch_bounds__(kSingleBlock) void k_finish(const typename P::acc_t
     if (threadIdx.x == 0) *out = (typename P::out_t)a;
 }
 
+// Single pass: every workgroup publishes its partial as a self-validating
+// tagged word (two words per slot), then draws a ticket; the workgroup with
+// the last ticket waits until every slot carries this call's epoch and
+// combines them in slot order (deterministic).  No fence is needed because a
+// slot is valid exactly when its tag says so.
 template <class P, class Src>
-__global__ __launch_bounds__(kBlock) void k_ticket(Src s, int64_t n,
-                                                   typename P::acc_t* partials,
-                                                   unsigned long long* ticket,
+__global__ __launch_bounds__(kBlock) void k_ticket(Src s, int64_t n, u64* slots,
+                                                   uint32_t epoch, u64* ticket, u64* err,
                                                    typename P::out_t* out) {
     using acc_t = typename P::acc_t;
     __shared__ acc_t lds[kBlock / kWave];
     __shared__ int is_last;
-    acc_t a = thread_acc<P>(s, n, (int64_t)blockIdx.x * kBlock + threadIdx.x,
-                            (int64_t)gridDim.x * kBlock);
+    acc_t a = thread_acc<P, kBlock>(s, n, blockIdx.x, gridDim.x);
     a = block_reduce<typename P::C>(a, lds);
     if (threadIdx.x == 0) {
-        store_coherent(&partials[blockIdx.x], a);
-        __threadfence();
-        unsigned long long t = atomicAdd(ticket, 1ull);
+        tagged_put(slots + 2 * blockIdx.x, kSlotReady, epoch, a);
+        const u64 t = atomicAdd(ticket, 1ull);
         is_last = (t == gridDim.x - 1) ? 1 : 0;
     }
     __syncthreads();
     if (!is_last) return;
-    __threadfence();
+    // each lane reads its slots i = base + k * kBlock + lane with all loads in
+    // flight at once; a retry re-reads only the slots not yet valid
     acc_t b = P::C::id();
-    for (unsigned i = threadIdx.x; i < gridDim.x; i += kBlock)
-        b = P::C::op(b, load_coherent(&partials[i]));
+    for (unsigned base = 0; base < gridDim.x; base += 4 * kBlock) {
+        acc_t v[4];
+        bool ready[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            v[k] = P::C::id();
+            ready[k] = base + k * kBlock + threadIdx.x >= gridDim.x;
+        }
+        uint32_t spins = 0;
+        while (true) {
+            bool all = true;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (ready[k]) continue;
+                const unsigned i = base + k * kBlock + threadIdx.x;
+                ready[k] = tagged_get(slots + 2 * i, epoch, v[k]) == kSlotReady;
+                all = all && ready[k];
+            }
+            if (all) break;
+            if (++spins > kSpinLimit) {  // bounded: flag it and finish
+                atomicOr(err, 2ull);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) b = P::C::op(b, ready[k] ? v[k] : P::C::id());
+    }
     b = block_reduce<typename P::C>(b, lds);
     if (threadIdx.x == 0) {
         *out = (typename P::out_t)b;
@@ -214,8 +241,7 @@ __device__ __forceinline__ void atomic_combine(typename P::out_t* out, typename 
 template <class P, class Src>
 __global__ __launch_bounds__(kBlock) void k_atomic(Src s, int64_t n, typename P::out_t* out) {
     __shared__ typename P::acc_t lds[kBlock / kWave];
-    auto a = thread_acc<P>(s, n, (int64_t)blockIdx.x * kBlock + threadIdx.x,
-                           (int64_t)gridDim.x * kBlock);
+    auto a = thread_acc<P, kBlock>(s, n, blockIdx.x, gridDim.x);
     a = block_reduce<typename P::C>(a, lds);
     if (threadIdx.x == 0) atomic_combine<P>(out, a);
 }
@@ -241,13 +267,13 @@ __device__ __forceinline__ void atomic_combine(typename P::out_t* out, typename 
 // --------------------------------------------------------------- launchers
 int64_t div_up(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-// grid of the streaming passes: enough 16-byte vectors per lane for kUnroll
-// loads in flight, at most 8 workgroups per CU
+// grid of the single-pass variants: one chunk of kBlock * kUnroll vectors per
+// workgroup at least, at most 4 workgroups per CU (measured best on MI355X)
 template <class P>
 int grid_for(int64_t n, const DevInfo& d) {
     int64_t g = div_up(n / P::E, (int64_t)kBlock * kUnroll);
     if (g < 1) g = 1;
-    int64_t cap = (int64_t)d.cus * 8;
+    int64_t cap = (int64_t)d.cus * 4;
     return (int)(g < cap ? g : cap);
 }
 
@@ -278,8 +304,13 @@ skel_status run_variant(int v, const Src& s, int64_t n, typename P::out_t* out,
     }
     case R2_TICKET: {
         int g = grid_for<P>(n, *lc.dev);
+        void* slots = nullptr;
+        uint32_t epoch = 0;
+        skel_status e = ws_status(lc, (size_t)g * 16, &slots, &epoch);
+        if (e != SKEL_OK) return e;
         k_ticket<P, Src><<<(unsigned)g, kBlock, 0, st>>>(
-            s, n, static_cast<acc_t*>(partial_mem), lc.ws->sync + SYNC_TICKET, out);
+            s, n, static_cast<u64*>(slots), epoch, lc.ws->sync + SYNC_TICKET,
+            lc.ws->sync + SYNC_ERROR, out);
         return launch_check("reduce_ticket");
     }
     default: {  // R3_ATOMIC

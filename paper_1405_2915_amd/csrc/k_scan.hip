@@ -1,13 +1,17 @@
 // Scan skeleton kernels (Section III, scan): inclusive out[i] = x[0] op ...
 // op x[i]; exclusive out[0] = identity, out[i] = x[0] op ... op x[i-1].
 //
-// Tile layout (all variants): a workgroup of 4 wavefronts owns a tile of
-// 8192 elements; each wavefront owns a contiguous quarter and walks it in
-// rows of 64 lanes x one 16-byte vector, so every load and store instruction
-// of a wavefront covers one contiguous 1 KiB span (no LDS transposition).
-// Inside a row a lane scans its own vector serially, the wavefront scans the
-// 64 lane totals with lane shifts, and rows are chained by a running carry;
-// the four wavefront totals meet in LDS.
+// Tile layout (all variants): a workgroup of NW wavefronts (16, or 8 for 8-byte
+// inputs) owns a tile of NW * 2048 elements; each wavefront owns a contiguous
+// slice of 2048 and walks
+// it in rows of 64 lanes x one 16-byte vector, so every load and store
+// instruction of a wavefront covers one contiguous 1 KiB span (no LDS
+// transposition).  Only the raw inputs stay in registers across the
+// inter-tile wait: phase 1 needs just each lane's sum and one wavefront
+// reduction to produce the tile total, and the row scans (a lane scans its
+// own vector serially, the wavefront scans the 64 lane totals with lane
+// shifts, rows are chained by a running carry) run after the tile's prefix is
+// known.
 //
 // Variants:
 //   S0  one workgroup walks all tiles in order carrying the prefix (small n)
@@ -15,29 +19,29 @@
 //       every tile rescans with its offset (three launches, input read twice)
 //   S2  single pass with decoupled look-back: each tile publishes its total
 //       as soon as it has it, then wavefront 0 inspects the 64 preceding tile
-//       descriptors at once and combines back to the nearest finished prefix.
+//       descriptors at once and combines back to the nearest finished prefix;
+//       on a retry only the descriptors that were not yet valid are re-read.
 //       Tiles are numbered by an atomic counter in start order, so every tile
 //       waited on is already resident: the wait always ends.
 //
-// Tile descriptors are 64-bit words [state:2 | epoch:30 | value:32], two per
-// tile for 64-bit values.  Each word is written and read with single-copy-
-// atomic device-scope accesses and validates itself (state and epoch agree),
-// so no fences and no clearing pass are needed; the host gives every call a
-// fresh epoch.  The look-back wait is bounded: on expiry the kernel raises a
-// flag that skel_sync reports, and finishes (with wrong values) instead of
-// hanging.
+// Tile descriptors are self-validating tagged words (two per tile), written
+// and read with single-copy-atomic device-scope accesses, so no fences and no
+// clearing pass are needed; the host gives every call a fresh epoch.  The
+// look-back wait is bounded: on expiry the kernel raises a flag that
+// skel_sync reports, and finishes (with wrong values) instead of hanging.
 #include "kcommon.hpp"
 #include "dispatch.hpp"
 #include "launch.hpp"
+
+#ifndef SKEL_SCAN_WAVES
+#define SKEL_SCAN_WAVES 16
+#endif
 
 namespace skel {
 namespace {
 
 using namespace dev;
-typedef unsigned long long u64;
 
-constexpr int kBlock = 256;
-constexpr int kWaves = kBlock / kWave;
 constexpr uint32_t kSpinLimit = 1u << 22;
 
 template <int DIN, int DOUT, int OP>
@@ -46,82 +50,102 @@ struct SP {
     using out_t = typename Stored<DOUT>::type;
     using acc_t = typename Acc<DIN, DOUT, OP>::type;
     using C = Comb<acc_t, OP>;
-    static constexpr int E = 16 / sizeof(in_t);         // elements per lane per row
+    static constexpr int E = 16 / sizeof(in_t);           // elements per lane per row
     static constexpr int R = sizeof(in_t) == 4 ? 8 : 16;  // rows per wavefront
     static constexpr int kWaveElems = kWave * E * R;      // 2048
-    static constexpr int kTile = kWaves * kWaveElems;     // 8192
+    // wavefronts per workgroup: 16 for 4-byte inputs; 8 for 8-byte inputs,
+    // whose raw rows need twice the registers
+    static constexpr int NW = sizeof(in_t) == 4 ? SKEL_SCAN_WAVES : SKEL_SCAN_WAVES / 2;
+    static constexpr int kBlock = NW * kWave;
+    static constexpr int64_t kTile = (int64_t)NW * kWaveElems;
 };
 
 template <class P>
-struct TileState {
-    typename P::acc_t v[P::R][P::E];  // lane-local inclusive scan of each row vector
-    typename P::acc_t lex[P::R];      // exclusive prefix of the lane within its row
-    typename P::acc_t rtot[P::R];     // row totals
-};
+using Raw = typename P::in_t[P::R][P::E];
 
-// Load the wavefront's quarter of `tile` and scan it locally.  Returns the
-// wavefront total.  Elements at or beyond n read as the identity.
+template <class P>
+__device__ __forceinline__ int64_t lane_base(int64_t tile) {
+    return tile * P::kTile + (int64_t)(threadIdx.x / kWave) * P::kWaveElems +
+           (int64_t)lane() * P::E;
+}
+
+// Load the lane's share of `tile` (rows of 16-byte vectors).
 template <class P, bool FULL>
-__device__ __forceinline__ typename P::acc_t tile_load_scan(const typename P::in_t* in,
-                                                            int64_t n, int64_t tile,
-                                                            TileState<P>& ts) {
-    using acc_t = typename P::acc_t;
-    using C = typename P::C;
-    constexpr int E = P::E, R = P::R;
-    const int w = threadIdx.x / kWave, l = lane();
-    const int64_t wbase = tile * P::kTile + (int64_t)w * P::kWaveElems + (int64_t)l * E;
-    typename P::in_t raw[R][E];
+__device__ __forceinline__ void tile_load(const typename P::in_t* in, int64_t n, int64_t tile,
+                                          Raw<P>& raw) {
+    const int64_t b = lane_base<P>(tile);
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int64_t idx = wbase + (int64_t)r * kWave * E;
-        if (FULL || idx + E <= n) {
+    for (int r = 0; r < P::R; ++r) {
+        const int64_t idx = b + (int64_t)r * kWave * P::E;
+        if (FULL || idx + P::E <= n) {
             load16(in + idx, raw[r]);
         } else {
 #pragma unroll
-            for (int e = 0; e < E; ++e) raw[r][e] = idx + e < n ? in[idx + e] : 0;
+            for (int e = 0; e < P::E; ++e) raw[r][e] = idx + e < n ? in[idx + e] : 0;
         }
     }
-    acc_t wtot = C::id();
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int64_t idx = wbase + (int64_t)r * kWave * E;
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-            acc_t x = (FULL || idx + e < n) ? widen<acc_t>(raw[r][e]) : C::id();
-            ts.v[r][e] = e == 0 ? x : C::op(ts.v[r][e - 1], x);
-        }
-        acc_t incl = wave_inclusive_scan<C>(ts.v[r][E - 1]);
-        ts.rtot[r] = __shfl(incl, kWave - 1);
-        acc_t ex = __shfl_up(incl, 1);
-        ts.lex[r] = l == 0 ? C::id() : ex;
-        wtot = C::op(wtot, ts.rtot[r]);
-    }
-    return wtot;
 }
 
-// Write the scanned quarter given the exclusive prefix of the wavefront.
+// op over the lane's elements below n
 template <class P, bool FULL>
-__device__ __forceinline__ void tile_store(typename P::out_t* out, int64_t n, int64_t tile,
-                                           const TileState<P>& ts,
-                                           typename P::acc_t prefix, bool exclusive) {
+__device__ __forceinline__ typename P::acc_t lane_total(int64_t n, int64_t tile,
+                                                        const Raw<P>& raw) {
+    using C = typename P::C;
+    const int64_t b = lane_base<P>(tile);
+    typename P::acc_t t = C::id();
+#pragma unroll
+    for (int r = 0; r < P::R; ++r)
+#pragma unroll
+        for (int e = 0; e < P::E; ++e)
+            if (FULL || b + (int64_t)r * kWave * P::E + e < n)
+                t = C::op(t, widen<typename P::acc_t>(raw[r][e]));
+    return t;
+}
+
+// Compiler-only barrier on the raw inputs (emits no instruction): without it
+// the compiler keeps the widened values of phase 1 alive across the tile wait
+// to reuse them in the store phase, which doubles the live registers.
+template <class P>
+__device__ __forceinline__ void keep_raw_only(Raw<P>& raw) {
+#pragma unroll
+    for (int r = 0; r < P::R; ++r)
+#pragma unroll
+        for (int e = 0; e < P::E; ++e) asm volatile("" : "+v"(raw[r][e]));
+}
+
+// Scan the wavefront's slice given its exclusive prefix, and store it.
+template <class P, bool FULL>
+__device__ __forceinline__ void tile_scan_store(typename P::out_t* out, int64_t n, int64_t tile,
+                                                const Raw<P>& raw, typename P::acc_t prefix,
+                                                bool exclusive) {
     using acc_t = typename P::acc_t;
     using out_t = typename P::out_t;
     using C = typename P::C;
-    constexpr int E = P::E, R = P::R;
-    const int w = threadIdx.x / kWave, l = lane();
-    const int64_t wbase = tile * P::kTile + (int64_t)w * P::kWaveElems + (int64_t)l * E;
+    constexpr int E = P::E;
+    const int l = lane();
+    const int64_t b = lane_base<P>(tile);
     acc_t running = prefix;
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int64_t idx = wbase + (int64_t)r * kWave * E;
-        const acc_t base = C::op(running, ts.lex[r]);
+    for (int r = 0; r < P::R; ++r) {
+        const int64_t idx = b + (int64_t)r * kWave * E;
+        acc_t loc[E];  // lane-local inclusive scan of the row vector
+        acc_t t = C::id();
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const acc_t x = (FULL || idx + e < n) ? widen<acc_t>(raw[r][e]) : C::id();
+            t = C::op(t, x);
+            loc[e] = t;
+        }
+        const acc_t incl = wave_inclusive_scan<C>(t);
+        const acc_t tot = __shfl(incl, kWave - 1);
+        const acc_t ex = __shfl_up(incl, 1);
+        const acc_t base = C::op(running, l == 0 ? C::id() : ex);
         out_t o[E];
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-            acc_t val;
-            if (exclusive) val = e == 0 ? base : C::op(base, ts.v[r][e - 1]);
-            else val = C::op(base, ts.v[r][e]);
-            o[e] = (out_t)val;
+            const acc_t v = exclusive ? (e == 0 ? base : C::op(base, loc[e - 1]))
+                                      : C::op(base, loc[e]);
+            o[e] = (out_t)v;
         }
         if (FULL || idx + E <= n) {
             store_nt<out_t, E>(out + idx, o);
@@ -130,66 +154,47 @@ __device__ __forceinline__ void tile_store(typename P::out_t* out, int64_t n, in
             for (int e = 0; e < E; ++e)
                 if (idx + e < n) out[idx + e] = o[e];
         }
-        running = C::op(running, ts.rtot[r]);
+        running = C::op(running, tot);
+        // one row at a time: keeps the live registers to one row's temporaries
+        // (interleaving rows would spill at 1024 lanes per workgroup)
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+// Wavefront totals -> LDS; returns (exclusive prefix of this wavefront within
+// the tile, tile total) in every thread.  Contains one barrier.
+template <class P>
+__device__ __forceinline__ void tile_totals(typename P::acc_t lane_t, typename P::acc_t* s_wtot,
+                                            typename P::acc_t* wex, typename P::acc_t* agg) {
+    using C = typename P::C;
+    const int w = threadIdx.x / kWave;
+    const typename P::acc_t wt = wave_reduce<C>(lane_t);
+    if (lane() == 0) s_wtot[w] = wt;
+    __syncthreads();
+    *wex = C::id();
+    *agg = C::id();
+#pragma unroll
+    for (int k = 0; k < P::NW; ++k) {
+        const typename P::acc_t t = s_wtot[k];
+        if (k < w) *wex = C::op(*wex, t);
+        *agg = C::op(*agg, t);
     }
 }
 
 // --------------------------------------------------------- tile descriptors
+// two self-validating words per tile (see tagged_put / tagged_get)
 enum { ST_INVALID = 0, ST_AGG = 1, ST_PREFIX = 2 };
 
 template <class A>
-__device__ __forceinline__ u64 to_bits(A v) {
-    if constexpr (sizeof(A) == 4) {
-        uint32_t b;
-        __builtin_memcpy(&b, &v, 4);
-        return b;
-    } else {
-        u64 b;
-        __builtin_memcpy(&b, &v, 8);
-        return b;
-    }
-}
-template <class A>
-__device__ __forceinline__ A from_bits(u64 b) {
-    A v;
-    if constexpr (sizeof(A) == 4) {
-        uint32_t b32 = (uint32_t)b;
-        __builtin_memcpy(&v, &b32, 4);
-    } else {
-        __builtin_memcpy(&v, &b, 8);
-    }
-    return v;
-}
-
-template <class A>
 __device__ __forceinline__ void publish(u64* st, int64_t t, int state, A val, uint32_t epoch) {
-    const u64 bits = to_bits(val);
-    const u64 tag = ((u64)state << 62) | ((u64)epoch << 32);
-    __hip_atomic_store(&st[2 * t], tag | (bits & 0xffffffffull), __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_AGENT);
-    if constexpr (sizeof(A) == 8)
-        __hip_atomic_store(&st[2 * t + 1], tag | (bits >> 32), __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-}
-
-template <class A>
-__device__ __forceinline__ int peek(u64* st, int64_t t, uint32_t epoch, A& val) {
-    const u64 lo = __hip_atomic_load(&st[2 * t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (((lo >> 32) & 0x3fffffffull) != epoch) return ST_INVALID;
-    u64 bits = lo & 0xffffffffull;
-    if constexpr (sizeof(A) == 8) {
-        const u64 hi = __hip_atomic_load(&st[2 * t + 1], __ATOMIC_RELAXED,
-                                         __HIP_MEMORY_SCOPE_AGENT);
-        if ((hi >> 32) != (lo >> 32)) return ST_INVALID;  // halves of different states
-        bits |= hi << 32;
-    }
-    val = from_bits<A>(bits);
-    return (int)(lo >> 62);
+    tagged_put(st + 2 * t, state, epoch, val);
 }
 
 // Run by one whole wavefront.  Publishes the tile total, finds the exclusive
 // prefix of the tile from its predecessors' descriptors, publishes the
-// inclusive prefix, and returns the exclusive prefix (in every lane).
+// inclusive prefix, and returns the exclusive prefix (in every lane).  Lane l
+// inspects tile base - l; a descriptor once seen valid (AGG or PREFIX) is
+// final for this call, so a retry re-reads only the lanes still invalid.
 template <class P>
 __device__ typename P::acc_t lookback(u64* status, int64_t tile, typename P::acc_t agg,
                                       uint32_t epoch, u64* err) {
@@ -204,10 +209,14 @@ __device__ typename P::acc_t lookback(u64* status, int64_t tile, typename P::acc
     acc_t excl = C::id();
     int64_t base = tile - 1;
     uint32_t spins = 0;
+    int s = ST_INVALID;
+    acc_t val = C::id();
     while (true) {
-        const int64_t j = base - l;
-        acc_t val = C::id();
-        const int s = j >= 0 ? peek(status, j, epoch, val) : ST_PREFIX;
+        if (s == ST_INVALID) {
+            const int64_t j = base - l;
+            s = j >= 0 ? tagged_get(status + 2 * j, epoch, val) : ST_PREFIX;
+            if (j < 0) val = C::id();
+        }
         const u64 pre = __ballot(s == ST_PREFIX);
         const u64 inv = __ballot(s == ST_INVALID);
         const int p = pre ? __ffsll((long long)pre) - 1 : kWave;
@@ -223,37 +232,41 @@ __device__ typename P::acc_t lookback(u64* status, int64_t tile, typename P::acc
         excl = C::op(excl, wave_reduce<C>(l <= p ? val : C::id()));
         if (p < kWave) break;
         base -= kWave;
+        s = ST_INVALID;
     }
     if (l == 0) publish(status, tile, ST_PREFIX, C::op(excl, agg), epoch);
     return excl;
 }
 
 // ------------------------------------------------------------------ kernels
-template <class P>
-__device__ __forceinline__ void combine_waves(typename P::acc_t* s_wtot, typename P::acc_t* wex,
-                                              typename P::acc_t* agg) {
-    using C = typename P::C;
-    const int w = threadIdx.x / kWave;
-    *wex = C::id();
-    *agg = C::id();
-#pragma unroll
-    for (int k = 0; k < kWaves; ++k) {
-        typename P::acc_t t = s_wtot[k];
-        if (k < w) *wex = C::op(*wex, t);
-        *agg = C::op(*agg, t);
+template <class P, bool FULL>
+__device__ __forceinline__ void lookback_tile(const typename P::in_t* in,
+                                              typename P::out_t* out, int64_t n, int64_t tile,
+                                              int exclusive, u64* status, u64* sync,
+                                              uint32_t epoch) {
+    using acc_t = typename P::acc_t;
+    __shared__ acc_t s_wtot[P::NW];
+    __shared__ acc_t s_prefix;
+    Raw<P> raw;
+    tile_load<P, FULL>(in, n, tile, raw);
+    acc_t wex, agg;
+    tile_totals<P>(lane_total<P, FULL>(n, tile, raw), s_wtot, &wex, &agg);
+    if (threadIdx.x < kWave) {
+        const acc_t e = lookback<P>(status, tile, agg, epoch, sync + SYNC_ERROR);
+        if (threadIdx.x == 0) s_prefix = e;
     }
+    __syncthreads();
+    keep_raw_only<P>(raw);
+    tile_scan_store<P, FULL>(out, n, tile, raw, P::C::op(s_prefix, wex), exclusive != 0);
 }
 
 template <class P>
-__global__ __launch_bounds__(kBlock) void scan_lookback(const typename P::in_t* in,
+__global__ __launch_bounds__(P::kBlock) void scan_lookback(const typename P::in_t* in,
                                                         typename P::out_t* out, int64_t n,
                                                         int64_t ntiles, int exclusive,
                                                         u64* status, u64* sync,
                                                         uint32_t epoch) {
-    using acc_t = typename P::acc_t;
     __shared__ int64_t s_tile;
-    __shared__ acc_t s_wtot[kWaves];
-    __shared__ acc_t s_prefix;
     if (threadIdx.x == 0) {
         const u64 t = atomicAdd(&sync[SYNC_TILE_COUNTER], 1ull);
         if (t == (u64)ntiles - 1)  // every other tile id has been taken
@@ -263,52 +276,29 @@ __global__ __launch_bounds__(kBlock) void scan_lookback(const typename P::in_t* 
     }
     __syncthreads();
     const int64_t tile = s_tile;
-    const bool full = (tile + 1) * P::kTile <= n;
-    TileState<P> ts;
-    acc_t wtot = full ? tile_load_scan<P, true>(in, n, tile, ts)
-                      : tile_load_scan<P, false>(in, n, tile, ts);
-    const int w = threadIdx.x / kWave;
-    if (lane() == 0) s_wtot[w] = wtot;
-    __syncthreads();
-    acc_t wex, agg;
-    combine_waves<P>(s_wtot, &wex, &agg);
-    if (w == 0) {
-        acc_t e = lookback<P>(status, tile, agg, epoch, sync + SYNC_ERROR);
-        if (lane() == 0) s_prefix = e;
-    }
-    __syncthreads();
-    const acc_t pre = P::C::op(s_prefix, wex);
-    if (full) tile_store<P, true>(out, n, tile, ts, pre, exclusive != 0);
-    else tile_store<P, false>(out, n, tile, ts, pre, exclusive != 0);
+    if ((tile + 1) * P::kTile <= n)
+        lookback_tile<P, true>(in, out, n, tile, exclusive, status, sync, epoch);
+    else
+        lookback_tile<P, false>(in, out, n, tile, exclusive, status, sync, epoch);
 }
 
 // S1 pass 1: tile totals
+template <class P, bool FULL>
+__device__ __forceinline__ typename P::acc_t tile_sum(const typename P::in_t* in, int64_t n,
+                                                      int64_t tile) {
+    Raw<P> raw;
+    tile_load<P, FULL>(in, n, tile, raw);
+    return lane_total<P, FULL>(n, tile, raw);
+}
+
 template <class P>
-__global__ __launch_bounds__(kBlock) void scan_tile_totals(const typename P::in_t* in, int64_t n,
+__global__ __launch_bounds__(P::kBlock) void scan_tile_totals(const typename P::in_t* in, int64_t n,
                                                            typename P::acc_t* sums) {
-    using acc_t = typename P::acc_t;
-    using C = typename P::C;
-    constexpr int E = P::E, R = P::R;
-    __shared__ acc_t lds[kWaves];
+    __shared__ typename P::acc_t lds[P::NW];
     const int64_t tile = blockIdx.x;
-    const int w = threadIdx.x / kWave, l = lane();
-    const int64_t wbase = tile * P::kTile + (int64_t)w * P::kWaveElems + (int64_t)l * E;
-    const bool full = (tile + 1) * P::kTile <= n;
-    acc_t a = C::id();
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int64_t idx = wbase + (int64_t)r * kWave * E;
-        typename P::in_t raw[E];
-        if (full || idx + E <= n) {
-            load16(in + idx, raw);
-#pragma unroll
-            for (int e = 0; e < E; ++e) a = C::op(a, widen<acc_t>(raw[e]));
-        } else {
-            for (int e = 0; e < E; ++e)
-                if (idx + e < n) a = C::op(a, widen<acc_t>(in[idx + e]));
-        }
-    }
-    a = block_reduce<C>(a, lds);
+    typename P::acc_t a = (tile + 1) * P::kTile <= n ? tile_sum<P, true>(in, n, tile)
+                                                     : tile_sum<P, false>(in, n, tile);
+    a = block_reduce<typename P::C>(a, lds);
     if (threadIdx.x == 0) sums[tile] = a;
 }
 
@@ -343,49 +333,57 @@ __global__ __launch_bounds__(1024) void scan_tile_offsets(typename P::acc_t* sum
 }
 
 // S1 pass 3: rescan every tile with its offset
+template <class P, bool FULL>
+__device__ __forceinline__ void apply_tile(const typename P::in_t* in, typename P::out_t* out,
+                                           int64_t n, int64_t tile, typename P::acc_t offset,
+                                           int exclusive) {
+    __shared__ typename P::acc_t s_wtot[P::NW];
+    Raw<P> raw;
+    tile_load<P, FULL>(in, n, tile, raw);
+    typename P::acc_t wex, agg;
+    tile_totals<P>(lane_total<P, FULL>(n, tile, raw), s_wtot, &wex, &agg);
+    keep_raw_only<P>(raw);
+    tile_scan_store<P, FULL>(out, n, tile, raw, P::C::op(offset, wex), exclusive != 0);
+}
+
 template <class P>
-__global__ __launch_bounds__(kBlock) void scan_tile_apply(const typename P::in_t* in,
+__global__ __launch_bounds__(P::kBlock) void scan_tile_apply(const typename P::in_t* in,
                                                           typename P::out_t* out, int64_t n,
                                                           const typename P::acc_t* offs,
                                                           int exclusive) {
-    using acc_t = typename P::acc_t;
-    __shared__ acc_t s_wtot[kWaves];
     const int64_t tile = blockIdx.x;
-    const bool full = (tile + 1) * P::kTile <= n;
-    TileState<P> ts;
-    acc_t wtot = full ? tile_load_scan<P, true>(in, n, tile, ts)
-                      : tile_load_scan<P, false>(in, n, tile, ts);
-    if (lane() == 0) s_wtot[threadIdx.x / kWave] = wtot;
-    __syncthreads();
-    acc_t wex, agg;
-    combine_waves<P>(s_wtot, &wex, &agg);
-    const acc_t pre = P::C::op(offs[tile], wex);
-    if (full) tile_store<P, true>(out, n, tile, ts, pre, exclusive != 0);
-    else tile_store<P, false>(out, n, tile, ts, pre, exclusive != 0);
+    if ((tile + 1) * P::kTile <= n)
+        apply_tile<P, true>(in, out, n, tile, offs[tile], exclusive);
+    else
+        apply_tile<P, false>(in, out, n, tile, offs[tile], exclusive);
 }
 
-// S0: one workgroup, tiles in order
+// S0: one workgroup, tiles in order; the carry is held identically by every
+// thread (it is combined from the same LDS totals)
+template <class P, bool FULL>
+__device__ __forceinline__ typename P::acc_t single_tile(const typename P::in_t* in,
+                                                         typename P::out_t* out, int64_t n,
+                                                         int64_t tile, typename P::acc_t carry,
+                                                         int exclusive) {
+    __shared__ typename P::acc_t s_wtot[P::NW];
+    Raw<P> raw;
+    tile_load<P, FULL>(in, n, tile, raw);
+    typename P::acc_t wex, agg;
+    tile_totals<P>(lane_total<P, FULL>(n, tile, raw), s_wtot, &wex, &agg);
+    keep_raw_only<P>(raw);
+    tile_scan_store<P, FULL>(out, n, tile, raw, P::C::op(carry, wex), exclusive != 0);
+    __syncthreads();  // s_wtot is rewritten by the next tile
+    return P::C::op(carry, agg);
+}
+
 template <class P>
-__global__ __launch_bounds__(kBlock) void scan_single(const typename P::in_t* in,
+__global__ __launch_bounds__(P::kBlock) void scan_single(const typename P::in_t* in,
                                                       typename P::out_t* out, int64_t n,
                                                       int64_t ntiles, int exclusive) {
-    using acc_t = typename P::acc_t;
-    __shared__ acc_t s_wtot[kWaves];
-    acc_t carry = P::C::id();
+    typename P::acc_t carry = P::C::id();
     for (int64_t tile = 0; tile < ntiles; ++tile) {
-        const bool full = (tile + 1) * P::kTile <= n;
-        TileState<P> ts;
-        acc_t wtot = full ? tile_load_scan<P, true>(in, n, tile, ts)
-                          : tile_load_scan<P, false>(in, n, tile, ts);
-        if (lane() == 0) s_wtot[threadIdx.x / kWave] = wtot;
-        __syncthreads();
-        acc_t wex, agg;
-        combine_waves<P>(s_wtot, &wex, &agg);
-        const acc_t pre = P::C::op(carry, wex);
-        if (full) tile_store<P, true>(out, n, tile, ts, pre, exclusive != 0);
-        else tile_store<P, false>(out, n, tile, ts, pre, exclusive != 0);
-        carry = P::C::op(carry, agg);
-        __syncthreads();
+        if ((tile + 1) * P::kTile <= n) carry = single_tile<P, true>(in, out, n, tile, carry, exclusive);
+        else carry = single_tile<P, false>(in, out, n, tile, carry, exclusive);
     }
 }
 
@@ -403,18 +401,18 @@ skel_status scan_typed(int v, int kind, const void* x, void* y, int64_t n, Launc
     hipStream_t st = lc.stream;
     switch (v) {
     case S0_SINGLE_WG:
-        scan_single<P><<<1, kBlock, 0, st>>>(in, out, n, ntiles, excl);
+        scan_single<P><<<1, P::kBlock, 0, st>>>(in, out, n, ntiles, excl);
         return launch_check("scan_single");
     case S1_REDUCE_THEN_SCAN: {
         void* mem = nullptr;
         skel_status e = ws_scratch(lc, (size_t)ntiles * sizeof(acc_t), &mem);
         if (e != SKEL_OK) return e;
         acc_t* sums = static_cast<acc_t*>(mem);
-        scan_tile_totals<P><<<(unsigned)ntiles, kBlock, 0, st>>>(in, n, sums);
+        scan_tile_totals<P><<<(unsigned)ntiles, P::kBlock, 0, st>>>(in, n, sums);
         if ((e = launch_check("scan_tile_totals")) != SKEL_OK) return e;
         scan_tile_offsets<P><<<1, 1024, 0, st>>>(sums, ntiles);
         if ((e = launch_check("scan_tile_offsets")) != SKEL_OK) return e;
-        scan_tile_apply<P><<<(unsigned)ntiles, kBlock, 0, st>>>(in, out, n, sums, excl);
+        scan_tile_apply<P><<<(unsigned)ntiles, P::kBlock, 0, st>>>(in, out, n, sums, excl);
         return launch_check("scan_tile_apply");
     }
     default: {  // S2_LOOKBACK
@@ -422,7 +420,7 @@ skel_status scan_typed(int v, int kind, const void* x, void* y, int64_t n, Launc
         uint32_t epoch = 0;
         skel_status e = ws_status(lc, (size_t)ntiles * 16, &status, &epoch);
         if (e != SKEL_OK) return e;
-        scan_lookback<P><<<(unsigned)ntiles, kBlock, 0, st>>>(
+        scan_lookback<P><<<(unsigned)ntiles, P::kBlock, 0, st>>>(
             in, out, n, ntiles, excl, static_cast<u64*>(status), lc.ws->sync, epoch);
         return launch_check("scan_lookback");
     }

@@ -137,10 +137,69 @@ __device__ __forceinline__ T block_reduce(T v, T* lds) {
     return v;
 }
 
+// ------------------------------------------------ self-validating words --
+// Inter-workgroup hand-off words [state:2 | epoch:30 | payload:32], written
+// and read with device-scope relaxed atomics.  A word is valid only if its
+// epoch matches the reader's, so the array never needs clearing (the host
+// gives each call a fresh epoch), and because state and payload travel in one
+// single-copy-atomic word, no release/acquire fence (an L2 write-back on this
+// multi-XCD part) is needed.  64-bit payloads use two words whose tags must
+// agree.
+typedef unsigned long long u64;
+
+__device__ __forceinline__ void tag_store(u64* w, int state, uint32_t epoch, uint32_t payload) {
+    const u64 v = ((u64)state << 62) | ((u64)epoch << 32) | payload;
+    __hip_atomic_store(w, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ u64 tag_load(u64* w) {
+    return __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <class A>
+__device__ __forceinline__ void tagged_put(u64* w2, int state, uint32_t epoch, A v) {
+    if constexpr (sizeof(A) == 4) {
+        uint32_t b;
+        __builtin_memcpy(&b, &v, 4);
+        tag_store(w2, state, epoch, b);
+    } else {
+        u64 b;
+        __builtin_memcpy(&b, &v, 8);
+        tag_store(w2, state, epoch, (uint32_t)b);
+        tag_store(w2 + 1, state, epoch, (uint32_t)(b >> 32));
+    }
+}
+
+// Returns the state (0 when the word is stale, i.e. of another epoch, or when
+// the two halves of a 64-bit payload carry different tags) and the payload.
+template <class A>
+__device__ __forceinline__ int tagged_get(u64* w2, uint32_t epoch, A& v) {
+    const u64 lo = tag_load(w2);
+    if (((lo >> 32) & 0x3fffffffull) != epoch) return 0;
+    if constexpr (sizeof(A) == 4) {
+        const uint32_t b = (uint32_t)lo;
+        __builtin_memcpy(&v, &b, 4);
+    } else {
+        const u64 hi = tag_load(w2 + 1);
+        if ((hi >> 32) != (lo >> 32)) return 0;
+        const u64 b = (lo & 0xffffffffull) | (hi << 32);
+        __builtin_memcpy(&v, &b, 8);
+    }
+    return (int)(lo >> 62);
+}
+
 // ---------------------------------------------------------- vector access --
 template <class T>
 __device__ __forceinline__ void load16(const T* p, T (&v)[16 / sizeof(T)]) {
     u32x4 raw = *reinterpret_cast<const u32x4*>(p);
+    __builtin_memcpy(&v, &raw, 16);
+}
+
+// streaming read of data used once (non-temporal: does not displace cache
+// lines that other accesses reuse)
+template <class T>
+__device__ __forceinline__ void load16_nt(const T* p, T (&v)[16 / sizeof(T)]) {
+    u32x4 raw = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(p));
     __builtin_memcpy(&v, &raw, 16);
 }
 

@@ -262,7 +262,8 @@ skel_status skel_sync(void* stream) {
     if (flag) {
         (void)hipMemset(w->sync + SYNC_ERROR, 0, sizeof flag);
         return fail(SKEL_E_TIMEOUT,
-                    "a scan look-back wait expired (flag 0x%llx); results of the "
+                    "a bounded inter-workgroup wait expired (flag 0x%llx: 1 = scan "
+                    "look-back, 2 = reduce partials); results of the "
                     "calls since the last skel_sync on this stream are invalid",
                     flag);
     }

@@ -272,6 +272,7 @@ skel_status skel_mapoverlap1d(skel_container* in, skel_container* out, const flo
     CallContext cc;
     cc.skeleton = SKEL_SK_MAPOVERLAP1D;
     cc.n = in->n;
+    cc.radius = radius;
     int v = choose_variant(variant, cc, &st);
     if (v < 0) return st;
     Operands ops;

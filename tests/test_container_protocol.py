@@ -167,6 +167,8 @@ def test_chain_of_twenty_device_calls(rt):
         st, _ = acquire(rt, h, DEVICE, RW)
         assert st == OK
         assert rt.skel_container_release(h, DEVICE, C.c_void_p(1)) == OK
+    # one stream: stream order is enough, no event marker was enqueued
+    assert counts(rt)["event_records"] == 0
     st, _ = acquire(rt, h, HOST, READ)
     assert st == OK and rt.skel_container_release(h, HOST, None) == OK
     s = stats(rt, h)
@@ -311,7 +313,7 @@ def name_of(lib, sk, v):
 
 
 def test_variant_registry(rt):
-    want = {SK_MAP: 3, SK_REDUCE: 4, SK_MAPREDUCE: 4, SK_OV1: 2, SK_OV2: 3, SK_SCAN: 3}
+    want = {SK_MAP: 3, SK_REDUCE: 4, SK_MAPREDUCE: 4, SK_OV1: 3, SK_OV2: 4, SK_SCAN: 3}
     for sk, k in want.items():
         assert rt.skel_variant_count(sk) == k
         names = [name_of(rt, sk, v) for v in range(k)]
@@ -327,8 +329,10 @@ def test_static_plan(rt):
     assert sel(SK_REDUCE, 1 << 26) == "R2_ticket"
     assert sel(SK_SCAN, 100, I32) == "S0_single_wg"
     assert sel(SK_SCAN, 1 << 27, I32) == "S2_decoupled_lookback"
-    assert sel(SK_OV2, 1 << 24, F32, 1) == "O2c_lds_separable"
+    assert sel(SK_OV2, 1 << 24, F32, 1) == "O2d_separable_l1"
     assert sel(SK_OV2, 1 << 24, F32, 0) == "O2b_lds_tile"  # separable not selectable
+    assert sel(SK_OV1, 1 << 20, F32, 2) == "O1c_shuffle"   # aux = radius
+    assert sel(SK_OV1, 1 << 20, F32, 7) == "O1b_lds_tile"  # beyond 4 neighbours
     assert sel(SK_MAP, 1 << 20) == "M2_vec4x4_nt"
     assert rt.skel_select_variant(17, F32, 10, 1, 10, 0) == -1
 

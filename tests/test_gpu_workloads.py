@@ -49,7 +49,7 @@ def test_gaussian_stencil_4096(skel, oracle_mod):
     g = si.gaussian_weights(4, 2.0)
     ref, mag = oracle_mod.mapoverlap2d(x, 4, 4, wy=g, wx=g)
     cx = skel.Container.from_numpy(x)
-    for v in (skel.VARIANT_AUTO, 0, 1, 2):
+    for v in (skel.VARIANT_AUTO, 0, 1, 2, 3):
         out = skel.Container.empty(skel.F32, H, W)
         skel.skel_mapoverlap2d(cx, out, wy=g, wx=g, edge=skel.EDGE_CLAMP, variant=v)
         got = out.to_numpy().astype(np.float64)
