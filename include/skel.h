@@ -104,7 +104,8 @@ typedef enum skel_skeleton {
     SKEL_SK_MAPOVERLAP1D = 3,
     SKEL_SK_MAPOVERLAP2D = 4,
     SKEL_SK_SCAN = 5,
-    SKEL_SK_COUNT = 6
+    SKEL_SK_REDUCE_SEGMENTS = 6,
+    SKEL_SK_COUNT = 7
 } skel_skeleton;
 
 #define SKEL_VARIANT_AUTO (-1)
@@ -240,6 +241,23 @@ skel_status skel_mapoverlap2d(skel_container *in, skel_container *out,
 skel_status skel_scan(skel_container *in, skel_container *out,
                       skel_scan_kind kind, skel_reduce_op op, int variant,
                       void *stream);
+
+/* Segmented Reduce: the Reduce skeleton applied to many vectors of uneven
+ * length at once (a batch of operands of one skeleton instance, Section III),
+ *     out[s] = op over in[offsets[s]] .. in[offsets[s+1] - 1],  0 <= s < nseg
+ * in: F32 with n elements (the vectors back to back); offsets: I64 with
+ * nseg + 1 nondecreasing entries in [0, n]; out: F32 with nseg elements.
+ * Empty segments give the identity.  The plain variant issues one Reduce per
+ * segment; the persistent variant reduces every segment in one launch over
+ * (segment, chunk) work items and combines each segment's partials in a fixed
+ * order (deterministic).  The persistent variant checks the offsets on the
+ * device: if they decrease or leave [0, n] it computes nothing and
+ * skel_sync reports SKEL_E_TIMEOUT with flag 4; the per-segment variant
+ * reads the offsets on the host and returns SKEL_E_INVAL.  No offsets can
+ * make either variant access memory outside the containers. */
+skel_status skel_reduce_segments(skel_reduce_op op, skel_container *in,
+                                 skel_container *offsets, skel_container *out,
+                                 int variant, void *stream);
 
 /* ------------------------------------------- variants and selection ---- */
 

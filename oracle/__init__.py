@@ -53,6 +53,15 @@ def _load():
     lib.oracle_map_f32.restype = C.c_int
     lib.oracle_reduce_f32.argtypes = [C.c_int, f32p, I64]
     lib.oracle_reduce_f32.restype = C.c_double
+    lib.oracle_reduce_segments_f32.argtypes = [C.c_int, f32p, I64, i64p, I64, f64p]
+    lib.oracle_reduce_segments_f32.restype = C.c_int
+    u16p = np.ctypeslib.ndpointer(np.uint16, flags="C_CONTIGUOUS")
+    lib.oracle_fsum_f64.argtypes = [f64p, I64]
+    lib.oracle_fsum_f64.restype = C.c_double
+    lib.oracle_sum_bf16_exact.argtypes = [u16p, I64]
+    lib.oracle_sum_bf16_exact.restype = C.c_double
+    lib.oracle_dot_bf16_exact.argtypes = [u16p, u16p, I64]
+    lib.oracle_dot_bf16_exact.restype = C.c_double
     lib.oracle_abs_sum_f32.argtypes = [f32p, I64]
     lib.oracle_abs_sum_f32.restype = C.c_double
     lib.oracle_reduce_i32_i32.argtypes = [C.c_int, i32p, I64]
@@ -137,6 +146,38 @@ def reduce(op: str, x, out_dtype=None):
     if x.dtype == np.int64:
         return int(lib.oracle_reduce_i64_i64(code, x, x.size))
     raise TypeError(f"oracle reduce: unsupported dtype {x.dtype}")
+
+
+def reduce_segments(op: str, x, offsets) -> np.ndarray:
+    """out[s] = reduce of x[offsets[s]:offsets[s+1]] in binary64."""
+    lib = _load()
+    x = np.ascontiguousarray(x, dtype=np.float32).reshape(-1)
+    off = np.ascontiguousarray(offsets, dtype=np.int64).reshape(-1)
+    out = np.empty(max(off.size - 1, 0), dtype=np.float64)
+    rc = lib.oracle_reduce_segments_f32(REDUCE_OPS[op], x, x.size, off, out.size, out)
+    if rc != 0:
+        raise ValueError("oracle reduce_segments: offsets must be nondecreasing in [0, n]")
+    return out
+
+
+def fsum(x) -> float:
+    """Exactly rounded binary64 sum of binary64 values."""
+    x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1)
+    return float(_load().oracle_fsum_f64(x, x.size))
+
+
+def sum_bf16_exact(bits) -> float:
+    """Exactly rounded sum of bfloat16 values given as uint16 bit patterns."""
+    b = np.ascontiguousarray(bits, dtype=np.uint16).reshape(-1)
+    return float(_load().oracle_sum_bf16_exact(b, b.size))
+
+
+def dot_bf16_exact(xbits, ybits) -> float:
+    """Exactly rounded sum of the products of two bfloat16 vectors."""
+    a = np.ascontiguousarray(xbits, dtype=np.uint16).reshape(-1)
+    b = np.ascontiguousarray(ybits, dtype=np.uint16).reshape(-1)
+    assert a.size == b.size
+    return float(_load().oracle_dot_bf16_exact(a, b, a.size))
 
 
 def abs_sum(x) -> float:

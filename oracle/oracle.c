@@ -15,6 +15,7 @@
 #include <math.h>
 #include <stddef.h>
 #include <stdint.h>
+#include <string.h>
 
 #ifdef _OPENMP
 #include <omp.h>
@@ -85,6 +86,98 @@ double oracle_reduce_f32(int op, const float *x, int64_t n)
         else acc = acc + v;
     }
     return acc;
+}
+
+int oracle_reduce_segments_f32(int op, const float *x, int64_t n, const int64_t *off,
+                               int64_t nseg, double *out)
+{
+    for (int64_t s = 0; s < nseg; ++s)
+        if (off[s] < 0 || off[s + 1] < off[s] || off[s + 1] > n) return -1;
+    for (int64_t s = 0; s < nseg; ++s)
+        out[s] = oracle_reduce_f32(op, x + off[s], off[s + 1] - off[s]);
+    return 0;
+}
+
+/* ------------------------------------------------ exactly rounded sums ---- */
+
+/* The exact sum is kept as a short list of non-overlapping binary64 partials,
+ * ordered by increasing magnitude; adding a value replaces the list by the
+ * exact two-term splits of the running sum against each partial. */
+#define MSUM_CAP 128
+
+typedef struct {
+    double p[MSUM_CAP];
+    int len;
+    int bad; /* a non-finite input or a list overflow was seen */
+} msum;
+
+static void msum_add(msum *m, double x)
+{
+    if (!isfinite(x)) { m->bad = 1; return; }
+    int i = 0;
+    for (int j = 0; j < m->len; ++j) {
+        double y = m->p[j];
+        if (fabs(x) < fabs(y)) { double t = x; x = y; y = t; }
+        double hi = x + y;
+        double lo = y - (hi - x); /* exact: |y| <= |x| */
+        if (lo != 0.0) m->p[i++] = lo;
+        x = hi;
+    }
+    if (i >= MSUM_CAP) { m->bad = 1; return; }
+    m->p[i++] = x;
+    m->len = i;
+}
+
+/* round the exact value sum(p) once to binary64 */
+static double msum_round(const msum *m)
+{
+    if (m->bad) return NAN;
+    int n = m->len;
+    if (n == 0) return 0.0;
+    double hi = m->p[--n], lo = 0.0;
+    while (n > 0) {
+        double x = hi, y = m->p[--n];
+        hi = x + y;
+        lo = y - (hi - x);
+        if (lo != 0.0) break;
+    }
+    /* hi + lo is the sum of the top partials; if lo is exactly half an ulp of
+     * hi and the remaining partials push the same way, round away from hi */
+    if (n > 0 && ((lo < 0.0 && m->p[n - 1] < 0.0) || (lo > 0.0 && m->p[n - 1] > 0.0))) {
+        double y = lo * 2.0;
+        double x = hi + y;
+        if (y == x - hi) hi = x;
+    }
+    return hi;
+}
+
+double oracle_fsum_f64(const double *x, int64_t n)
+{
+    msum m = {{0}, 0, 0};
+    for (int64_t i = 0; i < n; ++i) msum_add(&m, x[i]);
+    return msum_round(&m);
+}
+
+static double bf16_value(uint16_t h)
+{
+    uint32_t b = (uint32_t)h << 16;
+    float f;
+    memcpy(&f, &b, 4);
+    return (double)f;
+}
+
+double oracle_sum_bf16_exact(const uint16_t *x, int64_t n)
+{
+    msum m = {{0}, 0, 0};
+    for (int64_t i = 0; i < n; ++i) msum_add(&m, bf16_value(x[i]));
+    return msum_round(&m);
+}
+
+double oracle_dot_bf16_exact(const uint16_t *x, const uint16_t *y, int64_t n)
+{
+    msum m = {{0}, 0, 0};
+    for (int64_t i = 0; i < n; ++i) msum_add(&m, bf16_value(x[i]) * bf16_value(y[i]));
+    return msum_round(&m);
 }
 
 double oracle_abs_sum_f32(const float *x, int64_t n)

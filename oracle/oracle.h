@@ -61,6 +61,22 @@ double oracle_reduce_f32(int op, const float *x, int64_t n);
 /* sum of |x[i]| in binary64: the magnitude scale of a floating-point sum */
 double oracle_abs_sum_f32(const float *x, int64_t n);
 
+/* Segmented Reduce: out[s] = reduce of x[off[s]] .. x[off[s+1]-1] for
+ * 0 <= s < nseg (the Reduce definition applied to each segment).  Returns -1
+ * if the offsets decrease or leave [0, n]. */
+int oracle_reduce_segments_f32(int op, const float *x, int64_t n, const int64_t *off,
+                               int64_t nseg, double *out);
+
+/* Exactly rounded sums (the exact real sum, rounded once to binary64) by
+ * Shewchuk's non-overlapping-partials algorithm ("Adaptive precision
+ * floating-point arithmetic", 1997; the method of Python's math.fsum).
+ * bfloat16 inputs are given as their 16-bit patterns.  The dot form sums the
+ * products x[i]*y[i], each exact in binary64 (8-bit significands).
+ * Non-finite inputs give NaN. */
+double oracle_fsum_f64(const double *x, int64_t n);
+double oracle_sum_bf16_exact(const uint16_t *x, int64_t n);
+double oracle_dot_bf16_exact(const uint16_t *x, const uint16_t *y, int64_t n);
+
 /* integer Reduce, wrapping in the output width */
 int32_t oracle_reduce_i32_i32(int op, const int32_t *x, int64_t n);
 int64_t oracle_reduce_i32_i64(int op, const int32_t *x, int64_t n);

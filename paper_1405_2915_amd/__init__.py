@@ -22,6 +22,14 @@ import weakref
 
 import numpy as np
 
+try:
+    # torch ships its own HIP runtime (same soname, libamdhip64.so.7).  Loading
+    # it before libskel.so makes the library bind to that one runtime; loaded
+    # the other way round, the process would hold two HIP runtimes.
+    import torch  # noqa: F401
+except ImportError:
+    torch = None
+
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libskel.so")
 
@@ -38,7 +46,8 @@ EDGE_CLAMP, EDGE_CONST, EDGE_CYCLIC = 0, 1, 2
 INCLUSIVE, EXCLUSIVE = 0, 1
 SUM, MIN, MAX = 0, 1, 2
 MAP_IDENTITY, MAP_AXPY, MAP_AFFINE, MAP_TANH, MAP_AFFINE_TANH, MAP_MUL, MAP_SQUARE = range(7)
-SK_MAP, SK_REDUCE, SK_MAPREDUCE, SK_MAPOVERLAP1D, SK_MAPOVERLAP2D, SK_SCAN = range(6)
+SK_MAP, SK_REDUCE, SK_MAPREDUCE, SK_MAPOVERLAP1D, SK_MAPOVERLAP2D, SK_SCAN, \
+    SK_REDUCE_SEGMENTS = range(7)
 VARIANT_AUTO = -1
 MAX_RADIUS_1D, MAX_RADIUS_2D = 64, 8
 
@@ -104,6 +113,7 @@ def load_library(path: str = LIB_PATH):
         "skel_mapoverlap1d": (st, [vp, vp, fp, i, i, C.c_float, i, vp]),
         "skel_mapoverlap2d": (st, [vp, vp, fp, fp, fp, i, i, i, C.c_float, i, vp]),
         "skel_scan": (st, [vp, vp, i, i, i, vp]),
+        "skel_reduce_segments": (st, [i, vp, vp, vp, i, vp]),
         "skel_variant_count": (i, [i]),
         "skel_variant_name": (C.c_char_p, [i, i]),
         "skel_select_variant": (i, [i, i, i64, i64, i64, i]),
@@ -147,9 +157,27 @@ def _stream(stream) -> int:
 
 
 # ----------------------------------------------------------------- runtime
-def skel_init(device: int = 0, allocator: str = "torch") -> None:
+DEFAULT_PLAN = os.path.join(_HERE, "plans", "gfx950.plan")
+
+
+def skel_init(device: int = 0, allocator: str = "torch", plan: str | None = "default") -> None:
     """Bind the library to `device`.  allocator="torch" routes device memory
-    through torch's caching allocator; "hip" uses hipMalloc/hipFree."""
+    through torch's caching allocator; "hip" uses hipMalloc/hipFree.
+    plan: "default" loads the execution plan tuned for this GPU model
+    (plans/gfx950.plan, written by paper_1405_2915_amd.autotune) unless
+    SKEL_PLAN_FILE names another; a path loads that table; None uses the
+    static rules only."""
+    _init_device(device, allocator)
+    if plan == "default":
+        if not os.environ.get("SKEL_PLAN_FILE") and os.path.exists(DEFAULT_PLAN):
+            skel_load_plan(DEFAULT_PLAN)
+    elif plan is None:
+        skel_clear_plan()
+    else:
+        skel_load_plan(plan)
+
+
+def _init_device(device: int, allocator: str) -> None:
     global _device
     lib = load_library()
     _device = device
@@ -254,6 +282,13 @@ class Container:
 
     def stats(self) -> dict:
         return skel_container_stats(self)
+
+    def mark_device_written(self, stream=None) -> None:
+        """Tell the coherence protocol that the device copy was written outside
+        a skeleton call (e.g. by replaying a captured graph): a device write
+        acquire/release pair, which makes the host copy stale."""
+        skel_container_acquire(self, DEVICE, WRITE, stream)
+        skel_container_release(self, DEVICE, stream)
 
     def destroy(self) -> None:
         if self.handle:
@@ -404,6 +439,13 @@ def skel_scan(inp: Container, out: Container, kind: int = INCLUSIVE, op: int = S
               variant: int = VARIANT_AUTO, stream=None) -> None:
     _check(_L().skel_scan(_h(inp), _h(out), kind, op, variant, C.c_void_p(_stream(stream))),
            "skel_scan")
+
+
+def skel_reduce_segments(op: int, inp: Container, offsets: Container, out: Container,
+                         variant: int = VARIANT_AUTO, stream=None) -> None:
+    """out[s] = op over inp[offsets[s]:offsets[s+1]] for every segment s."""
+    _check(_L().skel_reduce_segments(op, _h(inp), _h(offsets), _h(out), variant,
+                                     C.c_void_p(_stream(stream))), "skel_reduce_segments")
 
 
 def skel_variant_count(skeleton: int) -> int:

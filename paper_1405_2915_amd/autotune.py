@@ -1,0 +1,144 @@
+"""Off-line tuning of the execution plan.
+
+Section II of the paper: besides on-line models, composition can use off-line
+tuning that precomputes a dispatch structure, looked up at run time, from
+sample executions; Section III: an execution plan attached to a skeleton gives
+the expected best implementation for a call context and is recomputed once per
+target system.  This module is that off-line step for one GPU:
+
+    python -m paper_1405_2915_amd.autotune [--out FILE] [--min 10] [--max 28]
+                                           [--reps 7] [--report FILE.json]
+
+For each tuned skeleton and each size n = 2^k it times every selectable
+variant (forced), as the median of `reps` runs measured with HIP events on the
+launch stream, with the 256 MiB Infinity Cache evicted before every timed call
+(by reading a 512 MiB buffer); it writes the fastest variant per
+(skeleton, dtype, log2 n) as a plan table (the text format of skel_load_plan)
+and a JSON report of every timing.  Single-workgroup variants are not timed
+above 2^22 elements (they use one CU of 256).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+DEFAULT_PLAN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "plans", "gfx950.plan")
+SINGLE_WG_MAX_LOG2 = 22
+
+
+def _timed(torch, fn, evict, reps):
+    st = torch.cuda.current_stream()
+    times = []
+    for _ in range(reps):
+        evict()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(st)
+        fn()
+        b.record(st)
+        b.synchronize()
+        times.append(a.elapsed_time(b) * 1e3)
+    return float(np.median(times))
+
+
+def tune(lo=10, hi=28, reps=7, log=print):
+    import torch
+
+    import paper_1405_2915_amd as skel
+    import synth_inputs as si
+
+    skel.skel_init(0, "torch", plan=None)  # time the variants, not a previous plan
+    flush = skel.Container.from_numpy(np.zeros(1 << 27, np.float32))
+    fl_out = skel.Container.empty(skel.F32, 1)
+    r1 = skel.variant_index(skel.SK_REDUCE, "R1_two_pass")
+
+    def evict():
+        skel.skel_reduce(skel.SUM, flush, fl_out, variant=r1)
+
+    evict()
+    torch.cuda.synchronize()
+    report = {"lo": lo, "hi": hi, "reps": reps, "unit": "us", "results": {}}
+    table = []
+    single = {skel.SK_REDUCE: "R0_single_wg", skel.SK_MAPREDUCE: "MR3_fused_single_wg",
+              skel.SK_SCAN: "S0_single_wg"}
+    for k in range(lo, hi + 1):
+        n = 1 << k
+        x = skel.Container.from_numpy(si.normal_f32(n, 2, 0))
+        y = skel.Container.from_numpy(si.normal_f32(n, 2, 1))
+        s = skel.Container.from_numpy(si.int_uniform_i32(n, 100, 2, 2))
+        so = skel.Container.empty(skel.I32, n)
+        out1 = skel.Container.empty(skel.F32, 1)
+        cases = {
+            ("REDUCE", "f32", skel.SK_REDUCE):
+                lambda v: skel.skel_reduce(skel.SUM, x, out1, variant=v),
+            ("MAPREDUCE", "f32", skel.SK_MAPREDUCE):
+                lambda v: skel.skel_mapreduce(skel.MAP_MUL, None, [x, y], skel.SUM, out1,
+                                              variant=v),
+            ("SCAN", "i32", skel.SK_SCAN):
+                lambda v: skel.skel_scan(s, so, skel.INCLUSIVE, skel.SUM, variant=v),
+            ("MAP", "f32", skel.SK_MAP):
+                lambda v: skel.skel_map(skel.MAP_AXPY, [2.5], [x, y], y, variant=v),
+        }
+        for (name, dt, sk), call in cases.items():
+            res = {}
+            for v in range(skel.skel_variant_count(sk)):
+                vname = skel.skel_variant_name(sk, v)
+                if vname == single.get(sk) and k > SINGLE_WG_MAX_LOG2:
+                    continue
+                res[vname] = round(_timed(torch, lambda: call(v), evict, reps), 3)
+            best = min(res, key=res.get)
+            report["results"].setdefault(name, {})[str(k)] = res
+            table.append((name, dt, k, best))
+            log(f"{name:10s} 2^{k:2d}: " + "  ".join(f"{a}={b:.1f}" for a, b in res.items())
+                + f"  -> {best}")
+        for c in (x, y, s, so, out1):
+            c.destroy()
+    return table, report
+
+
+def write_plan(table, path, header):
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    with open(path, "w") as f:
+        f.write("# execution plan: fastest variant per (skeleton, dtype, log2 n)\n")
+        for line in header:
+            f.write(f"# {line}\n")
+        # keep only the sizes where the choice changes (nearest lower key rules)
+        last = {}
+        for name, dt, k, v in table:
+            if last.get((name, dt)) != v:
+                f.write(f"{name} {dt} {k} {v}\n")
+                last[(name, dt)] = v
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default=DEFAULT_PLAN)
+    ap.add_argument("--report", default=None)
+    ap.add_argument("--min", type=int, default=10)
+    ap.add_argument("--max", type=int, default=28)
+    ap.add_argument("--reps", type=int, default=7)
+    args = ap.parse_args()
+    log = lambda m: print(f"[autotune] {m}", file=sys.stderr, flush=True)
+    table, report = tune(args.min, args.max, args.reps, log)
+    import torch
+    dev = torch.cuda.get_device_properties(0)
+    write_plan(table, args.out, [f"device: {dev.name} ({dev.gcnArchName}), "
+                                 f"{dev.multi_processor_count} CUs",
+                                 f"sizes 2^{args.min}..2^{args.max}, median of {args.reps}, "
+                                 "Infinity Cache evicted before each timed call"])
+    if args.report:
+        with open(args.report, "w") as f:
+            json.dump(report, f, indent=1)
+    print(json.dumps({"plan": args.out, "entries": len(table)}))
+
+
+if __name__ == "__main__":
+    main()

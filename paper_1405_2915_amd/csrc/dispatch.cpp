@@ -13,17 +13,21 @@ namespace {
 
 const char* const kMap[] = {"M0_scalar", "M1_vec4", "M2_vec4x4_nt"};
 const char* const kReduce[] = {"R0_single_wg", "R1_two_pass", "R2_ticket",
-                               "R3_atomic"};
+                               "R3_atomic", "R4_compensated"};
 const char* const kMapReduce[] = {"MR0_unfused", "MR1_fused_two_pass",
-                                  "MR2_fused_ticket", "MR3_fused_single_wg"};
+                                  "MR2_fused_ticket", "MR3_fused_single_wg",
+                                  "MR4_compensated"};
 const char* const kOverlap1D[] = {"O1a_direct", "O1b_lds_tile", "O1c_shuffle"};
 const char* const kOverlap2D[] = {"O2a_direct", "O2b_lds_tile", "O2c_lds_separable",
                                   "O2d_separable_l1"};
 const char* const kScan[] = {"S0_single_wg", "S1_reduce_then_scan",
                              "S2_decoupled_lookback"};
 
-const char* const kSkeletonNames[] = {"MAP", "REDUCE", "MAPREDUCE",
-                                      "MAPOVERLAP1D", "MAPOVERLAP2D", "SCAN"};
+const char* const kSegments[] = {"B0_per_segment", "B1_persistent"};
+
+const char* const kSkeletonNames[] = {"MAP",          "REDUCE", "MAPREDUCE",
+                                      "MAPOVERLAP1D", "MAPOVERLAP2D", "SCAN",
+                                      "REDUCE_SEGMENTS"};
 
 struct TableEntry {
     int skeleton;
@@ -59,6 +63,7 @@ int static_rule(const CallContext& c) {
     case SKEL_SK_MAPOVERLAP1D: return c.radius <= 4 ? O1C_SHUFFLE : O1B_LDS_TILE;
     case SKEL_SK_MAPOVERLAP2D: return c.separable ? O2D_SEPARABLE_L1 : O2B_LDS_TILE;
     case SKEL_SK_SCAN: return c.n <= (INT64_C(1) << 15) ? S0_SINGLE_WG : S2_LOOKBACK;
+    case SKEL_SK_REDUCE_SEGMENTS: return B1_PERSISTENT;
     }
     return -1;
 }
@@ -97,6 +102,7 @@ int variant_count(int skeleton) {
     case SKEL_SK_MAPOVERLAP1D: return OVERLAP1D_NVAR;
     case SKEL_SK_MAPOVERLAP2D: return OVERLAP2D_NVAR;
     case SKEL_SK_SCAN: return SCAN_NVAR;
+    case SKEL_SK_REDUCE_SEGMENTS: return SEGMENTS_NVAR;
     }
     return 0;
 }
@@ -110,6 +116,7 @@ const char* variant_name(int skeleton, int v) {
     case SKEL_SK_MAPOVERLAP1D: return kOverlap1D[v];
     case SKEL_SK_MAPOVERLAP2D: return kOverlap2D[v];
     case SKEL_SK_SCAN: return kScan[v];
+    case SKEL_SK_REDUCE_SEGMENTS: return kSegments[v];
     }
     return nullptr;
 }
@@ -131,11 +138,20 @@ bool selectable(int v, const CallContext& c, const char** why) {
             *why = "atomic finish supports floating-point SUM only";
             return false;
         }
+        if (v == R4_COMPENSATED &&
+            (c.op != SKEL_SUM || (c.din != SKEL_F32 && c.din != SKEL_BF16))) {
+            *why = "compensated summation applies to floating-point SUM only";
+            return false;
+        }
         return true;
     case SKEL_SK_MAPREDUCE:
         // the unfused form stores the mapped values with the F32 Map skeleton
         if (v == MR0_UNFUSED && c.din != SKEL_F32) {
             *why = "unfused form needs F32 inputs (Map is F32)";
+            return false;
+        }
+        if (v == MR4_COMPENSATED && c.op != SKEL_SUM) {
+            *why = "compensated summation applies to SUM only";
             return false;
         }
         return true;

@@ -11,6 +11,9 @@
 //             partials in index order, so the result is deterministic
 //   R3        one pass with a hardware atomic finish (order-dependent for
 //             floating point)
+//   R4 / MR4  the R2 pass with compensated (TwoSum / TwoProduct) binary32
+//             accumulation: accuracy of a doubled working precision for the
+//             same HBM traffic, for long sums of bf16 or f32 data
 //   MR0       the composed plain form: Map into a temporary, then R1
 // Every lane streams 16-byte vectors with four loads in flight and keeps four
 // independent accumulators; partials are combined by 64-lane butterflies and
@@ -19,6 +22,7 @@
 
 #include "kcommon.hpp"
 #include "dispatch.hpp"
+#include "kepoch.hpp"
 #include "launch.hpp"
 
 namespace skel {
@@ -102,6 +106,116 @@ struct MapSrc {
     }
 };
 
+// ------------------------------------------------------- compensated sums
+// R4 / MR4: a running sum carried as s + c in two binary32 numbers.  Every
+// addition is split exactly into its rounded sum and its rounding error
+// (TwoSum, Knuth), the errors are accumulated in c, and products are split
+// exactly with a fused multiply-add (TwoProduct), so the accumulated error
+// is that of a sum kept to about twice the working precision; s + c is
+// rounded once at the end.
+struct Comp {
+    float s, c;
+    __device__ explicit operator float() const { return s + c; }
+};
+
+__device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
+    s = a + b;
+    const float bp = s - a;
+    e = (a - (s - bp)) + (b - bp);
+}
+
+__device__ __forceinline__ Comp comp_add(Comp a, float x) {
+    float s, e;
+    two_sum(a.s, x, s, e);
+    return {s, a.c + e};
+}
+
+struct CombComp {
+    static __device__ __forceinline__ Comp id() { return {0.0f, 0.0f}; }
+    static __device__ __forceinline__ Comp op(Comp a, Comp b) {
+        float s, e;
+        two_sum(a.s, b.s, s, e);
+        return {s, (a.c + b.c) + e};
+    }
+};
+
+__device__ __forceinline__ Comp xshfl(Comp v, int o) {
+    return {__shfl_xor(v.s, o), __shfl_xor(v.c, o)};
+}
+
+template <int DIN>
+struct RPC {
+    using in_t = typename Stored<DIN>::type;
+    using out_t = float;
+    using acc_t = Comp;
+    using C = CombComp;
+    static constexpr int E = 16 / sizeof(in_t);
+    static constexpr int kOp = SKEL_SUM;
+};
+
+template <class P>
+struct CompSrc {
+    using acc_t = Comp;
+    using in_t = typename P::in_t;
+    static constexpr int E = P::E;
+    struct Vec {
+        in_t a[E];
+    };
+    const in_t* x;
+    __device__ __forceinline__ void load(int64_t vi, Vec& v) const { load16_nt(x + vi * E, v.a); }
+    __device__ __forceinline__ void accum(const Vec& v, Comp& acc) const {
+#pragma unroll
+        for (int e = 0; e < E; ++e) acc = comp_add(acc, widen<float>(v.a[e]));
+    }
+    __device__ __forceinline__ Comp at(int64_t i) const { return {widen<float>(x[i]), 0.0f}; }
+};
+
+// f(x, y) added with compensation; products (MUL, SQUARE) add their exact
+// rounding error as well
+template <int MOP>
+__device__ __forceinline__ Comp comp_add_mapped(Comp acc, float xv, float yv, float p0,
+                                                float p1) {
+#pragma clang fp contract(off)
+    if constexpr (MOP == SKEL_MAP_MUL || MOP == SKEL_MAP_SQUARE) {
+        const float b = MOP == SKEL_MAP_MUL ? yv : xv;
+        const float p = xv * b;
+        const float err = __builtin_fmaf(xv, b, -p);  // x*b - p exactly
+        acc = comp_add(acc, p);
+        acc.c += err;
+        return acc;
+    } else {
+        return comp_add(acc, fmap<MOP>(xv, yv, p0, p1));
+    }
+}
+
+template <class P, int MOP>
+struct CompMapSrc {
+    using acc_t = Comp;
+    using in_t = typename P::in_t;
+    static constexpr int E = P::E;
+    struct Vec {
+        in_t a[E], b[E];
+    };
+    const in_t* x;
+    const in_t* y;
+    float p0, p1;
+    __device__ __forceinline__ void load(int64_t vi, Vec& v) const {
+        load16_nt(x + vi * E, v.a);
+        if constexpr (two_inputs<MOP>()) load16_nt(y + vi * E, v.b);
+    }
+    __device__ __forceinline__ void accum(const Vec& v, Comp& acc) const {
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+            acc = comp_add_mapped<MOP>(acc, widen<float>(v.a[e]),
+                                       two_inputs<MOP>() ? widen<float>(v.b[e]) : 0.0f, p0,
+                                       p1);
+    }
+    __device__ __forceinline__ Comp at(int64_t i) const {
+        return comp_add_mapped<MOP>(CombComp::id(), widen<float>(x[i]),
+                                    two_inputs<MOP>() ? widen<float>(y[i]) : 0.0f, p0, p1);
+    }
+};
+
 // One lane's share of workgroup `blk` of `nblk`: the workgroup walks chunks of
 // NT * kUnroll consecutive 16-byte vectors (chunk blk, blk + nblk, ...), every
 // lane with kUnroll loads in flight; then the vectors after the last whole
@@ -177,21 +291,28 @@ __global__ __launch_bounds__(kSingleBlock) void k_finish(const typename P::acc_t
 // combines them in slot order (deterministic).  No fence is needed because a
 // slot is valid exactly when its tag says so.
 template <class P, class Src>
-__global__ __launch_bounds__(kBlock) void k_ticket(Src s, int64_t n, u64* slots,
-                                                   uint32_t epoch, u64* ticket, u64* err,
+__global__ __launch_bounds__(kBlock) void k_ticket(Src s, int64_t n, u64* slots, u64* sync,
                                                    typename P::out_t* out) {
     using acc_t = typename P::acc_t;
     __shared__ acc_t lds[kBlock / kWave];
     __shared__ int is_last;
+    __shared__ uint32_t s_epoch;
+    u64* ticket = sync + SYNC_TICKET;
+    u64* err = sync + SYNC_ERROR;
     acc_t a = thread_acc<P, kBlock>(s, n, blockIdx.x, gridDim.x);
     a = block_reduce<typename P::C>(a, lds);
     if (threadIdx.x == 0) {
+        // the epoch is read before the ticket, and advanced only by the holder
+        // of the last ticket after it has read every slot
+        const uint32_t epoch = epoch_of_call(sync);
+        s_epoch = epoch;
         tagged_put(slots + 2 * blockIdx.x, kSlotReady, epoch, a);
         const u64 t = atomicAdd(ticket, 1ull);
         is_last = (t == gridDim.x - 1) ? 1 : 0;
     }
     __syncthreads();
     if (!is_last) return;
+    const uint32_t epoch = s_epoch;
     // each lane reads its slots i = base + k * kBlock + lane with all loads in
     // flight at once; a retry re-reads only the slots not yet valid
     acc_t b = P::C::id();
@@ -227,6 +348,7 @@ __global__ __launch_bounds__(kBlock) void k_ticket(Src s, int64_t n, u64* slots,
     if (threadIdx.x == 0) {
         *out = (typename P::out_t)b;
         __hip_atomic_store(ticket, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        epoch_advance(sync);
     }
 }
 
@@ -281,6 +403,18 @@ int grid_for(int64_t n, const DevInfo& d) {
 // accumulators, rounded to 256 bytes
 size_t partial_bytes(const DevInfo& d) { return ((size_t)d.cus * 8 * 8 + 255) & ~size_t(255); }
 
+// single-pass ticket launch (R2, MR2 and the compensated forms R4, MR4)
+template <class P, class Src>
+skel_status launch_ticket(const Src& s, int64_t n, typename P::out_t* out, LaunchCtx& lc) {
+    int g = grid_for<P>(n, *lc.dev);
+    void* slots = nullptr;
+    skel_status e = ws_status(lc, (size_t)g * 16, &slots);
+    if (e != SKEL_OK) return e;
+    k_ticket<P, Src><<<(unsigned)g, kBlock, 0, lc.stream>>>(s, n, static_cast<u64*>(slots),
+                                                            lc.ws->sync, out);
+    return launch_check("reduce_ticket");
+}
+
 template <class P, class Src>
 skel_status run_variant(int v, const Src& s, int64_t n, typename P::out_t* out,
                         LaunchCtx& lc, void* partial_mem) {
@@ -302,18 +436,8 @@ skel_status run_variant(int v, const Src& s, int64_t n, typename P::out_t* out,
         k_finish<P><<<1, kSingleBlock, 0, st>>>(part, (int)g, out);
         return launch_check("reduce_finish");
     }
-    case R2_TICKET: {
-        int g = grid_for<P>(n, *lc.dev);
-        void* slots = nullptr;
-        uint32_t epoch = 0;
-        skel_status e = ws_status(lc, (size_t)g * 16, &slots, &epoch);
-        if (e != SKEL_OK) return e;
-        k_ticket<P, Src><<<(unsigned)g, kBlock, 0, st>>>(
-            s, n, static_cast<u64*>(slots), epoch, lc.ws->sync + SYNC_TICKET,
-            lc.ws->sync + SYNC_ERROR, out);
-        return launch_check("reduce_ticket");
-    }
-    default: {  // R3_ATOMIC
+    case R2_TICKET: return launch_ticket<P>(s, n, out, lc);
+    case R3_ATOMIC: {
         int g = grid_for<P>(n, *lc.dev);
         k_set_identity<P><<<1, 1, 0, st>>>(out);
         skel_status e = launch_check("reduce_set_identity");
@@ -321,12 +445,18 @@ skel_status run_variant(int v, const Src& s, int64_t n, typename P::out_t* out,
         k_atomic<P, Src><<<(unsigned)g, kBlock, 0, st>>>(s, n, out);
         return launch_check("reduce_atomic");
     }
+    default: return fail(SKEL_E_UNSUPPORTED, "reduce variant %d", v);
     }
 }
 
 template <int DIN, int DOUT, int OP>
 skel_status reduce_typed(int v, const void* x, int64_t n, void* out, LaunchCtx& lc) {
     using P = RP<DIN, DOUT, OP>;
+    if constexpr (DOUT == SKEL_F32 && OP == SKEL_SUM) if (v == R4_COMPENSATED) {
+        using PC = RPC<DIN>;
+        CompSrc<PC> cs{static_cast<const typename PC::in_t*>(x)};
+        return launch_ticket<PC>(cs, n, static_cast<float*>(out), lc);
+    }
     void* part = nullptr;
     skel_status e = ws_scratch(lc, partial_bytes(*lc.dev), &part);
     if (e != SKEL_OK) return e;
@@ -349,6 +479,11 @@ skel_status mapreduce_typed(int v, float p0, float p1, const void* x, const void
     using P = RP<DIN, SKEL_F32, OP>;
     using in_t = typename P::in_t;
     MapSrc<P, MOP> s{static_cast<const in_t*>(x), static_cast<const in_t*>(y), p0, p1};
+    if constexpr (OP == SKEL_SUM) if (v == MR4_COMPENSATED) {
+        using PC = RPC<DIN>;
+        CompMapSrc<PC, MOP> cs{static_cast<const in_t*>(x), static_cast<const in_t*>(y), p0, p1};
+        return launch_ticket<PC>(cs, n, out, lc);
+    }
     if constexpr (DIN == SKEL_F32) if (v == MR0_UNFUSED) {
         // Map into a temporary with the Map skeleton's vector kernel, then the
         // plain two-pass Reduce over the temporary
@@ -372,7 +507,9 @@ skel_status mapreduce_typed(int v, float p0, float p1, const void* x, const void
     if (e != SKEL_OK) return e;
     int rv = v == MR1_FUSED_TWO_PASS ? R1_TWO_PASS
              : v == MR2_FUSED_TICKET ? R2_TICKET
-                                     : R0_SINGLE_WG;
+             : v == MR3_FUSED_SINGLE_WG ? R0_SINGLE_WG
+                                        : -1;
+    if (rv < 0) return fail(SKEL_E_UNSUPPORTED, "mapreduce variant %d", v);
     return run_variant<P>(rv, s, n, out, lc, part);
 }
 

@@ -31,6 +31,7 @@
 // skel_sync reports, and finishes (with wrong values) instead of hanging.
 #include "kcommon.hpp"
 #include "dispatch.hpp"
+#include "kepoch.hpp"
 #include "launch.hpp"
 
 #ifndef SKEL_SCAN_WAVES
@@ -264,10 +265,11 @@ template <class P>
 __global__ __launch_bounds__(P::kBlock) void scan_lookback(const typename P::in_t* in,
                                                         typename P::out_t* out, int64_t n,
                                                         int64_t ntiles, int exclusive,
-                                                        u64* status, u64* sync,
-                                                        uint32_t epoch) {
+                                                        u64* status, u64* sync) {
     __shared__ int64_t s_tile;
+    __shared__ uint32_t s_epoch;
     if (threadIdx.x == 0) {
+        s_epoch = epoch_of_call(sync);  // before taking a tile id (see below)
         const u64 t = atomicAdd(&sync[SYNC_TILE_COUNTER], 1ull);
         if (t == (u64)ntiles - 1)  // every other tile id has been taken
             __hip_atomic_store(&sync[SYNC_TILE_COUNTER], 0ull, __ATOMIC_RELAXED,
@@ -276,10 +278,22 @@ __global__ __launch_bounds__(P::kBlock) void scan_lookback(const typename P::in_
     }
     __syncthreads();
     const int64_t tile = s_tile;
+    const uint32_t epoch = s_epoch;
     if ((tile + 1) * P::kTile <= n)
         lookback_tile<P, true>(in, out, n, tile, exclusive, status, sync, epoch);
     else
         lookback_tile<P, false>(in, out, n, tile, exclusive, status, sync, epoch);
+    // The workgroup that finishes last (every other one has passed its last
+    // descriptor access) resets the counter and advances the epoch for the
+    // next call.
+    if (threadIdx.x == 0) {
+        const u64 d = atomicAdd(&sync[SYNC_DONE], 1ull);
+        if (d == (u64)ntiles - 1) {
+            __hip_atomic_store(&sync[SYNC_DONE], 0ull, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+            epoch_advance(sync);
+        }
+    }
 }
 
 // S1 pass 1: tile totals
@@ -417,11 +431,10 @@ skel_status scan_typed(int v, int kind, const void* x, void* y, int64_t n, Launc
     }
     default: {  // S2_LOOKBACK
         void* status = nullptr;
-        uint32_t epoch = 0;
-        skel_status e = ws_status(lc, (size_t)ntiles * 16, &status, &epoch);
+        skel_status e = ws_status(lc, (size_t)ntiles * 16, &status);
         if (e != SKEL_OK) return e;
         scan_lookback<P><<<(unsigned)ntiles, P::kBlock, 0, st>>>(
-            in, out, n, ntiles, excl, static_cast<u64*>(status), lc.ws->sync, epoch);
+            in, out, n, ntiles, excl, static_cast<u64*>(status), lc.ws->sync);
         return launch_check("scan_lookback");
     }
     }

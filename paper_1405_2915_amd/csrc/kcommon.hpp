@@ -101,12 +101,19 @@ __device__ __forceinline__ uint64_t widen<uint64_t, int32_t>(int32_t v) {
 }
 
 // ------------------------------------------------------- wave primitives --
+// lane exchange; accumulator types made of several words provide their own
+// overload, found by argument-dependent lookup
+template <class T>
+__device__ __forceinline__ T xshfl(T v, int o) {
+    return __shfl_xor(v, o);
+}
+
 // 64-lane butterfly reduction: every lane ends with the full result, combined
 // in a fixed order (deterministic for a fixed launch shape).
 template <class C, class T>
 __device__ __forceinline__ T wave_reduce(T v) {
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = C::op(v, __shfl_xor(v, o));
+    for (int o = 32; o > 0; o >>= 1) v = C::op(v, xshfl(v, o));
     return v;
 }
 

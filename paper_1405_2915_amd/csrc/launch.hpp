@@ -18,10 +18,12 @@ struct DevInfo {
 };
 
 // Per-stream device scratch.  `sync` is a small persistent area that is zero
-// when allocated and that kernels keep zero between calls (each ticket or tile
-// counter is reset by the workgroup that takes its last value); `status` holds
-// the decoupled look-back tile descriptors, tagged with `epoch` so they never
-// need clearing between calls.
+// when allocated and that kernels keep consistent between calls: each ticket
+// or counter is reset by the workgroup that takes its last value, and the
+// descriptor epoch is advanced on the device by the last workgroup of each
+// call that uses `status` (so calls captured in a graph replay correctly).
+// `status` holds self-validating descriptors tagged with that epoch, so it
+// never needs clearing between calls.
 struct Workspace {
     void* stream = nullptr;
     void* scratch = nullptr;
@@ -29,16 +31,25 @@ struct Workspace {
     unsigned long long* sync = nullptr;
     void* status = nullptr;
     size_t status_bytes = 0;
-    uint32_t epoch = 0;
+    uint64_t epoch_calls = 0;  // calls that advanced the device epoch since its last reset
+    void* counters = nullptr;  // zero when allocated; every user resets what it counts
+    size_t counters_bytes = 0;
 };
 
-// slots of the sync area (64-bit words)
+// slots of the sync area, as indices of 64-bit words; each slot has its own
+// 128-byte cache line, because every workgroup of a call hits some of them
+// atomically and sharing a line serialises those accesses
 enum SyncSlot {
-    SYNC_TICKET = 0,      // reduce / mapreduce "last workgroup" ticket
-    SYNC_TILE_COUNTER = 1,  // scan dynamic tile id counter
-    SYNC_ERROR = 2,       // nonzero: a kernel's bounded wait expired
-    SYNC_SLOTS = 64
+    SYNC_TICKET = 0,         // reduce / mapreduce "last workgroup" ticket
+    SYNC_TILE_COUNTER = 16,  // scan dynamic tile id counter
+    SYNC_ERROR = 32,         // nonzero: a kernel's bounded wait expired
+    SYNC_EPOCH = 48,         // descriptor epoch - 1 (0 when allocated)
+    SYNC_DONE = 64,          // finished-workgroup counter
+    SYNC_SLOTS = 128
 };
+
+// descriptor epochs run 1 .. kEpochMax (30 bits, never 0)
+constexpr uint32_t kEpochMax = (1u << 30) - 1;
 
 struct LaunchCtx {
     hipStream_t stream;
@@ -50,8 +61,13 @@ struct LaunchCtx {
 const DevInfo& device_info();
 skel_status workspace_for(void* stream, Workspace** out);
 skel_status ws_scratch(LaunchCtx& lc, size_t bytes, void** p);
-// status array of at least `bytes`, and a fresh nonzero epoch for one call
-skel_status ws_status(LaunchCtx& lc, size_t bytes, void** p, uint32_t* epoch);
+void retire(Workspace* w, void* p);  // free at skel_finalize, not before
+// zero-initialised counter array of at least `bytes` (kernels leave it zero)
+skel_status ws_counters(LaunchCtx& lc, size_t bytes, void** p);
+// descriptor array of at least `bytes` for one call that advances the device
+// epoch; fails with SKEL_E_STATE if the array would have to grow (or be
+// cleared) while the stream is being captured into a graph
+skel_status ws_status(LaunchCtx& lc, size_t bytes, void** p);
 skel_status hip_check(hipError_t e, const char* what);
 skel_status launch_check(const char* kernel);
 
@@ -70,6 +86,9 @@ skel_status launch_overlap2d(int variant, const float* x, float* out,
                              int64_t rows, int64_t cols, const float* w2d,
                              const float* wy, const float* wx, int ry, int rx,
                              int edge, float pad, LaunchCtx& lc);
+skel_status launch_reduce_segments(int variant, int op, const float* x, int64_t n,
+                                   const int64_t* off_dev, const int64_t* off_host,
+                                   int64_t nseg, float* out, LaunchCtx& lc);
 skel_status launch_scan(int variant, int kind, int op, skel_dtype din,
                         skel_dtype dout, const void* x, void* out, int64_t n,
                         LaunchCtx& lc);

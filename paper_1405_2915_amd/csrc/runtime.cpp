@@ -6,6 +6,7 @@
 #include <cstring>
 #include <mutex>
 #include <unordered_map>
+#include <vector>
 
 #include "common.hpp"
 #include "dispatch.hpp"
@@ -105,15 +106,26 @@ DevInfo g_dev;
 std::mutex g_ws_mu;
 std::unordered_map<void*, Workspace*> g_ws;
 
+// Superseded workspace buffers, kept until skel_finalize because a graph
+// captured before they were replaced may still reference them.
+std::unordered_map<Workspace*, std::vector<void*>> g_retired;
+
 void free_workspace(Workspace* w) {
     const skel_allocator& a = rt().allocator;
     dev_mfree(a, w->scratch, w->stream);
     dev_mfree(a, w->sync, w->stream);
     dev_mfree(a, w->status, w->stream);
+    dev_mfree(a, w->counters, w->stream);
+    for (void* p : g_retired[w]) dev_mfree(a, p, w->stream);
+    g_retired.erase(w);
     delete w;
 }
 
 }  // namespace
+
+void retire(Workspace* w, void* p) {
+    if (p) g_retired[w].push_back(p);
+}
 
 const DevInfo& device_info() { return g_dev; }
 
@@ -125,6 +137,15 @@ skel_status workspace_for(void* stream, Workspace** out) {
         *out = it->second;
         return SKEL_OK;
     }
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(S(stream), &cs) != hipSuccess) {
+        (void)hipGetLastError();
+        cs = hipStreamCaptureStatusNone;
+    }
+    if (cs != hipStreamCaptureStatusNone)
+        return fail(SKEL_E_STATE,
+                    "first use of this stream is inside a graph capture; run a call on the "
+                    "stream once before capturing (its workspace is cleared by a fill)");
     auto* w = new Workspace();
     w->stream = stream;
     size_t sb = SYNC_SLOTS * sizeof(unsigned long long);
@@ -146,9 +167,18 @@ skel_status workspace_for(void* stream, Workspace** out) {
 skel_status ws_scratch(LaunchCtx& lc, size_t bytes, void** p) {
     Workspace* w = lc.ws;
     if (w->scratch_bytes < bytes) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(lc.stream, &cs) != hipSuccess) {
+            (void)hipGetLastError();
+            cs = hipStreamCaptureStatusNone;
+        }
+        if (cs != hipStreamCaptureStatusNone)
+            return fail(SKEL_E_STATE,
+                        "the scratch workspace must grow to %zu bytes while the stream is "
+                        "captured; run the same call once before capture", bytes);
         size_t want = bytes < (size_t(1) << 20) ? (size_t(1) << 20) : bytes;
         want = (want + 4095) & ~size_t(4095);
-        dev_mfree(rt().allocator, w->scratch, w->stream);
+        retire(w, w->scratch);  // a graph captured earlier may still use it
         w->scratch = nullptr;
         w->scratch_bytes = 0;
         void* q = dev_malloc(rt().allocator, want, w->stream);
@@ -160,35 +190,74 @@ skel_status ws_scratch(LaunchCtx& lc, size_t bytes, void** p) {
     return SKEL_OK;
 }
 
-skel_status ws_status(LaunchCtx& lc, size_t bytes, void** p, uint32_t* epoch) {
+skel_status ws_counters(LaunchCtx& lc, size_t bytes, void** p) {
     Workspace* w = lc.ws;
-    const uint32_t kMaxEpoch = (1u << 30) - 1;
-    if (w->status_bytes < bytes) {
-        size_t want = bytes < (size_t(1) << 16) ? (size_t(1) << 16) : bytes;
-        want = (want + 4095) & ~size_t(4095);
-        dev_mfree(rt().allocator, w->status, w->stream);
-        w->status = nullptr;
-        w->status_bytes = 0;
+    if (w->counters_bytes < bytes) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(lc.stream, &cs) != hipSuccess) {
+            (void)hipGetLastError();
+            cs = hipStreamCaptureStatusNone;
+        }
+        if (cs != hipStreamCaptureStatusNone)
+            return fail(SKEL_E_STATE,
+                        "the counter workspace must grow while the stream is captured; run "
+                        "the same call once before capture");
+        size_t want = bytes < 4096 ? 4096 : ((bytes + 4095) & ~size_t(4095));
         void* q = dev_malloc(rt().allocator, want, w->stream);
-        if (!q) return fail(SKEL_E_NOMEM, "status allocation of %zu bytes failed", want);
+        if (!q) return fail(SKEL_E_NOMEM, "counter allocation of %zu bytes failed", want);
         skel_status st = hip_check(hipMemsetAsync(q, 0, want, lc.stream), "hipMemsetAsync");
         if (st != SKEL_OK) {
             dev_mfree(rt().allocator, q, w->stream);
             return st;
         }
+        retire(w, w->counters);
+        w->counters = q;
+        w->counters_bytes = want;
+    }
+    *p = w->counters;
+    return SKEL_OK;
+}
+
+skel_status ws_status(LaunchCtx& lc, size_t bytes, void** p) {
+    Workspace* w = lc.ws;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(lc.stream, &cs) != hipSuccess) {
+        (void)hipGetLastError();
+        cs = hipStreamCaptureStatusNone;
+    }
+    const bool capturing = cs != hipStreamCaptureStatusNone;
+    // Growing the array, or clearing it before the device epoch can wrap onto
+    // words of an earlier cycle, resets the epoch; both enqueue fills, which
+    // must not happen inside a captured graph.
+    const bool grow = w->status_bytes < bytes;
+    const bool wrap = w->epoch_calls >= (uint64_t)kEpochMax - 1;
+    if ((grow || wrap) && capturing)
+        return fail(SKEL_E_STATE,
+                    "the descriptor workspace must be %s while the stream is captured; "
+                    "run the same call once before capture",
+                    grow ? "enlarged" : "reset");
+    if (grow) {
+        size_t want = bytes < (size_t(1) << 16) ? (size_t(1) << 16) : bytes;
+        want = (want + 4095) & ~size_t(4095);
+        retire(w, w->status);  // a graph captured earlier may still use it
+        w->status = nullptr;
+        w->status_bytes = 0;
+        void* q = dev_malloc(rt().allocator, want, w->stream);
+        if (!q) return fail(SKEL_E_NOMEM, "status allocation of %zu bytes failed", want);
         w->status = q;
         w->status_bytes = want;
-        w->epoch = 0;
     }
-    if (w->epoch >= kMaxEpoch) {
+    if (grow || wrap) {
         skel_status st = hip_check(hipMemsetAsync(w->status, 0, w->status_bytes, lc.stream),
                                    "hipMemsetAsync");
+        if (st == SKEL_OK)
+            st = hip_check(hipMemsetAsync(w->sync + SYNC_EPOCH, 0, 8, lc.stream),
+                           "hipMemsetAsync");
         if (st != SKEL_OK) return st;
-        w->epoch = 0;
+        w->epoch_calls = 0;
     }
-    w->epoch += 1;
+    w->epoch_calls += 1;
     *p = w->status;
-    *epoch = w->epoch;
     return SKEL_OK;
 }
 

@@ -7,6 +7,7 @@
 // waits: results stay on the device until a host acquire.
 #include <cmath>
 #include <cstring>
+#include <vector>
 
 #include "container.hpp"
 #include "dispatch.hpp"
@@ -320,6 +321,55 @@ skel_status skel_mapoverlap2d(skel_container* in, skel_container* out, const flo
         return launch_overlap2d(v, (const float*)ops.ptr(in), (float*)ops.ptr(out),
                                 in->rows, in->cols, w2d, w2d ? nullptr : wy,
                                 w2d ? nullptr : wx, ry, rx, edge, pad, lc);
+    });
+}
+
+skel_status skel_reduce_segments(skel_reduce_op op, skel_container* in,
+                                 skel_container* offsets, skel_container* out, int variant,
+                                 void* stream) {
+    LaunchCtx lc;
+    skel_status st = begin(stream, &lc);
+    if (st != SKEL_OK) return st;
+    if (!reduce_op_valid(op)) return fail(SKEL_E_INVAL, "unknown reduce op %d", (int)op);
+    if (!in || !offsets || !out) return fail(SKEL_E_INVAL, "null container");
+    if (in == out || in == offsets || offsets == out)
+        return fail(SKEL_E_INVAL, "segmented Reduce operands must be distinct containers");
+    if (in->dtype != SKEL_F32 || out->dtype != SKEL_F32 || offsets->dtype != SKEL_I64)
+        return fail(SKEL_E_DTYPE, "segmented Reduce takes f32 values, i64 offsets, f32 out");
+    if (offsets->n != out->n + 1)
+        return fail(SKEL_E_SHAPE, "offsets must hold one more element than out");
+    CallContext cc;
+    cc.skeleton = SKEL_SK_REDUCE_SEGMENTS;
+    cc.n = in->n;
+    cc.op = op;
+    int v = choose_variant(variant, cc, &st);
+    if (v < 0) return st;
+    const int64_t nseg = out->n;
+    std::vector<int64_t> off_host;
+    if (v == B0_PER_SEGMENT && nseg > 0) {
+        // the per-segment loop reads the offsets on the host (lazily copied)
+        void* hp = nullptr;
+        st = acquire(offsets, SKEL_HOST, SKEL_READ, stream, &hp);
+        if (st != SKEL_OK) return st;
+        const int64_t* o = static_cast<const int64_t*>(hp);
+        off_host.assign(o, o + nseg + 1);
+        release(offsets, SKEL_HOST, stream);
+        for (int64_t s = 0; s < nseg; ++s)
+            if (off_host[s] < 0 || off_host[s + 1] < off_host[s] || off_host[s + 1] > in->n)
+                return fail(SKEL_E_INVAL, "offsets[%lld..%lld] = %lld, %lld not within [0, %lld]"
+                            " and nondecreasing", (long long)s, (long long)s + 1,
+                            (long long)off_host[s], (long long)off_host[s + 1], (long long)in->n);
+    }
+    Operands ops;
+    ops.add(in, SKEL_READ);
+    ops.add(offsets, SKEL_READ);
+    ops.add(out, SKEL_WRITE);
+    return run(ops, stream, lc, [&]() -> skel_status {
+        if (nseg == 0) return SKEL_OK;
+        return launch_reduce_segments(v, op, (const float*)ops.ptr(in), in->n,
+                                      (const int64_t*)ops.ptr(offsets),
+                                      off_host.empty() ? nullptr : off_host.data(), nseg,
+                                      (float*)ops.ptr(out), lc);
     });
 }
 

@@ -304,7 +304,7 @@ def test_create_validation(rt):
 
 # ------------------------------------------------------------ execution plan
 
-SK_MAP, SK_REDUCE, SK_MAPREDUCE, SK_OV1, SK_OV2, SK_SCAN = range(6)
+SK_MAP, SK_REDUCE, SK_MAPREDUCE, SK_OV1, SK_OV2, SK_SCAN, SK_SEG = range(7)
 
 
 def name_of(lib, sk, v):
@@ -313,7 +313,8 @@ def name_of(lib, sk, v):
 
 
 def test_variant_registry(rt):
-    want = {SK_MAP: 3, SK_REDUCE: 4, SK_MAPREDUCE: 4, SK_OV1: 3, SK_OV2: 4, SK_SCAN: 3}
+    want = {SK_MAP: 3, SK_REDUCE: 5, SK_MAPREDUCE: 5, SK_OV1: 3, SK_OV2: 4, SK_SCAN: 3,
+            SK_SEG: 2}
     for sk, k in want.items():
         assert rt.skel_variant_count(sk) == k
         names = [name_of(rt, sk, v) for v in range(k)]
@@ -367,6 +368,13 @@ def test_environment_override(rt, monkeypatch):
         == "R1_two_pass"
     monkeypatch.setenv("SKEL_VARIANT_REDUCE", "3")
     assert rt.skel_select_variant(SK_REDUCE, F32, 100, 1, 100, 0) == 3
+    # the compensated variant is floating-point SUM only: an integer call
+    # falls through to the static rule
+    monkeypatch.setenv("SKEL_VARIANT_REDUCE", "R4_compensated")
+    assert rt.skel_select_variant(SK_REDUCE, F32, 100, 1, 100, 0) == 4
+    assert rt.skel_select_variant(SK_REDUCE, BF16, 100, 1, 100, 0) == 4
+    assert name_of(rt, SK_REDUCE, rt.skel_select_variant(SK_REDUCE, I32, 100, 1, 100, 0)) \
+        == "R0_single_wg"
     monkeypatch.setenv("SKEL_VARIANT_MAPOVERLAP2D", "O2c_lds_separable")
     # override not selectable (weights not separable): falls through
     assert name_of(rt, SK_OV2, rt.skel_select_variant(SK_OV2, F32, 100, 10, 10, 0)) \

@@ -118,7 +118,9 @@ def test_cross_stream_dependence(skel):
 def test_variant_names_and_plan(skel):
     names = {sk: [skel.skel_variant_name(sk, v) for v in range(skel.skel_variant_count(sk))]
              for sk in range(6)}
-    assert names[skel.SK_REDUCE] == ["R0_single_wg", "R1_two_pass", "R2_ticket", "R3_atomic"]
+    assert names[skel.SK_REDUCE] == ["R0_single_wg", "R1_two_pass", "R2_ticket", "R3_atomic",
+                                     "R4_compensated"]
+    assert names[skel.SK_MAPREDUCE][4] == "MR4_compensated"
     assert names[skel.SK_SCAN][2] == "S2_decoupled_lookback"
     assert skel.skel_select_variant(skel.SK_SCAN, skel.I32, 1 << 27) == 2
 

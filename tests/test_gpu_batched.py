@@ -1,0 +1,135 @@
+"""Batching: segmented Reduce over many uneven vectors in one persistent
+launch, and chains of skeleton calls captured in a graph and replayed.
+
+Segment lengths follow the batched workload: floor(exp(U[ln 32, ln 2^20])),
+values N(0, 1); parity against the oracle's per-segment binary64 Reduce with
+|r - r*| <= 1e-5 * sum |x| of the segment (MIN / MAX exact).
+"""
+import numpy as np
+import pytest
+
+import synth_inputs as si
+
+pytestmark = pytest.mark.gpu
+
+RED_OPS = {"sum": 0, "min": 1, "max": 2}
+
+
+def check_segments(skel, oracle_mod, x, off, op, variant):
+    out = skel.Container.empty(skel.F32, off.size - 1)
+    skel.skel_reduce_segments(RED_OPS[op], skel.Container.from_numpy(x),
+                              skel.Container.from_numpy(off), out, variant=variant)
+    got = out.to_numpy().astype(np.float64)
+    ref = oracle_mod.reduce_segments(op, x, off)
+    if op == "sum":
+        mag = oracle_mod.reduce_segments("sum", np.abs(x), off)
+        bad = np.abs(got - ref) > 1e-5 * mag + 1e-30
+    else:
+        bad = got != ref
+    assert not bad.any(), (op, variant, np.flatnonzero(bad)[:5])
+
+
+@pytest.mark.parametrize("op", list(RED_OPS))
+def test_segments_small_and_edge_cases(skel, oracle_mod, op):
+    x = si.normal_f32(200003, 2, 0)
+    cases = [
+        np.array([0, x.size], np.int64),                      # one segment
+        np.array([0, 0, 0], np.int64),                        # only empty segments
+        np.array([0, 1, 2, 3, 16387, 16387, 50000, 200003], np.int64),  # mixed, ragged
+        np.array([0, 16384, 32768, 32769, 200003], np.int64),  # chunk boundaries
+        np.array([5, 9, 17], np.int64),                       # not starting at 0, unaligned
+    ]
+    for off in cases:
+        for v in range(skel.skel_variant_count(skel.SK_REDUCE_SEGMENTS)):
+            check_segments(skel, oracle_mod, x, off, op, v)
+    skel.skel_sync()
+
+
+def test_segments_log_uniform_batch(skel, oracle_mod):
+    lens = si.log_uniform_lengths(512, 32, 1 << 20, config=2, index=10)
+    off = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    x = si.normal_f32(int(off[-1]), 2, 11)
+    for v in (0, 1):
+        check_segments(skel, oracle_mod, x, off, "sum", v)
+    # repeated calls reuse the counters and slots (fresh epoch per call)
+    for k in range(3):
+        check_segments(skel, oracle_mod, x, off, "max", 1)
+    skel.skel_sync()
+
+
+def test_segments_reject_bad_offsets(skel):
+    x = skel.Container.from_numpy(np.ones(1000, np.float32))
+    bad = skel.Container.from_numpy(np.array([0, 600, 500, 1000], np.int64))
+    out = skel.Container.empty(skel.F32, 3)
+    with pytest.raises(skel.SkelError) as e:
+        skel.skel_reduce_segments(skel.SUM, x, bad, out, variant=0)
+    assert e.value.status == skel.E_INVAL
+    # the persistent variant checks on the device: no work, flag at sync
+    skel.skel_reduce_segments(skel.SUM, x, bad, out, variant=1)
+    with pytest.raises(skel.SkelError) as e:
+        skel.skel_sync()
+    assert e.value.status == skel.E_TIMEOUT and "flag 0x4" in str(e.value)
+    skel.skel_sync()  # the flag was cleared
+    # and the next good call is unaffected
+    good = skel.Container.from_numpy(np.array([0, 500, 600, 1000], np.int64))
+    skel.skel_reduce_segments(skel.SUM, x, good, out, variant=1)
+    assert out.to_numpy().tolist() == [500.0, 100.0, 400.0]
+    with pytest.raises(skel.SkelError) as e:
+        skel.skel_reduce_segments(skel.SUM, x, good, skel.Container.empty(skel.F32, 2))
+    assert e.value.status == skel.E_SHAPE
+
+
+def test_graph_capture_replays(skel, oracle_mod):
+    """A chain Map -> MapReduce -> Scan captured once and replayed with new
+    inputs between replays; every replay is checked against the oracle.  The
+    look-back scan and the ticket reduction hand values between workgroups
+    through epoch-tagged words, so a replay that reused the previous replay's
+    epoch would read stale descriptors: the changing inputs catch that."""
+    import torch
+    n = (1 << 20) + 5
+    x0 = si.normal_f32(n, 5, 0)
+    y = si.normal_f32(n, 5, 1)
+    ci = si.int_uniform_i32(n, 1000, 5, 2)
+    cx, cy = skel.Container.from_numpy(x0), skel.Container.from_numpy(y)
+    cz = skel.Container.empty(skel.F32, n)
+    r = skel.Container.empty(skel.F32, 1)
+    csi = skel.Container.from_numpy(ci)
+    cso = skel.Container.empty(skel.I64, n)
+    stream = torch.cuda.Stream()
+
+    def chain():
+        skel.skel_map(skel.MAP_AFFINE, [2.0, 1.0], [cx], cz, stream=stream)
+        skel.skel_mapreduce(skel.MAP_MUL, None, [cz, cy], skel.SUM, r, variant=2,
+                            stream=stream)
+        skel.skel_scan(csi, cso, skel.EXCLUSIVE, skel.SUM, variant=2, stream=stream)
+
+    with torch.cuda.stream(stream):
+        chain()  # outside capture: sizes workspaces, makes device copies valid
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=stream):
+            chain()
+    torch.cuda.synchronize()
+    for rep in range(4):
+        xk = si.normal_f32(n, 6, rep)
+        ik = si.int_uniform_i32(n, 1000, 6, 10 + rep)
+        cx.write_numpy(xk)
+        csi.write_numpy(ik)
+        for c in (cx, csi):  # eager device reads make the new data resident
+            skel.skel_container_acquire(c, skel.DEVICE, skel.READ, stream)
+            skel.skel_container_release(c, skel.DEVICE, stream)
+        # eager work of the same kinds between replays
+        tmp = skel.Container.empty(skel.I64, n)
+        skel.skel_scan(csi, tmp, skel.INCLUSIVE, skel.SUM, variant=2, stream=stream)
+        with torch.cuda.stream(stream):
+            g.replay()
+        for c in (cz, r, cso):
+            c.mark_device_written(stream)
+        zref = oracle_mod.map_f32("affine", [2.0, 1.0], xk).astype(np.float32)
+        ref, mag = oracle_mod.mapreduce("mul", None, zref, y)
+        assert abs(float(r.to_numpy()[0]) - ref) <= 1e-5 * mag, rep
+        assert np.array_equal(cso.to_numpy(), oracle_mod.scan(ik, "exclusive", "sum",
+                                                              np.int64)), rep
+        assert np.array_equal(tmp.to_numpy(), oracle_mod.scan(ik, "inclusive", "sum",
+                                                              np.int64)), rep
+    skel.skel_sync(stream)

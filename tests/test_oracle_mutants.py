@@ -48,6 +48,11 @@ MUTANTS = [
      "for (int64_t i = 0; i < n; ++i) acc = (uint32_t)(acc + (uint64_t)(int64_t)x[i]);", 0),
     ("min_is_max", "if (op == ORC_MIN) acc = v < acc ? v : acc;",
      "if (op == ORC_MIN) acc = v > acc ? v : acc;", 0),
+    ("fsum_drops_low_parts", "if (lo != 0.0) m->p[i++] = lo;", "(void)lo;", 0),
+    ("fsum_no_halfway_fix", "if (y == x - hi) hi = x;", "(void)x;", 0),
+    ("segments_drop_last", "out[s] = oracle_reduce_f32(op, x + off[s], off[s + 1] - off[s]);",
+     "out[s] = oracle_reduce_f32(op, x + off[s], off[s + 1] - off[s] - (off[s + 1] > off[s]));",
+     0),
 ]
 
 

@@ -204,6 +204,59 @@ def test_reduce_fsum_and_bruteforce(oracle_mod):
         assert oracle_mod.reduce("sum", xl) == ((t + 2 ** 63) % 2 ** 64) - 2 ** 63
 
 
+def test_reduce_segments_pins(oracle_mod):
+    # segments of 0..n-1: each sum is the closed form of an arithmetic range
+    n = 100000
+    x = np.arange(n, dtype=np.float32)
+    off = np.array([0, 0, 1, 17, 17, 5000, 65536, n], np.int64)
+    out = oracle_mod.reduce_segments("sum", x, off)
+    for s in range(off.size - 1):
+        a, b = int(off[s]), int(off[s + 1])
+        assert out[s] == (b * (b - 1) - a * (a - 1)) // 2  # sum of a..b-1
+    # empty segments give the identity of each operator
+    assert out[0] == 0 and out[3] == 0
+    mn = oracle_mod.reduce_segments("min", x, off)
+    assert mn[0] == math.inf and mn[2] == 1.0 and mn[4] == 17.0
+    mx = oracle_mod.reduce_segments("max", x, off)
+    assert mx[0] == -math.inf and mx[-1] == n - 1
+    # one segment over everything is the plain Reduce
+    y = si.normal_f32(4097, 2, 7)
+    assert oracle_mod.reduce_segments("sum", y, [0, 4097])[0] == oracle_mod.reduce("sum", y)
+    with pytest.raises(ValueError):
+        oracle_mod.reduce_segments("sum", y, [0, 10, 5, 4097])
+    with pytest.raises(ValueError):
+        oracle_mod.reduce_segments("sum", y, [0, 4098])
+
+
+def test_exact_sums_pins(oracle_mod):
+    # the exactly rounded sum equals Python's math.fsum (the same published
+    # algorithm, independently implemented) on hard inputs
+    g = si.rng(12, 0)
+    for trial in range(20):
+        x = g.standard_normal(500) * np.exp(g.uniform(-60, 60, 500))
+        x = np.concatenate([x, -x[: 200] * (1 + 2.0 ** -50)])
+        g.shuffle(x)
+        assert oracle_mod.fsum(x) == math.fsum(x.tolist())
+    # exact cancellation, and a half-way case plain summation gets wrong
+    assert oracle_mod.fsum([1e16, 1.0, -1e16]) == 1.0
+    assert oracle_mod.fsum([1.0, 2.0 ** -53, 2.0 ** -106]) == 1.0 + 2.0 ** -52
+    assert oracle_mod.fsum([]) == 0.0
+    # bf16 sums: values on a 2^-17 grid below 2^10 sum exactly as scaled
+    # integers, so the exact sum is known independently
+    bits = si.log_uniform_signed_bf16(200000, config=4, index=3)
+    vals = si.bf16_bits_to_f32(bits).astype(np.float64)
+    scaled = sum(int(v * 2 ** 17) for v in vals)
+    assert all(float(v * 2 ** 17).is_integer() for v in vals[:1000])
+    assert oracle_mod.sum_bf16_exact(bits) == scaled / 2 ** 17
+    # bf16 dot: products are exact in binary64; compare with math.fsum of them
+    b2 = si.log_uniform_signed_bf16(200000, config=4, index=4)
+    v2 = si.bf16_bits_to_f32(b2).astype(np.float64)
+    assert oracle_mod.dot_bf16_exact(bits, b2) == math.fsum((vals * v2).tolist())
+    # and it stays close to (but is not always equal to) the sequential sum
+    assert abs(oracle_mod.sum_bf16_exact(bits) - float(np.sum(vals))) <= \
+        vals.size * 2.0 ** -52 * float(np.sum(np.abs(vals)))
+
+
 # --------------------------------------------------------------- MapReduce --
 
 def test_mapreduce_identities(oracle_mod):
