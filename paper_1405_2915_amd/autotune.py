@@ -15,7 +15,10 @@ launch stream, with the 256 MiB Infinity Cache evicted before every timed call
 (by reading a 512 MiB buffer); it writes the fastest variant per
 (skeleton, dtype, log2 n) as a plan table (the text format of skel_load_plan)
 and a JSON report of every timing.  Single-workgroup variants are not timed
-above 2^22 elements (they use one CU of 256).
+above 2^22 elements (they use one CU of 256).  The atomic-finish Reduce (R3),
+whose floating-point result depends on the order the workgroups finish in, is
+left out of the plan unless --allow-order-dependent is given: a tuned plan
+keeps every automatic call deterministic.
 """
 from __future__ import annotations
 
@@ -49,7 +52,10 @@ def _timed(torch, fn, evict, reps):
     return float(np.median(times))
 
 
-def tune(lo=10, hi=28, reps=7, log=print):
+ORDER_DEPENDENT = {"R3_atomic"}
+
+
+def tune(lo=10, hi=28, reps=7, log=print, allow_order_dependent=False):
     import torch
 
     import paper_1405_2915_amd as skel
@@ -66,7 +72,6 @@ def tune(lo=10, hi=28, reps=7, log=print):
     evict()
     torch.cuda.synchronize()
     report = {"lo": lo, "hi": hi, "reps": reps, "unit": "us", "results": {}}
-    table = []
     single = {skel.SK_REDUCE: "R0_single_wg", skel.SK_MAPREDUCE: "MR3_fused_single_wg",
               skel.SK_SCAN: "S0_single_wg"}
     for k in range(lo, hi + 1):
@@ -87,21 +92,40 @@ def tune(lo=10, hi=28, reps=7, log=print):
             ("MAP", "f32", skel.SK_MAP):
                 lambda v: skel.skel_map(skel.MAP_AXPY, [2.5], [x, y], y, variant=v),
         }
-        for (name, dt, sk), call in cases.items():
+        for (name, _dt, sk), call in cases.items():
             res = {}
             for v in range(skel.skel_variant_count(sk)):
                 vname = skel.skel_variant_name(sk, v)
                 if vname == single.get(sk) and k > SINGLE_WG_MAX_LOG2:
                     continue
                 res[vname] = round(_timed(torch, lambda: call(v), evict, reps), 3)
-            best = min(res, key=res.get)
             report["results"].setdefault(name, {})[str(k)] = res
-            table.append((name, dt, k, best))
-            log(f"{name:10s} 2^{k:2d}: " + "  ".join(f"{a}={b:.1f}" for a, b in res.items())
-                + f"  -> {best}")
+            log(f"{name:10s} 2^{k:2d}: " + "  ".join(f"{a}={b:.1f}" for a, b in res.items()))
         for c in (x, y, s, so, out1):
             c.destroy()
-    return table, report
+    report["dtypes"] = {"REDUCE": "f32", "MAPREDUCE": "f32", "SCAN": "i32", "MAP": "f32"}
+    return plan_from_report(report, allow_order_dependent=allow_order_dependent), report
+
+
+def plan_from_report(report, tol=0.05, allow_order_dependent=False):
+    """Plan entries (skeleton, dtype, log2 n, variant) from measured times.
+
+    Sizes are visited in increasing order and the previous size's choice is
+    kept while it stays within `tol` of the fastest variant, so timing noise
+    between near-equal variants does not make the plan flip back and forth."""
+    table = []
+    for name, per_k in report["results"].items():
+        dt = report.get("dtypes", {}).get(name, "f32")
+        prev = None
+        for k in sorted(per_k, key=int):
+            res = {a: b for a, b in per_k[k].items()
+                   if allow_order_dependent or a not in ORDER_DEPENDENT}
+            best = min(res, key=res.get)
+            if prev in res and res[prev] <= (1 + tol) * res[best]:
+                best = prev
+            table.append((name, dt, int(k), best))
+            prev = best
+    return table
 
 
 def write_plan(table, path, header):
@@ -125,15 +149,28 @@ def main():
     ap.add_argument("--min", type=int, default=10)
     ap.add_argument("--max", type=int, default=28)
     ap.add_argument("--reps", type=int, default=7)
+    ap.add_argument("--allow-order-dependent", action="store_true",
+                    help="let the plan pick the atomic-finish Reduce")
+    ap.add_argument("--from-report", default=None,
+                    help="write the plan from a saved JSON report, without timing")
     args = ap.parse_args()
+    if args.from_report:
+        with open(args.from_report) as f:
+            report = json.load(f)
+        table = plan_from_report(report, allow_order_dependent=args.allow_order_dependent)
+        write_plan(table, args.out, report.get("header", []))
+        print(json.dumps({"plan": args.out, "entries": len(table)}))
+        return
     log = lambda m: print(f"[autotune] {m}", file=sys.stderr, flush=True)
-    table, report = tune(args.min, args.max, args.reps, log)
+    table, report = tune(args.min, args.max, args.reps, log, args.allow_order_dependent)
     import torch
     dev = torch.cuda.get_device_properties(0)
-    write_plan(table, args.out, [f"device: {dev.name} ({dev.gcnArchName}), "
-                                 f"{dev.multi_processor_count} CUs",
-                                 f"sizes 2^{args.min}..2^{args.max}, median of {args.reps}, "
-                                 "Infinity Cache evicted before each timed call"])
+    report["header"] = [f"device: {dev.name} ({dev.gcnArchName}), "
+                        f"{dev.multi_processor_count} CUs",
+                        f"sizes 2^{args.min}..2^{args.max}, median of {args.reps}, "
+                        "Infinity Cache evicted before each timed call; a choice is kept "
+                        "while within 5% of the fastest"]
+    write_plan(table, args.out, report["header"])
     if args.report:
         with open(args.report, "w") as f:
             json.dump(report, f, indent=1)
