@@ -289,7 +289,10 @@ __global__ __launch_bounds__(kSingleBlock) void k_finish(const typename P::acc_t
 // tagged word (two words per slot), then draws a ticket; the workgroup with
 // the last ticket waits until every slot carries this call's epoch and
 // combines them in slot order (deterministic).  No fence is needed because a
-// slot is valid exactly when its tag says so.
+// slot is valid exactly when its tag says so.  Tickets are two-level: device-
+// scope atomics on one word serialise (about 10 ns each measured on MI355X,
+// 10 us for 1024 workgroups), so workgroup b draws from first-level ticket
+// b % kSubTickets, and only the last drawer of each draws the top ticket.
 template <class P, class Src>
 __global__ __launch_bounds__(kBlock) void k_ticket(Src s, int64_t n, u64* slots, u64* sync,
                                                    typename P::out_t* out) {
@@ -307,8 +310,17 @@ __global__ __launch_bounds__(kBlock) void k_ticket(Src s, int64_t n, u64* slots,
         const uint32_t epoch = epoch_of_call(sync);
         s_epoch = epoch;
         tagged_put(slots + 2 * blockIdx.x, kSlotReady, epoch, a);
-        const u64 t = atomicAdd(ticket, 1ull);
-        is_last = (t == gridDim.x - 1) ? 1 : 0;
+        const unsigned c = blockIdx.x % kSubTickets;
+        u64* sub = sync + SYNC_SUB_TICKET + 16 * c;
+        const u64 drawers = (gridDim.x - c + kSubTickets - 1) / kSubTickets;
+        int last = 0;
+        if (atomicAdd(sub, 1ull) == drawers - 1) {
+            // every workgroup of this first-level ticket has drawn: reset it
+            __hip_atomic_store(sub, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const u64 groups = gridDim.x < (unsigned)kSubTickets ? gridDim.x : kSubTickets;
+            last = atomicAdd(ticket, 1ull) == groups - 1;
+        }
+        is_last = last;
     }
     __syncthreads();
     if (!is_last) return;

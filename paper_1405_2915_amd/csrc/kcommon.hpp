@@ -210,14 +210,25 @@ __device__ __forceinline__ void load16_nt(const T* p, T (&v)[16 / sizeof(T)]) {
     __builtin_memcpy(&v, &raw, 16);
 }
 
+// Output stores.  Which kind streams an output to HBM faster depends on the
+// access pattern and was measured per kernel on MI355X: plain vector stores
+// win where a lane keeps many stores outstanding (the scan's widening rows,
+// the 1D stencil), non-temporal ones where each lane writes a few vectors of
+// a dense chunk (Map M2, the 2D tiles).
+template <class V>
+__device__ __forceinline__ void store_vec_nt(V v, V* p) {
+    __builtin_nontemporal_store(v, p);
+}
+
+// E elements as whole 16-byte vectors, plain stores
 template <class T, int E>
-__device__ __forceinline__ void store_nt(T* p, const T (&v)[E]) {
+__device__ __forceinline__ void store_vecs(T* p, const T (&v)[E]) {
     static_assert((sizeof(T) * E) % 16 == 0, "whole 16-byte vectors only");
 #pragma unroll
     for (int k = 0; k < (int)(sizeof(T) * E / 16); ++k) {
         u32x4 raw;
         __builtin_memcpy(&raw, reinterpret_cast<const char*>(&v) + 16 * k, 16);
-        __builtin_nontemporal_store(raw, reinterpret_cast<u32x4*>(p) + k);
+        reinterpret_cast<u32x4*>(p)[k] = raw;
     }
 }
 

@@ -45,8 +45,14 @@ enum SyncSlot {
     SYNC_ERROR = 32,         // nonzero: a kernel's bounded wait expired
     SYNC_EPOCH = 48,         // descriptor epoch - 1 (0 when allocated)
     SYNC_DONE = 64,          // finished-workgroup counter
-    SYNC_SLOTS = 128
+    SYNC_SUB_TICKET = 128,   // kSubTickets first-level reduce tickets, 16 words apart
+    SYNC_SLOTS = 128 + 16 * 16
 };
+
+// first-level tickets of the single-pass reduce: workgroup b draws from
+// ticket b % kSubTickets, and the last drawer of each draws from the
+// top-level ticket, so no counter takes more than g / kSubTickets atomics
+constexpr int kSubTickets = 16;
 
 // descriptor epochs run 1 .. kEpochMax (30 bits, never 0)
 constexpr uint32_t kEpochMax = (1u << 30) - 1;
