@@ -200,6 +200,105 @@ def traffic_from_profile(name, per_launch_bytes):
     return float(m_bytes.group(1))
 
 
+def time_call(torch, fn, reps):
+    """Median kernel time (ms) of fn() from HIP events on the launch stream."""
+    st = torch.cuda.current_stream()
+    fn()
+    torch.cuda.synchronize()
+    ev = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(st)
+        fn()
+        b.record(st)
+        ev.append((a, b))
+    torch.cuda.synchronize()
+    return float(np.median([a.elapsed_time(b) for a, b in ev]))
+
+
+def batched_reduce(skel, torch):
+    """4096 float32 N(0, 1) vectors with log-uniform lengths in [32, 2^20) (about
+    4.1e8 elements): one persistent launch (B1) against one reduction launch
+    pair per vector (B0, the per-vector loop)."""
+    import synth_inputs as si
+    lens = si.log_uniform_lengths(4096, 32, 1 << 20, config=3, index=10)
+    off = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    n = int(off[-1])
+    x = skel.Container.from_numpy(si.normal_f32(n, 3, 0))
+    offs = skel.Container.from_numpy(off)
+    out = skel.Container.empty(skel.F32, len(lens))
+    res = {"segments": len(lens), "elements": n, "bytes": 4 * n + 8 * len(off)}
+    for name, reps in (("B1_persistent", 10), ("B0_per_segment", 3)):
+        v = skel.variant_index(skel.SK_REDUCE_SEGMENTS, name)
+        ms = time_call(torch, lambda: skel.skel_reduce_segments(skel.SUM, x, offs, out,
+                                                                variant=v), reps)
+        res[name] = {"us": round(ms * 1e3, 1), "GBps": round(res["bytes"] / (ms * 1e-3) / 1e9, 1)}
+    res["speedup_persistent_vs_per_segment"] = round(
+        res["B0_per_segment"]["us"] / res["B1_persistent"]["us"], 2)
+    for c in (x, offs, out):
+        c.destroy()
+    return res
+
+
+def bf16_sums(skel, torch):
+    """2^28 bfloat16 values, |x| log-uniform in [1e-3, 1e3] with random signs:
+    plain (R2 / MR2) against compensated (R4 / MR4) Reduce and dot.  Accuracy
+    against exactly rounded sums is checked by the GPU precision tests."""
+    import synth_inputs as si
+    n = 1 << 28
+    xb = skel.Container.from_numpy(si.log_uniform_signed_bf16(n, config=5, index=0), skel.BF16)
+    yb = skel.Container.from_numpy(si.log_uniform_signed_bf16(n, config=5, index=1), skel.BF16)
+    out = skel.Container.empty(skel.F32, 1)
+    res = {"elements": n}
+    for name in ("R2_ticket", "R4_compensated"):
+        v = skel.variant_index(skel.SK_REDUCE, name)
+        ms = time_call(torch, lambda: skel.skel_reduce(skel.SUM, xb, out, variant=v), 10)
+        res["reduce_" + name] = {"us": round(ms * 1e3, 1),
+                                 "GBps": round(2 * n / (ms * 1e-3) / 1e9, 1)}
+    for name in ("MR2_fused_ticket", "MR4_compensated"):
+        v = skel.variant_index(skel.SK_MAPREDUCE, name)
+        ms = time_call(torch, lambda: skel.skel_mapreduce(skel.MAP_MUL, None, [xb, yb],
+                                                          skel.SUM, out, variant=v), 10)
+        res["dot_" + name] = {"us": round(ms * 1e3, 1),
+                              "GBps": round(4 * n / (ms * 1e-3) / 1e9, 1)}
+    for c in (xb, yb, out):
+        c.destroy()
+    return res
+
+
+def graph_replay(skel, torch, wl, steps):
+    """One step captured into a HIP graph (torch.cuda.CUDAGraph) and replayed,
+    against the same step issued call by call on the same stream."""
+    calls = wl.calls()
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        for _, fn in calls:  # sizes this stream's workspace outside the capture
+            fn()
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=stream):
+            for _, fn in calls:
+                fn()
+        torch.cuda.synchronize()
+
+        def timed(body):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                body()
+            b.record(stream)
+            b.synchronize()
+            return a.elapsed_time(b) / steps, (time.perf_counter() - t0) / steps * 1e3
+
+        eager_gpu, eager_wall = timed(lambda: [fn() for _, fn in calls])
+        graph_gpu, graph_wall = timed(g.replay)
+    skel.skel_sync(stream)
+    return {"eager_ms_per_step": round(eager_gpu, 4), "graph_ms_per_step": round(graph_gpu, 4),
+            "eager_host_ms_per_step": round(eager_wall, 4),
+            "graph_host_ms_per_step": round(graph_wall, 4)}
+
+
 def cpu_baseline(wl):
     """The oracle (as it is, not tuned) over one full step on the host."""
     import oracle
@@ -232,6 +331,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-variant pass")
+    ap.add_argument("--no-next", action="store_true",
+                    help="skip the batched, bf16 and graph-replay measurements")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -315,6 +416,14 @@ def main():
         "per_skeleton": per,
         "speedup_vs_plain": speedup,
     }
+    if not args.no_next:
+        log("graph replay of one step")
+        nxt = {"graph_step": graph_replay(skel, torch, wl, max(args.steps, 5))}
+        log("batched Reduce over 4096 uneven vectors")
+        nxt["batched_reduce"] = batched_reduce(skel, torch)
+        log("bf16 plain vs compensated sums, 2^28")
+        nxt["bf16_sums"] = bf16_sums(skel, torch)
+        out["next_rows"] = nxt
     if not args.no_cpu:
         log("timing the CPU oracle on one step")
         out["cpu_baseline"] = cpu_baseline(wl)

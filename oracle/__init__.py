@@ -27,7 +27,8 @@ MAP_OPS = {"identity": 0, "axpy": 1, "affine": 2, "tanh": 3,
            "affine_tanh": 4, "mul": 5, "square": 6}
 TWO_INPUT_MAP_OPS = {"axpy", "mul"}
 REDUCE_OPS = {"sum": 0, "min": 1, "max": 2}
-SCAN_KINDS = {"inclusive": 0, "exclusive": 1}
+SCAN_KINDS = {"inclusive": 0, "exclusive": 1, "reverse_inclusive": 2,
+              "reverse_exclusive": 3}
 EDGES = {"clamp": 0, "const": 1, "cyclic": 2}
 
 _lib = None
@@ -73,6 +74,15 @@ def _load():
     lib.oracle_mapreduce_f32.argtypes = [C.c_int, vp, C.c_int, f32p, vp, I64,
                                          C.c_int, C.POINTER(C.c_double)]
     lib.oracle_mapreduce_f32.restype = C.c_double
+    lib.oracle_map_grad_f32.argtypes = [C.c_int, vp, C.c_int, f32p, vp, f32p, I64,
+                                        f64p, vp, vp, vp]
+    lib.oracle_map_grad_f32.restype = C.c_int
+    lib.oracle_mapoverlap1d_adjoint_f32.argtypes = [f32p, I64, f32p, C.c_int, C.c_int,
+                                                    f64p, vp]
+    lib.oracle_mapoverlap1d_adjoint_f32.restype = C.c_int
+    lib.oracle_mapoverlap2d_adjoint_f32.argtypes = [f32p, I64, I64, vp, vp, vp, C.c_int,
+                                                    C.c_int, C.c_int, f64p, vp]
+    lib.oracle_mapoverlap2d_adjoint_f32.restype = C.c_int
     lib.oracle_mapoverlap1d_f32.argtypes = [f32p, I64, f32p, C.c_int, C.c_int,
                                             C.c_float, f64p, vp]
     lib.oracle_mapoverlap1d_f32.restype = C.c_int
@@ -257,6 +267,58 @@ def mapoverlap2d_at(x, ry: int, rx: int, i: int, j: int, w2d=None, wy=None,
                                        EDGES[edge], pad, int(i), int(j),
                                        C.byref(mag))
     return float(v), float(mag.value)
+
+
+def map_grad(map_op: str, params, x, g, y=None):
+    """Reverse-mode derivative of Map: (dx, dy or None, dparams, dparams_mag),
+    binary64, with g = dL/d(out) of the same length as x."""
+    lib = _load()
+    x = np.ascontiguousarray(x, dtype=np.float32).reshape(-1)
+    g = np.ascontiguousarray(g, dtype=np.float32).reshape(-1)
+    assert g.size == x.size
+    two = map_op in TWO_INPUT_MAP_OPS
+    if two:
+        y = np.ascontiguousarray(y, dtype=np.float32).reshape(-1)
+        assert y.size == x.size
+    p, np_ = _params(params)
+    dx = np.empty(x.size, dtype=np.float64)
+    dy = np.empty(x.size, dtype=np.float64) if two else None
+    dp = np.zeros(max(np_, 1), dtype=np.float64)
+    dpm = np.zeros(max(np_, 1), dtype=np.float64)
+    rc = lib.oracle_map_grad_f32(MAP_OPS[map_op], _ptr(p), np_, x, _ptr(y if two else None),
+                                 g, x.size, dx, _ptr(dy), _ptr(dp), _ptr(dpm))
+    if rc != 0:
+        raise ValueError("oracle map_grad: bad op/operands")
+    return dx, dy, dp[:np_], dpm[:np_]
+
+
+def mapoverlap1d_adjoint(g, w, r: int, edge: str = "clamp"):
+    """(dx, mag): the transpose of the 1D neighbourhood map applied to g."""
+    lib = _load()
+    g = np.ascontiguousarray(g, dtype=np.float32).reshape(-1)
+    w = np.ascontiguousarray(w, dtype=np.float32)
+    assert w.size == 2 * r + 1
+    dx = np.empty(g.size, dtype=np.float64)
+    mag = np.empty(g.size, dtype=np.float64)
+    if lib.oracle_mapoverlap1d_adjoint_f32(g, g.size, w, r, EDGES[edge], dx, _ptr(mag)):
+        raise ValueError("oracle mapoverlap1d_adjoint: bad arguments")
+    return dx, mag
+
+
+def mapoverlap2d_adjoint(g, ry: int, rx: int, w2d=None, wy=None, wx=None,
+                         edge: str = "clamp"):
+    """(dx, mag): the transpose of the 2D neighbourhood map applied to g."""
+    lib = _load()
+    g = np.ascontiguousarray(g, dtype=np.float32)
+    assert g.ndim == 2
+    w2d, wy, wx = _weights2d(w2d, wy, wx, ry, rx)
+    dx = np.empty(g.shape, dtype=np.float64)
+    mag = np.empty(g.shape, dtype=np.float64)
+    if lib.oracle_mapoverlap2d_adjoint_f32(g.reshape(-1), g.shape[0], g.shape[1], _ptr(w2d),
+                                           _ptr(wy), _ptr(wx), ry, rx, EDGES[edge],
+                                           dx.reshape(-1), _ptr(mag)):
+        raise ValueError("oracle mapoverlap2d_adjoint: bad arguments")
+    return dx, mag
 
 
 def scan(x, kind: str = "inclusive", op: str = "sum", out_dtype=None):

@@ -360,21 +360,37 @@ int oracle_mapoverlap2d_f32(const float *x, int64_t rows, int64_t cols,
 
 /* scan: running combination in index order (Section III, "scan").  The
  * exclusive form starts from the operator's identity. */
+/* the reverse kinds visit the same indices from the end */
+static int scan_kind_valid(int kind)
+{
+    return kind == ORC_INCLUSIVE || kind == ORC_EXCLUSIVE ||
+           kind == ORC_REVERSE_INCLUSIVE || kind == ORC_REVERSE_EXCLUSIVE;
+}
+static int scan_excludes_self(int kind)
+{
+    return kind == ORC_EXCLUSIVE || kind == ORC_REVERSE_EXCLUSIVE;
+}
+static int64_t scan_index(int kind, int64_t t, int64_t n)
+{
+    return kind >= ORC_REVERSE_INCLUSIVE ? n - 1 - t : t;
+}
+
 #define ORC_SCAN_INT(NAME, TIN, TOUT, UACC, TMIN, TMAX)                       \
     int NAME(const TIN *x, int64_t n, int kind, int op, TOUT *out)             \
     {                                                                          \
-        if (kind != ORC_INCLUSIVE && kind != ORC_EXCLUSIVE) return -1;         \
+        if (!scan_kind_valid(kind)) return -1;                                 \
         if (op != ORC_SUM && op != ORC_MIN && op != ORC_MAX) return -1;        \
         UACC sacc = 0;                                                         \
         TOUT macc = op == ORC_MIN ? TMAX : TMIN;                               \
-        for (int64_t i = 0; i < n; ++i) {                                      \
-            if (kind == ORC_EXCLUSIVE)                                         \
+        for (int64_t t = 0; t < n; ++t) {                                      \
+            const int64_t i = scan_index(kind, t, n);                          \
+            if (scan_excludes_self(kind))                                      \
                 out[i] = op == ORC_SUM ? (TOUT)sacc : macc;                    \
             TOUT v = (TOUT)x[i];                                               \
             if (op == ORC_SUM) sacc = sacc + (UACC)v;                          \
             else if (op == ORC_MIN) macc = v < macc ? v : macc;                \
             else macc = v > macc ? v : macc;                                   \
-            if (kind == ORC_INCLUSIVE)                                         \
+            if (!scan_excludes_self(kind))                                     \
                 out[i] = op == ORC_SUM ? (TOUT)sacc : macc;                    \
         }                                                                      \
         return 0;                                                              \
@@ -390,12 +406,13 @@ ORC_SCAN_INT(oracle_scan_i64_i64, int64_t, int64_t, uint64_t, INT64_MIN,
 int oracle_scan_f32(const float *x, int64_t n, int kind, int op, double *out,
                     double *mag)
 {
-    if (kind != ORC_INCLUSIVE && kind != ORC_EXCLUSIVE) return -1;
+    if (!scan_kind_valid(kind)) return -1;
     if (op != ORC_SUM && op != ORC_MIN && op != ORC_MAX) return -1;
     double acc = op == ORC_MIN ? INFINITY : (op == ORC_MAX ? -INFINITY : 0.0);
     double m = 0.0;
-    for (int64_t i = 0; i < n; ++i) {
-        if (kind == ORC_EXCLUSIVE) {
+    for (int64_t t = 0; t < n; ++t) {
+        const int64_t i = scan_index(kind, t, n);
+        if (scan_excludes_self(kind)) {
             out[i] = acc;
             if (mag) mag[i] = m;
         }
@@ -404,9 +421,126 @@ int oracle_scan_f32(const float *x, int64_t n, int kind, int op, double *out,
         else if (op == ORC_MIN) acc = v < acc ? v : acc;
         else acc = v > acc ? v : acc;
         m = m + fabs(v);
-        if (kind == ORC_INCLUSIVE) {
+        if (!scan_excludes_self(kind)) {
             out[i] = acc;
             if (mag) mag[i] = m;
+        }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------ adjoints ---- */
+
+/* partial derivatives of the element function at (x, y): df/dx, df/dy and
+ * df/dp_k, from the definitions in elem_fn */
+static void elem_partials(int op, const double *p, double x, double y, double *fx,
+                          double *fy, double *fp0, double *fp1)
+{
+    *fx = 0.0; *fy = 0.0; *fp0 = 0.0; *fp1 = 0.0;
+    switch (op) {
+    case ORC_MAP_IDENTITY: *fx = 1.0; break;
+    case ORC_MAP_AXPY: *fx = p[0]; *fy = 1.0; *fp0 = x; break;
+    case ORC_MAP_AFFINE: *fx = p[0]; *fp0 = x; *fp1 = 1.0; break;
+    case ORC_MAP_TANH: {
+        double t = tanh(x);
+        *fx = 1.0 - t * t;
+        break;
+    }
+    case ORC_MAP_AFFINE_TANH: {
+        double t = tanh(p[0] * x + p[1]);
+        double d = 1.0 - t * t; /* tanh' at the pre-activation */
+        *fx = p[0] * d;
+        *fp0 = x * d;
+        *fp1 = d;
+        break;
+    }
+    case ORC_MAP_MUL: *fx = y; *fy = x; break;
+    case ORC_MAP_SQUARE: *fx = 2.0 * x; break;
+    default: break;
+    }
+}
+
+int oracle_map_grad_f32(int op, const double *params, int nparams, const float *x,
+                        const float *y, const float *g, int64_t n, double *dx,
+                        double *dy, double *dparams, double *dparams_mag)
+{
+    double probe;
+    if (elem_fn(op, params, nparams, 0.0, 0.0, &probe) != 0) return -1;
+    if (needs_y(op) && (y == NULL || dy == NULL)) return -1;
+    double s0 = 0.0, s1 = 0.0, m0 = 0.0, m1 = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double fx, fy, fp0, fp1;
+        double xi = (double)x[i], yi = y ? (double)y[i] : 0.0, gi = (double)g[i];
+        elem_partials(op, params, xi, yi, &fx, &fy, &fp0, &fp1);
+        dx[i] = gi * fx;
+        if (needs_y(op)) dy[i] = gi * fy;
+        s0 = s0 + gi * fp0;
+        s1 = s1 + gi * fp1;
+        m0 = m0 + fabs(gi * fp0);
+        m1 = m1 + fabs(gi * fp1);
+    }
+    if (dparams) {
+        if (nparams > 0) dparams[0] = s0;
+        if (nparams > 1) dparams[1] = s1;
+    }
+    if (dparams_mag) {
+        if (nparams > 0) dparams_mag[0] = m0;
+        if (nparams > 1) dparams_mag[1] = m1;
+    }
+    return 0;
+}
+
+/* every forward term w[k] * x[e(i+k-r)] of out[i] sends w[k] * g[i] back to
+ * the element it read */
+int oracle_mapoverlap1d_adjoint_f32(const float *g, int64_t n, const float *w, int r,
+                                    int edge, double *dx, double *mag)
+{
+    if (r < 0 || w == NULL) return -1;
+    if (edge != ORC_EDGE_CLAMP && edge != ORC_EDGE_CONST &&
+        edge != ORC_EDGE_CYCLIC)
+        return -1;
+    for (int64_t j = 0; j < n; ++j) {
+        dx[j] = 0.0;
+        if (mag) mag[j] = 0.0;
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        for (int k = 0; k <= 2 * r; ++k) {
+            int64_t src;
+            if (!border_index(i + k - r, n, edge, &src)) continue; /* the pad */
+            double t = (double)w[k] * (double)g[i];
+            dx[src] = dx[src] + t;
+            if (mag) mag[src] = mag[src] + fabs(t);
+        }
+    }
+    return 0;
+}
+
+int oracle_mapoverlap2d_adjoint_f32(const float *g, int64_t rows, int64_t cols,
+                                    const float *w2d, const float *wy,
+                                    const float *wx, int ry, int rx, int edge,
+                                    double *dx, double *mag)
+{
+    if (ry < 0 || rx < 0) return -1;
+    if (w2d == NULL && (wy == NULL || wx == NULL)) return -1;
+    if (edge != ORC_EDGE_CLAMP && edge != ORC_EDGE_CONST &&
+        edge != ORC_EDGE_CYCLIC)
+        return -1;
+    for (int64_t s = 0; s < rows * cols; ++s) {
+        dx[s] = 0.0;
+        if (mag) mag[s] = 0.0;
+    }
+    for (int64_t i = 0; i < rows; ++i) {
+        for (int64_t j = 0; j < cols; ++j) {
+            for (int a = 0; a <= 2 * ry; ++a) {
+                for (int b = 0; b <= 2 * rx; ++b) {
+                    int64_t si, sj;
+                    if (!border_index(i + a - ry, rows, edge, &si)) continue;
+                    if (!border_index(j + b - rx, cols, edge, &sj)) continue;
+                    double t = weight2d(w2d, wy, wx, rx, a, b) * (double)g[i * cols + j];
+                    dx[si * cols + sj] = dx[si * cols + sj] + t;
+                    if (mag) mag[si * cols + sj] = mag[si * cols + sj] + fabs(t);
+                }
+            }
         }
     }
     return 0;

@@ -41,7 +41,10 @@ enum {
 
 /* combining operator of Reduce / Scan */
 enum { ORC_SUM = 0, ORC_MIN = 1, ORC_MAX = 2 };
-enum { ORC_INCLUSIVE = 0, ORC_EXCLUSIVE = 1 };
+/* scan kinds; the reverse forms combine from the end of the array (suffix
+ * scans), which is also the adjoint of the forward sum scans */
+enum { ORC_INCLUSIVE = 0, ORC_EXCLUSIVE = 1, ORC_REVERSE_INCLUSIVE = 2,
+       ORC_REVERSE_EXCLUSIVE = 3 };
 /* border handling of MapOverlap */
 enum { ORC_EDGE_CLAMP = 0, ORC_EDGE_CONST = 1, ORC_EDGE_CYCLIC = 2 };
 
@@ -112,6 +115,8 @@ double oracle_mapoverlap2d_at_f32(const float *x, int64_t rows, int64_t cols,
 /* Scan (prefix combination):
  *   inclusive out[i] = x[0] op ... op x[i]
  *   exclusive out[0] = identity, out[i] = x[0] op ... op x[i-1]
+ *   reverse inclusive out[i] = x[i] op ... op x[n-1]
+ *   reverse exclusive out[n-1] = identity, out[i] = x[i+1] op ... op x[n-1]
  * Return 0, or -1 for a bad op / kind. */
 int oracle_scan_i32_i32(const int32_t *x, int64_t n, int kind, int op,
                         int32_t *out);
@@ -123,6 +128,35 @@ int oracle_scan_i64_i64(const int64_t *x, int64_t n, int kind, int op,
  * over the terms of out[i] */
 int oracle_scan_f32(const float *x, int64_t n, int kind, int op, double *out,
                     double *mag);
+
+/* ------------------------------------------------------------ adjoints --
+ * Reverse-mode derivatives of the skeletons, for a scalar loss L with
+ * upstream gradient g = dL/d(out).  Each is the plain definition of the
+ * transposed linear map (or of the chain rule), evaluated in binary64. */
+
+/* Map: dx[i] = g[i] * df/dx(x[i], y[i]), dy[i] = g[i] * df/dy (only for the
+ * two-input functions; dy may be NULL otherwise), and
+ * dparams[k] = sum_i g[i] * df/dp_k (summed in index order; dparams may be
+ * NULL; it has nparams entries).  dparams_mag[k] (may be NULL) receives
+ * sum_i |g[i] * df/dp_k|.  Returns 0, or -1 for a bad op / operand. */
+int oracle_map_grad_f32(int op, const double *params, int nparams, const float *x,
+                        const float *y, const float *g, int64_t n, double *dx,
+                        double *dy, double *dparams, double *dparams_mag);
+
+/* MapOverlap 1D adjoint: the transpose of x -> out, applied to g:
+ *   dx[j] = sum over (i, k) with e(i + k - r) = j of w[k] * g[i]
+ * (a read of the constant pad contributes to no x).  mag[j] (may be NULL)
+ * receives the sum of |w[k] * g[i]| over the same terms. */
+int oracle_mapoverlap1d_adjoint_f32(const float *g, int64_t n, const float *w, int r,
+                                    int edge, double *dx, double *mag);
+
+/* MapOverlap 2D adjoint on a rows x cols image, same weights as the forward:
+ *   dx[s][t] = sum over (i, j, a, b) with e(i+a-ry) = s, e(j+b-rx) = t of
+ *              W[a][b] * g[i][j] */
+int oracle_mapoverlap2d_adjoint_f32(const float *g, int64_t rows, int64_t cols,
+                                    const float *w2d, const float *wy,
+                                    const float *wx, int ry, int rx, int edge,
+                                    double *dx, double *mag);
 
 #ifdef __cplusplus
 }

@@ -38,12 +38,25 @@ MUTANTS = [
     ("scan_identity_swapped", "TOUT macc = op == ORC_MIN ? TMAX : TMIN;",
      "TOUT macc = op == ORC_MIN ? TMIN : TMAX;", 0),
     ("scan_inclusive_is_exclusive",
-     "            if (kind == ORC_INCLUSIVE)                                         \\\n"
+     "            if (!scan_excludes_self(kind))                                     \\\n"
      "                out[i] = op == ORC_SUM ? (TOUT)sacc : macc;",
-     "            if (kind == ORC_INCLUSIVE)                                         \\\n"
+     "            if (!scan_excludes_self(kind))                                     \\\n"
      "                out[i] = op == ORC_SUM ? (TOUT)(sacc - (UACC)v) : macc;", 0),
-    ("scan_f32_mag_without_abs", "m = m + fabs(v);\n        if (kind == ORC_INCLUSIVE)",
-     "m = m + v;\n        if (kind == ORC_INCLUSIVE)", 0),
+    ("scan_f32_mag_without_abs", "m = m + fabs(v);\n        if (!scan_excludes_self(kind)) {",
+     "m = m + v;\n        if (!scan_excludes_self(kind)) {", 0),
+    ("reverse_exclusive_keeps_self",
+     "return kind == ORC_EXCLUSIVE || kind == ORC_REVERSE_EXCLUSIVE;",
+     "return kind == ORC_EXCLUSIVE;", 0),
+    ("reverse_scan_runs_forward", "return kind >= ORC_REVERSE_INCLUSIVE ? n - 1 - t : t;",
+     "return t;", 0),
+    ("adjoint1d_mirrored", "if (!border_index(i + k - r, n, edge, &src)) continue;",
+     "if (!border_index(i - k + r, n, edge, &src)) continue;", 0),
+    ("adjoint2d_cols_mirrored", "if (!border_index(j + b - rx, cols, edge, &sj)) continue;",
+     "if (!border_index(j - b + rx, cols, edge, &sj)) continue;", 0),
+    ("grad_affine_tanh_drops_scale", "*fx = p[0] * d;", "*fx = d;", 0),
+    ("grad_tanh_wrong", "*fx = 1.0 - t * t;", "*fx = 1.0 - t;", 0),
+    ("grad_axpy_param", "case ORC_MAP_AXPY: *fx = p[0]; *fy = 1.0; *fp0 = x; break;",
+     "case ORC_MAP_AXPY: *fx = p[0]; *fy = 1.0; *fp0 = 1.0; break;", 0),
     ("reduce_i64_wraps_at_32", "for (int64_t i = 0; i < n; ++i) acc = acc + (uint64_t)(int64_t)x[i];",
      "for (int64_t i = 0; i < n; ++i) acc = (uint32_t)(acc + (uint64_t)(int64_t)x[i]);", 0),
     ("min_is_max", "if (op == ORC_MIN) acc = v < acc ? v : acc;",

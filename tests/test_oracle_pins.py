@@ -8,6 +8,7 @@ scipy.ndimage.correlate*), and exact rational brute force on tiny inputs.  The
 checks are chosen so that a dropped term, a wrong sign or index, a swapped
 operand or an off-by-one in inclusive/exclusive fails at least one of them.
 """
+import functools
 import json
 import math
 import os
@@ -68,7 +69,7 @@ def test_golden_mapreduce(oracle_mod):
 def test_golden_scan(oracle_mod, name, op):
     g = GOLD[name]
     x = np.array(g["x"], np.int32)
-    for kind in ("inclusive", "exclusive"):
+    for kind in ("inclusive", "exclusive", "reverse_inclusive", "reverse_exclusive"):
         assert oracle_mod.scan(x, kind, op).tolist() == g[kind]
         if op == "sum":
             assert oracle_mod.scan(x, kind, op, np.int64).tolist() == g[kind]
@@ -86,6 +87,15 @@ def test_golden_mapoverlap1d(oracle_mod, name, edge):
                                      np.array(g["w"], np.float32), g["r"],
                                      edge, g.get("pad", 0.0))
     assert out.tolist() == g["out"]
+
+
+@pytest.mark.parametrize("edge", ["clamp", "const", "cyclic"])
+def test_golden_mapoverlap1d_adjoint(oracle_mod, edge):
+    g = GOLD["mapoverlap1d_adjoint_" + edge]
+    dx, mag = oracle_mod.mapoverlap1d_adjoint(np.array(g["g"], np.float32),
+                                              np.array(g["w"], np.float32), g["r"], edge)
+    assert dx.tolist() == g["dx"]
+    assert mag.tolist() == g["dx"]  # every term is positive here
 
 
 def test_golden_mapoverlap2d(oracle_mod):
@@ -468,6 +478,12 @@ def test_scan_bruteforce_tiny(oracle_mod):
                 inc.append(acc)
             assert oracle_mod.scan(x, "inclusive", op).tolist() == inc
             assert oracle_mod.scan(x, "exclusive", op).tolist() == exc
+            # suffix forms, brute force from the definition
+            rinc = [functools.reduce(fn, [int(v) for v in x[i:]]) for i in range(n)]
+            rexc = [functools.reduce(fn, [int(v) for v in x[i + 1:]], ident)
+                    for i in range(n)]
+            assert oracle_mod.scan(x, "reverse_inclusive", op).tolist() == rinc
+            assert oracle_mod.scan(x, "reverse_exclusive", op).tolist() == rexc
 
 
 # ------------------------------------------------------------ generators --
@@ -486,3 +502,129 @@ def test_generators_reproducible_and_on_grid():
     assert lens.min() >= 32 and lens.max() <= 1 << 20
     h = si.bf16_bits_from_f32(np.array([1.0, -2.5, 3.0e-3, 1.00390625], np.float32))
     assert h.tolist() == [0x3F80, 0xC020, 0x3B45, 0x3F80]  # last: tie to even
+
+
+# ------------------------------------------------------------- adjoints --
+
+def test_reverse_scan_f32_and_widening(oracle_mod):
+    x = si.normal_f32(2000, 0, 12)
+    xd = x.astype(np.float64)
+    ri, rmag = oracle_mod.scan(x, "reverse_inclusive")
+    assert np.array_equal(ri, np.cumsum(xd[::-1])[::-1])
+    assert np.array_equal(rmag, np.cumsum(np.abs(xd[::-1]))[::-1])
+    re_, _ = oracle_mod.scan(x, "reverse_exclusive")
+    assert re_[-1] == 0.0 and np.array_equal(re_[:-1], ri[1:])
+    xi = si.rng(5, 6).integers(-2 ** 31, 2 ** 31, 500, dtype=np.int64).astype(np.int32)
+    wide = oracle_mod.scan(xi, "reverse_inclusive", "sum", np.int64)
+    exact = np.cumsum(xi.astype(object)[::-1])[::-1]
+    assert wide.tolist() == [int(v) for v in exact]
+    narrow = oracle_mod.scan(xi, "reverse_inclusive", "sum")
+    assert narrow.tolist() == [((int(v) + 2 ** 31) % 2 ** 32) - 2 ** 31 for v in exact]
+
+
+def _dense_1d(oracle_mod, n, w, r, edge):
+    """The forward map as a dense matrix, column j = forward(e_j) (pad 0)."""
+    a = np.zeros((n, n))
+    for j in range(n):
+        e = np.zeros(n, np.float32)
+        e[j] = 1.0
+        a[:, j], _ = oracle_mod.mapoverlap1d(e, w, r, edge, 0.0)
+    return a
+
+
+@pytest.mark.parametrize("edge", ["clamp", "const", "cyclic"])
+@pytest.mark.parametrize("n,r", [(1, 0), (1, 2), (3, 2), (7, 2), (12, 3), (5, 4)])
+def test_mapoverlap1d_adjoint_is_transpose(oracle_mod, edge, n, r):
+    w = si.uniform_f32(2 * r + 1, -1.0, 1.0, 6, r)
+    g = si.uniform_f32(n, -1.0, 1.0, 6, 10 + n)
+    a = _dense_1d(oracle_mod, n, w, r, edge)
+    dx, _ = oracle_mod.mapoverlap1d_adjoint(g, w, r, edge)
+    np.testing.assert_allclose(dx, a.T @ g.astype(np.float64), rtol=1e-13, atol=1e-15)
+
+
+@pytest.mark.parametrize("edge", ["clamp", "const", "cyclic"])
+def test_mapoverlap1d_adjoint_inner_products(oracle_mod, edge):
+    # <A x, g> = <x, A^T g> with A x from the forward map (the pad term of the
+    # constant border is affine, so it is zero here)
+    n, r = 4099, 3
+    w = si.uniform_f32(2 * r + 1, -1.0, 1.0, 6, 40)
+    x = si.normal_f32(n, 6, 41)
+    g = si.normal_f32(n, 6, 42)
+    ax, _ = oracle_mod.mapoverlap1d(x, w, r, edge, 0.0)
+    atg, _ = oracle_mod.mapoverlap1d_adjoint(g, w, r, edge)
+    lhs = math.fsum(ax * g.astype(np.float64))
+    rhs = math.fsum(x.astype(np.float64) * atg)
+    assert abs(lhs - rhs) <= 1e-12 * math.fsum(np.abs(ax * g))
+
+
+@pytest.mark.parametrize("edge", ["clamp", "const", "cyclic"])
+@pytest.mark.parametrize("shape,ry,rx", [((1, 1), 1, 1), ((5, 4), 2, 1), ((6, 9), 1, 3),
+                                         ((3, 3), 0, 2)])
+def test_mapoverlap2d_adjoint_is_transpose(oracle_mod, edge, shape, ry, rx):
+    rows, cols = shape
+    w2d = si.uniform_f32((2 * ry + 1) * (2 * rx + 1), -1.0, 1.0, 6, 50).reshape(
+        2 * ry + 1, 2 * rx + 1)
+    g = si.uniform_f32(rows * cols, -1.0, 1.0, 6, 51).reshape(rows, cols)
+    a = np.zeros((rows * cols, rows * cols))
+    for s in range(rows * cols):
+        e = np.zeros(rows * cols, np.float32)
+        e[s] = 1.0
+        col, _ = oracle_mod.mapoverlap2d(e.reshape(rows, cols), ry, rx, w2d=w2d, edge=edge)
+        a[:, s] = col.reshape(-1)
+    dx, _ = oracle_mod.mapoverlap2d_adjoint(g, ry, rx, w2d=w2d, edge=edge)
+    np.testing.assert_allclose(dx.reshape(-1), a.T @ g.reshape(-1).astype(np.float64),
+                               rtol=1e-13, atol=1e-15)
+    # separable factors give the same map as their outer product
+    wy = si.uniform_f32(2 * ry + 1, -1.0, 1.0, 6, 52)
+    wx = si.uniform_f32(2 * rx + 1, -1.0, 1.0, 6, 53)
+    d1, _ = oracle_mod.mapoverlap2d_adjoint(g, ry, rx, wy=wy, wx=wx, edge=edge)
+    outer = (wy.astype(np.float64)[:, None] * wx.astype(np.float64)[None, :])
+    d2 = np.zeros_like(d1)
+    for s in range(rows * cols):  # A^T g for the outer-product weights, by columns
+        e = np.zeros(rows * cols, np.float32)
+        e[s] = 1.0
+        col, _ = oracle_mod.mapoverlap2d(e.reshape(rows, cols), ry, rx, wy=wy, wx=wx,
+                                         edge=edge)
+        d2.reshape(-1)[s] = float(col.reshape(-1) @ g.reshape(-1).astype(np.float64))
+    np.testing.assert_allclose(d1, d2, rtol=1e-13, atol=1e-15)
+    assert outer.shape == (2 * ry + 1, 2 * rx + 1)
+
+
+MAP_GRAD_CASES = [("identity", []), ("axpy", [2.5]), ("affine", [0.75, -0.5]),
+                  ("tanh", []), ("affine_tanh", [1.5, 0.25]), ("mul", []), ("square", [])]
+
+
+@pytest.mark.parametrize("op,params", MAP_GRAD_CASES)
+def test_map_grad_finite_differences(oracle_mod, op, params):
+    # central differences of the forward oracle in binary64: inputs on a
+    # 2^-8 grid in [-1, 1), step 2^-12, so x +- h is exact in binary32
+    n = 64
+    rng = si.rng(6, 60)
+    x = (rng.integers(-256, 256, n) / 256.0).astype(np.float32)
+    y = (rng.integers(-256, 256, n) / 256.0).astype(np.float32)
+    g = si.uniform_f32(n, -1.0, 1.0, 6, 61)
+    two = op in oracle_mod.TWO_INPUT_MAP_OPS
+    dx, dy, dp, _ = oracle_mod.map_grad(op, params, x, g, y if two else None)
+    h = 2.0 ** -12
+
+    def f(xx, yy, pp):
+        return oracle_mod.map_f32(op, pp, xx, yy if two else None)
+
+    fd_x = (f(x + np.float32(h), y, params) - f(x - np.float32(h), y, params)) / (2 * h)
+    np.testing.assert_allclose(dx, g.astype(np.float64) * fd_x, rtol=1e-5, atol=1e-7)
+    if two:
+        fd_y = (f(x, y + np.float32(h), params) - f(x, y - np.float32(h), params)) / (2 * h)
+        np.testing.assert_allclose(dy, g.astype(np.float64) * fd_y, rtol=1e-5, atol=1e-7)
+    for k in range(len(params)):
+        pp, pm = list(params), list(params)
+        pp[k] += h
+        pm[k] -= h
+        fd_p = (f(x, y, pp) - f(x, y, pm)) / (2 * h)
+        assert abs(dp[k] - math.fsum(g.astype(np.float64) * fd_p)) <= 1e-5 * (
+            math.fsum(np.abs(g.astype(np.float64) * fd_p)) + 1e-12), (op, k)
+
+
+def test_map_grad_rejects_bad_ops(oracle_mod):
+    x = np.ones(4, np.float32)
+    with pytest.raises(ValueError):
+        oracle_mod.map_grad("affine", [1.0], x, x)  # needs two parameters
