@@ -78,7 +78,16 @@ typedef enum skel_edge {
     SKEL_EDGE_CYCLIC = 2
 } skel_edge;
 
-typedef enum skel_scan_kind { SKEL_INCLUSIVE = 0, SKEL_EXCLUSIVE = 1 } skel_scan_kind;
+/* scan kinds.  The reverse kinds combine from the end of the array (suffix
+ * scans); they are the adjoints of the forward SUM scans:
+ *   d(inclusive)/dx applied to g = reverse inclusive scan of g,
+ *   d(exclusive)/dx applied to g = reverse exclusive scan of g. */
+typedef enum skel_scan_kind {
+    SKEL_INCLUSIVE = 0,
+    SKEL_EXCLUSIVE = 1,
+    SKEL_REVERSE_INCLUSIVE = 2,
+    SKEL_REVERSE_EXCLUSIVE = 3
+} skel_scan_kind;
 
 /* associative and commutative combining operator of Reduce / Scan */
 typedef enum skel_reduce_op { SKEL_SUM = 0, SKEL_MIN = 1, SKEL_MAX = 2 } skel_reduce_op;
@@ -163,8 +172,21 @@ const char *skel_last_error(void);
 skel_status skel_container_create(skel_dtype dtype, int64_t rows, int64_t cols,
                                   const void *host_src, skel_container **out);
 
+/* Wrap caller-owned device memory as a container (for frameworks that hold
+ * their tensors themselves).  dev_ptr holds rows*cols elements of `dtype`,
+ * 16-byte aligned (the kernels use 16-byte vectors; SKEL_E_INVAL otherwise),
+ * and is the container's valid device copy; its contents count as written on
+ * `stream`, so a later access on another stream waits for that stream's work
+ * enqueued before the wrap.  The library never frees dev_ptr, and a host copy
+ * is allocated only if the host acquires the container.  The memory must
+ * stay allocated until skel_container_destroy returns. */
+skel_status skel_container_wrap_device(skel_dtype dtype, int64_t rows, int64_t cols,
+                                       void *dev_ptr, void *stream,
+                                       skel_container **out);
+
 /* Destroy a container with no outstanding acquire; device memory is released
- * stream-ordered after the last device access. */
+ * stream-ordered after the last device access (wrapped device memory is left
+ * to its owner). */
 skel_status skel_container_destroy(skel_container *c);
 
 /* Section IV coherence protocol.  Make the copy at `place` usable for
@@ -235,9 +257,12 @@ skel_status skel_mapoverlap2d(skel_container *in, skel_container *out,
                               float pad, int variant, void *stream);
 
 /* Scan (Section III): inclusive out[i] = in[0] op ... op in[i]; exclusive
- * out[0] = identity, out[i] = in[0] op ... op in[i-1].  Type pairs: I32 ->
- * I32 (wraps), I32 -> I64, I64 -> I64 (exact, wrapping), F32 -> F32.  out may
- * equal in when the types agree. */
+ * out[0] = identity, out[i] = in[0] op ... op in[i-1]; reverse inclusive
+ * out[i] = in[i] op ... op in[n-1]; reverse exclusive out[n-1] = identity,
+ * out[i] = in[i+1] op ... op in[n-1].  Type pairs: I32 -> I32 (wraps), I32 ->
+ * I64, I64 -> I64 (exact, wrapping), F32 -> F32.  out may equal in when the
+ * types agree.  The reverse kinds run in the single-pass variant only (a
+ * forced S0 or S1 gives SKEL_E_UNSUPPORTED). */
 skel_status skel_scan(skel_container *in, skel_container *out,
                       skel_scan_kind kind, skel_reduce_op op, int variant,
                       void *stream);
@@ -259,6 +284,47 @@ skel_status skel_reduce_segments(skel_reduce_op op, skel_container *in,
                                  skel_container *offsets, skel_container *out,
                                  int variant, void *stream);
 
+/* --------------------------------------------------------- adjoints ---- */
+/* Reverse-mode derivatives for a scalar loss L, given the upstream gradient
+ * g = dL/d(out) of a forward call.  All operands are F32 containers; outputs
+ * are overwritten (not accumulated into).  They back the torch.autograd
+ * functions of the Python binding.  Reduce SUM backward is
+ * skel_map_backward(IDENTITY) with a one-element g; MapReduce SUM backward is
+ * skel_map_backward of its element function with a one-element g; Scan SUM
+ * backward is skel_scan with the reverse kind. */
+
+/* Map backward (chain rule of the element function, Section III map):
+ *   grad_in[0][i] = g[i] * df/dx(x[i], y[i]),
+ *   grad_in[1][i] = g[i] * df/dy(x[i], y[i])      (two-input ops only),
+ *   grad_params[k] = sum_i g[i] * df/dp_k          (if grad_params != NULL)
+ * in: the forward inputs (nin as the op requires); g: n elements, or one
+ * element broadcast to every i; grad_in: nin containers of n elements, none
+ * of them an input or g; grad_params: nparams elements (f32), summed over i
+ * deterministically.  Tanh-based ops recompute tanh from x. */
+skel_status skel_map_backward(skel_map_op op, const double *params, int nparams,
+                              skel_container *const *in, int nin, skel_container *g,
+                              skel_container *const *grad_in, skel_container *grad_params,
+                              void *stream);
+
+/* MapOverlap 1D backward: the transpose of in -> out applied to g,
+ *   grad_in[j] = sum over (i, k) with e(i + k - r) = j of w[k] * g[i];
+ * reads of the CONST pad send nothing back; with CLAMP the reads past either
+ * end accumulate onto the end elements.  Same w, radius and edge as the
+ * forward call; grad_in != g. */
+skel_status skel_mapoverlap1d_backward(skel_container *g, skel_container *grad_in,
+                                       const float *w, int radius, skel_edge edge,
+                                       void *stream);
+
+/* MapOverlap 2D backward: the transpose of the 2D neighbourhood map,
+ *   grad_in[s][t] = sum over (i, j, a, b) with e(i+a-ry) = s, e(j+b-rx) = t
+ *                   of W[a][b] * g[i][j]
+ * with the forward call's weights (w2d, or the factors wy, wx), radii and
+ * edge rule; grad_in != g. */
+skel_status skel_mapoverlap2d_backward(skel_container *g, skel_container *grad_in,
+                                       const float *w2d, const float *wy,
+                                       const float *wx, int ry, int rx, skel_edge edge,
+                                       void *stream);
+
 /* ------------------------------------------- variants and selection ---- */
 
 int skel_variant_count(int skeleton);
@@ -268,8 +334,8 @@ const char *skel_variant_name(int skeleton, int variant); /* NULL if out of rang
  * running anything: returns the variant index, or -1 if none is selectable.
  * n is the element count (rows*cols for 2D); dtype is the input element type;
  * `aux` is the radius for SKEL_SK_MAPOVERLAP1D, 1 when the 2D weights are
- * given as separable factors for SKEL_SK_MAPOVERLAP2D, and ignored
- * otherwise. */
+ * given as separable factors for SKEL_SK_MAPOVERLAP2D, 1 for the reverse
+ * kinds of SKEL_SK_SCAN, and ignored otherwise. */
 int skel_select_variant(int skeleton, skel_dtype dtype, int64_t n,
                         int64_t rows, int64_t cols, int aux);
 

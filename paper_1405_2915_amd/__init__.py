@@ -43,7 +43,7 @@ F32, BF16, I32, I64 = 0, 1, 2, 3
 HOST, DEVICE = 0, 1
 READ, WRITE, RW = 1, 2, 3
 EDGE_CLAMP, EDGE_CONST, EDGE_CYCLIC = 0, 1, 2
-INCLUSIVE, EXCLUSIVE = 0, 1
+INCLUSIVE, EXCLUSIVE, REVERSE_INCLUSIVE, REVERSE_EXCLUSIVE = 0, 1, 2, 3
 SUM, MIN, MAX = 0, 1, 2
 MAP_IDENTITY, MAP_AXPY, MAP_AFFINE, MAP_TANH, MAP_AFFINE_TANH, MAP_MUL, MAP_SQUARE = range(7)
 SK_MAP, SK_REDUCE, SK_MAPREDUCE, SK_MAPOVERLAP1D, SK_MAPOVERLAP2D, SK_SCAN, \
@@ -114,6 +114,10 @@ def load_library(path: str = LIB_PATH):
         "skel_mapoverlap2d": (st, [vp, vp, fp, fp, fp, i, i, i, C.c_float, i, vp]),
         "skel_scan": (st, [vp, vp, i, i, i, vp]),
         "skel_reduce_segments": (st, [i, vp, vp, vp, i, vp]),
+        "skel_container_wrap_device": (st, [i, i64, i64, vp, vp, C.POINTER(vp)]),
+        "skel_map_backward": (st, [i, dp, i, C.POINTER(vp), i, vp, C.POINTER(vp), vp, vp]),
+        "skel_mapoverlap1d_backward": (st, [vp, vp, fp, i, i, vp]),
+        "skel_mapoverlap2d_backward": (st, [vp, vp, fp, fp, fp, i, i, i, vp]),
         "skel_variant_count": (i, [i]),
         "skel_variant_name": (C.c_char_p, [i, i]),
         "skel_select_variant": (i, [i, i, i64, i64, i64, i]),
@@ -329,6 +333,37 @@ def skel_container_destroy(c: Container) -> None:
     c.destroy()
 
 
+def skel_container_wrap_device(dtype: int, rows: int, cols: int, dev_ptr: int,
+                               stream=None) -> Container:
+    """A container over caller-owned device memory (its valid device copy);
+    the library never frees it."""
+    out = C.c_void_p()
+    _check(load_library().skel_container_wrap_device(dtype, rows, cols, C.c_void_p(dev_ptr),
+                                                     C.c_void_p(_stream(stream)),
+                                                     C.byref(out)),
+           "skel_container_wrap_device")
+    return Container(out.value, dtype, rows, cols)
+
+
+_TORCH_DTYPE = None
+
+
+def wrap_tensor(t, stream=None) -> Container:
+    """A container viewing a contiguous CUDA tensor's memory (f32, bf16 bits as
+    int16/bfloat16, int32, int64); the tensor must outlive the container."""
+    import torch
+    global _TORCH_DTYPE
+    if _TORCH_DTYPE is None:
+        _TORCH_DTYPE = {torch.float32: F32, torch.bfloat16: BF16, torch.int32: I32,
+                        torch.int64: I64}
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("wrap_tensor needs a contiguous CUDA tensor")
+    if t.dtype not in _TORCH_DTYPE:
+        raise TypeError(f"unsupported tensor dtype {t.dtype}")
+    rows, cols = (1, t.numel()) if t.dim() <= 1 else (t.shape[0], t.numel() // t.shape[0])
+    return skel_container_wrap_device(_TORCH_DTYPE[t.dtype], rows, cols, t.data_ptr(), stream)
+
+
 def skel_container_acquire(c: Container, place: int, access: int, stream=None) -> int:
     ptr = C.c_void_p()
     _check(_L().skel_container_acquire(_h(c), place, access, C.c_void_p(_stream(stream)),
@@ -446,6 +481,49 @@ def skel_reduce_segments(op: int, inp: Container, offsets: Container, out: Conta
     """out[s] = op over inp[offsets[s]:offsets[s+1]] for every segment s."""
     _check(_L().skel_reduce_segments(op, _h(inp), _h(offsets), _h(out), variant,
                                      C.c_void_p(_stream(stream))), "skel_reduce_segments")
+
+
+def skel_map_backward(map_op: int, params, ins, g: Container, grad_ins,
+                      grad_params: Container | None = None, stream=None) -> None:
+    """grad_ins[k] = g * df/d(input k); grad_params[k] = sum_i g df/dp_k.
+    g has n elements or one (broadcast)."""
+    for c in list(ins) + list(grad_ins):
+        _h(c)
+    p, pp, np_ = _params(params)
+    arr, nin = _handles(ins)
+    garr, ng = _handles(grad_ins)
+    if ng != nin:
+        raise ValueError("one gradient output per input")
+    _check(_L().skel_map_backward(map_op, pp, np_, arr, nin, _h(g), garr, _h(grad_params),
+                                  C.c_void_p(_stream(stream))), "skel_map_backward")
+
+
+def skel_mapoverlap1d_backward(g: Container, grad_in: Container, w, radius: int,
+                               edge: int = EDGE_CLAMP, stream=None) -> None:
+    wa, wp = _floats(w)
+    if wa is None or wa.size != 2 * radius + 1:
+        raise ValueError("w must hold 2*radius+1 weights")
+    _check(_L().skel_mapoverlap1d_backward(_h(g), _h(grad_in), wp, radius, edge,
+                                           C.c_void_p(_stream(stream))),
+           "skel_mapoverlap1d_backward")
+
+
+def skel_mapoverlap2d_backward(g: Container, grad_in: Container, w2d=None, wy=None, wx=None,
+                               ry: int | None = None, rx: int | None = None,
+                               edge: int = EDGE_CLAMP, stream=None) -> None:
+    a2, p2 = _floats(w2d)
+    ay, py = _floats(wy)
+    ax, px = _floats(wx)
+    if w2d is not None:
+        shp = np.shape(w2d)
+        ry = (shp[0] - 1) // 2 if ry is None else ry
+        rx = (shp[1] - 1) // 2 if rx is None else rx
+    else:
+        ry = (ay.size - 1) // 2 if ry is None else ry
+        rx = (ax.size - 1) // 2 if rx is None else rx
+    _check(_L().skel_mapoverlap2d_backward(_h(g), _h(grad_in), p2, py, px, ry, rx, edge,
+                                           C.c_void_p(_stream(stream))),
+           "skel_mapoverlap2d_backward")
 
 
 def skel_variant_count(skeleton: int) -> int:

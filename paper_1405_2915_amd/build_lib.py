@@ -25,7 +25,7 @@ HOSTTEST_LIB = os.path.join(PKG, "libskel_hosttest.so")
 
 HIP_SOURCES = ["common.cpp", "container.cpp", "dispatch.cpp", "runtime.cpp",
                "skeletons.cpp", "k_map.hip", "k_reduce.hip", "k_scan.hip",
-               "k_overlap.hip", "k_segments.hip"]
+               "k_overlap.hip", "k_segments.hip", "k_grad.hip"]
 HOST_SOURCES = ["common.cpp", "container.cpp", "dispatch.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -228,14 +228,63 @@ skel_status skel_container_create(skel_dtype dtype, int64_t rows, int64_t cols,
     return SKEL_OK;
 }
 
+skel_status skel_container_wrap_device(skel_dtype dtype, int64_t rows, int64_t cols,
+                                       void* dev_ptr, void* stream, skel_container** out) {
+    if (!rt().initialized) return fail(SKEL_E_NOINIT, "skel_init has not been called");
+    if (!out) return fail(SKEL_E_INVAL, "null output pointer");
+    if (!dtype_valid(dtype)) return fail(SKEL_E_DTYPE, "unknown dtype %d", (int)dtype);
+    if (rows < 1 || cols < 0)
+        return fail(SKEL_E_SHAPE, "bad shape %lld x %lld", (long long)rows, (long long)cols);
+    const int64_t lim = INT64_C(1) << 31;
+    if (rows > lim || cols > lim || (cols > 0 && rows > (INT64_C(1) << 40) / cols))
+        return fail(SKEL_E_SHAPE, "shape %lld x %lld too large", (long long)rows,
+                    (long long)cols);
+    const size_t bytes = (size_t)(rows * cols) * dtype_size(dtype);
+    if (bytes > 0 && !dev_ptr) return fail(SKEL_E_INVAL, "null device pointer");
+    if ((reinterpret_cast<uintptr_t>(dev_ptr) & 15) != 0)
+        return fail(SKEL_E_INVAL, "wrapped device memory must be 16-byte aligned");
+    auto* c = new (std::nothrow) skel_container();
+    if (!c) return fail(SKEL_E_NOMEM, "out of host memory");
+    c->dtype = dtype;
+    c->rows = rows;
+    c->cols = cols;
+    c->n = rows * cols;
+    c->bytes = bytes;
+    c->allocator = rt().allocator;
+    if (bytes == 0) {
+        c->host_valid = c->dev_valid = true;
+    } else {
+        c->dev = dev_ptr;
+        c->dev_external = true;
+        c->dev_valid = true;
+        // the contents were produced in `stream` order: treat that as the
+        // container's last device access (its event is recorded when another
+        // stream or the host first needs it)
+        skel_status st = SKEL_OK;
+        auto* e = event_for(c, stream, &st);
+        if (!e) {
+            delete c;
+            return st;
+        }
+        e->pending = true;
+        c->last_stream = stream;
+    }
+    *out = c;
+    return SKEL_OK;
+}
+
 skel_status skel_container_destroy(skel_container* c) {
     if (!c) return fail(SKEL_E_INVAL, "null container");
     if (c->writer != -1 || c->host_readers || c->dev_readers)
         return fail(SKEL_E_STATE, "destroy with an outstanding acquire");
     Backend* be = rt().backend;
-    skel_status st = wait_device_idle(c);
-    if (st != SKEL_OK) return st;
-    if (c->dev) be->dev_free(c->allocator, c->dev, c->last_stream);
+    // a wrapped container without a host copy frees nothing that its device
+    // work still uses, so destroying it does not wait
+    if (!(c->dev_external && !c->host)) {
+        skel_status st = wait_device_idle(c);
+        if (st != SKEL_OK) return st;
+    }
+    if (c->dev && !c->dev_external) be->dev_free(c->allocator, c->dev, c->last_stream);
     if (c->host) be->host_free(c->host);
     for (auto& e : c->events) be->event_destroy(e.event);
     delete c;

@@ -17,6 +17,7 @@ struct skel_container {
 
     void* host = nullptr;  // pinned host copy, allocated on first need
     void* dev = nullptr;   // device copy, allocated on first device acquire
+    bool dev_external = false;  // dev is caller-owned (wrapped): never freed here
     bool host_valid = false;
     bool dev_valid = false;
 

@@ -62,7 +62,8 @@ int static_rule(const CallContext& c) {
         return c.n <= (INT64_C(1) << 15) ? MR3_FUSED_SINGLE_WG : MR2_FUSED_TICKET;
     case SKEL_SK_MAPOVERLAP1D: return c.radius <= 4 ? O1C_SHUFFLE : O1B_LDS_TILE;
     case SKEL_SK_MAPOVERLAP2D: return c.separable ? O2D_SEPARABLE_L1 : O2B_LDS_TILE;
-    case SKEL_SK_SCAN: return c.n <= (INT64_C(1) << 15) ? S0_SINGLE_WG : S2_LOOKBACK;
+    case SKEL_SK_SCAN:
+        return c.n <= (INT64_C(1) << 15) && !c.reverse ? S0_SINGLE_WG : S2_LOOKBACK;
     case SKEL_SK_REDUCE_SEGMENTS: return B1_PERSISTENT;
     }
     return -1;
@@ -164,6 +165,12 @@ bool selectable(int v, const CallContext& c, const char** why) {
     case SKEL_SK_MAPOVERLAP2D:
         if ((v == O2C_LDS_SEPARABLE || v == O2D_SEPARABLE_L1) && !c.separable) {
             *why = "separable variants need the weights as factors wy, wx";
+            return false;
+        }
+        return true;
+    case SKEL_SK_SCAN:
+        if (c.reverse && v != S2_LOOKBACK) {
+            *why = "reverse scans run in the single-pass variant only";
             return false;
         }
         return true;
@@ -287,6 +294,7 @@ int skel_select_variant(int skeleton, skel_dtype dtype, int64_t n, int64_t rows,
     c.rows = rows;
     c.cols = cols;
     if (skeleton == SKEL_SK_MAPOVERLAP1D) c.radius = aux;
+    else if (skeleton == SKEL_SK_SCAN) c.reverse = aux;
     else c.separable = aux;
     skel_status st;
     return skel::choose_variant(SKEL_VARIANT_AUTO, c, &st);

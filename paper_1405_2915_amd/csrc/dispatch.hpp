@@ -34,6 +34,7 @@ struct CallContext {
     int map_op = 0;     // MapReduce's element function
     int separable = 0;  // MapOverlap2D: weights given as factors
     int radius = 0;     // MapOverlap1D radius
+    int reverse = 0;    // Scan: a reverse (suffix) kind
 };
 
 int variant_count(int skeleton);

@@ -1,0 +1,302 @@
+// Reverse-mode kernels: the adjoints of Map and MapOverlap for a scalar loss
+// (the scan adjoint is the reverse scan in k_scan.hip, the Reduce adjoint is
+// the Map adjoint of the identity with a broadcast gradient).
+//
+//   map_grad       dx = g * df/dx, dy = g * df/dy, and per-workgroup partial
+//                  sums of g * df/dp_k combined in order by map_grad_finish;
+//                  16-byte vectors, the gradient optionally one broadcast
+//                  value (Reduce / MapReduce backward)
+//   ov1_adjoint    transpose of the 1D neighbourhood map as a gather: element
+//                  j collects w[k] * g[j - k + r] (wrapping for CYCLIC), and
+//                  with CLAMP the two end elements also collect every read
+//                  that fell past their end
+//   ov2_adjoint    the same per axis for the 2D map: for each tap (a, b) the
+//                  rows i that read row s form a contiguous range (one row
+//                  inside the image, up to ry + 1 rows at a clamped edge)
+//
+// All are HBM streams (map_grad: 12 to 20 bytes per element; adjoints: 8
+// bytes per element plus the cached neighbourhood reads).
+#include "kcommon.hpp"
+#include "launch.hpp"
+
+namespace skel {
+namespace {
+
+using dev::f32x4;
+
+constexpr int kBlock = 256;
+
+template <int OP>
+constexpr bool grad_two_inputs() { return OP == SKEL_MAP_AXPY || OP == SKEL_MAP_MUL; }
+template <int OP>
+constexpr int grad_nparams() {
+    return OP == SKEL_MAP_AXPY ? 1 : (OP == SKEL_MAP_AFFINE || OP == SKEL_MAP_AFFINE_TANH) ? 2 : 0;
+}
+
+// g * partial derivatives of f at (x, y): dx, dy and the parameter terms
+template <int OP>
+__device__ __forceinline__ void elem_grad(float x, float y, float g, float p0, float p1,
+                                          float& dx, float& dy, float& s0, float& s1) {
+    dy = 0.0f;
+    s0 = 0.0f;
+    s1 = 0.0f;
+    if constexpr (OP == SKEL_MAP_IDENTITY) {
+        dx = g;
+    } else if constexpr (OP == SKEL_MAP_AXPY) {
+        dx = p0 * g;
+        dy = g;
+        s0 = g * x;
+    } else if constexpr (OP == SKEL_MAP_AFFINE) {
+        dx = p0 * g;
+        s0 = g * x;
+        s1 = g;
+    } else if constexpr (OP == SKEL_MAP_TANH) {
+        const float t = tanhf(x);
+        dx = g * (1.0f - t * t);
+    } else if constexpr (OP == SKEL_MAP_AFFINE_TANH) {
+        const float t = tanhf(__builtin_fmaf(p0, x, p1));
+        const float gd = g * (1.0f - t * t);  // g * tanh' at the pre-activation
+        dx = gd * p0;
+        s0 = gd * x;
+        s1 = gd;
+    } else if constexpr (OP == SKEL_MAP_MUL) {
+        dx = g * y;
+        dy = g * x;
+    } else {  // SQUARE
+        dx = 2.0f * g * x;
+    }
+}
+
+template <int OP, bool BCAST>
+__global__ __launch_bounds__(kBlock) void map_grad(const float* x, const float* y,
+                                                   const float* g, float* dx, float* dy,
+                                                   int64_t n, float p0, float p1,
+                                                   float* partials) {
+    constexpr bool TWO = grad_two_inputs<OP>();
+    constexpr int NP = grad_nparams<OP>();
+    const float gb = BCAST ? g[0] : 0.0f;
+    float a0 = 0.0f, a1 = 0.0f;
+    const int64_t nv = n / 4;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < nv; i += stride) {
+        const f32x4 xv = reinterpret_cast<const f32x4*>(x)[i];
+        const f32x4 yv = TWO ? reinterpret_cast<const f32x4*>(y)[i] : f32x4{0.f, 0.f, 0.f, 0.f};
+        const f32x4 gv = BCAST ? f32x4{gb, gb, gb, gb} : reinterpret_cast<const f32x4*>(g)[i];
+        f32x4 ox, oy;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            float ddx, ddy, s0, s1;
+            elem_grad<OP>(xv[e], yv[e], gv[e], p0, p1, ddx, ddy, s0, s1);
+            ox[e] = ddx;
+            oy[e] = ddy;
+            a0 += s0;
+            a1 += s1;
+        }
+        reinterpret_cast<f32x4*>(dx)[i] = ox;
+        if constexpr (TWO) reinterpret_cast<f32x4*>(dy)[i] = oy;
+    }
+    // the n % 4 tail, one element per low lane of the first workgroup
+    const int64_t t = nv * 4 + (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (blockIdx.x == 0 && t < n) {
+        float ddx, ddy, s0, s1;
+        elem_grad<OP>(x[t], TWO ? y[t] : 0.0f, BCAST ? gb : g[t], p0, p1, ddx, ddy, s0, s1);
+        dx[t] = ddx;
+        if constexpr (TWO) dy[t] = ddy;
+        a0 += s0;
+        a1 += s1;
+    }
+    if constexpr (NP > 0) {
+        __shared__ float l0[kBlock / dev::kWave], l1[kBlock / dev::kWave];
+        using C = dev::Comb<float, SKEL_SUM>;
+        a0 = dev::block_reduce<C>(a0, l0);
+        a1 = dev::block_reduce<C>(a1, l1);
+        if (threadIdx.x == 0) {
+            partials[2 * blockIdx.x] = a0;
+            partials[2 * blockIdx.x + 1] = a1;
+        }
+    }
+}
+
+// parameter gradients: the workgroups' partials summed in workgroup order
+__global__ __launch_bounds__(kBlock) void map_grad_finish(const float* partials, int groups,
+                                                          int nparams, float* out) {
+    __shared__ float l0[kBlock / dev::kWave], l1[kBlock / dev::kWave];
+    using C = dev::Comb<float, SKEL_SUM>;
+    float a0 = 0.0f, a1 = 0.0f;
+    for (int b = threadIdx.x; b < groups; b += kBlock) {
+        a0 += partials[2 * b];
+        a1 += partials[2 * b + 1];
+    }
+    a0 = dev::block_reduce<C>(a0, l0);
+    a1 = dev::block_reduce<C>(a1, l1);
+    if (threadIdx.x == 0) {
+        out[0] = a0;
+        if (nparams > 1) out[1] = a1;
+    }
+}
+
+// --------------------------------------------------------- MapOverlap 1D ---
+struct WA1 {
+    float w[2 * SKEL_MAX_RADIUS_1D + 1];
+};
+
+__device__ __forceinline__ int64_t wrap_index(int64_t i, int64_t n) {
+    int64_t m = i % n;
+    return m < 0 ? m + n : m;
+}
+
+__global__ __launch_bounds__(kBlock) void ov1_adjoint(const float* g, float* dx, int64_t n,
+                                                      WA1 w, int r, int edge) {
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += stride) {
+        float acc = 0.0f;
+        if (edge == SKEL_EDGE_CYCLIC) {
+            for (int k = 0; k <= 2 * r; ++k) acc = __builtin_fmaf(w.w[k], g[wrap_index(j - k + r, n)], acc);
+        } else {
+            for (int k = 0; k <= 2 * r; ++k) {
+                const int64_t i = j - k + r;  // the output whose tap k read x[j]
+                if (i >= 0 && i < n) acc = __builtin_fmaf(w.w[k], g[i], acc);
+            }
+            if (edge == SKEL_EDGE_CLAMP) {
+                // reads below index 0 (i + k - r < 0) land on element 0, reads
+                // above n - 1 on element n - 1
+                if (j == 0)
+                    for (int k = 0; k < r; ++k)
+                        for (int64_t i = 0; i < n && i < r - k; ++i)
+                            acc = __builtin_fmaf(w.w[k], g[i], acc);
+                if (j == n - 1)
+                    for (int k = r + 1; k <= 2 * r; ++k)
+                        for (int64_t i = n - 1; i >= 0 && i > n - 1 + r - k; --i)
+                            acc = __builtin_fmaf(w.w[k], g[i], acc);
+            }
+        }
+        dx[j] = acc;
+    }
+}
+
+// --------------------------------------------------------- MapOverlap 2D ---
+struct WA2 {
+    float w[(2 * SKEL_MAX_RADIUS_2D + 1) * (2 * SKEL_MAX_RADIUS_2D + 1)];
+};
+
+// rows i of a length-len axis whose tap a (radius r) reads row s: the range
+// [*lo, *hi] (empty if lo > hi).  Inside the axis it is the single row
+// s - a + r; a clamped end also collects every read that fell past it; with
+// CYCLIC the single row wraps.
+__device__ __forceinline__ void tap_range(int64_t s, int a, int r, int64_t len, int edge,
+                                          int64_t* lo, int64_t* hi) {
+    const int64_t i = s - a + r;
+    if (edge == SKEL_EDGE_CYCLIC) {
+        *lo = *hi = wrap_index(i, len);
+        return;
+    }
+    *lo = i;
+    *hi = i;
+    if (edge == SKEL_EDGE_CLAMP) {
+        if (s == 0) *lo = -((int64_t)1 << 40);     // reads at or below 0
+        if (s == len - 1) *hi = (int64_t)1 << 40;  // reads at or above len - 1
+    }
+    if (*lo < 0) *lo = 0;
+    if (*hi > len - 1) *hi = len - 1;
+}
+
+__global__ __launch_bounds__(kBlock) void ov2_adjoint(const float* g, float* dx, int64_t rows,
+                                                      int64_t cols, WA2 w, int ry, int rx,
+                                                      int edge) {
+    const int64_t total = rows * cols;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    const int nx = 2 * rx + 1;
+    for (int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x; p < total; p += stride) {
+        const int64_t s = p / cols, t = p - s * cols;
+        float acc = 0.0f;
+        for (int a = 0; a <= 2 * ry; ++a) {
+            int64_t ilo, ihi;
+            tap_range(s, a, ry, rows, edge, &ilo, &ihi);
+            for (int b = 0; b <= 2 * rx; ++b) {
+                int64_t jlo, jhi;
+                tap_range(t, b, rx, cols, edge, &jlo, &jhi);
+                const float wab = w.w[a * nx + b];
+                for (int64_t i = ilo; i <= ihi; ++i)
+                    for (int64_t j = jlo; j <= jhi; ++j)
+                        acc = __builtin_fmaf(wab, g[i * cols + j], acc);
+            }
+        }
+        dx[p] = acc;
+    }
+}
+
+int grid_for(int64_t units, const DevInfo& d) {
+    int64_t g = (units + kBlock - 1) / kBlock;
+    const int64_t cap = (int64_t)d.cus * 8;
+    if (g > cap) g = cap;
+    return g < 1 ? 1 : (int)g;
+}
+
+template <int OP>
+skel_status map_grad_op(float p0, float p1, const float* x, const float* y, const float* g,
+                        bool bcast, float* dx, float* dy, int64_t n, float* dparams,
+                        LaunchCtx& lc) {
+    constexpr int NP = grad_nparams<OP>();
+    const int groups = grid_for((n + 3) / 4, *lc.dev);
+    float* partials = nullptr;
+    if (NP > 0 && dparams) {
+        void* mem = nullptr;
+        skel_status e = ws_scratch(lc, (size_t)groups * 2 * sizeof(float), &mem);
+        if (e != SKEL_OK) return e;
+        partials = static_cast<float*>(mem);
+    }
+    if (bcast)
+        map_grad<OP, true><<<groups, kBlock, 0, lc.stream>>>(x, y, g, dx, dy, n, p0, p1, partials);
+    else
+        map_grad<OP, false><<<groups, kBlock, 0, lc.stream>>>(x, y, g, dx, dy, n, p0, p1, partials);
+    skel_status e = launch_check("map_grad");
+    if (e != SKEL_OK || !partials) return e;
+    map_grad_finish<<<1, kBlock, 0, lc.stream>>>(partials, groups, NP, dparams);
+    return launch_check("map_grad_finish");
+}
+
+}  // namespace
+
+skel_status launch_map_backward(int op, float p0, float p1, const float* x, const float* y,
+                                const float* g, bool g_broadcast, float* dx, float* dy,
+                                int64_t n, float* dparams, LaunchCtx& lc) {
+    switch (op) {
+    case SKEL_MAP_IDENTITY:
+        return map_grad_op<SKEL_MAP_IDENTITY>(p0, p1, x, y, g, g_broadcast, dx, dy, n, dparams, lc);
+    case SKEL_MAP_AXPY:
+        return map_grad_op<SKEL_MAP_AXPY>(p0, p1, x, y, g, g_broadcast, dx, dy, n, dparams, lc);
+    case SKEL_MAP_AFFINE:
+        return map_grad_op<SKEL_MAP_AFFINE>(p0, p1, x, y, g, g_broadcast, dx, dy, n, dparams, lc);
+    case SKEL_MAP_TANH:
+        return map_grad_op<SKEL_MAP_TANH>(p0, p1, x, y, g, g_broadcast, dx, dy, n, dparams, lc);
+    case SKEL_MAP_AFFINE_TANH:
+        return map_grad_op<SKEL_MAP_AFFINE_TANH>(p0, p1, x, y, g, g_broadcast, dx, dy, n,
+                                                 dparams, lc);
+    case SKEL_MAP_MUL:
+        return map_grad_op<SKEL_MAP_MUL>(p0, p1, x, y, g, g_broadcast, dx, dy, n, dparams, lc);
+    default:
+        return map_grad_op<SKEL_MAP_SQUARE>(p0, p1, x, y, g, g_broadcast, dx, dy, n, dparams, lc);
+    }
+}
+
+skel_status launch_overlap1d_adjoint(const float* g, float* dx, int64_t n, const float* w,
+                                     int r, int edge, LaunchCtx& lc) {
+    WA1 wk{};
+    for (int k = 0; k <= 2 * r; ++k) wk.w[k] = w[k];
+    ov1_adjoint<<<grid_for(n, *lc.dev), kBlock, 0, lc.stream>>>(g, dx, n, wk, r, edge);
+    return launch_check("ov1_adjoint");
+}
+
+skel_status launch_overlap2d_adjoint(const float* g, float* dx, int64_t rows, int64_t cols,
+                                     const float* w2d, const float* wy, const float* wx,
+                                     int ry, int rx, int edge, LaunchCtx& lc) {
+    WA2 wk{};
+    const int ny = 2 * ry + 1, nx = 2 * rx + 1;
+    for (int a = 0; a < ny; ++a)
+        for (int b = 0; b < nx; ++b) wk.w[a * nx + b] = w2d ? w2d[a * nx + b] : wy[a] * wx[b];
+    ov2_adjoint<<<grid_for(rows * cols, *lc.dev), kBlock, 0, lc.stream>>>(g, dx, rows, cols, wk,
+                                                                         ry, rx, edge);
+    return launch_check("ov2_adjoint");
+}
+
+}  // namespace skel

@@ -1,5 +1,9 @@
 // Scan skeleton kernels (Section III, scan): inclusive out[i] = x[0] op ...
-// op x[i]; exclusive out[0] = identity, out[i] = x[0] op ... op x[i-1].
+// op x[i]; exclusive out[0] = identity, out[i] = x[0] op ... op x[i-1].  The
+// reverse kinds combine from the end (out[i] = x[i] op ... op x[n-1], and its
+// exclusive form); they are the adjoints of the forward sum scans and run in
+// the single-pass variant, which visits tiles, rows, lanes and vector
+// elements in descending order while keeping the ascending 16-byte layout.
 //
 // Tile layout (all variants): a workgroup of NW wavefronts (16, or 8 for 8-byte
 // inputs) owns a tile of NW * 2048 elements; each wavefront owns a contiguous
@@ -117,8 +121,10 @@ __device__ __forceinline__ void keep_raw_only(Raw<P>& raw) {
         for (int e = 0; e < P::E; ++e) asm volatile("" : "+v"(raw[r][e]));
 }
 
-// Scan the wavefront's slice given its exclusive prefix, and store it.
-template <class P, bool FULL>
+// Scan the wavefront's slice given its exclusive prefix, and store it.  REV:
+// the slice is combined from its last element down (the prefix then holds
+// everything after the slice).
+template <class P, bool FULL, bool REV = false>
 __device__ __forceinline__ void tile_scan_store(typename P::out_t* out, int64_t n, int64_t tile,
                                                 const Raw<P>& raw, typename P::acc_t prefix,
                                                 bool exclusive) {
@@ -130,24 +136,29 @@ __device__ __forceinline__ void tile_scan_store(typename P::out_t* out, int64_t 
     const int64_t b = lane_base<P>(tile);
     acc_t running = prefix;
 #pragma unroll
-    for (int r = 0; r < P::R; ++r) {
+    for (int rr = 0; rr < P::R; ++rr) {
+        const int r = REV ? P::R - 1 - rr : rr;
         const int64_t idx = b + (int64_t)r * kWave * E;
-        acc_t loc[E];  // lane-local inclusive scan of the row vector
+        acc_t loc[E];  // lane-local inclusive scan of the row vector (in scan order)
         acc_t t = C::id();
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
+        for (int ee = 0; ee < E; ++ee) {
+            const int e = REV ? E - 1 - ee : ee;
             const acc_t x = (FULL || idx + e < n) ? widen<acc_t>(raw[r][e]) : C::id();
             t = C::op(t, x);
             loc[e] = t;
         }
-        const acc_t incl = wave_inclusive_scan<C>(t);
-        const acc_t tot = __shfl(incl, kWave - 1);
-        const acc_t ex = __shfl_up(incl, 1);
-        const acc_t base = C::op(running, l == 0 ? C::id() : ex);
+        const acc_t incl = REV ? wave_inclusive_suffix_scan<C>(t) : wave_inclusive_scan<C>(t);
+        const acc_t tot = __shfl(incl, REV ? 0 : kWave - 1);
+        const acc_t ex = REV ? __shfl_down(incl, 1) : __shfl_up(incl, 1);
+        const bool first = REV ? l == kWave - 1 : l == 0;
+        const acc_t base = C::op(running, first ? C::id() : ex);
         out_t o[E];
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-            const acc_t v = exclusive ? (e == 0 ? base : C::op(base, loc[e - 1]))
+            const int before = REV ? e + 1 : e - 1;  // previous element in scan order
+            const bool none = REV ? e == E - 1 : e == 0;
+            const acc_t v = exclusive ? (none ? base : C::op(base, loc[before]))
                                       : C::op(base, loc[e]);
             o[e] = (out_t)v;
         }
@@ -170,7 +181,7 @@ __device__ __forceinline__ void tile_scan_store(typename P::out_t* out, int64_t 
 
 // Wavefront totals -> LDS; returns (exclusive prefix of this wavefront within
 // the tile, tile total) in every thread.  Contains one barrier.
-template <class P>
+template <class P, bool REV = false>
 __device__ __forceinline__ void tile_totals(typename P::acc_t lane_t, typename P::acc_t* s_wtot,
                                             typename P::acc_t* wex, typename P::acc_t* agg) {
     using C = typename P::C;
@@ -183,7 +194,7 @@ __device__ __forceinline__ void tile_totals(typename P::acc_t lane_t, typename P
 #pragma unroll
     for (int k = 0; k < P::NW; ++k) {
         const typename P::acc_t t = s_wtot[k];
-        if (k < w) *wex = C::op(*wex, t);
+        if (REV ? k > w : k < w) *wex = C::op(*wex, t);
         *agg = C::op(*agg, t);
     }
 }
@@ -246,28 +257,30 @@ __device__ typename P::acc_t lookback(u64* status, int64_t tile, typename P::acc
 }
 
 // ------------------------------------------------------------------ kernels
-template <class P, bool FULL>
+// `seq` is the tile's position in scan order (descriptor index), `tile` the
+// data tile it covers (they differ for the reverse kinds)
+template <class P, bool FULL, bool REV>
 __device__ __forceinline__ void lookback_tile(const typename P::in_t* in,
-                                              typename P::out_t* out, int64_t n, int64_t tile,
-                                              int exclusive, u64* status, u64* sync,
-                                              uint32_t epoch) {
+                                              typename P::out_t* out, int64_t n, int64_t seq,
+                                              int64_t tile, int exclusive, u64* status,
+                                              u64* sync, uint32_t epoch) {
     using acc_t = typename P::acc_t;
     __shared__ acc_t s_wtot[P::NW];
     __shared__ acc_t s_prefix;
     Raw<P> raw;
     tile_load<P, FULL, true>(in, n, tile, raw);
     acc_t wex, agg;
-    tile_totals<P>(lane_total<P, FULL>(n, tile, raw), s_wtot, &wex, &agg);
+    tile_totals<P, REV>(lane_total<P, FULL>(n, tile, raw), s_wtot, &wex, &agg);
     if (threadIdx.x < kWave) {
-        const acc_t e = lookback<P>(status, tile, agg, epoch, sync + SYNC_ERROR);
+        const acc_t e = lookback<P>(status, seq, agg, epoch, sync + SYNC_ERROR);
         if (threadIdx.x == 0) s_prefix = e;
     }
     __syncthreads();
     keep_raw_only<P>(raw);
-    tile_scan_store<P, FULL>(out, n, tile, raw, P::C::op(s_prefix, wex), exclusive != 0);
+    tile_scan_store<P, FULL, REV>(out, n, tile, raw, P::C::op(s_prefix, wex), exclusive != 0);
 }
 
-template <class P>
+template <class P, bool REV>
 __global__ __launch_bounds__(P::kBlock) void scan_lookback(const typename P::in_t* in,
                                                         typename P::out_t* out, int64_t n,
                                                         int64_t ntiles, int exclusive,
@@ -283,12 +296,13 @@ __global__ __launch_bounds__(P::kBlock) void scan_lookback(const typename P::in_
         s_tile = (int64_t)t;
     }
     __syncthreads();
-    const int64_t tile = s_tile;
+    const int64_t seq = s_tile;
+    const int64_t tile = REV ? ntiles - 1 - seq : seq;  // data tile in scan order
     const uint32_t epoch = s_epoch;
     if ((tile + 1) * P::kTile <= n)
-        lookback_tile<P, true>(in, out, n, tile, exclusive, status, sync, epoch);
+        lookback_tile<P, true, REV>(in, out, n, seq, tile, exclusive, status, sync, epoch);
     else
-        lookback_tile<P, false>(in, out, n, tile, exclusive, status, sync, epoch);
+        lookback_tile<P, false, REV>(in, out, n, seq, tile, exclusive, status, sync, epoch);
     // The workgroup that finishes last (every other one has passed its last
     // descriptor access) resets the counter and advances the epoch for the
     // next call.
@@ -417,8 +431,11 @@ skel_status scan_typed(int v, int kind, const void* x, void* y, int64_t n, Launc
     const in_t* in = static_cast<const in_t*>(x);
     out_t* out = static_cast<out_t*>(y);
     const int64_t ntiles = (n + P::kTile - 1) / P::kTile;
-    const int excl = kind == SKEL_EXCLUSIVE ? 1 : 0;
+    const bool rev = kind == SKEL_REVERSE_INCLUSIVE || kind == SKEL_REVERSE_EXCLUSIVE;
+    const int excl = (kind == SKEL_EXCLUSIVE || kind == SKEL_REVERSE_EXCLUSIVE) ? 1 : 0;
     hipStream_t st = lc.stream;
+    if (rev && v != S2_LOOKBACK)
+        return fail(SKEL_E_UNSUPPORTED, "reverse scans run in the single-pass variant only");
     switch (v) {
     case S0_SINGLE_WG:
         scan_single<P><<<1, P::kBlock, 0, st>>>(in, out, n, ntiles, excl);
@@ -439,8 +456,12 @@ skel_status scan_typed(int v, int kind, const void* x, void* y, int64_t n, Launc
         void* status = nullptr;
         skel_status e = ws_status(lc, (size_t)ntiles * 16, &status);
         if (e != SKEL_OK) return e;
-        scan_lookback<P><<<(unsigned)ntiles, P::kBlock, 0, st>>>(
-            in, out, n, ntiles, excl, static_cast<u64*>(status), lc.ws->sync);
+        if (rev)
+            scan_lookback<P, true><<<(unsigned)ntiles, P::kBlock, 0, st>>>(
+                in, out, n, ntiles, excl, static_cast<u64*>(status), lc.ws->sync);
+        else
+            scan_lookback<P, false><<<(unsigned)ntiles, P::kBlock, 0, st>>>(
+                in, out, n, ntiles, excl, static_cast<u64*>(status), lc.ws->sync);
         return launch_check("scan_lookback");
     }
     }

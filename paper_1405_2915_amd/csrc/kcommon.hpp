@@ -129,6 +129,19 @@ __device__ __forceinline__ T wave_inclusive_scan(T v) {
     return v;
 }
 
+// Inclusive suffix scan over the 64 lanes: lane l ends with v[l] op ... op
+// v[63] (lane shifts downwards).
+template <class C, class T>
+__device__ __forceinline__ T wave_inclusive_suffix_scan(T v) {
+    const int l = lane();
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        T u = __shfl_down(v, d);
+        if (l + d < kWave) v = C::op(v, u);
+    }
+    return v;
+}
+
 // Block reduction for blocks of up to 1024 threads.  `lds` holds one T per
 // wavefront.  The result is valid in every lane of wavefront 0.
 template <class C, class T>

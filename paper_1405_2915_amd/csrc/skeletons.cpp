@@ -85,9 +85,9 @@ class Operands {
         uint64_t k = ((a & SKEL_READ) ? 1 : 0) + ((a & SKEL_WRITE) ? 1 : 0);
         pending_[pending_n_++] = {c, k};
     }
-    Op ops_[4];
+    Op ops_[8];
     int n_ = 0;
-    Pending pending_[8];
+    Pending pending_[16];
     int pending_n_ = 0;
 };
 
@@ -379,7 +379,7 @@ skel_status skel_scan(skel_container* in, skel_container* out, skel_scan_kind ki
     skel_status st = begin(stream, &lc);
     if (st != SKEL_OK) return st;
     if (!in || !out) return fail(SKEL_E_INVAL, "null container");
-    if (kind != SKEL_INCLUSIVE && kind != SKEL_EXCLUSIVE)
+    if (kind < SKEL_INCLUSIVE || kind > SKEL_REVERSE_EXCLUSIVE)
         return fail(SKEL_E_INVAL, "unknown scan kind %d", (int)kind);
     if (!reduce_op_valid(op)) return fail(SKEL_E_INVAL, "unknown scan op %d", (int)op);
     const skel_dtype a = in->dtype, b = out->dtype;
@@ -395,6 +395,7 @@ skel_status skel_scan(skel_container* in, skel_container* out, skel_scan_kind ki
     cc.dout = b;
     cc.n = in->n;
     cc.op = op;
+    cc.reverse = kind == SKEL_REVERSE_INCLUSIVE || kind == SKEL_REVERSE_EXCLUSIVE;
     int v = choose_variant(variant, cc, &st);
     if (v < 0) return st;
     Operands ops;
@@ -403,6 +404,113 @@ skel_status skel_scan(skel_container* in, skel_container* out, skel_scan_kind ki
     return run(ops, stream, lc, [&]() -> skel_status {
         if (in->n == 0) return SKEL_OK;
         return launch_scan(v, kind, op, a, b, ops.ptr(in), ops.ptr(out), in->n, lc);
+    });
+}
+
+skel_status skel_map_backward(skel_map_op op, const double* params, int nparams,
+                              skel_container* const* in, int nin, skel_container* g,
+                              skel_container* const* grad_in, skel_container* grad_params,
+                              void* stream) {
+    LaunchCtx lc;
+    skel_status st = begin(stream, &lc);
+    if (st != SKEL_OK) return st;
+    float p0, p1;
+    st = check_map_args(op, params, nparams, in, nin, &p0, &p1);
+    if (st != SKEL_OK) return st;
+    if (!g || !grad_in) return fail(SKEL_E_INVAL, "null gradient argument");
+    const int64_t n = in[0]->n;
+    for (int i = 0; i < nin; ++i) {
+        if (!grad_in[i]) return fail(SKEL_E_INVAL, "null gradient container %d", i);
+        if (in[i]->dtype != SKEL_F32 || grad_in[i]->dtype != SKEL_F32)
+            return fail(SKEL_E_DTYPE, "Map backward operands must be f32");
+        if (in[i]->n != n || grad_in[i]->n != n)
+            return fail(SKEL_E_SHAPE, "Map backward operand sizes differ");
+        if (grad_in[i] == g) return fail(SKEL_E_INVAL, "gradient output aliases g");
+        for (int k = 0; k < nin; ++k)
+            if (grad_in[i] == in[k]) return fail(SKEL_E_INVAL, "gradient output aliases an input");
+        if (i == 1 && grad_in[1] == grad_in[0])
+            return fail(SKEL_E_INVAL, "the two gradient outputs alias");
+    }
+    if (g->dtype != SKEL_F32) return fail(SKEL_E_DTYPE, "g must be f32");
+    const bool bcast = g->n == 1 && n != 1;
+    if (!bcast && g->n != n) return fail(SKEL_E_SHAPE, "g has %lld elements, expected %lld or 1",
+                                         (long long)g->n, (long long)n);
+    const int np = op == SKEL_MAP_AXPY ? 1 : (op == SKEL_MAP_AFFINE || op == SKEL_MAP_AFFINE_TANH) ? 2 : 0;
+    if (grad_params) {
+        if (grad_params->dtype != SKEL_F32) return fail(SKEL_E_DTYPE, "grad_params must be f32");
+        if (grad_params->n != np)
+            return fail(SKEL_E_SHAPE, "grad_params has %lld elements, the op has %d parameter(s)",
+                        (long long)grad_params->n, np);
+        for (int k = 0; k < nin; ++k)
+            if (grad_params == in[k] || grad_params == grad_in[k] || grad_params == g)
+                return fail(SKEL_E_INVAL, "grad_params aliases another operand");
+    }
+    Operands ops;
+    for (int i = 0; i < nin; ++i) ops.add(in[i], SKEL_READ);
+    ops.add(g, SKEL_READ);
+    for (int i = 0; i < nin; ++i) ops.add(grad_in[i], SKEL_WRITE);
+    if (grad_params && np > 0) ops.add(grad_params, SKEL_WRITE);
+    return run(ops, stream, lc, [&]() -> skel_status {
+        float* dp = grad_params && np > 0 ? (float*)ops.ptr(grad_params) : nullptr;
+        if (n == 0 && !dp) return SKEL_OK;  // (n = 0 with parameters: empty sums, zeros)
+        const float* x = (const float*)ops.ptr(in[0]);
+        const float* y = nin > 1 ? (const float*)ops.ptr(in[1]) : nullptr;
+        float* dy = nin > 1 ? (float*)ops.ptr(grad_in[1]) : nullptr;
+        return launch_map_backward(op, p0, p1, x, y, (const float*)ops.ptr(g), bcast,
+                                   (float*)ops.ptr(grad_in[0]), dy, n, dp, lc);
+    });
+}
+
+skel_status skel_mapoverlap1d_backward(skel_container* g, skel_container* grad_in,
+                                       const float* w, int radius, skel_edge edge,
+                                       void* stream) {
+    LaunchCtx lc;
+    skel_status st = begin(stream, &lc);
+    if (st != SKEL_OK) return st;
+    if (!g || !grad_in || !w) return fail(SKEL_E_INVAL, "null argument");
+    if (g == grad_in) return fail(SKEL_E_INVAL, "MapOverlap backward cannot run in place");
+    if (radius < 0 || radius > SKEL_MAX_RADIUS_1D)
+        return fail(SKEL_E_INVAL, "radius %d outside 0..%d", radius, SKEL_MAX_RADIUS_1D);
+    if (edge < SKEL_EDGE_CLAMP || edge > SKEL_EDGE_CYCLIC)
+        return fail(SKEL_E_INVAL, "unknown edge rule %d", (int)edge);
+    if (g->dtype != SKEL_F32 || grad_in->dtype != SKEL_F32)
+        return fail(SKEL_E_DTYPE, "MapOverlap backward operands must be f32");
+    if (g->n != grad_in->n) return fail(SKEL_E_SHAPE, "MapOverlap backward sizes differ");
+    Operands ops;
+    ops.add(g, SKEL_READ);
+    ops.add(grad_in, SKEL_WRITE);
+    return run(ops, stream, lc, [&]() -> skel_status {
+        if (g->n == 0) return SKEL_OK;
+        return launch_overlap1d_adjoint((const float*)ops.ptr(g), (float*)ops.ptr(grad_in),
+                                        g->n, w, radius, edge, lc);
+    });
+}
+
+skel_status skel_mapoverlap2d_backward(skel_container* g, skel_container* grad_in,
+                                       const float* w2d, const float* wy, const float* wx,
+                                       int ry, int rx, skel_edge edge, void* stream) {
+    LaunchCtx lc;
+    skel_status st = begin(stream, &lc);
+    if (st != SKEL_OK) return st;
+    if (!g || !grad_in) return fail(SKEL_E_INVAL, "null container");
+    if (g == grad_in) return fail(SKEL_E_INVAL, "MapOverlap backward cannot run in place");
+    if (!w2d && (!wy || !wx))
+        return fail(SKEL_E_INVAL, "need w2d or both separable factors wy, wx");
+    if (ry < 0 || rx < 0 || ry > SKEL_MAX_RADIUS_2D || rx > SKEL_MAX_RADIUS_2D)
+        return fail(SKEL_E_INVAL, "radii (%d, %d) outside 0..%d", ry, rx, SKEL_MAX_RADIUS_2D);
+    if (edge < SKEL_EDGE_CLAMP || edge > SKEL_EDGE_CYCLIC)
+        return fail(SKEL_E_INVAL, "unknown edge rule %d", (int)edge);
+    if (g->dtype != SKEL_F32 || grad_in->dtype != SKEL_F32)
+        return fail(SKEL_E_DTYPE, "MapOverlap backward operands must be f32");
+    if (g->rows != grad_in->rows || g->cols != grad_in->cols)
+        return fail(SKEL_E_SHAPE, "MapOverlap backward shapes differ");
+    Operands ops;
+    ops.add(g, SKEL_READ);
+    ops.add(grad_in, SKEL_WRITE);
+    return run(ops, stream, lc, [&]() -> skel_status {
+        if (g->n == 0) return SKEL_OK;
+        return launch_overlap2d_adjoint((const float*)ops.ptr(g), (float*)ops.ptr(grad_in),
+                                        g->rows, g->cols, w2d, wy, wx, ry, rx, edge, lc);
     });
 }
 

@@ -379,3 +379,59 @@ def test_environment_override(rt, monkeypatch):
     # override not selectable (weights not separable): falls through
     assert name_of(rt, SK_OV2, rt.skel_select_variant(SK_OV2, F32, 100, 10, 10, 0)) \
         == "O2b_lds_tile"
+
+
+# ---------------------------------------------------- wrapped device memory
+
+def test_wrap_device_memory(rt):
+    """A container over caller-owned device memory: the device copy is valid
+    from the start, device reads copy nothing, a host read copies once, and
+    destroy never frees the caller's memory."""
+    rt.skel_container_wrap_device.argtypes = [C.c_int, C.c_int64, C.c_int64, C.c_void_p,
+                                              C.c_void_p, C.POINTER(C.c_void_p)]
+    buf = np.arange(64, dtype=np.float32)  # stands in for device memory (fake backend)
+    h = C.c_void_p()
+    assert rt.skel_container_wrap_device(F32, 1, 64, C.c_void_p(buf.ctypes.data),
+                                         C.c_void_p(1), C.byref(h)) == OK
+    before = counts(rt)
+    st, p = acquire(rt, h, DEVICE, READ, stream=1)
+    assert st == OK and p == buf.ctypes.data
+    assert rt.skel_container_release(h, DEVICE, C.c_void_p(1)) == OK
+    assert counts(rt)["h2d"] == before["h2d"] and counts(rt)["dev_allocs"] == 0
+    # another stream orders after the wrap's stream: one event, one wait
+    st, _ = acquire(rt, h, DEVICE, READ, stream=2)
+    assert st == OK and rt.skel_container_release(h, DEVICE, C.c_void_p(2)) == OK
+    assert counts(rt)["stream_waits"] == before["stream_waits"] + 1
+    st, hp = acquire(rt, h, HOST, READ)
+    assert st == OK
+    got = np.ctypeslib.as_array(C.cast(hp, C.POINTER(C.c_float)), shape=(64,)).copy()
+    assert rt.skel_container_release(h, HOST, None) == OK
+    assert np.array_equal(got, buf) and counts(rt)["d2h"] == before["d2h"] + 1
+    assert rt.skel_container_destroy(h) == OK
+    c = counts(rt)
+    assert c["dev_frees"] == 0 and c["host_frees"] == c["host_allocs"]
+
+
+def test_wrap_device_rejects_bad_arguments(rt):
+    rt.skel_container_wrap_device.argtypes = [C.c_int, C.c_int64, C.c_int64, C.c_void_p,
+                                              C.c_void_p, C.POINTER(C.c_void_p)]
+    h = C.c_void_p()
+    buf = np.zeros(32, np.float32)
+    assert rt.skel_container_wrap_device(F32, 1, 8, None, None, C.byref(h)) == E_INVAL
+    assert rt.skel_container_wrap_device(F32, 1, 8, C.c_void_p(buf.ctypes.data + 4), None,
+                                         C.byref(h)) == E_INVAL  # not 16-byte aligned
+    assert rt.skel_container_wrap_device(F32, 0, 8, C.c_void_p(buf.ctypes.data), None,
+                                         C.byref(h)) == E_SHAPE
+    assert rt.skel_container_wrap_device(9, 1, 8, C.c_void_p(buf.ctypes.data), None,
+                                         C.byref(h)) == E_DTYPE
+    # an empty wrapped container needs no memory
+    assert rt.skel_container_wrap_device(F32, 1, 0, None, None, C.byref(h)) == OK
+    assert rt.skel_container_destroy(h) == OK
+
+
+def test_reverse_scan_plan(rt):
+    sel = lambda n, aux: name_of(rt, SK_SCAN, rt.skel_select_variant(SK_SCAN, I32, n, 1, n,
+                                                                     aux))
+    assert sel(100, 0) == "S0_single_wg"
+    assert sel(100, 1) == "S2_decoupled_lookback"  # reverse kinds: single pass only
+    assert sel(1 << 27, 1) == "S2_decoupled_lookback"
