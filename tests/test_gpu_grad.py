@@ -93,10 +93,17 @@ def grad_scale(op, p, x, y):
     """magnitude of the derivative's factors (dx, dy) for the elementwise bar"""
     ax, ay = np.abs(x.astype(np.float64)), np.abs(y.astype(np.float64))
     one = np.ones_like(ax)
-    return {"identity": (one, None), "axpy": (abs(p[0]) * one, one),
-            "affine": (abs(p[0]) * one, None), "tanh": (one, None),
-            "affine_tanh": (max(1.0, abs(p[0])) * one, None), "mul": (ay, ax),
-            "square": (2 * ax, None)}[op]
+    if op in ("identity", "tanh"):
+        return one, None
+    if op == "axpy":
+        return abs(p[0]) * one, one
+    if op == "affine":
+        return abs(p[0]) * one, None
+    if op == "affine_tanh":
+        return max(1.0, abs(p[0])) * one, None
+    if op == "mul":
+        return ay, ax
+    return 2 * ax, None
 
 
 @pytest.mark.parametrize("op", list(MAP_OPS))
