@@ -203,6 +203,26 @@ skel_status skel_container_acquire(skel_container *c, skel_place place,
                                    skel_access access, void *stream,
                                    void **ptr_out);
 
+/* Range-granular form of skel_container_acquire (Section IV: partial copies).
+ * Validity is tracked per element range of each copy, so the protocol above
+ * applies to elements [first, first + count) only: READ copies just the parts
+ * of the range that are stale at `place` (one transfer per stale run), WRITE
+ * makes the range current at `place` and stale at the other place and copies
+ * nothing.  *ptr_out receives the address of element `first` of the copy.
+ * Whole-container acquires (and the skeletons' operands) are the range
+ * [0, n), so a container of which the host rewrote a few elements sends only
+ * those elements to the device at its next device read.  Errors as for
+ * skel_container_acquire, plus SKEL_E_INVAL for a range outside [0, n). */
+skel_status skel_container_acquire_range(skel_container *c, skel_place place,
+                                         skel_access access, int64_t first,
+                                         int64_t count, void *stream, void **ptr_out);
+
+/* The current element ranges of the copy at `place`: *count receives their
+ * number and pairs[2k], pairs[2k+1] (for k < max_pairs) the k-th range
+ * [first, last), in increasing order.  pairs may be NULL. */
+skel_status skel_container_valid_ranges(const skel_container *c, skel_place place,
+                                        int64_t *pairs, int64_t max_pairs, int64_t *count);
+
 /* End the access begun by the matching acquire at `place`; a device release
  * records the container's last-access event on `stream`. */
 skel_status skel_container_release(skel_container *c, skel_place place,

@@ -115,6 +115,8 @@ def load_library(path: str = LIB_PATH):
         "skel_scan": (st, [vp, vp, i, i, i, vp]),
         "skel_reduce_segments": (st, [i, vp, vp, vp, i, vp]),
         "skel_container_wrap_device": (st, [i, i64, i64, vp, vp, C.POINTER(vp)]),
+        "skel_container_acquire_range": (st, [vp, i, i, i64, i64, vp, C.POINTER(vp)]),
+        "skel_container_valid_ranges": (st, [vp, i, C.POINTER(i64), i64, C.POINTER(i64)]),
         "skel_map_backward": (st, [i, dp, i, C.POINTER(vp), i, vp, C.POINTER(vp), vp, vp]),
         "skel_mapoverlap1d_backward": (st, [vp, vp, fp, i, i, vp]),
         "skel_mapoverlap2d_backward": (st, [vp, vp, fp, fp, fp, i, i, i, vp]),
@@ -284,6 +286,34 @@ class Container:
         finally:
             skel_container_release(self, HOST)
 
+    def write_range(self, first: int, arr: np.ndarray) -> None:
+        """Host WRITE of elements [first, first + len(arr)): only that range
+        becomes stale on the device."""
+        dt = NP_DTYPE[self.dtype]
+        arr = np.ascontiguousarray(arr, dtype=dt).reshape(-1)
+        ptr = skel_container_acquire_range(self, HOST, WRITE, first, arr.size)
+        try:
+            if arr.size:
+                C.memmove(ptr, arr.ctypes.data, arr.size * dt.itemsize)
+        finally:
+            skel_container_release(self, HOST)
+
+    def read_range(self, first: int, count: int) -> np.ndarray:
+        """Host READ of elements [first, first + count): copies from the
+        device only the stale parts of that range."""
+        dt = NP_DTYPE[self.dtype]
+        ptr = skel_container_acquire_range(self, HOST, READ, first, count)
+        try:
+            out = np.empty(count, dtype=dt)
+            if count:
+                C.memmove(out.ctypes.data, ptr, count * dt.itemsize)
+        finally:
+            skel_container_release(self, HOST)
+        return out
+
+    def valid_ranges(self, place: int):
+        return skel_container_valid_ranges(self, place)
+
     def stats(self) -> dict:
         return skel_container_stats(self)
 
@@ -369,6 +399,28 @@ def skel_container_acquire(c: Container, place: int, access: int, stream=None) -
     _check(_L().skel_container_acquire(_h(c), place, access, C.c_void_p(_stream(stream)),
                                        C.byref(ptr)), "skel_container_acquire")
     return ptr.value or 0
+
+
+def skel_container_acquire_range(c: Container, place: int, access: int, first: int,
+                                 count: int, stream=None) -> int:
+    """Acquire elements [first, first + count) only; returns the address of
+    element `first` of the copy at `place`."""
+    ptr = C.c_void_p()
+    _check(_L().skel_container_acquire_range(_h(c), place, access, int(first), int(count),
+                                             C.c_void_p(_stream(stream)), C.byref(ptr)),
+           "skel_container_acquire_range")
+    return ptr.value or 0
+
+
+def skel_container_valid_ranges(c: Container, place: int):
+    """[(first, last), ...] element ranges that are current at `place`."""
+    cnt = C.c_int64()
+    _check(_L().skel_container_valid_ranges(_h(c), place, None, 0, C.byref(cnt)),
+           "skel_container_valid_ranges")
+    buf = (C.c_int64 * (2 * max(cnt.value, 1)))()
+    _check(_L().skel_container_valid_ranges(_h(c), place, buf, cnt.value, C.byref(cnt)),
+           "skel_container_valid_ranges")
+    return [(buf[2 * k], buf[2 * k + 1]) for k in range(cnt.value)]
 
 
 def skel_container_release(c: Container, place: int, stream=None) -> None:

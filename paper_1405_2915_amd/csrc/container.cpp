@@ -84,13 +84,66 @@ skel_status ensure_host(skel_container* c) {
 
 }  // namespace
 
-skel_status check_acquire(const skel_container* c, skel_place place,
-                          skel_access access) {
+void ranges_add(skel_ranges& s, int64_t lo, int64_t hi) {
+    if (lo >= hi) return;
+    std::vector<std::pair<int64_t, int64_t>> out;
+    out.reserve(s.r.size() + 1);
+    bool placed = false;
+    for (const auto& q : s.r) {
+        if (q.second < lo) {
+            out.push_back(q);  // entirely before (not touching)
+        } else if (q.first > hi) {
+            if (!placed) out.emplace_back(lo, hi), placed = true;
+            out.push_back(q);  // entirely after
+        } else {  // overlaps or touches: merge into [lo, hi)
+            lo = q.first < lo ? q.first : lo;
+            hi = q.second > hi ? q.second : hi;
+        }
+    }
+    if (!placed) out.emplace_back(lo, hi);
+    s.r.swap(out);
+}
+
+void ranges_sub(skel_ranges& s, int64_t lo, int64_t hi) {
+    if (lo >= hi) return;
+    std::vector<std::pair<int64_t, int64_t>> out;
+    out.reserve(s.r.size() + 1);
+    for (const auto& q : s.r) {
+        if (q.second <= lo || q.first >= hi) {
+            out.push_back(q);
+            continue;
+        }
+        if (q.first < lo) out.emplace_back(q.first, lo);
+        if (q.second > hi) out.emplace_back(hi, q.second);
+    }
+    s.r.swap(out);
+}
+
+std::vector<std::pair<int64_t, int64_t>> ranges_missing(const skel_ranges& s, int64_t lo,
+                                                        int64_t hi) {
+    std::vector<std::pair<int64_t, int64_t>> gaps;
+    int64_t at = lo;
+    for (const auto& q : s.r) {
+        if (q.second <= at) continue;
+        if (q.first >= hi) break;
+        if (q.first > at) gaps.emplace_back(at, q.first);
+        at = q.second;
+        if (at >= hi) break;
+    }
+    if (at < hi) gaps.emplace_back(at, hi);
+    return gaps;
+}
+
+skel_status check_acquire(const skel_container* c, skel_place place, skel_access access,
+                          int64_t lo, int64_t hi) {
     if (!c) return fail(SKEL_E_INVAL, "null container");
     if (place != SKEL_HOST && place != SKEL_DEVICE)
         return fail(SKEL_E_INVAL, "bad place %d", (int)place);
     if (access != SKEL_READ && access != SKEL_WRITE && access != SKEL_RW)
         return fail(SKEL_E_INVAL, "bad access mode %d", (int)access);
+    if (lo < 0 || hi < lo || hi > c->n)
+        return fail(SKEL_E_INVAL, "element range [%lld, %lld) outside [0, %lld)", (long long)lo,
+                    (long long)hi, (long long)c->n);
     if (c->writer != -1)
         return fail(SKEL_E_STATE, "container has an outstanding %s write access",
                     c->writer == SKEL_HOST ? "host" : "device");
@@ -98,16 +151,23 @@ skel_status check_acquire(const skel_container* c, skel_place place,
         return fail(SKEL_E_STATE,
                     "write access requested while %d read access(es) are outstanding",
                     c->host_readers + c->dev_readers);
-    if (has_read(access) && !c->host_valid && !c->dev_valid)
-        return fail(SKEL_E_STATE, "read of an uninitialised container");
+    if (has_read(access)) {
+        // every element read must be current in one of the copies
+        for (const auto& m : ranges_missing(c->valid_host, lo, hi))
+            if (!ranges_missing(c->valid_dev, m.first, m.second).empty())
+                return fail(SKEL_E_STATE, "read of an uninitialised container (elements "
+                            "[%lld, %lld) were never written)", (long long)m.first,
+                            (long long)m.second);
+    }
     return SKEL_OK;
 }
 
-skel_status acquire(skel_container* c, skel_place place, skel_access access,
-                    void* stream, void** ptr) {
-    skel_status st = check_acquire(c, place, access);
+skel_status acquire(skel_container* c, skel_place place, skel_access access, int64_t lo,
+                    int64_t hi, void* stream, void** ptr) {
+    skel_status st = check_acquire(c, place, access, lo, hi);
     if (st != SKEL_OK) return st;
     Backend* be = rt().backend;
+    const size_t es = dtype_size(c->dtype);
 
     if (place == SKEL_DEVICE) {
         if (c->bytes > 0) {
@@ -118,45 +178,60 @@ skel_status acquire(skel_container* c, skel_place place, skel_access access,
             // order after device work on other streams (Section V dependences)
             st = order_after_other_streams(c, stream);
             if (st != SKEL_OK) return st;
-            if (has_read(access) && !c->dev_valid) {
-                st = be->copy_h2d(c->dev, c->host, c->bytes, stream);
-                if (st != SKEL_OK) return st;
-                c->stats.h2d += 1;
-                c->stats.h2d_bytes += c->bytes;
+            if (has_read(access)) {
+                // copy only the stale parts of the range (partial copies)
+                for (const auto& m : ranges_missing(c->valid_dev, lo, hi)) {
+                    const size_t off = (size_t)m.first * es, len = (size_t)(m.second - m.first) * es;
+                    st = be->copy_h2d(static_cast<char*>(c->dev) + off,
+                                      static_cast<const char*>(c->host) + off, len, stream);
+                    if (st != SKEL_OK) return st;
+                    c->stats.h2d += 1;
+                    c->stats.h2d_bytes += len;
+                    ranges_add(c->valid_dev, m.first, m.second);
+                }
             }
         }
-        c->dev_valid = true;
-        if (has_write(access)) c->host_valid = false;
+        ranges_add(c->valid_dev, lo, hi);
+        if (has_write(access)) ranges_sub(c->valid_host, lo, hi);
         c->last_stream = stream;
         if (has_write(access)) c->writer = SKEL_DEVICE;
         else c->dev_readers += 1;
-        *ptr = c->dev;
+        *ptr = c->dev ? static_cast<char*>(c->dev) + (size_t)lo * es : nullptr;
     } else {
         st = wait_device_idle(c);
         if (st != SKEL_OK) return st;
         if (c->bytes > 0) {
             st = ensure_host(c);
             if (st != SKEL_OK) return st;
-            if (has_read(access) && !c->host_valid) {
-                st = be->copy_d2h(c->host, c->dev, c->bytes, c->last_stream);
-                if (st != SKEL_OK) return st;
-                skel_container::StreamEvent* e = event_for(c, c->last_stream, &st);
-                if (!e) return st;
-                st = be->event_record(e->event, c->last_stream);
-                if (st == SKEL_OK) st = be->event_sync(e->event);
-                if (st != SKEL_OK) return st;
-                e->recorded = true;
-                e->pending = false;
-                e->gen += 1;
-                c->stats.d2h += 1;
-                c->stats.d2h_bytes += c->bytes;
+            if (has_read(access)) {
+                const auto gaps = ranges_missing(c->valid_host, lo, hi);
+                for (const auto& m : gaps) {
+                    const size_t off = (size_t)m.first * es, len = (size_t)(m.second - m.first) * es;
+                    st = be->copy_d2h(static_cast<char*>(c->host) + off,
+                                      static_cast<const char*>(c->dev) + off, len,
+                                      c->last_stream);
+                    if (st != SKEL_OK) return st;
+                    c->stats.d2h += 1;
+                    c->stats.d2h_bytes += len;
+                }
+                if (!gaps.empty()) {
+                    skel_container::StreamEvent* e = event_for(c, c->last_stream, &st);
+                    if (!e) return st;
+                    st = be->event_record(e->event, c->last_stream);
+                    if (st == SKEL_OK) st = be->event_sync(e->event);
+                    if (st != SKEL_OK) return st;
+                    e->recorded = true;
+                    e->pending = false;
+                    e->gen += 1;
+                    for (const auto& m : gaps) ranges_add(c->valid_host, m.first, m.second);
+                }
             }
         }
-        c->host_valid = true;
-        if (has_write(access)) c->dev_valid = false;
+        ranges_add(c->valid_host, lo, hi);
+        if (has_write(access)) ranges_sub(c->valid_dev, lo, hi);
         if (has_write(access)) c->writer = SKEL_HOST;
         else c->host_readers += 1;
-        *ptr = c->host;
+        *ptr = c->host ? static_cast<char*>(c->host) + (size_t)lo * es : nullptr;
     }
     c->stats.acquires += 1;
     return SKEL_OK;
@@ -214,7 +289,7 @@ skel_status skel_container_create(skel_dtype dtype, int64_t rows, int64_t cols,
     c->bytes = (size_t)c->n * dtype_size(dtype);
     c->allocator = rt().allocator;
     if (c->bytes == 0) {
-        c->host_valid = c->dev_valid = true;  // nothing to hold
+        // nothing to hold: every (empty) range is current
     } else if (host_src) {
         skel_status st = rt().backend->host_alloc(&c->host, c->bytes);
         if (st != SKEL_OK) {
@@ -222,7 +297,7 @@ skel_status skel_container_create(skel_dtype dtype, int64_t rows, int64_t cols,
             return st;
         }
         std::memcpy(c->host, host_src, c->bytes);
-        c->host_valid = true;
+        ranges_add(c->valid_host, 0, c->n);
     }
     *out = c;
     return SKEL_OK;
@@ -251,12 +326,10 @@ skel_status skel_container_wrap_device(skel_dtype dtype, int64_t rows, int64_t c
     c->n = rows * cols;
     c->bytes = bytes;
     c->allocator = rt().allocator;
-    if (bytes == 0) {
-        c->host_valid = c->dev_valid = true;
-    } else {
+    if (bytes > 0) {
         c->dev = dev_ptr;
         c->dev_external = true;
-        c->dev_valid = true;
+        ranges_add(c->valid_dev, 0, c->n);
         // the contents were produced in `stream` order: treat that as the
         // container's last device access (its event is recorded when another
         // stream or the host first needs it)
@@ -297,6 +370,30 @@ skel_status skel_container_acquire(skel_container* c, skel_place place,
     if (!rt().initialized) return fail(SKEL_E_NOINIT, "skel_init has not been called");
     if (!ptr_out) return fail(SKEL_E_INVAL, "null ptr_out");
     return acquire(c, place, access, stream, ptr_out);
+}
+
+skel_status skel_container_acquire_range(skel_container* c, skel_place place,
+                                         skel_access access, int64_t first, int64_t count,
+                                         void* stream, void** ptr_out) {
+    if (!rt().initialized) return fail(SKEL_E_NOINIT, "skel_init has not been called");
+    if (!ptr_out) return fail(SKEL_E_INVAL, "null ptr_out");
+    if (count < 0 || first < 0) return fail(SKEL_E_INVAL, "negative range");
+    return acquire(c, place, access, first, first + count, stream, ptr_out);
+}
+
+skel_status skel_container_valid_ranges(const skel_container* c, skel_place place,
+                                        int64_t* pairs, int64_t max_pairs, int64_t* count) {
+    if (!c || !count) return fail(SKEL_E_INVAL, "null argument");
+    if (place != SKEL_HOST && place != SKEL_DEVICE)
+        return fail(SKEL_E_INVAL, "bad place %d", (int)place);
+    const auto& s = place == SKEL_HOST ? c->valid_host : c->valid_dev;
+    *count = (int64_t)s.r.size();
+    if (pairs)
+        for (int64_t k = 0; k < *count && k < max_pairs; ++k) {
+            pairs[2 * k] = s.r[k].first;
+            pairs[2 * k + 1] = s.r[k].second;
+        }
+    return SKEL_OK;
 }
 
 skel_status skel_container_release(skel_container* c, skel_place place,

@@ -9,6 +9,12 @@
 
 #include "common.hpp"
 
+// Sorted, disjoint element ranges [first, last) of one copy that hold current
+// data (range-granular coherence: Section IV's partial copies).
+struct skel_ranges {
+    std::vector<std::pair<int64_t, int64_t>> r;
+};
+
 struct skel_container {
     skel_dtype dtype;
     int64_t rows, cols, n;
@@ -18,8 +24,9 @@ struct skel_container {
     void* host = nullptr;  // pinned host copy, allocated on first need
     void* dev = nullptr;   // device copy, allocated on first device acquire
     bool dev_external = false;  // dev is caller-owned (wrapped): never freed here
-    bool host_valid = false;
-    bool dev_valid = false;
+    // element ranges of each copy that are current; every acquire updates
+    // them for the range it names (a whole-container acquire names [0, n))
+    skel_ranges valid_host, valid_dev;
 
     // One event per stream that has accessed the device copy.  A device release
     // only marks the stream `pending`; the event is recorded when someone must
@@ -47,13 +54,30 @@ struct skel_container {
 
 namespace skel {
 
-// Check, without side effects, that `access` at `place` would succeed.
-skel_status check_acquire(const skel_container* c, skel_place place,
-                          skel_access access);
+// interval-set operations on skel_ranges
+void ranges_add(skel_ranges& s, int64_t lo, int64_t hi);
+void ranges_sub(skel_ranges& s, int64_t lo, int64_t hi);
+// the parts of [lo, hi) that `s` does not cover, in order
+std::vector<std::pair<int64_t, int64_t>> ranges_missing(const skel_ranges& s, int64_t lo,
+                                                        int64_t hi);
 
-// The coherence protocol proper (see skel_container_acquire in skel.h).
-skel_status acquire(skel_container* c, skel_place place, skel_access access,
-                    void* stream, void** ptr);
+// Check, without side effects, that `access` to elements [lo, hi) at `place`
+// would succeed (whole container: lo = 0, hi = n).
+skel_status check_acquire(const skel_container* c, skel_place place, skel_access access,
+                          int64_t lo, int64_t hi);
+inline skel_status check_acquire(const skel_container* c, skel_place place,
+                                 skel_access access) {
+    return check_acquire(c, place, access, 0, c ? c->n : 0);
+}
+
+// The coherence protocol proper (see skel_container_acquire in skel.h); *ptr
+// receives the address of element lo of the copy.
+skel_status acquire(skel_container* c, skel_place place, skel_access access, int64_t lo,
+                    int64_t hi, void* stream, void** ptr);
+inline skel_status acquire(skel_container* c, skel_place place, skel_access access,
+                           void* stream, void** ptr) {
+    return acquire(c, place, access, 0, c ? c->n : 0, stream, ptr);
+}
 skel_status release(skel_container* c, skel_place place, void* stream);
 
 }  // namespace skel

@@ -435,3 +435,164 @@ def test_reverse_scan_plan(rt):
     assert sel(100, 0) == "S0_single_wg"
     assert sel(100, 1) == "S2_decoupled_lookback"  # reverse kinds: single pass only
     assert sel(1 << 27, 1) == "S2_decoupled_lookback"
+
+
+# ------------------------------------------------- range-granular coherence
+
+def _runs(mask):
+    """[(first, last), ...] runs of True in a boolean array."""
+    out, i, n = [], 0, len(mask)
+    while i < n:
+        if mask[i]:
+            j = i
+            while j < n and mask[j]:
+                j += 1
+            out.append((i, j))
+            i = j
+        else:
+            i += 1
+    return out
+
+
+def _ranges(rt, h, place):
+    cnt = C.c_int64()
+    assert rt.skel_container_valid_ranges(h, place, None, 0, C.byref(cnt)) == OK
+    buf = (C.c_int64 * (2 * max(cnt.value, 1)))()
+    assert rt.skel_container_valid_ranges(h, place, buf, cnt.value, C.byref(cnt)) == OK
+    return [(buf[2 * k], buf[2 * k + 1]) for k in range(cnt.value)]
+
+
+def _setup_range_api(rt):
+    rt.skel_container_acquire_range.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int64,
+                                                C.c_int64, C.c_void_p, C.POINTER(C.c_void_p)]
+    rt.skel_container_valid_ranges.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_int64),
+                                               C.c_int64, C.POINTER(C.c_int64)]
+
+
+def _acq_range(rt, h, place, access, first, count, stream=1):
+    p = C.c_void_p()
+    st = rt.skel_container_acquire_range(h, place, access, first, count, C.c_void_p(stream),
+                                         C.byref(p))
+    return st, p.value
+
+
+def test_partial_host_write_sends_only_that_range(rt):
+    _setup_range_api(rt)
+    n = 1000
+    data = np.arange(n, dtype=np.float32)
+    h = create(rt, n, data)
+    st, _ = acquire(rt, h, DEVICE, READ)          # first device read: whole copy
+    assert st == OK and rt.skel_container_release(h, DEVICE, C.c_void_p(1)) == OK
+    s0 = stats(rt, h)
+    assert s0["h2d"] == 1 and s0["h2d_bytes"] == 4 * n
+    st, p = _acq_range(rt, h, HOST, WRITE, 100, 50)
+    assert st == OK
+    C.memmove(p, np.full(50, -1.0, np.float32).ctypes.data, 200)
+    assert rt.skel_container_release(h, HOST, None) == OK
+    assert _ranges(rt, h, DEVICE) == [(0, 100), (150, n)]
+    assert _ranges(rt, h, HOST) == [(0, n)]
+    st, dp = acquire(rt, h, DEVICE, READ)          # whole read: copies the 50 only
+    assert st == OK and rt.skel_container_release(h, DEVICE, C.c_void_p(1)) == OK
+    s1 = stats(rt, h)
+    assert s1["h2d"] == 2 and s1["h2d_bytes"] == 4 * n + 200
+    dev = np.ctypeslib.as_array(C.cast(dp, C.POINTER(C.c_float)), shape=(n,))
+    want = data.copy()
+    want[100:150] = -1.0
+    assert np.array_equal(dev, want)
+
+
+def test_partial_host_read_copies_only_the_range(rt):
+    _setup_range_api(rt)
+    n = 512
+    h = create(rt, n, np.zeros(n, np.float32))
+    st, dp = acquire(rt, h, DEVICE, WRITE)        # a kernel rewrites everything
+    C.memmove(dp, np.arange(n, dtype=np.float32).ctypes.data, 4 * n)
+    assert rt.skel_container_release(h, DEVICE, C.c_void_p(1)) == OK
+    assert _ranges(rt, h, HOST) == []
+    st, p = _acq_range(rt, h, HOST, READ, 10, 20)
+    got = np.ctypeslib.as_array(C.cast(p, C.POINTER(C.c_float)), shape=(20,)).copy()
+    assert rt.skel_container_release(h, HOST, None) == OK
+    assert np.array_equal(got, np.arange(10, 30, dtype=np.float32))
+    s = stats(rt, h)
+    assert s["d2h"] == 1 and s["d2h_bytes"] == 80
+    assert _ranges(rt, h, HOST) == [(10, 30)]
+    # a range that is already current copies nothing
+    st, _ = _acq_range(rt, h, HOST, READ, 12, 5)
+    assert st == OK and rt.skel_container_release(h, HOST, None) == OK
+    assert stats(rt, h)["d2h"] == 1
+
+
+def test_range_errors(rt):
+    _setup_range_api(rt)
+    h = create(rt, 16)                             # uninitialised
+    st, _ = _acq_range(rt, h, HOST, WRITE, 0, 8)
+    assert st == OK and rt.skel_container_release(h, HOST, None) == OK
+    assert _acq_range(rt, h, DEVICE, READ, 0, 8)[0] == OK
+    assert rt.skel_container_release(h, DEVICE, C.c_void_p(1)) == OK
+    assert _acq_range(rt, h, DEVICE, READ, 4, 8)[0] == E_STATE   # [8, 12) never written
+    assert _acq_range(rt, h, HOST, READ, 10, 10)[0] == E_INVAL   # past the end
+    assert _acq_range(rt, h, HOST, READ, -1, 2)[0] == E_INVAL
+    assert _acq_range(rt, h, HOST, READ, 3, 0)[0] == OK          # empty range
+    assert rt.skel_container_release(h, HOST, None) == OK
+
+
+def test_range_protocol_random_traces(rt):
+    """Random range reads and writes at both places against a model of the
+    per-element validity and of the data; every transfer is counted."""
+    _setup_range_api(rt)
+    rng = np.random.default_rng(1405)
+    for trial in range(30):
+        n = int(rng.integers(1, 300))
+        truth = rng.standard_normal(n).astype(np.float32)
+        h = create(rt, n, truth)
+        hv, dv = np.ones(n, bool), np.zeros(n, bool)
+        h2d = d2h = h2d_b = d2h_b = 0
+        for step in range(60):
+            a = int(rng.integers(0, n + 1))
+            b = int(rng.integers(a, n + 1))
+            if rng.random() < 0.2:
+                a, b = 0, n
+            kind = int(rng.integers(0, 4))
+            if kind == 0:    # host write
+                vals = rng.standard_normal(b - a).astype(np.float32)
+                st, p = _acq_range(rt, h, HOST, WRITE, a, b - a)
+                assert st == OK
+                if b > a:
+                    C.memmove(p, vals.ctypes.data, 4 * (b - a))
+                assert rt.skel_container_release(h, HOST, None) == OK
+                truth[a:b] = vals
+                hv[a:b], dv[a:b] = True, False
+            elif kind == 1:  # device write (stands in for a kernel)
+                vals = rng.standard_normal(b - a).astype(np.float32)
+                st, p = _acq_range(rt, h, DEVICE, WRITE, a, b - a)
+                assert st == OK
+                if b > a:
+                    C.memmove(p, vals.ctypes.data, 4 * (b - a))
+                assert rt.skel_container_release(h, DEVICE, C.c_void_p(1)) == OK
+                truth[a:b] = vals
+                dv[a:b], hv[a:b] = True, False
+            else:            # read at one place
+                place = HOST if kind == 2 else DEVICE
+                valid = hv if place == HOST else dv
+                gaps = _runs(~valid[a:b])
+                st, p = _acq_range(rt, h, place, READ, a, b - a)
+                assert st == OK, (trial, step)
+                got = (np.ctypeslib.as_array(C.cast(p, C.POINTER(C.c_float)), shape=(b - a,))
+                       .copy() if b > a else np.zeros(0, np.float32))
+                assert rt.skel_container_release(h, place, None if place == HOST
+                                                 else C.c_void_p(1)) == OK
+                assert np.array_equal(got, truth[a:b]), (trial, step)
+                moved = sum(e - s for s, e in gaps)
+                if place == HOST:
+                    d2h += len(gaps)
+                    d2h_b += 4 * moved
+                else:
+                    h2d += len(gaps)
+                    h2d_b += 4 * moved
+                valid[a:b] = True
+            s = stats(rt, h)
+            assert (s["h2d"], s["h2d_bytes"], s["d2h"], s["d2h_bytes"]) == (h2d, h2d_b, d2h, d2h_b), \
+                (trial, step)
+            assert _ranges(rt, h, HOST) == _runs(hv)
+            assert _ranges(rt, h, DEVICE) == _runs(dv)
+        assert rt.skel_container_destroy(h) == OK

@@ -128,3 +128,31 @@ def test_variant_names_and_plan(skel):
 def test_sync_reports_no_error(skel):
     skel.skel_sync()
     skel.skel_sync(0)
+
+
+def test_range_granular_coherence(skel, oracle_mod):
+    """After the host rewrites a few elements of a device-resident operand,
+    the next skeleton call moves only those elements; a host read of part of
+    a device-written result moves only that part."""
+    import synth_inputs as si
+    n = (1 << 22) + 3
+    xh = si.normal_f32(n, 11, 0)
+    x = skel.Container.from_numpy(xh)
+    y = skel.Container.empty(skel.F32, n)
+    skel.skel_map(skel.MAP_AFFINE, [2.0, 1.0], [x], y)
+    assert x.stats()["h2d_bytes"] == 4 * n
+    patch = si.normal_f32(1000, 11, 1)
+    x.write_range(123457, patch)
+    xh[123457:124457] = patch
+    assert x.valid_ranges(skel.DEVICE) == [(0, 123457), (124457, n)]
+    skel.skel_map(skel.MAP_AFFINE, [2.0, 1.0], [x], y)
+    s = x.stats()
+    assert s["h2d"] == 2 and s["h2d_bytes"] == 4 * n + 4000
+    part = y.read_range(123000, 2000)
+    assert y.stats()["d2h_bytes"] == 8000
+    ref = oracle_mod.map_f32("affine", [2.0, 1.0], xh[123000:125000])
+    assert np.all(np.abs(part - ref) <= 1e-6 * (2 * np.abs(xh[123000:125000]) + 1))
+    full = y.to_numpy()  # the rest of the result, in two runs around the part read
+    assert y.stats()["d2h"] == 3 and y.stats()["d2h_bytes"] == 4 * n
+    assert np.all(np.abs(full - oracle_mod.map_f32("affine", [2.0, 1.0], xh))
+                  <= 1e-6 * (2 * np.abs(xh) + 1))
