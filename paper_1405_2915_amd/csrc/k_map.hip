@@ -6,9 +6,9 @@
 //       form every GPU port starts from);
 //   M1  16-byte vector loads/stores (4 floats per lane per step), grid-stride;
 //   M2  each lane moves four 16-byte vectors of one 4096-element chunk per
-//       workgroup (all loads issued before any arithmetic); non-temporal
-//       stores (measured faster than plain ones for this pattern: saxpy on
-//       2^26 floats 123 us against 150 us).
+//       workgroup (all loads issued before any arithmetic), with
+//       non-temporal loads and stores (measured in the bench step, saxpy on
+//       2^26 floats: 128 us, against 145-161 us with plain loads or stores).
 // All three are HBM-bound streams: 8 or 12 bytes per element, 1-2 flops.
 #include "kcommon.hpp"
 #include "launch.hpp"
@@ -86,8 +86,9 @@ __global__ __launch_bounds__(kBlock) void map_m2(const float* x, const float* y,
         f32x4 a[kM2Unroll], b[kM2Unroll];
 #pragma unroll
         for (int u = 0; u < kM2Unroll; ++u) {
-            a[u] = xv[u * kBlock + threadIdx.x];
-            b[u] = two_inputs<OP>() ? yv[u * kBlock + threadIdx.x] : f32x4{0.f, 0.f, 0.f, 0.f};
+            a[u] = __builtin_nontemporal_load(&xv[u * kBlock + threadIdx.x]);
+            b[u] = two_inputs<OP>() ? __builtin_nontemporal_load(&yv[u * kBlock + threadIdx.x])
+                                    : f32x4{0.f, 0.f, 0.f, 0.f};
         }
 #pragma unroll
         for (int u = 0; u < kM2Unroll; ++u)

@@ -132,55 +132,88 @@ __global__ __launch_bounds__(kBlock) void ov1_lds(const float* x, float* out, in
     }
 }
 
-// O1c: no LDS and no barrier.  Each wavefront owns 256 consecutive outputs
-// (one 16-byte vector per lane); the r <= 4 neighbours on either side of a
-// lane's vector come from the adjacent lanes by cross-lane shuffles, and the
-// two lanes at the wavefront's ends read one extra vector each (from cache).
-// Wavefront rows that touch the array ends take the scalar path.
+// O1c: no LDS and no barrier.  Each wavefront owns kShflRows consecutive rows
+// of 256 outputs (one 16-byte vector per lane per row, every row's load
+// issued before any arithmetic); the r <= 4 neighbours on either side of a
+// lane's vector come from the adjacent lanes by cross-lane shuffles, a row's
+// end lanes take theirs from the adjacent row's end lane, and the first and
+// last lanes of the group read one extra vector each (from cache).  Groups
+// that touch the array ends take the scalar path.
+// rows of 64 vectors per wavefront: one measured fastest in the bench step
+// (5-point stencil on 2^26 floats: 103 us with one row, 112 with two or four,
+// 123 with eight); more rows mean fewer, longer-lived wavefronts
+#ifndef SKEL_O1C_ROWS
+#define SKEL_O1C_ROWS 1
+#endif
+constexpr int kShflRows = SKEL_O1C_ROWS;
+
 template <int RT>
 __global__ __launch_bounds__(kBlock) void ov1_shfl(const float* x, float* out, int64_t n, W1 w,
                                                    int r_, int edge, float pad) {
     constexpr int MR = RT >= 0 ? RT : 4;
+    constexpr int U = kShflRows;
     const int r = RT >= 0 ? RT : r_;
     const int l = dev::lane();
-    const int64_t wb = ((int64_t)blockIdx.x * kBlock + threadIdx.x - l) * 4;  // row start
-    if (wb >= n) return;
-    const bool interior = wb - 4 >= 0 && wb + 4 * dev::kWave + 4 <= n;
+    // this wavefront's U consecutive rows of 64 x 4 elements
+    const int64_t wb0 = ((int64_t)blockIdx.x * kBlock + threadIdx.x - l) * 4 * U;
+    if (wb0 >= n) return;
+    const bool interior = wb0 - 4 >= 0 && wb0 + 4 * dev::kWave * U + 4 <= n;
     if (interior) {
-        const f32x4* xv = reinterpret_cast<const f32x4*>(x + wb);
-        const f32x4 c = xv[l];
-        f32x4 lt, rt;
-        lt.x = __shfl_up(c.x, 1);
-        lt.y = __shfl_up(c.y, 1);
-        lt.z = __shfl_up(c.z, 1);
-        lt.w = __shfl_up(c.w, 1);
-        rt.x = __shfl_down(c.x, 1);
-        rt.y = __shfl_down(c.y, 1);
-        rt.z = __shfl_down(c.z, 1);
-        rt.w = __shfl_down(c.w, 1);
-        if (l == 0) lt = xv[-1];
-        if (l == dev::kWave - 1) rt = xv[dev::kWave];
-        const float v[12] = {lt.x, lt.y, lt.z, lt.w, c.x, c.y, c.z, c.w,
-                             rt.x, rt.y, rt.z, rt.w};
-        float acc[4] = {0.f, 0.f, 0.f, 0.f};
+        const f32x4* xv = reinterpret_cast<const f32x4*>(x + wb0);
+        f32x4 c[U];
 #pragma unroll
-        for (int k = 0; k <= 2 * MR; ++k) {
-            if (k > 2 * r) break;
+        for (int k = 0; k < U; ++k) c[k] = xv[k * dev::kWave + l];  // all loads in flight
+        f32x4 edge_l = {0.f, 0.f, 0.f, 0.f}, edge_r = {0.f, 0.f, 0.f, 0.f};
+        if (l == 0) edge_l = xv[-1];
+        if (l == dev::kWave - 1) edge_r = xv[U * dev::kWave];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) acc[q] = __builtin_fmaf(w.w[k], v[4 + q + k - r], acc[q]);
+        for (int k = 0; k < U; ++k) {
+            // neighbours: adjacent lanes of the same row; at the row ends, the
+            // adjacent row's end lane (or the extra halo vectors)
+            const f32x4 prev = k > 0 ? c[k - 1] : edge_l;
+            const f32x4 next = k + 1 < U ? c[k + 1] : edge_r;
+            f32x4 lt, rt;
+            lt.x = __shfl_up(c[k].x, 1);
+            lt.y = __shfl_up(c[k].y, 1);
+            lt.z = __shfl_up(c[k].z, 1);
+            lt.w = __shfl_up(c[k].w, 1);
+            rt.x = __shfl_down(c[k].x, 1);
+            rt.y = __shfl_down(c[k].y, 1);
+            rt.z = __shfl_down(c[k].z, 1);
+            rt.w = __shfl_down(c[k].w, 1);
+            const f32x4 pl = {__shfl(prev.x, dev::kWave - 1), __shfl(prev.y, dev::kWave - 1),
+                              __shfl(prev.z, dev::kWave - 1), __shfl(prev.w, dev::kWave - 1)};
+            const f32x4 nf = {__shfl(next.x, 0), __shfl(next.y, 0), __shfl(next.z, 0),
+                              __shfl(next.w, 0)};
+            if (l == 0) lt = k > 0 ? pl : edge_l;
+            if (l == dev::kWave - 1) rt = k + 1 < U ? nf : edge_r;
+            const float v[12] = {lt.x, lt.y, lt.z, lt.w, c[k].x, c[k].y, c[k].z, c[k].w,
+                                 rt.x, rt.y, rt.z, rt.w};
+            float acc[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int kk = 0; kk <= 2 * MR; ++kk) {
+                if (kk > 2 * r) break;
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    acc[q] = __builtin_fmaf(w.w[kk], v[4 + q + kk - r], acc[q]);
+            }
+            // plain store: measured faster than non-temporal here (5-point
+            // stencil on 2^26 floats: 96 us against 103 us)
+            reinterpret_cast<f32x4*>(out + wb0)[k * dev::kWave + l] =
+                f32x4{acc[0], acc[1], acc[2], acc[3]};
         }
-        // plain store: measured faster than non-temporal here (5-point
-        // stencil on 2^26 floats: 96 us against 103 us)
-        reinterpret_cast<f32x4*>(out + wb)[l] = f32x4{acc[0], acc[1], acc[2], acc[3]};
     } else {
+        for (int k = 0; k < U; ++k) {
+            const int64_t wb = wb0 + (int64_t)k * 4 * dev::kWave;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int64_t i = wb + 4 * l + q;
-            if (i >= n) break;
-            float acc = 0.0f;
-            for (int k = 0; k <= 2 * r; ++k)
-                acc = __builtin_fmaf(w.w[k], fetch1(x, n, i + k - r, edge, pad), acc);
-            out[i] = acc;
+            for (int q = 0; q < 4; ++q) {
+                const int64_t i = wb + 4 * l + q;
+                if (i >= n) break;
+                float acc = 0.0f;
+                for (int kk = 0; kk <= 2 * r; ++kk)
+                    acc = __builtin_fmaf(w.w[kk], fetch1(x, n, i + kk - r, edge, pad), acc);
+                out[i] = acc;
+            }
         }
     }
 }
@@ -472,8 +505,8 @@ skel_status run1d(int v, const float* x, float* out, int64_t n, const W1& w, int
         return launch_check("overlap1d_direct");
     }
     if (v == O1C_SHUFFLE) {  // selectable for r <= 4 only
-        ov1_shfl<RT><<<(unsigned)div_up(n, 4 * kBlock), kBlock, 0, st>>>(x, out, n, w, r, edge,
-                                                                           pad);
+        ov1_shfl<RT><<<(unsigned)div_up(n, 4 * kBlock * kShflRows), kBlock, 0, st>>>(
+            x, out, n, w, r, edge, pad);
         return launch_check("overlap1d_shuffle");
     }
     ov1_lds<RT><<<(unsigned)div_up(n, kT1), kBlock, 0, st>>>(x, out, n, w, r, edge, pad);
