@@ -419,7 +419,10 @@ __global__ __launch_bounds__(kBlock) void ov2_sep(const float* x, float* out, in
 // row-pass result of a 64 x 32 tile.  The small LDS footprint allows full
 // occupancy, and the 32-row tile keeps 4x more workgroups in flight than the
 // 64 x 64 tile.
-constexpr int kTY2 = 32;
+#ifndef SKEL_O2D_TY
+#define SKEL_O2D_TY 32
+#endif
+constexpr int kTY2 = SKEL_O2D_TY;
 
 template <int RY, int RX>
 __global__ __launch_bounds__(kBlock) void ov2_sep_l1(const float* x, float* out, int64_t rows,
@@ -441,31 +444,42 @@ __global__ __launch_bounds__(kBlock) void ov2_sep_l1(const float* x, float* out,
                           x0 + kTX + HX <= cols && (cols & 3) == 0;
     const int cg = threadIdx.x % 16, rg = threadIdx.x / 16;
     const int nrows = kTY2 + 2 * ry;
-    for (int y = rg; y < nrows; y += 16) {
+    // row pass: every row this lane handles is loaded before any arithmetic
+    // (kIt rows of NV 16-byte vectors in flight per lane)
+    constexpr int kIt = (LH + 15) / 16;
+    float seg[kIt][4 + 2 * HX];
+#pragma unroll
+    for (int it = 0; it < kIt; ++it) {
+        const int y = rg + 16 * it;
+        if (y >= nrows) continue;
         const int64_t gy = y0 - ry + y;
-        float seg[4 + 2 * HX];
         if (interior) {
             const float* src = x + gy * cols + (x0 - HX + 4 * cg);
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
                 const f32x4 t = *reinterpret_cast<const f32x4*>(src + 4 * v);
-                seg[4 * v] = t.x;
-                seg[4 * v + 1] = t.y;
-                seg[4 * v + 2] = t.z;
-                seg[4 * v + 3] = t.w;
+                seg[it][4 * v] = t.x;
+                seg[it][4 * v + 1] = t.y;
+                seg[it][4 * v + 2] = t.z;
+                seg[it][4 * v + 3] = t.w;
             }
         } else {
 #pragma unroll
             for (int t = 0; t < 4 + 2 * HX; ++t)
-                seg[t] = fetch2(x, rows, cols, gy, x0 - HX + 4 * cg + t, edge, pad);
+                seg[it][t] = fetch2(x, rows, cols, gy, x0 - HX + 4 * cg + t, edge, pad);
         }
+    }
+#pragma unroll
+    for (int it = 0; it < kIt; ++it) {
+        const int y = rg + 16 * it;
+        if (y >= nrows) continue;
         float h[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int b = 0; b <= 2 * MX; ++b) {
             if (b > 2 * rx) break;
 #pragma unroll
             for (int c = 0; c < 4; ++c)
-                h[c] = __builtin_fmaf(w.wx[b], seg[c + b + HX - rx], h[c]);
+                h[c] = __builtin_fmaf(w.wx[b], seg[it][c + b + HX - rx], h[c]);
         }
         *reinterpret_cast<f32x4*>(th + y * HW + 4 * cg) = f32x4{h[0], h[1], h[2], h[3]};
     }
