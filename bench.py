@@ -300,28 +300,68 @@ def graph_replay(skel, torch, wl, steps):
 
 
 def cpu_baseline(wl):
-    """The oracle (as it is, not tuned) over one full step on the host."""
+    """The oracle (as it is, not tuned) over full steps on the host: on all
+    of the process's cores (about 8 s), and on one thread (one step)."""
     import oracle
     model, ncpu = host_info()
     threads = min(ncpu, 64)
-    oracle.set_threads(threads)
-    reps, el = 0, 0.0
-    while reps < 20 and (reps == 0 or el < 8.0):  # bounded: about 8 s of host work
-        t0 = time.perf_counter()
+
+    def step():
         oracle.map_f32("axpy", [2.5], wl.x_h, wl.y_h)
         o1, _ = oracle.mapoverlap1d(wl.z_h, wl.w5, 2)
         oracle.scan(wl.s_h, "exclusive", "sum", np.int64)
         oracle.mapreduce("mul", None, wl.x_h, wl.y_h)
         oracle.mapoverlap2d(wl.img_h, 4, 4, wy=wl.g9, wx=wl.g9)
         oracle.reduce("sum", o1.astype(np.float32))
+
+    oracle.set_threads(threads)
+    reps, el = 0, 0.0
+    while reps < 20 and (reps == 0 or el < 8.0):  # bounded: about 8 s of host work
+        t0 = time.perf_counter()
+        step()
         el += time.perf_counter() - t0
         reps += 1
+    oracle.set_threads(1)
+    t0 = time.perf_counter()
+    step()
+    el1 = time.perf_counter() - t0
     total = sum(BYTES.values())
     return {"value": round(total * reps / el / 1e9, 3), "unit": "GB/s", "cores": threads,
             "kind": "oracle",
             "sample": f"{reps} full step(s) (all six skeletons, same sizes) in {el:.2f} s; "
                       f"binary64/exact C oracle, OpenMP over independent outputs "
-                      f"(map, stencils), sequential reductions and scans; host {model}"}
+                      f"(map, stencils), sequential reductions and scans; host {model}",
+            "one_thread": {"value": round(total / el1 / 1e9, 3), "unit": "GB/s",
+                           "sample": f"1 full step on 1 thread in {el1:.2f} s"}}
+
+
+def small_config(skel, torch):
+    """The small configuration (2^20 elements, resident in the 256 MiB
+    Infinity Cache, launch-bound): median kernel time per call."""
+    import synth_inputs as si
+    n = 1 << 20
+    x = skel.Container.from_numpy(si.uniform_f32(n, -1.0, 1.0, 0, 0))
+    y = skel.Container.from_numpy(si.uniform_f32(n, -1.0, 1.0, 0, 1))
+    s = skel.Container.from_numpy(si.int_uniform_i32(n, 100, 0, 2))
+    so = skel.Container.empty(skel.I32, n)
+    z = skel.Container.from_numpy(si.uniform_f32(n, -1.0, 1.0, 0, 3))
+    o = skel.Container.empty(skel.F32, n)
+    r = skel.Container.empty(skel.F32, 1)
+    w5 = si.binomial5_weights()
+    calls = {
+        "map_saxpy": (12 * n, lambda: skel.skel_map(skel.MAP_AXPY, [2.5], [x, y], y)),
+        "reduce_sum": (4 * n, lambda: skel.skel_reduce(skel.SUM, x, r)),
+        "scan_incl_i32": (8 * n, lambda: skel.skel_scan(s, so, skel.INCLUSIVE, skel.SUM)),
+        "mapoverlap1d_5pt": (8 * n, lambda: skel.skel_mapoverlap1d(z, o, w5, 2,
+                                                                   skel.EDGE_CLAMP)),
+    }
+    res = {"elements": n}
+    for name, (nbytes, fn) in calls.items():
+        ms = time_call(torch, fn, 50)
+        res[name] = {"us": round(ms * 1e3, 2), "GBps": round(nbytes / (ms * 1e-3) / 1e9, 1)}
+    for c in (x, y, s, so, z, o, r):
+        c.destroy()
+    return res
 
 
 def main():
@@ -424,6 +464,8 @@ def main():
         log("bf16 plain vs compensated sums, 2^28")
         nxt["bf16_sums"] = bf16_sums(skel, torch)
         out["next_rows"] = nxt
+        log("small configuration, 2^20")
+        out["small_config"] = small_config(skel, torch)
     if not args.no_cpu:
         log("timing the CPU oracle on one step")
         out["cpu_baseline"] = cpu_baseline(wl)
