@@ -9,8 +9,9 @@ target system.  This module is that off-line step for one GPU:
     python -m paper_1405_2915_amd.autotune [--out FILE] [--min 10] [--max 28]
                                            [--reps 7] [--report FILE.json]
 
-For each tuned skeleton and each size n = 2^k it times every selectable
-variant (forced), as the median of `reps` runs measured with HIP events on the
+For each tuned skeleton (sum Reduce, dot MapReduce, inclusive int32 Scan,
+saxpy Map, 5-point MapOverlap1D, 9x9 separable MapOverlap2D on a near-square
+image) and each size n = 2^k it times every selectable variant (forced), as the median of `reps` runs measured with HIP events on the
 launch stream, with the 256 MiB Infinity Cache evicted before every timed call
 (by reading a 512 MiB buffer); it writes the fastest variant per
 (skeleton, dtype, log2 n) as a plan table (the text format of skel_load_plan)
@@ -74,6 +75,8 @@ def tune(lo=10, hi=28, reps=7, log=print, allow_order_dependent=False):
     report = {"lo": lo, "hi": hi, "reps": reps, "unit": "us", "results": {}}
     single = {skel.SK_REDUCE: "R0_single_wg", skel.SK_MAPREDUCE: "MR3_fused_single_wg",
               skel.SK_SCAN: "S0_single_wg"}
+    w5 = si.binomial5_weights()
+    g9 = si.gaussian_weights(4, 2.0)
     for k in range(lo, hi + 1):
         n = 1 << k
         x = skel.Container.from_numpy(si.normal_f32(n, 2, 0))
@@ -81,6 +84,11 @@ def tune(lo=10, hi=28, reps=7, log=print, allow_order_dependent=False):
         s = skel.Container.from_numpy(si.int_uniform_i32(n, 100, 2, 2))
         so = skel.Container.empty(skel.I32, n)
         out1 = skel.Container.empty(skel.F32, 1)
+        o1 = skel.Container.empty(skel.F32, n)
+        rows = 1 << (k // 2)  # the 2D cases: a rows x (n / rows) image
+        img = skel.Container.from_numpy(si.uniform_f32(n, 0.0, 1.0, 2, 3).reshape(rows,
+                                                                                   n // rows))
+        imo = skel.Container.empty(skel.F32, rows, n // rows)
         cases = {
             ("REDUCE", "f32", skel.SK_REDUCE):
                 lambda v: skel.skel_reduce(skel.SUM, x, out1, variant=v),
@@ -91,6 +99,11 @@ def tune(lo=10, hi=28, reps=7, log=print, allow_order_dependent=False):
                 lambda v: skel.skel_scan(s, so, skel.INCLUSIVE, skel.SUM, variant=v),
             ("MAP", "f32", skel.SK_MAP):
                 lambda v: skel.skel_map(skel.MAP_AXPY, [2.5], [x, y], y, variant=v),
+            ("MAPOVERLAP1D", "f32", skel.SK_MAPOVERLAP1D):
+                lambda v: skel.skel_mapoverlap1d(x, o1, w5, 2, skel.EDGE_CLAMP, variant=v),
+            ("MAPOVERLAP2D", "f32", skel.SK_MAPOVERLAP2D):
+                lambda v: skel.skel_mapoverlap2d(img, imo, wy=g9, wx=g9, edge=skel.EDGE_CLAMP,
+                                                 variant=v),
         }
         for (name, _dt, sk), call in cases.items():
             res = {}
@@ -101,9 +114,10 @@ def tune(lo=10, hi=28, reps=7, log=print, allow_order_dependent=False):
                 res[vname] = round(_timed(torch, lambda: call(v), evict, reps), 3)
             report["results"].setdefault(name, {})[str(k)] = res
             log(f"{name:10s} 2^{k:2d}: " + "  ".join(f"{a}={b:.1f}" for a, b in res.items()))
-        for c in (x, y, s, so, out1):
+        for c in (x, y, s, so, out1, o1, img, imo):
             c.destroy()
-    report["dtypes"] = {"REDUCE": "f32", "MAPREDUCE": "f32", "SCAN": "i32", "MAP": "f32"}
+    report["dtypes"] = {"REDUCE": "f32", "MAPREDUCE": "f32", "SCAN": "i32", "MAP": "f32",
+                        "MAPOVERLAP1D": "f32", "MAPOVERLAP2D": "f32"}
     return plan_from_report(report, allow_order_dependent=allow_order_dependent), report
 
 
