@@ -384,3 +384,49 @@ def test_scan_repeated_calls_reuse_descriptors(skel, oracle_mod):
         assert np.array_equal(out.to_numpy(), oracle_mod.scan(x, "exclusive", "sum",
                                                               np.int64)), k
     skel.skel_sync()
+
+
+# ------------------------------------------- drawn tiny shapes (hypothesis)
+from hypothesis import HealthCheck, given, settings, strategies as st  # noqa: E402
+
+
+@settings(max_examples=60, deadline=None, suppress_health_check=list(HealthCheck))
+@given(rows=st.integers(1, 40), cols=st.integers(1, 40), ry=st.integers(0, 8),
+       rx=st.integers(0, 8), edge=st.sampled_from(list(EDGES)), sep=st.booleans(),
+       seed=st.integers(0, 1000))
+def test_mapoverlap2d_drawn_shapes(skel, oracle_mod, rows, cols, ry, rx, edge, sep, seed):
+    img = si.uniform_f32(rows * cols, -1.0, 1.0, 13, seed).reshape(rows, cols)
+    wy = si.uniform_f32(2 * ry + 1, -1.0, 1.0, 13, 2000 + seed)
+    wx = si.uniform_f32(2 * rx + 1, -1.0, 1.0, 13, 3000 + seed)
+    kw = {"wy": wy, "wx": wx} if sep else {
+        "w2d": (wy.astype(np.float64)[:, None] * wx.astype(np.float64)[None, :]).astype(
+            np.float32)}
+    ref, mag = oracle_mod.mapoverlap2d(img, ry, rx, edge=edge, pad=0.375, **kw)
+    for v in variants(skel, skel.SK_MAPOVERLAP2D):
+        if v in (2, 3) and not sep:
+            continue
+        out = skel.Container.empty(skel.F32, rows, cols)
+        skel.skel_mapoverlap2d(cont(skel, img), out, ry=ry, rx=rx, edge=EDGES[edge],
+                               pad=0.375, variant=v, **kw)
+        got = out.to_numpy().reshape(rows, cols).astype(np.float64)
+        assert np.all(np.abs(got - ref) <= 1e-6 * mag + 1e-30), (v, rows, cols, ry, rx, edge)
+
+
+@settings(max_examples=60, deadline=None, suppress_health_check=list(HealthCheck))
+@given(n=st.integers(1, 3000), r=st.integers(0, 9), edge=st.sampled_from(list(EDGES)),
+       seed=st.integers(0, 1000))
+def test_mapoverlap1d_drawn_sizes(skel, oracle_mod, n, r, edge, seed):
+    x = si.uniform_f32(n, -1.0, 1.0, 14, seed)
+    w = si.uniform_f32(2 * r + 1, -1.0, 1.0, 14, 2000 + seed)
+    ref, mag = oracle_mod.mapoverlap1d(x, w, r, edge, -0.5)
+    for v in variants(skel, skel.SK_MAPOVERLAP1D):
+        if v == 2 and r > 4:
+            continue
+        out = skel.Container.empty(skel.F32, n)
+        skel.skel_mapoverlap1d(cont(skel, x), out, w, r, EDGES[edge], -0.5, variant=v)
+        assert np.all(np.abs(out.to_numpy() - ref) <= 1e-6 * mag + 1e-30), (v, n, r, edge)
+    # and the adjoint on the same draw
+    ga, gm = oracle_mod.mapoverlap1d_adjoint(x, w, r, edge)
+    out = skel.Container.empty(skel.F32, n)
+    skel.skel_mapoverlap1d_backward(cont(skel, x), out, w, r, EDGES[edge])
+    assert np.all(np.abs(out.to_numpy() - ga) <= 1e-6 * gm + 1e-30), (n, r, edge)

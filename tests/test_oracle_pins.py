@@ -628,3 +628,26 @@ def test_map_grad_rejects_bad_ops(oracle_mod):
     x = np.ones(4, np.float32)
     with pytest.raises(ValueError):
         oracle_mod.map_grad("affine", [1.0], x, x)  # needs two parameters
+
+
+def test_oracle_threads_do_not_change_results(oracle_mod):
+    """The element-parallel loops (map, stencils) give bit-identical results on
+    one thread and on several (each output is computed alone, in a fixed
+    order)."""
+    x = si.normal_f32(10007, 7, 0)
+    y = si.normal_f32(10007, 7, 1)
+    img = si.uniform_f32(97 * 101, 0.0, 1.0, 7, 2).reshape(97, 101)
+    w5, g9 = si.binomial5_weights(), si.gaussian_weights(4, 2.0)
+    before = oracle_mod.get_threads()
+    try:
+        res = []
+        for th in (1, 8):
+            oracle_mod.set_threads(th)
+            res.append((oracle_mod.map_f32("affine_tanh", [1.5, 0.25], x),
+                        oracle_mod.map_f32("axpy", [2.5], x, y),
+                        oracle_mod.mapoverlap1d(x, w5, 2, "cyclic")[0],
+                        oracle_mod.mapoverlap2d(img, 4, 4, wy=g9, wx=g9, edge="clamp")[0]))
+        for a, b in zip(*res):
+            assert np.array_equal(a, b)
+    finally:
+        oracle_mod.set_threads(before)
