@@ -266,6 +266,41 @@ def bf16_sums(skel, torch):
     return res
 
 
+def backward_kernels(skel, torch, wl):
+    """The adjoints at the large sizes: Map backward of saxpy (x, g read; dx,
+    dy written; the parameter gradient summed), the 1D and 2D stencil
+    transposes in both variants, and the reverse scan."""
+    n, res = N_VEC, {}
+    g = skel.Container.from_numpy(wl.z_h)
+    dx, dy = skel.Container.empty(skel.F32, n), skel.Container.empty(skel.F32, n)
+    dp = skel.Container.empty(skel.F32, 1)
+    ms = time_call(torch, lambda: skel.skel_map_backward(skel.MAP_AXPY, [2.5], [wl.x, wl.y], g,
+                                                         [dx, dy], dp), 10)
+    res["map_backward_saxpy"] = {"us": round(ms * 1e3, 1),
+                                 "GBps": round(16 * n / (ms * 1e-3) / 1e9, 1)}
+    for v in range(skel.skel_variant_count(skel.SK_MAPOVERLAP1D_BACKWARD)):
+        name = skel.skel_variant_name(skel.SK_MAPOVERLAP1D_BACKWARD, v)
+        ms = time_call(torch, lambda: skel.skel_mapoverlap1d_backward(
+            g, dx, wl.w5, 2, skel.EDGE_CLAMP, variant=v), 10)
+        res["mapoverlap1d_5pt_backward_" + name] = {"us": round(ms * 1e3, 1),
+                                                    "GBps": round(8 * n / (ms * 1e-3) / 1e9, 1)}
+    gi = skel.Container.from_numpy(wl.img_h)
+    di = skel.Container.empty(skel.F32, IMG, IMG)
+    for v in range(skel.skel_variant_count(skel.SK_MAPOVERLAP2D_BACKWARD)):
+        name = skel.skel_variant_name(skel.SK_MAPOVERLAP2D_BACKWARD, v)
+        ms = time_call(torch, lambda: skel.skel_mapoverlap2d_backward(
+            gi, di, wy=wl.g9, wx=wl.g9, edge=skel.EDGE_CLAMP, variant=v), 10)
+        res["mapoverlap2d_9x9_backward_" + name] = {
+            "us": round(ms * 1e3, 1), "GBps": round(8 * IMG * IMG / (ms * 1e-3) / 1e9, 1)}
+    ms = time_call(torch, lambda: skel.skel_scan(wl.s, wl.so, skel.REVERSE_EXCLUSIVE, skel.SUM),
+                   10)
+    res["scan_reverse_excl_i32_i64"] = {"us": round(ms * 1e3, 1),
+                                        "GBps": round(12 * N_SCAN / (ms * 1e-3) / 1e9, 1)}
+    for c in (g, dx, dy, dp, gi, di):
+        c.destroy()
+    return res
+
+
 def graph_replay(skel, torch, wl, steps):
     """One step captured into a HIP graph (torch.cuda.CUDAGraph) and replayed,
     against the same step issued call by call on the same stream."""
@@ -375,8 +410,8 @@ def main():
                     help="skip the batched, bf16 and graph-replay measurements")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(how the skeletons would shard is described in DESIGN.md)", file=sys.stderr)
+        print(f"bench.py: the skeletons run on one GPU; --gpus {args.gpus} is not supported "
+              "(multi-GPU partitioning of the containers is not built)", file=sys.stderr)
         sys.exit(2)
     import torch
     import paper_1405_2915_amd as skel
@@ -464,6 +499,8 @@ def main():
         log("bf16 plain vs compensated sums, 2^28")
         nxt["bf16_sums"] = bf16_sums(skel, torch)
         out["next_rows"] = nxt
+        log("backward kernels")
+        nxt["backward"] = backward_kernels(skel, torch, wl)
         log("small configuration, 2^20")
         out["small_config"] = small_config(skel, torch)
     if not args.no_cpu:

@@ -114,7 +114,9 @@ typedef enum skel_skeleton {
     SKEL_SK_MAPOVERLAP2D = 4,
     SKEL_SK_SCAN = 5,
     SKEL_SK_REDUCE_SEGMENTS = 6,
-    SKEL_SK_COUNT = 7
+    SKEL_SK_MAPOVERLAP1D_BACKWARD = 7,
+    SKEL_SK_MAPOVERLAP2D_BACKWARD = 8,
+    SKEL_SK_COUNT = 9
 } skel_skeleton;
 
 #define SKEL_VARIANT_AUTO (-1)
@@ -330,20 +332,28 @@ skel_status skel_map_backward(skel_map_op op, const double *params, int nparams,
  *   grad_in[j] = sum over (i, k) with e(i + k - r) = j of w[k] * g[i];
  * reads of the CONST pad send nothing back; with CLAMP the reads past either
  * end accumulate onto the end elements.  Same w, radius and edge as the
- * forward call; grad_in != g. */
+ * forward call; grad_in != g.  Variants (skeleton id
+ * SKEL_SK_MAPOVERLAP1D_BACKWARD): 0 gathers the transpose directly for every
+ * element; 1 runs the forward stencil kernel on g with the weights reversed
+ * (the transpose of a correlation inside the array) and a zero pad or the
+ * cyclic rule, then recomputes the two end elements for CLAMP. */
 skel_status skel_mapoverlap1d_backward(skel_container *g, skel_container *grad_in,
                                        const float *w, int radius, skel_edge edge,
-                                       void *stream);
+                                       int variant, void *stream);
 
 /* MapOverlap 2D backward: the transpose of the 2D neighbourhood map,
  *   grad_in[s][t] = sum over (i, j, a, b) with e(i+a-ry) = s, e(j+b-rx) = t
  *                   of W[a][b] * g[i][j]
  * with the forward call's weights (w2d, or the factors wy, wx), radii and
- * edge rule; grad_in != g. */
+ * edge rule; grad_in != g.  Variants (skeleton id
+ * SKEL_SK_MAPOVERLAP2D_BACKWARD): 0 gathers directly for every pixel; 1 runs
+ * the forward stencil kernels on g with the weights reversed along both axes
+ * and a zero pad or the cyclic rule, then recomputes the first and last rows
+ * and columns for CLAMP. */
 skel_status skel_mapoverlap2d_backward(skel_container *g, skel_container *grad_in,
                                        const float *w2d, const float *wy,
                                        const float *wx, int ry, int rx, skel_edge edge,
-                                       void *stream);
+                                       int variant, void *stream);
 
 /* ------------------------------------------- variants and selection ---- */
 
@@ -353,9 +363,9 @@ const char *skel_variant_name(int skeleton, int variant); /* NULL if out of rang
 /* The execution plan's choice (Section III) for a call context, without
  * running anything: returns the variant index, or -1 if none is selectable.
  * n is the element count (rows*cols for 2D); dtype is the input element type;
- * `aux` is the radius for SKEL_SK_MAPOVERLAP1D, 1 when the 2D weights are
- * given as separable factors for SKEL_SK_MAPOVERLAP2D, 1 for the reverse
- * kinds of SKEL_SK_SCAN, and ignored otherwise. */
+ * `aux` is the radius for SKEL_SK_MAPOVERLAP1D(_BACKWARD), 1 when the 2D
+ * weights are given as separable factors for SKEL_SK_MAPOVERLAP2D(_BACKWARD),
+ * 1 for the reverse kinds of SKEL_SK_SCAN, and ignored otherwise. */
 int skel_select_variant(int skeleton, skel_dtype dtype, int64_t n,
                         int64_t rows, int64_t cols, int aux);
 

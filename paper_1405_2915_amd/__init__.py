@@ -47,7 +47,7 @@ INCLUSIVE, EXCLUSIVE, REVERSE_INCLUSIVE, REVERSE_EXCLUSIVE = 0, 1, 2, 3
 SUM, MIN, MAX = 0, 1, 2
 MAP_IDENTITY, MAP_AXPY, MAP_AFFINE, MAP_TANH, MAP_AFFINE_TANH, MAP_MUL, MAP_SQUARE = range(7)
 SK_MAP, SK_REDUCE, SK_MAPREDUCE, SK_MAPOVERLAP1D, SK_MAPOVERLAP2D, SK_SCAN, \
-    SK_REDUCE_SEGMENTS = range(7)
+    SK_REDUCE_SEGMENTS, SK_MAPOVERLAP1D_BACKWARD, SK_MAPOVERLAP2D_BACKWARD = range(9)
 VARIANT_AUTO = -1
 MAX_RADIUS_1D, MAX_RADIUS_2D = 64, 8
 
@@ -118,8 +118,8 @@ def load_library(path: str = LIB_PATH):
         "skel_container_acquire_range": (st, [vp, i, i, i64, i64, vp, C.POINTER(vp)]),
         "skel_container_valid_ranges": (st, [vp, i, C.POINTER(i64), i64, C.POINTER(i64)]),
         "skel_map_backward": (st, [i, dp, i, C.POINTER(vp), i, vp, C.POINTER(vp), vp, vp]),
-        "skel_mapoverlap1d_backward": (st, [vp, vp, fp, i, i, vp]),
-        "skel_mapoverlap2d_backward": (st, [vp, vp, fp, fp, fp, i, i, i, vp]),
+        "skel_mapoverlap1d_backward": (st, [vp, vp, fp, i, i, i, vp]),
+        "skel_mapoverlap2d_backward": (st, [vp, vp, fp, fp, fp, i, i, i, i, vp]),
         "skel_variant_count": (i, [i]),
         "skel_variant_name": (C.c_char_p, [i, i]),
         "skel_select_variant": (i, [i, i, i64, i64, i64, i]),
@@ -551,18 +551,20 @@ def skel_map_backward(map_op: int, params, ins, g: Container, grad_ins,
 
 
 def skel_mapoverlap1d_backward(g: Container, grad_in: Container, w, radius: int,
-                               edge: int = EDGE_CLAMP, stream=None) -> None:
+                               edge: int = EDGE_CLAMP, variant: int = VARIANT_AUTO,
+                               stream=None) -> None:
     wa, wp = _floats(w)
     if wa is None or wa.size != 2 * radius + 1:
         raise ValueError("w must hold 2*radius+1 weights")
-    _check(_L().skel_mapoverlap1d_backward(_h(g), _h(grad_in), wp, radius, edge,
+    _check(_L().skel_mapoverlap1d_backward(_h(g), _h(grad_in), wp, radius, edge, variant,
                                            C.c_void_p(_stream(stream))),
            "skel_mapoverlap1d_backward")
 
 
 def skel_mapoverlap2d_backward(g: Container, grad_in: Container, w2d=None, wy=None, wx=None,
                                ry: int | None = None, rx: int | None = None,
-                               edge: int = EDGE_CLAMP, stream=None) -> None:
+                               edge: int = EDGE_CLAMP, variant: int = VARIANT_AUTO,
+                               stream=None) -> None:
     a2, p2 = _floats(w2d)
     ay, py = _floats(wy)
     ax, px = _floats(wx)
@@ -574,7 +576,7 @@ def skel_mapoverlap2d_backward(g: Container, grad_in: Container, w2d=None, wy=No
         ry = (ay.size - 1) // 2 if ry is None else ry
         rx = (ax.size - 1) // 2 if rx is None else rx
     _check(_L().skel_mapoverlap2d_backward(_h(g), _h(grad_in), p2, py, px, ry, rx, edge,
-                                           C.c_void_p(_stream(stream))),
+                                           variant, C.c_void_p(_stream(stream))),
            "skel_mapoverlap2d_backward")
 
 

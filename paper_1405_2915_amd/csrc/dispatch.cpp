@@ -24,10 +24,12 @@ const char* const kScan[] = {"S0_single_wg", "S1_reduce_then_scan",
                              "S2_decoupled_lookback"};
 
 const char* const kSegments[] = {"B0_per_segment", "B1_persistent"};
+const char* const kAdjoint[] = {"A0_gather", "A1_flipped_forward"};
 
 const char* const kSkeletonNames[] = {"MAP",          "REDUCE", "MAPREDUCE",
                                       "MAPOVERLAP1D", "MAPOVERLAP2D", "SCAN",
-                                      "REDUCE_SEGMENTS"};
+                                      "REDUCE_SEGMENTS", "MAPOVERLAP1D_BACKWARD",
+                                      "MAPOVERLAP2D_BACKWARD"};
 
 struct TableEntry {
     int skeleton;
@@ -65,6 +67,8 @@ int static_rule(const CallContext& c) {
     case SKEL_SK_SCAN:
         return c.n <= (INT64_C(1) << 15) && !c.reverse ? S0_SINGLE_WG : S2_LOOKBACK;
     case SKEL_SK_REDUCE_SEGMENTS: return B1_PERSISTENT;
+    case SKEL_SK_MAPOVERLAP1D_BACKWARD:
+    case SKEL_SK_MAPOVERLAP2D_BACKWARD: return A1_FLIPPED_FORWARD;
     }
     return -1;
 }
@@ -104,6 +108,8 @@ int variant_count(int skeleton) {
     case SKEL_SK_MAPOVERLAP2D: return OVERLAP2D_NVAR;
     case SKEL_SK_SCAN: return SCAN_NVAR;
     case SKEL_SK_REDUCE_SEGMENTS: return SEGMENTS_NVAR;
+    case SKEL_SK_MAPOVERLAP1D_BACKWARD:
+    case SKEL_SK_MAPOVERLAP2D_BACKWARD: return ADJOINT_NVAR;
     }
     return 0;
 }
@@ -118,6 +124,8 @@ const char* variant_name(int skeleton, int v) {
     case SKEL_SK_MAPOVERLAP2D: return kOverlap2D[v];
     case SKEL_SK_SCAN: return kScan[v];
     case SKEL_SK_REDUCE_SEGMENTS: return kSegments[v];
+    case SKEL_SK_MAPOVERLAP1D_BACKWARD:
+    case SKEL_SK_MAPOVERLAP2D_BACKWARD: return kAdjoint[v];
     }
     return nullptr;
 }
@@ -293,7 +301,8 @@ int skel_select_variant(int skeleton, skel_dtype dtype, int64_t n, int64_t rows,
     c.n = n;
     c.rows = rows;
     c.cols = cols;
-    if (skeleton == SKEL_SK_MAPOVERLAP1D) c.radius = aux;
+    if (skeleton == SKEL_SK_MAPOVERLAP1D || skeleton == SKEL_SK_MAPOVERLAP1D_BACKWARD)
+        c.radius = aux;
     else if (skeleton == SKEL_SK_SCAN) c.reverse = aux;
     else c.separable = aux;
     skel_status st;

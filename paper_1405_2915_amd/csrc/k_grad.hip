@@ -17,6 +17,7 @@
 // All are HBM streams (map_grad: 12 to 20 bytes per element; adjoints: 8
 // bytes per element plus the cached neighbourhood reads).
 #include "kcommon.hpp"
+#include "dispatch.hpp"
 #include "launch.hpp"
 
 namespace skel {
@@ -80,7 +81,9 @@ __global__ __launch_bounds__(kBlock) void map_grad(const float* x, const float* 
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < nv; i += stride) {
         const f32x4 xv = reinterpret_cast<const f32x4*>(x)[i];
-        const f32x4 yv = TWO ? reinterpret_cast<const f32x4*>(y)[i] : f32x4{0.f, 0.f, 0.f, 0.f};
+        // y enters the derivatives of MUL only (AXPY's are 1 and p0)
+        const f32x4 yv = OP == SKEL_MAP_MUL ? reinterpret_cast<const f32x4*>(y)[i]
+                                            : f32x4{0.f, 0.f, 0.f, 0.f};
         const f32x4 gv = BCAST ? f32x4{gb, gb, gb, gb} : reinterpret_cast<const f32x4*>(g)[i];
         f32x4 ox, oy;
 #pragma unroll
@@ -99,7 +102,8 @@ __global__ __launch_bounds__(kBlock) void map_grad(const float* x, const float* 
     const int64_t t = nv * 4 + (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (blockIdx.x == 0 && t < n) {
         float ddx, ddy, s0, s1;
-        elem_grad<OP>(x[t], TWO ? y[t] : 0.0f, BCAST ? gb : g[t], p0, p1, ddx, ddy, s0, s1);
+        elem_grad<OP>(x[t], OP == SKEL_MAP_MUL ? y[t] : 0.0f, BCAST ? gb : g[t], p0, p1, ddx,
+                      ddy, s0, s1);
         dx[t] = ddx;
         if constexpr (TWO) dy[t] = ddy;
         a0 += s0;
@@ -145,33 +149,44 @@ __device__ __forceinline__ int64_t wrap_index(int64_t i, int64_t n) {
     return m < 0 ? m + n : m;
 }
 
+// the transpose at element j, gathered: the outputs i whose tap k read x[j]
+__device__ __forceinline__ float adj1_at(const float* g, int64_t n, const WA1& w, int r, int edge,
+                                         int64_t j) {
+    float acc = 0.0f;
+    if (edge == SKEL_EDGE_CYCLIC) {
+        for (int k = 0; k <= 2 * r; ++k)
+            acc = __builtin_fmaf(w.w[k], g[wrap_index(j - k + r, n)], acc);
+        return acc;
+    }
+    for (int k = 0; k <= 2 * r; ++k) {
+        const int64_t i = j - k + r;
+        if (i >= 0 && i < n) acc = __builtin_fmaf(w.w[k], g[i], acc);
+    }
+    if (edge == SKEL_EDGE_CLAMP) {
+        // reads below index 0 (i + k - r < 0) land on element 0, reads above
+        // n - 1 on element n - 1
+        if (j == 0)
+            for (int k = 0; k < r; ++k)
+                for (int64_t i = 0; i < n && i < r - k; ++i) acc = __builtin_fmaf(w.w[k], g[i], acc);
+        if (j == n - 1)
+            for (int k = r + 1; k <= 2 * r; ++k)
+                for (int64_t i = n - 1; i >= 0 && i > n - 1 + r - k; --i)
+                    acc = __builtin_fmaf(w.w[k], g[i], acc);
+    }
+    return acc;
+}
+
 __global__ __launch_bounds__(kBlock) void ov1_adjoint(const float* g, float* dx, int64_t n,
                                                       WA1 w, int r, int edge) {
     const int64_t stride = (int64_t)gridDim.x * kBlock;
-    for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += stride) {
-        float acc = 0.0f;
-        if (edge == SKEL_EDGE_CYCLIC) {
-            for (int k = 0; k <= 2 * r; ++k) acc = __builtin_fmaf(w.w[k], g[wrap_index(j - k + r, n)], acc);
-        } else {
-            for (int k = 0; k <= 2 * r; ++k) {
-                const int64_t i = j - k + r;  // the output whose tap k read x[j]
-                if (i >= 0 && i < n) acc = __builtin_fmaf(w.w[k], g[i], acc);
-            }
-            if (edge == SKEL_EDGE_CLAMP) {
-                // reads below index 0 (i + k - r < 0) land on element 0, reads
-                // above n - 1 on element n - 1
-                if (j == 0)
-                    for (int k = 0; k < r; ++k)
-                        for (int64_t i = 0; i < n && i < r - k; ++i)
-                            acc = __builtin_fmaf(w.w[k], g[i], acc);
-                if (j == n - 1)
-                    for (int k = r + 1; k <= 2 * r; ++k)
-                        for (int64_t i = n - 1; i >= 0 && i > n - 1 + r - k; --i)
-                            acc = __builtin_fmaf(w.w[k], g[i], acc);
-            }
-        }
-        dx[j] = acc;
-    }
+    for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += stride)
+        dx[j] = adj1_at(g, n, w, r, edge, j);
+}
+
+// elements 0 and n - 1 only (where clamped reads land)
+__global__ void ov1_adjoint_ends(const float* g, float* dx, int64_t n, WA1 w, int r, int edge) {
+    const int64_t j = threadIdx.x == 0 ? 0 : n - 1;
+    if (threadIdx.x < 2) dx[j] = adj1_at(g, n, w, r, edge, j);
 }
 
 // --------------------------------------------------------- MapOverlap 2D ---
@@ -200,28 +215,58 @@ __device__ __forceinline__ void tap_range(int64_t s, int a, int r, int64_t len, 
     if (*hi > len - 1) *hi = len - 1;
 }
 
+// the transpose at pixel (s, t), gathered
+__device__ __forceinline__ float adj2_at(const float* g, int64_t rows, int64_t cols, const WA2& w,
+                                         int ry, int rx, int edge, int64_t s, int64_t t) {
+    const int nx = 2 * rx + 1;
+    float acc = 0.0f;
+    for (int a = 0; a <= 2 * ry; ++a) {
+        int64_t ilo, ihi;
+        tap_range(s, a, ry, rows, edge, &ilo, &ihi);
+        for (int b = 0; b <= 2 * rx; ++b) {
+            int64_t jlo, jhi;
+            tap_range(t, b, rx, cols, edge, &jlo, &jhi);
+            const float wab = w.w[a * nx + b];
+            for (int64_t i = ilo; i <= ihi; ++i)
+                for (int64_t j = jlo; j <= jhi; ++j) acc = __builtin_fmaf(wab, g[i * cols + j], acc);
+        }
+    }
+    return acc;
+}
+
 __global__ __launch_bounds__(kBlock) void ov2_adjoint(const float* g, float* dx, int64_t rows,
                                                       int64_t cols, WA2 w, int ry, int rx,
                                                       int edge) {
     const int64_t total = rows * cols;
     const int64_t stride = (int64_t)gridDim.x * kBlock;
-    const int nx = 2 * rx + 1;
     for (int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x; p < total; p += stride) {
-        const int64_t s = p / cols, t = p - s * cols;
-        float acc = 0.0f;
-        for (int a = 0; a <= 2 * ry; ++a) {
-            int64_t ilo, ihi;
-            tap_range(s, a, ry, rows, edge, &ilo, &ihi);
-            for (int b = 0; b <= 2 * rx; ++b) {
-                int64_t jlo, jhi;
-                tap_range(t, b, rx, cols, edge, &jlo, &jhi);
-                const float wab = w.w[a * nx + b];
-                for (int64_t i = ilo; i <= ihi; ++i)
-                    for (int64_t j = jlo; j <= jhi; ++j)
-                        acc = __builtin_fmaf(wab, g[i * cols + j], acc);
-            }
+        const int64_t s = p / cols;
+        dx[p] = adj2_at(g, rows, cols, w, ry, rx, edge, s, p - s * cols);
+    }
+}
+
+// the first and last rows and columns only (the pixels that clamped reads
+// land on), in order: row 0, row rows-1, then column 0 and column cols-1 of
+// the rows in between
+__global__ __launch_bounds__(kBlock) void ov2_adjoint_border(const float* g, float* dx,
+                                                             int64_t rows, int64_t cols, WA2 w,
+                                                             int ry, int rx, int edge) {
+    const int64_t nrow = rows > 1 ? 2 : 1;
+    const int64_t ncol = cols > 1 ? 2 : 1;
+    const int64_t mid = rows > 2 ? rows - 2 : 0;
+    const int64_t total = nrow * cols + ncol * mid;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x; p < total; p += stride) {
+        int64_t s, t;
+        if (p < nrow * cols) {
+            s = p < cols ? 0 : rows - 1;
+            t = p < cols ? p : p - cols;
+        } else {
+            const int64_t q = p - nrow * cols;
+            s = 1 + q / ncol;
+            t = (q % ncol) == 0 ? 0 : cols - 1;
         }
-        dx[p] = acc;
+        dx[s * cols + t] = adj2_at(g, rows, cols, w, ry, rx, edge, s, t);
     }
 }
 
@@ -279,24 +324,64 @@ skel_status launch_map_backward(int op, float p0, float p1, const float* x, cons
     }
 }
 
-skel_status launch_overlap1d_adjoint(const float* g, float* dx, int64_t n, const float* w,
-                                     int r, int edge, LaunchCtx& lc) {
+// A1 (both dimensions): the transpose of a correlation with weights w inside
+// the array is the correlation with the reversed weights, so the forward
+// kernels compute it with a zero pad (CONST edges send nothing back, and for
+// CLAMP this is every element but the ends) or with the cyclic rule (exact);
+// for CLAMP the elements that clamped reads land on are then recomputed by
+// the gather.
+skel_status launch_overlap1d_adjoint(int v, const float* g, float* dx, int64_t n,
+                                     const float* w, int r, int edge, LaunchCtx& lc) {
     WA1 wk{};
     for (int k = 0; k <= 2 * r; ++k) wk.w[k] = w[k];
-    ov1_adjoint<<<grid_for(n, *lc.dev), kBlock, 0, lc.stream>>>(g, dx, n, wk, r, edge);
-    return launch_check("ov1_adjoint");
+    if (v == A0_GATHER) {
+        ov1_adjoint<<<grid_for(n, *lc.dev), kBlock, 0, lc.stream>>>(g, dx, n, wk, r, edge);
+        return launch_check("ov1_adjoint");
+    }
+    float wf[2 * SKEL_MAX_RADIUS_1D + 1];
+    for (int k = 0; k <= 2 * r; ++k) wf[k] = w[2 * r - k];
+    const int fwd = r <= 4 ? O1C_SHUFFLE : O1B_LDS_TILE;
+    skel_status e = launch_overlap1d(fwd, g, dx, n, wf, r,
+                                     edge == SKEL_EDGE_CYCLIC ? SKEL_EDGE_CYCLIC : SKEL_EDGE_CONST,
+                                     0.0f, lc);
+    if (e != SKEL_OK || edge != SKEL_EDGE_CLAMP) return e;
+    ov1_adjoint_ends<<<1, dev::kWave, 0, lc.stream>>>(g, dx, n, wk, r, edge);
+    return launch_check("ov1_adjoint_ends");
 }
 
-skel_status launch_overlap2d_adjoint(const float* g, float* dx, int64_t rows, int64_t cols,
-                                     const float* w2d, const float* wy, const float* wx,
-                                     int ry, int rx, int edge, LaunchCtx& lc) {
+skel_status launch_overlap2d_adjoint(int v, const float* g, float* dx, int64_t rows,
+                                     int64_t cols, const float* w2d, const float* wy,
+                                     const float* wx, int ry, int rx, int edge,
+                                     LaunchCtx& lc) {
     WA2 wk{};
     const int ny = 2 * ry + 1, nx = 2 * rx + 1;
     for (int a = 0; a < ny; ++a)
         for (int b = 0; b < nx; ++b) wk.w[a * nx + b] = w2d ? w2d[a * nx + b] : wy[a] * wx[b];
-    ov2_adjoint<<<grid_for(rows * cols, *lc.dev), kBlock, 0, lc.stream>>>(g, dx, rows, cols, wk,
-                                                                         ry, rx, edge);
-    return launch_check("ov2_adjoint");
+    if (v == A0_GATHER) {
+        ov2_adjoint<<<grid_for(rows * cols, *lc.dev), kBlock, 0, lc.stream>>>(g, dx, rows, cols,
+                                                                             wk, ry, rx, edge);
+        return launch_check("ov2_adjoint");
+    }
+    const int fe = edge == SKEL_EDGE_CYCLIC ? SKEL_EDGE_CYCLIC : SKEL_EDGE_CONST;
+    skel_status e;
+    if (w2d) {
+        float wf[(2 * SKEL_MAX_RADIUS_2D + 1) * (2 * SKEL_MAX_RADIUS_2D + 1)];
+        for (int a = 0; a < ny; ++a)
+            for (int b = 0; b < nx; ++b) wf[a * nx + b] = w2d[(ny - 1 - a) * nx + (nx - 1 - b)];
+        e = launch_overlap2d(O2B_LDS_TILE, g, dx, rows, cols, wf, nullptr, nullptr, ry, rx, fe,
+                             0.0f, lc);
+    } else {
+        float fy[2 * SKEL_MAX_RADIUS_2D + 1], fx[2 * SKEL_MAX_RADIUS_2D + 1];
+        for (int a = 0; a < ny; ++a) fy[a] = wy[ny - 1 - a];
+        for (int b = 0; b < nx; ++b) fx[b] = wx[nx - 1 - b];
+        e = launch_overlap2d(O2D_SEPARABLE_L1, g, dx, rows, cols, nullptr, fy, fx, ry, rx, fe,
+                             0.0f, lc);
+    }
+    if (e != SKEL_OK || edge != SKEL_EDGE_CLAMP) return e;
+    const int64_t border = 2 * cols + 2 * rows;
+    ov2_adjoint_border<<<grid_for(border, *lc.dev), kBlock, 0, lc.stream>>>(g, dx, rows, cols,
+                                                                           wk, ry, rx, edge);
+    return launch_check("ov2_adjoint_border");
 }
 
 }  // namespace skel

@@ -102,10 +102,10 @@ skel_status launch_scan(int variant, int kind, int op, skel_dtype din,
 skel_status launch_map_backward(int op, float p0, float p1, const float* x, const float* y,
                                 const float* g, bool g_broadcast, float* dx, float* dy,
                                 int64_t n, float* dparams, LaunchCtx& lc);
-skel_status launch_overlap1d_adjoint(const float* g, float* dx, int64_t n, const float* w,
-                                     int r, int edge, LaunchCtx& lc);
-skel_status launch_overlap2d_adjoint(const float* g, float* dx, int64_t rows, int64_t cols,
-                                     const float* w2d, const float* wy, const float* wx,
-                                     int ry, int rx, int edge, LaunchCtx& lc);
+skel_status launch_overlap1d_adjoint(int variant, const float* g, float* dx, int64_t n,
+                                     const float* w, int r, int edge, LaunchCtx& lc);
+skel_status launch_overlap2d_adjoint(int variant, const float* g, float* dx, int64_t rows,
+                                     int64_t cols, const float* w2d, const float* wy,
+                                     const float* wx, int ry, int rx, int edge, LaunchCtx& lc);
 
 }  // namespace skel

@@ -463,7 +463,7 @@ skel_status skel_map_backward(skel_map_op op, const double* params, int nparams,
 
 skel_status skel_mapoverlap1d_backward(skel_container* g, skel_container* grad_in,
                                        const float* w, int radius, skel_edge edge,
-                                       void* stream) {
+                                       int variant, void* stream) {
     LaunchCtx lc;
     skel_status st = begin(stream, &lc);
     if (st != SKEL_OK) return st;
@@ -476,19 +476,26 @@ skel_status skel_mapoverlap1d_backward(skel_container* g, skel_container* grad_i
     if (g->dtype != SKEL_F32 || grad_in->dtype != SKEL_F32)
         return fail(SKEL_E_DTYPE, "MapOverlap backward operands must be f32");
     if (g->n != grad_in->n) return fail(SKEL_E_SHAPE, "MapOverlap backward sizes differ");
+    CallContext cc;
+    cc.skeleton = SKEL_SK_MAPOVERLAP1D_BACKWARD;
+    cc.n = g->n;
+    cc.radius = radius;
+    int v = choose_variant(variant, cc, &st);
+    if (v < 0) return st;
     Operands ops;
     ops.add(g, SKEL_READ);
     ops.add(grad_in, SKEL_WRITE);
     return run(ops, stream, lc, [&]() -> skel_status {
         if (g->n == 0) return SKEL_OK;
-        return launch_overlap1d_adjoint((const float*)ops.ptr(g), (float*)ops.ptr(grad_in),
+        return launch_overlap1d_adjoint(v, (const float*)ops.ptr(g), (float*)ops.ptr(grad_in),
                                         g->n, w, radius, edge, lc);
     });
 }
 
 skel_status skel_mapoverlap2d_backward(skel_container* g, skel_container* grad_in,
                                        const float* w2d, const float* wy, const float* wx,
-                                       int ry, int rx, skel_edge edge, void* stream) {
+                                       int ry, int rx, skel_edge edge, int variant,
+                                       void* stream) {
     LaunchCtx lc;
     skel_status st = begin(stream, &lc);
     if (st != SKEL_OK) return st;
@@ -504,12 +511,20 @@ skel_status skel_mapoverlap2d_backward(skel_container* g, skel_container* grad_i
         return fail(SKEL_E_DTYPE, "MapOverlap backward operands must be f32");
     if (g->rows != grad_in->rows || g->cols != grad_in->cols)
         return fail(SKEL_E_SHAPE, "MapOverlap backward shapes differ");
+    CallContext cc;
+    cc.skeleton = SKEL_SK_MAPOVERLAP2D_BACKWARD;
+    cc.n = g->n;
+    cc.rows = g->rows;
+    cc.cols = g->cols;
+    cc.separable = w2d ? 0 : 1;
+    int v = choose_variant(variant, cc, &st);
+    if (v < 0) return st;
     Operands ops;
     ops.add(g, SKEL_READ);
     ops.add(grad_in, SKEL_WRITE);
     return run(ops, stream, lc, [&]() -> skel_status {
         if (g->n == 0) return SKEL_OK;
-        return launch_overlap2d_adjoint((const float*)ops.ptr(g), (float*)ops.ptr(grad_in),
+        return launch_overlap2d_adjoint(v, (const float*)ops.ptr(g), (float*)ops.ptr(grad_in),
                                         g->rows, g->cols, w2d, wy, wx, ry, rx, edge, lc);
     });
 }

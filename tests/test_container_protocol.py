@@ -304,7 +304,7 @@ def test_create_validation(rt):
 
 # ------------------------------------------------------------ execution plan
 
-SK_MAP, SK_REDUCE, SK_MAPREDUCE, SK_OV1, SK_OV2, SK_SCAN, SK_SEG = range(7)
+SK_MAP, SK_REDUCE, SK_MAPREDUCE, SK_OV1, SK_OV2, SK_SCAN, SK_SEG, SK_OV1B, SK_OV2B = range(9)
 
 
 def name_of(lib, sk, v):
@@ -314,7 +314,7 @@ def name_of(lib, sk, v):
 
 def test_variant_registry(rt):
     want = {SK_MAP: 3, SK_REDUCE: 5, SK_MAPREDUCE: 5, SK_OV1: 3, SK_OV2: 4, SK_SCAN: 3,
-            SK_SEG: 2}
+            SK_SEG: 2, SK_OV1B: 2, SK_OV2B: 2}
     for sk, k in want.items():
         assert rt.skel_variant_count(sk) == k
         names = [name_of(rt, sk, v) for v in range(k)]
@@ -335,6 +335,8 @@ def test_static_plan(rt):
     assert sel(SK_OV1, 1 << 20, F32, 2) == "O1c_shuffle"   # aux = radius
     assert sel(SK_OV1, 1 << 20, F32, 7) == "O1b_lds_tile"  # beyond 4 neighbours
     assert sel(SK_MAP, 1 << 20) == "M2_vec4x4_nt"
+    assert sel(SK_OV1B, 1 << 20, F32, 2) == "A1_flipped_forward"
+    assert sel(SK_OV2B, 1 << 20, F32, 1) == "A1_flipped_forward"
     assert rt.skel_select_variant(17, F32, 10, 1, 10, 0) == -1
 
 

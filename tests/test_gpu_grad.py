@@ -163,10 +163,11 @@ def test_mapoverlap1d_backward(skel, oracle_mod, edge, r):
     for n in (1, 2, 5, 17, 1000, 1025, 4099, (1 << 20) + 2):
         g = si.uniform_f32(n, -1.0, 1.0, 9, 3)
         ref, mag = oracle_mod.mapoverlap1d_adjoint(g, w, r, edge)
-        out = skel.Container.empty(skel.F32, n)
-        skel.skel_mapoverlap1d_backward(cont(skel, g), out, w, r, EDGES[edge])
-        bad = np.abs(out.to_numpy().astype(np.float64) - ref) > 1e-6 * mag + 1e-30
-        assert not bad.any(), (edge, r, n, np.flatnonzero(bad)[:5])
+        for v in range(skel.skel_variant_count(skel.SK_MAPOVERLAP1D_BACKWARD)):
+            out = skel.Container.empty(skel.F32, n)
+            skel.skel_mapoverlap1d_backward(cont(skel, g), out, w, r, EDGES[edge], variant=v)
+            bad = np.abs(out.to_numpy().astype(np.float64) - ref) > 1e-6 * mag + 1e-30
+            assert not bad.any(), (edge, r, n, v, np.flatnonzero(bad)[:5])
 
 
 SHAPES_2D = [(1, 1), (1, 17), (13, 1), (3, 5), (64, 64), (65, 63), (257, 300)]
@@ -183,12 +184,14 @@ def test_mapoverlap2d_backward(skel, oracle_mod, edge, ry, rx):
         g = si.uniform_f32(rows * cols, -1.0, 1.0, 9, 23).reshape(rows, cols)
         for kw in ({"w2d": w2d}, {"wy": wy, "wx": wx}):
             ref, mag = oracle_mod.mapoverlap2d_adjoint(g, ry, rx, edge=edge, **kw)
-            out = skel.Container.empty(skel.F32, rows, cols)
-            skel.skel_mapoverlap2d_backward(cont(skel, g), out, ry=ry, rx=rx, edge=EDGES[edge],
-                                            **kw)
-            bad = np.abs(out.to_numpy().reshape(rows, cols).astype(np.float64) - ref) \
-                > 1e-6 * mag + 1e-30
-            assert not bad.any(), (edge, ry, rx, rows, cols, list(kw), np.argwhere(bad)[:5])
+            for v in range(skel.skel_variant_count(skel.SK_MAPOVERLAP2D_BACKWARD)):
+                out = skel.Container.empty(skel.F32, rows, cols)
+                skel.skel_mapoverlap2d_backward(cont(skel, g), out, ry=ry, rx=rx,
+                                                edge=EDGES[edge], variant=v, **kw)
+                bad = np.abs(out.to_numpy().reshape(rows, cols).astype(np.float64) - ref) \
+                    > 1e-6 * mag + 1e-30
+                assert not bad.any(), (edge, ry, rx, rows, cols, v, list(kw),
+                                       np.argwhere(bad)[:5])
 
 
 # ----------------------------------------------------------- autograd layer

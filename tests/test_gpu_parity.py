@@ -427,6 +427,7 @@ def test_mapoverlap1d_drawn_sizes(skel, oracle_mod, n, r, edge, seed):
         assert np.all(np.abs(out.to_numpy() - ref) <= 1e-6 * mag + 1e-30), (v, n, r, edge)
     # and the adjoint on the same draw
     ga, gm = oracle_mod.mapoverlap1d_adjoint(x, w, r, edge)
-    out = skel.Container.empty(skel.F32, n)
-    skel.skel_mapoverlap1d_backward(cont(skel, x), out, w, r, EDGES[edge])
-    assert np.all(np.abs(out.to_numpy() - ga) <= 1e-6 * gm + 1e-30), (n, r, edge)
+    for v in range(skel.skel_variant_count(skel.SK_MAPOVERLAP1D_BACKWARD)):
+        out = skel.Container.empty(skel.F32, n)
+        skel.skel_mapoverlap1d_backward(cont(skel, x), out, w, r, EDGES[edge], variant=v)
+        assert np.all(np.abs(out.to_numpy() - ga) <= 1e-6 * gm + 1e-30), (n, r, edge, v)
