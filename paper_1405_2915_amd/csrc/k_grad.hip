@@ -247,7 +247,9 @@ __global__ __launch_bounds__(kBlock) void ov2_adjoint(const float* g, float* dx,
 
 // the first and last rows and columns only (the pixels that clamped reads
 // land on), in order: row 0, row rows-1, then column 0 and column cols-1 of
-// the rows in between
+// the rows in between.  One wavefront per pixel: the lanes share the taps
+// (a, b), each gathering its taps' row and column ranges, and the lane sums
+// are combined by a fixed butterfly.
 __global__ __launch_bounds__(kBlock) void ov2_adjoint_border(const float* g, float* dx,
                                                              int64_t rows, int64_t cols, WA2 w,
                                                              int ry, int rx, int edge) {
@@ -255,8 +257,11 @@ __global__ __launch_bounds__(kBlock) void ov2_adjoint_border(const float* g, flo
     const int64_t ncol = cols > 1 ? 2 : 1;
     const int64_t mid = rows > 2 ? rows - 2 : 0;
     const int64_t total = nrow * cols + ncol * mid;
-    const int64_t stride = (int64_t)gridDim.x * kBlock;
-    for (int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x; p < total; p += stride) {
+    const int l = dev::lane();
+    const int nx = 2 * rx + 1, taps = (2 * ry + 1) * nx;
+    const int64_t waves = (int64_t)gridDim.x * (kBlock / dev::kWave);
+    for (int64_t p = (int64_t)blockIdx.x * (kBlock / dev::kWave) + threadIdx.x / dev::kWave;
+         p < total; p += waves) {
         int64_t s, t;
         if (p < nrow * cols) {
             s = p < cols ? 0 : rows - 1;
@@ -266,7 +271,18 @@ __global__ __launch_bounds__(kBlock) void ov2_adjoint_border(const float* g, flo
             s = 1 + q / ncol;
             t = (q % ncol) == 0 ? 0 : cols - 1;
         }
-        dx[s * cols + t] = adj2_at(g, rows, cols, w, ry, rx, edge, s, t);
+        float acc = 0.0f;
+        for (int q = l; q < taps; q += dev::kWave) {
+            const int a = q / nx, b = q - a * nx;
+            int64_t ilo, ihi, jlo, jhi;
+            tap_range(s, a, ry, rows, edge, &ilo, &ihi);
+            tap_range(t, b, rx, cols, edge, &jlo, &jhi);
+            const float wab = w.w[q];
+            for (int64_t i = ilo; i <= ihi; ++i)
+                for (int64_t j = jlo; j <= jhi; ++j) acc = __builtin_fmaf(wab, g[i * cols + j], acc);
+        }
+        acc = dev::wave_reduce<dev::Comb<float, SKEL_SUM>>(acc);
+        if (l == 0) dx[s * cols + t] = acc;
     }
 }
 
@@ -378,9 +394,9 @@ skel_status launch_overlap2d_adjoint(int v, const float* g, float* dx, int64_t r
                              0.0f, lc);
     }
     if (e != SKEL_OK || edge != SKEL_EDGE_CLAMP) return e;
-    const int64_t border = 2 * cols + 2 * rows;
-    ov2_adjoint_border<<<grid_for(border, *lc.dev), kBlock, 0, lc.stream>>>(g, dx, rows, cols,
-                                                                           wk, ry, rx, edge);
+    const int64_t border = 2 * cols + 2 * rows;  // one wavefront per border pixel
+    ov2_adjoint_border<<<grid_for(border * dev::kWave, *lc.dev), kBlock, 0, lc.stream>>>(
+        g, dx, rows, cols, wk, ry, rx, edge);
     return launch_check("ov2_adjoint_border");
 }
 
