@@ -301,6 +301,37 @@ def backward_kernels(skel, torch, wl):
     return res
 
 
+def dispatch_overhead(skel, torch):
+    """Host cost of the execution plan and of a whole skeleton call (argument
+    checks, plan, container protocol, launch), from Python through the C ABI,
+    on a tiny operand so the GPU never holds the host back."""
+    import ctypes
+    lib = skel.load_library()
+    reps = 20000
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        lib.skel_select_variant(skel.SK_REDUCE, skel.F32, 1 << 20, 1, 1 << 20, 0)
+    sel_ns = (time.perf_counter() - t0) / reps * 1e9
+    x = skel.Container.from_numpy(np.ones(256, np.float32))
+    y = skel.Container.empty(skel.F32, 256)
+    skel.skel_map(skel.MAP_AFFINE, [2.0, 1.0], [x], y)
+    torch.cuda.synchronize()
+    calls = 5000
+    t0 = time.perf_counter()
+    for _ in range(calls):
+        skel.skel_map(skel.MAP_AFFINE, [2.0, 1.0], [x], y)
+    host_us = (time.perf_counter() - t0) / calls * 1e6
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        lib.skel_variant_count(skel.SK_MAP)  # a bare ctypes round trip, for comparison
+    ctypes_ns = (time.perf_counter() - t0) / reps * 1e9
+    x.destroy()
+    y.destroy()
+    return {"plan_lookup_ns": round(sel_ns, 1), "ctypes_call_ns": round(ctypes_ns, 1),
+            "map_call_host_us": round(host_us, 2)}
+
+
 def graph_replay(skel, torch, wl, steps):
     """One step captured into a HIP graph (torch.cuda.CUDAGraph) and replayed,
     against the same step issued call by call on the same stream."""
@@ -503,6 +534,7 @@ def main():
         nxt["backward"] = backward_kernels(skel, torch, wl)
         log("small configuration, 2^20")
         out["small_config"] = small_config(skel, torch)
+        out["small_config"]["dispatch"] = dispatch_overhead(skel, torch)
     if not args.no_cpu:
         log("timing the CPU oracle on one step")
         out["cpu_baseline"] = cpu_baseline(wl)

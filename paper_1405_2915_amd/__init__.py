@@ -144,13 +144,15 @@ def _check(status: int, where: str) -> None:
         raise SkelError(status, where, msg.decode() if msg else "")
 
 
+# torch's raw current-stream query (no Stream object per call), when present
+_RAW_STREAM = getattr(getattr(torch, "_C", None), "_cuda_getCurrentRawStream", None)
+
+
 def _current_stream() -> int:
-    try:
-        import torch
-        if torch.cuda.is_initialized():
-            return torch.cuda.current_stream().cuda_stream
-    except ImportError:
-        pass
+    if torch is not None and torch.cuda.is_initialized():
+        if _RAW_STREAM is not None:
+            return _RAW_STREAM(_device)
+        return torch.cuda.current_stream().cuda_stream
     return 0
 
 
@@ -443,9 +445,12 @@ def skel_container_info(c: Container):
 
 # --------------------------------------------------------------- skeletons
 def _params(params):
-    p = np.ascontiguousarray(np.asarray(params if params is not None else [],
-                                        dtype=np.float64))
-    return p, (p.ctypes.data_as(C.POINTER(C.c_double)) if p.size else None), p.size
+    """(keep-alive object, pointer argument, count) for a parameter list."""
+    if params is None or len(params) == 0:
+        return None, None, 0
+    vals = [float(v) for v in params]
+    arr = (C.c_double * len(vals))(*vals)
+    return arr, arr, len(vals)
 
 
 def _handles(cs):

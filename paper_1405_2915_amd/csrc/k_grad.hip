@@ -75,28 +75,45 @@ __global__ __launch_bounds__(kBlock) void map_grad(const float* x, const float* 
                                                    float* partials) {
     constexpr bool TWO = grad_two_inputs<OP>();
     constexpr int NP = grad_nparams<OP>();
+    constexpr int U = 4;  // vectors in flight per lane and input
     const float gb = BCAST ? g[0] : 0.0f;
     float a0 = 0.0f, a1 = 0.0f;
     const int64_t nv = n / 4;
-    const int64_t stride = (int64_t)gridDim.x * kBlock;
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < nv; i += stride) {
-        const f32x4 xv = reinterpret_cast<const f32x4*>(x)[i];
-        // y enters the derivatives of MUL only (AXPY's are 1 and p0)
-        const f32x4 yv = OP == SKEL_MAP_MUL ? reinterpret_cast<const f32x4*>(y)[i]
-                                            : f32x4{0.f, 0.f, 0.f, 0.f};
-        const f32x4 gv = BCAST ? f32x4{gb, gb, gb, gb} : reinterpret_cast<const f32x4*>(g)[i];
-        f32x4 ox, oy;
+    const f32x4* xv = reinterpret_cast<const f32x4*>(x);
+    const f32x4* yv = reinterpret_cast<const f32x4*>(y);
+    const f32x4* gv = reinterpret_cast<const f32x4*>(g);
+    // chunks of U * kBlock vectors, every load of a chunk issued before the
+    // arithmetic; single-use inputs and outputs are streamed non-temporally
+    for (int64_t c = (int64_t)blockIdx.x * U * kBlock; c < nv; c += (int64_t)gridDim.x * U * kBlock) {
+        f32x4 xa[U], ya[U], ga[U];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            float ddx, ddy, s0, s1;
-            elem_grad<OP>(xv[e], yv[e], gv[e], p0, p1, ddx, ddy, s0, s1);
-            ox[e] = ddx;
-            oy[e] = ddy;
-            a0 += s0;
-            a1 += s1;
+        for (int u = 0; u < U; ++u) {
+            const int64_t i = c + u * kBlock + threadIdx.x;
+            const bool in = i < nv;
+            xa[u] = in ? __builtin_nontemporal_load(&xv[i]) : f32x4{0.f, 0.f, 0.f, 0.f};
+            // y enters the derivatives of MUL only (AXPY's are 1 and p0)
+            ya[u] = (OP == SKEL_MAP_MUL && in) ? __builtin_nontemporal_load(&yv[i])
+                                               : f32x4{0.f, 0.f, 0.f, 0.f};
+            ga[u] = BCAST ? f32x4{gb, gb, gb, gb}
+                          : (in ? __builtin_nontemporal_load(&gv[i]) : f32x4{0.f, 0.f, 0.f, 0.f});
         }
-        reinterpret_cast<f32x4*>(dx)[i] = ox;
-        if constexpr (TWO) reinterpret_cast<f32x4*>(dy)[i] = oy;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t i = c + u * kBlock + threadIdx.x;
+            if (i >= nv) break;
+            f32x4 ox, oy;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                float ddx, ddy, s0, s1;
+                elem_grad<OP>(xa[u][e], ya[u][e], ga[u][e], p0, p1, ddx, ddy, s0, s1);
+                ox[e] = ddx;
+                oy[e] = ddy;
+                a0 += s0;
+                a1 += s1;
+            }
+            dev::store_vec_nt(ox, reinterpret_cast<f32x4*>(dx) + i);
+            if constexpr (TWO) dev::store_vec_nt(oy, reinterpret_cast<f32x4*>(dy) + i);
+        }
     }
     // the n % 4 tail, one element per low lane of the first workgroup
     const int64_t t = nv * 4 + (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -298,7 +315,7 @@ skel_status map_grad_op(float p0, float p1, const float* x, const float* y, cons
                         bool bcast, float* dx, float* dy, int64_t n, float* dparams,
                         LaunchCtx& lc) {
     constexpr int NP = grad_nparams<OP>();
-    const int groups = grid_for((n + 3) / 4, *lc.dev);
+    const int groups = grid_for((n + 15) / 16, *lc.dev);  // 4 vectors of 4 per lane
     float* partials = nullptr;
     if (NP > 0 && dparams) {
         void* mem = nullptr;
