@@ -56,6 +56,13 @@ PLAIN = {"map_saxpy": "M0_scalar", "mapoverlap1d_5pt": "O1a_direct",
          "scan_excl_i32_i64": "S1_reduce_then_scan", "mapreduce_dot": "MR0_unfused",
          "mapoverlap2d_9x9": "O2a_direct", "reduce_sum": "R1_two_pass"}
 DOMINANT = "scan_excl_i32_i64"
+# kernels of each Scan variant (int32 -> int64, exclusive sum)
+SCAN_KERNELS = {
+    "S0_single_wg": "scan_single<int32 -> int64, exclusive sum>",
+    "S1_reduce_then_scan": "scan_tile_totals + scan_tile_offsets + scan_tile_apply",
+    "S2_decoupled_lookback": "scan_lookback<int32 -> int64, exclusive sum>",
+    "S3_persistent_lookback": "scan_lookback_persist<int32 -> int64, exclusive sum>",
+}
 KERNEL_SRC = {"scan_excl_i32_i64": "k_scan.hip"}
 
 
@@ -181,9 +188,10 @@ def copy_ceiling(skel, torch, reps=10):
     return 8 * n / (ms * 1e-3) / 1e9, ms
 
 
-def traffic_from_profile(name, per_launch_bytes):
+def traffic_from_profile(name, per_launch_bytes, variant):
     """HBM bytes per launch measured by rocprofv3 counters, from the committed
-    summary in profiles/, or None when the kernel source changed since."""
+    summary in profiles/, or None when the kernel source changed since or the
+    counters were taken on another variant than the one the plan picks."""
     src = KERNEL_SRC.get(name)
     path = os.path.join(ROOT, "profiles", f"{name}_traffic.txt")
     if not src or not os.path.exists(path):
@@ -191,7 +199,8 @@ def traffic_from_profile(name, per_launch_bytes):
     text = open(path).read()
     m_hash = re.search(r"source_sha256:\s*([0-9a-f]{64})", text)
     m_bytes = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
-    if not m_hash or not m_bytes:
+    m_var = re.search(r"variant:\s*(\S+)", text)
+    if not m_hash or not m_bytes or not m_var or m_var.group(1) != variant:
         return None
     cur = hashlib.sha256(open(os.path.join(ROOT, "paper_1405_2915_amd", "csrc", src),
                               "rb").read()).hexdigest()
@@ -498,12 +507,14 @@ def main():
             per[name]["plain_us"] = round(p * 1e3, 2)
 
     ceil_gbs, ceil_ms = copy_ceiling(skel, torch)
+    dom_variant = per[DOMINANT]["variant"]
+    dom_kernel = SCAN_KERNELS.get(dom_variant, dom_variant)
     dom_us = float(np.mean(ms_dom[DOMINANT])) * 1e3  # timed region, launch stream
     achieved = BYTES[DOMINANT] / (dom_us * 1e-6) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic_from_profile(DOMINANT, BYTES[DOMINANT]),
-                "kernel": "scan_lookback<int32 -> int64, exclusive sum>",
+                "traffic": traffic_from_profile(DOMINANT, BYTES[DOMINANT], dom_variant),
+                "kernel": dom_kernel,
                 "kernel_us": round(dom_us, 2),
                 "algorithmic_bytes_per_launch": BYTES[DOMINANT]}
     out = {

@@ -21,7 +21,7 @@ const char* const kOverlap1D[] = {"O1a_direct", "O1b_lds_tile", "O1c_shuffle"};
 const char* const kOverlap2D[] = {"O2a_direct", "O2b_lds_tile", "O2c_lds_separable",
                                   "O2d_separable_l1"};
 const char* const kScan[] = {"S0_single_wg", "S1_reduce_then_scan",
-                             "S2_decoupled_lookback"};
+                             "S2_decoupled_lookback", "S3_persistent_lookback"};
 
 const char* const kSegments[] = {"B0_per_segment", "B1_persistent"};
 const char* const kAdjoint[] = {"A0_gather", "A1_flipped_forward"};
@@ -65,7 +65,7 @@ int static_rule(const CallContext& c) {
     case SKEL_SK_MAPOVERLAP1D: return c.radius <= 4 ? O1C_SHUFFLE : O1B_LDS_TILE;
     case SKEL_SK_MAPOVERLAP2D: return c.separable ? O2D_SEPARABLE_L1 : O2B_LDS_TILE;
     case SKEL_SK_SCAN:
-        return c.n <= (INT64_C(1) << 15) && !c.reverse ? S0_SINGLE_WG : S2_LOOKBACK;
+        return c.n <= (INT64_C(1) << 15) && !c.reverse ? S0_SINGLE_WG : S3_PERSISTENT_LOOKBACK;
     case SKEL_SK_REDUCE_SEGMENTS: return B1_PERSISTENT;
     case SKEL_SK_MAPOVERLAP1D_BACKWARD:
     case SKEL_SK_MAPOVERLAP2D_BACKWARD: return A1_FLIPPED_FORWARD;
@@ -177,8 +177,8 @@ bool selectable(int v, const CallContext& c, const char** why) {
         }
         return true;
     case SKEL_SK_SCAN:
-        if (c.reverse && v != S2_LOOKBACK) {
-            *why = "reverse scans run in the single-pass variant only";
+        if (c.reverse && v != S2_LOOKBACK && v != S3_PERSISTENT_LOOKBACK) {
+            *why = "reverse scans run in the single-pass variants only";
             return false;
         }
         return true;

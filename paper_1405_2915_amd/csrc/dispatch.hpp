@@ -22,7 +22,7 @@ enum Overlap1DVariant { O1A_DIRECT = 0, O1B_LDS_TILE = 1, O1C_SHUFFLE = 2, OVERL
 enum Overlap2DVariant { O2A_DIRECT = 0, O2B_LDS_TILE = 1, O2C_LDS_SEPARABLE = 2,
                         O2D_SEPARABLE_L1 = 3, OVERLAP2D_NVAR };
 enum ScanVariant { S0_SINGLE_WG = 0, S1_REDUCE_THEN_SCAN = 1, S2_LOOKBACK = 2,
-                   SCAN_NVAR };
+                   S3_PERSISTENT_LOOKBACK = 3, SCAN_NVAR };
 enum SegmentsVariant { B0_PER_SEGMENT = 0, B1_PERSISTENT = 1, SEGMENTS_NVAR };
 // MapOverlap adjoints (1D and 2D share the names)
 enum AdjointVariant { A0_GATHER = 0, A1_FLIPPED_FORWARD = 1, ADJOINT_NVAR };

@@ -76,6 +76,9 @@ skel_status ws_counters(LaunchCtx& lc, size_t bytes, void** p);
 skel_status ws_status(LaunchCtx& lc, size_t bytes, void** p);
 skel_status hip_check(hipError_t e, const char* what);
 skel_status launch_check(const char* kernel);
+// workgroups of `block` threads of `kernel` that the device holds at once
+// (0 if the kernel does not fit); queried once per kernel
+int64_t resident_slots(const void* kernel, int block, LaunchCtx& lc);
 
 // kernels (k_*.hip); all return SKEL_OK or SKEL_E_HIP
 skel_status launch_map(int variant, int op, float p0, float p1, const float* x,

@@ -25,6 +25,23 @@ skel_status launch_check(const char* kernel) {
     return fail(SKEL_E_HIP, "launch of %s: %s", kernel, hipGetErrorString(e));
 }
 
+int64_t resident_slots(const void* kernel, int block, LaunchCtx& lc) {
+    // per kernel and block size, on the single device the library drives
+    static std::mutex mu;
+    static std::unordered_map<const void*, int> per_cu;
+    std::lock_guard<std::mutex> g(mu);
+    auto it = per_cu.find(kernel);
+    if (it == per_cu.end()) {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, block, 0) != hipSuccess) {
+            (void)hipGetLastError();
+            nb = 0;
+        }
+        it = per_cu.emplace(kernel, nb).first;
+    }
+    return (int64_t)it->second * lc.dev->cus;
+}
+
 namespace {
 
 hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }

@@ -313,7 +313,7 @@ def name_of(lib, sk, v):
 
 
 def test_variant_registry(rt):
-    want = {SK_MAP: 3, SK_REDUCE: 5, SK_MAPREDUCE: 5, SK_OV1: 3, SK_OV2: 4, SK_SCAN: 3,
+    want = {SK_MAP: 3, SK_REDUCE: 5, SK_MAPREDUCE: 5, SK_OV1: 3, SK_OV2: 4, SK_SCAN: 4,
             SK_SEG: 2, SK_OV1B: 2, SK_OV2B: 2}
     for sk, k in want.items():
         assert rt.skel_variant_count(sk) == k
@@ -329,7 +329,7 @@ def test_static_plan(rt):
     assert sel(SK_REDUCE, 1000) == "R0_single_wg"
     assert sel(SK_REDUCE, 1 << 26) == "R2_ticket"
     assert sel(SK_SCAN, 100, I32) == "S0_single_wg"
-    assert sel(SK_SCAN, 1 << 27, I32) == "S2_decoupled_lookback"
+    assert sel(SK_SCAN, 1 << 27, I32) == "S3_persistent_lookback"
     assert sel(SK_OV2, 1 << 24, F32, 1) == "O2d_separable_l1"
     assert sel(SK_OV2, 1 << 24, F32, 0) == "O2b_lds_tile"  # separable not selectable
     assert sel(SK_OV1, 1 << 20, F32, 2) == "O1c_shuffle"   # aux = radius
@@ -352,7 +352,7 @@ def test_plan_table(rt, tmp_path):
     assert sel(SK_REDUCE, 1 << 28) == "R3_atomic"          # extrapolate beyond
     assert sel(SK_REDUCE, 16) == "R1_two_pass"             # below the table
     assert sel(SK_SCAN, 1 << 20, I32) == "S1_reduce_then_scan"
-    assert sel(SK_SCAN, 1 << 20, I64) == "S2_decoupled_lookback"  # no entry: static
+    assert sel(SK_SCAN, 1 << 20, I64) == "S3_persistent_lookback"  # no entry: static
     # table entry not selectable for this call: static rule instead
     assert sel(SK_OV2, 1 << 20, F32, 0) == "O2b_lds_tile"
     # a bad file is rejected whole and the old table stays
@@ -435,8 +435,8 @@ def test_reverse_scan_plan(rt):
     sel = lambda n, aux: name_of(rt, SK_SCAN, rt.skel_select_variant(SK_SCAN, I32, n, 1, n,
                                                                      aux))
     assert sel(100, 0) == "S0_single_wg"
-    assert sel(100, 1) == "S2_decoupled_lookback"  # reverse kinds: single pass only
-    assert sel(1 << 27, 1) == "S2_decoupled_lookback"
+    assert sel(100, 1) == "S3_persistent_lookback"  # reverse kinds: single pass only
+    assert sel(1 << 27, 1) == "S3_persistent_lookback"
 
 
 # ------------------------------------------------- range-granular coherence

@@ -28,6 +28,9 @@ def cont(skel, a, dtype=None):
 
 
 # ------------------------------------------------------------ reverse scans
+SINGLE_PASS = (2, 3)  # S2 decoupled look-back, S3 its persistent form
+
+
 @pytest.mark.parametrize("pair", ["i32_i32", "i32_i64", "i64_i64"])
 @pytest.mark.parametrize("op", list(RED_OPS))
 def test_reverse_scan_int_bit_exact(skel, oracle_mod, pair, op):
@@ -43,11 +46,12 @@ def test_reverse_scan_int_bit_exact(skel, oracle_mod, pair, op):
         for kind, code in (("reverse_inclusive", skel.REVERSE_INCLUSIVE),
                            ("reverse_exclusive", skel.REVERSE_EXCLUSIVE)):
             ref = oracle_mod.scan(x, kind, op, npd)
-            out = skel.Container.empty(dout, n)
-            skel.skel_scan(cont(skel, x), out, code, RED_OPS[op])
-            got = out.to_numpy()
-            assert np.array_equal(got, ref), (pair, op, n, kind,
-                                              np.flatnonzero(got != ref)[:5])
+            for v in SINGLE_PASS:
+                out = skel.Container.empty(dout, n)
+                skel.skel_scan(cont(skel, x), out, code, RED_OPS[op], variant=v)
+                got = out.to_numpy()
+                assert np.array_equal(got, ref), (pair, op, n, kind, v,
+                                                  np.flatnonzero(got != ref)[:5])
 
 
 def test_reverse_scan_f32(skel, oracle_mod):
@@ -56,15 +60,16 @@ def test_reverse_scan_f32(skel, oracle_mod):
         for kind, code in (("reverse_inclusive", skel.REVERSE_INCLUSIVE),
                            ("reverse_exclusive", skel.REVERSE_EXCLUSIVE)):
             ref, mag = oracle_mod.scan(x, kind)
-            out = skel.Container.empty(skel.F32, n)
-            skel.skel_scan(cont(skel, x), out, code, skel.SUM)
-            bad = np.abs(out.to_numpy().astype(np.float64) - ref) > 1e-5 * mag + 1e-30
-            assert not bad.any(), (n, kind, np.flatnonzero(bad)[:5])
+            for v in SINGLE_PASS:
+                out = skel.Container.empty(skel.F32, n)
+                skel.skel_scan(cont(skel, x), out, code, skel.SUM, variant=v)
+                bad = np.abs(out.to_numpy().astype(np.float64) - ref) > 1e-5 * mag + 1e-30
+                assert not bad.any(), (n, kind, v, np.flatnonzero(bad)[:5])
 
 
 def test_reverse_scan_variants_and_full_size(skel, oracle_mod):
     x = si.int_uniform_i32(4097, 1000, 8, 2)
-    for v, ok in ((0, False), (1, False), (2, True)):
+    for v, ok in ((0, False), (1, False), (2, True), (3, True)):
         out = skel.Container.empty(skel.I64, x.size)
         if ok:
             skel.skel_scan(cont(skel, x), out, skel.REVERSE_EXCLUSIVE, skel.SUM, variant=v)

@@ -2,7 +2,9 @@
 (look-back scan, ticket reductions, the persistent batched Reduce): every run
 must give the bit-identical result.  A race in the hand-off (a descriptor read
 before it is valid, a stale epoch, a lost ticket) would show as a differing
-run.  Each launch has far more workgroups than can be resident at once.  The
+run.  The launches have far more tiles or work items than the device holds
+workgroups at once (S2 starts one workgroup per tile; the persistent forms
+loop each resident workgroup over many).  The
 comparison runs on the device (torch), against the oracle's result uploaded
 once."""
 import numpy as np
@@ -13,7 +15,8 @@ import synth_inputs as si
 pytestmark = pytest.mark.gpu
 
 
-def test_lookback_scan_repeated(skel, oracle_mod):
+@pytest.mark.parametrize("variant", [2, 3])
+def test_lookback_scan_repeated(skel, oracle_mod, variant):
     import torch
     n = 1 << 27
     xh = si.int_uniform_i32(n, 1000, 1, 2)
@@ -23,13 +26,13 @@ def test_lookback_scan_repeated(skel, oracle_mod):
     cx, co = skel.wrap_tensor(x), skel.wrap_tensor(out)
     for rep in range(40):
         out.fill_(-1)
-        skel.skel_scan(cx, co, skel.EXCLUSIVE, skel.SUM, variant=2)
+        skel.skel_scan(cx, co, skel.EXCLUSIVE, skel.SUM, variant=variant)
         assert torch.equal(out, ref), rep
     # the reverse form walks the tiles in the other order
     rref = torch.from_numpy(oracle_mod.scan(xh, "reverse_inclusive", "sum", np.int64)).cuda()
     for rep in range(10):
         out.fill_(-1)
-        skel.skel_scan(cx, co, skel.REVERSE_INCLUSIVE, skel.SUM, variant=2)
+        skel.skel_scan(cx, co, skel.REVERSE_INCLUSIVE, skel.SUM, variant=variant)
         assert torch.equal(out, rref), rep
     skel.skel_sync()
     cx.destroy()
