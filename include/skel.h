@@ -116,7 +116,8 @@ typedef enum skel_skeleton {
     SKEL_SK_REDUCE_SEGMENTS = 6,
     SKEL_SK_MAPOVERLAP1D_BACKWARD = 7,
     SKEL_SK_MAPOVERLAP2D_BACKWARD = 8,
-    SKEL_SK_COUNT = 9
+    SKEL_SK_SCAN_ROWS = 9,
+    SKEL_SK_COUNT = 10
 } skel_skeleton;
 
 #define SKEL_VARIANT_AUTO (-1)
@@ -289,6 +290,21 @@ skel_status skel_scan(skel_container *in, skel_container *out,
                       skel_scan_kind kind, skel_reduce_op op, int variant,
                       void *stream);
 
+/* Row-wise Scan: the Scan skeleton applied to every row of a rows x cols
+ * matrix on its own (a batch of Scan instances of one length, Section III),
+ *     out[r][c] = in[r][0] op ... op in[r][c]        (inclusive; the other
+ * kinds as skel_scan, within each row).  in and out have the same shape; type
+ * pairs, kinds, ops and in-place use as skel_scan.  Variants
+ * (SKEL_SK_SCAN_ROWS): 0 runs one flat single-pass Scan per row (the plan's
+ * choice for the row length; selectable only when every row starts 16-byte
+ * aligned, i.e. cols * element size is a multiple of 16 for both types); 1
+ * runs one wavefront per row in a single launch, with 16-byte accesses when
+ * the rows are so aligned and element accesses otherwise.  The static rule
+ * takes 0 for fewer than 64 aligned rows of at least 2^20 elements, else 1. */
+skel_status skel_scan_rows(skel_container *in, skel_container *out,
+                           skel_scan_kind kind, skel_reduce_op op, int variant,
+                           void *stream);
+
 /* Segmented Reduce: the Reduce skeleton applied to many vectors of uneven
  * length at once (a batch of operands of one skeleton instance, Section III),
  *     out[s] = op over in[offsets[s]] .. in[offsets[s+1] - 1],  0 <= s < nseg
@@ -365,7 +381,9 @@ const char *skel_variant_name(int skeleton, int variant); /* NULL if out of rang
  * n is the element count (rows*cols for 2D); dtype is the input element type;
  * `aux` is the radius for SKEL_SK_MAPOVERLAP1D(_BACKWARD), 1 when the 2D
  * weights are given as separable factors for SKEL_SK_MAPOVERLAP2D(_BACKWARD),
- * 1 for the reverse kinds of SKEL_SK_SCAN, and ignored otherwise. */
+ * 1 for the reverse kinds of SKEL_SK_SCAN and SKEL_SK_SCAN_ROWS, and ignored
+ * otherwise (for SKEL_SK_SCAN_ROWS, rows and cols give the matrix shape and
+ * dtype serves as both types). */
 int skel_select_variant(int skeleton, skel_dtype dtype, int64_t n,
                         int64_t rows, int64_t cols, int aux);
 

@@ -349,3 +349,21 @@ def scan(x, kind: str = "inclusive", op: str = "sum", out_dtype=None):
     if rc:
         raise ValueError("oracle scan: bad kind/op")
     return out
+
+
+def scan_rows(x, kind: str = "inclusive", op: str = "sum", out_dtype=None):
+    """The scan of Section III applied to every row of a 2D array on its own:
+    row r of the result is scan(x[r]).  Same types and returns as scan (for
+    float32 input: (binary64 out, mag), both shaped like x)."""
+    x = np.asarray(x)
+    if x.ndim != 2:
+        raise ValueError("oracle scan_rows: x must be 2D")
+    res = [scan(x[r], kind, op, out_dtype) for r in range(x.shape[0])]
+    if x.dtype == np.float32:
+        if not res:
+            return np.empty(x.shape), np.empty(x.shape)
+        return (np.stack([o for o, _ in res]).reshape(x.shape),
+                np.stack([m for _, m in res]).reshape(x.shape))
+    if not res:
+        return np.empty(x.shape, dtype=np.int64 if out_dtype is not None else x.dtype)
+    return np.stack(res).reshape(x.shape)

@@ -47,7 +47,7 @@ INCLUSIVE, EXCLUSIVE, REVERSE_INCLUSIVE, REVERSE_EXCLUSIVE = 0, 1, 2, 3
 SUM, MIN, MAX = 0, 1, 2
 MAP_IDENTITY, MAP_AXPY, MAP_AFFINE, MAP_TANH, MAP_AFFINE_TANH, MAP_MUL, MAP_SQUARE = range(7)
 SK_MAP, SK_REDUCE, SK_MAPREDUCE, SK_MAPOVERLAP1D, SK_MAPOVERLAP2D, SK_SCAN, \
-    SK_REDUCE_SEGMENTS, SK_MAPOVERLAP1D_BACKWARD, SK_MAPOVERLAP2D_BACKWARD = range(9)
+    SK_REDUCE_SEGMENTS, SK_MAPOVERLAP1D_BACKWARD, SK_MAPOVERLAP2D_BACKWARD, SK_SCAN_ROWS = range(10)
 VARIANT_AUTO = -1
 MAX_RADIUS_1D, MAX_RADIUS_2D = 64, 8
 
@@ -113,6 +113,7 @@ def load_library(path: str = LIB_PATH):
         "skel_mapoverlap1d": (st, [vp, vp, fp, i, i, C.c_float, i, vp]),
         "skel_mapoverlap2d": (st, [vp, vp, fp, fp, fp, i, i, i, C.c_float, i, vp]),
         "skel_scan": (st, [vp, vp, i, i, i, vp]),
+        "skel_scan_rows": (st, [vp, vp, i, i, i, vp]),
         "skel_reduce_segments": (st, [i, vp, vp, vp, i, vp]),
         "skel_container_wrap_device": (st, [i, i64, i64, vp, vp, C.POINTER(vp)]),
         "skel_container_acquire_range": (st, [vp, i, i, i64, i64, vp, C.POINTER(vp)]),
@@ -127,7 +128,11 @@ def load_library(path: str = LIB_PATH):
         "skel_clear_plan": (st, []),
     }
     for name, (res, args) in sig.items():
-        fn = getattr(lib, name)
+        try:
+            fn = getattr(lib, name)
+        except AttributeError as e:
+            raise ImportError(f"{path} lacks {name}: it is older than the sources; rebuild it "
+                              "with `python -m paper_1405_2915_amd.build_lib`") from e
         fn.restype = res
         fn.argtypes = args
     _lib = lib
@@ -533,6 +538,13 @@ def skel_scan(inp: Container, out: Container, kind: int = INCLUSIVE, op: int = S
            "skel_scan")
 
 
+def skel_scan_rows(inp: Container, out: Container, kind: int = INCLUSIVE, op: int = SUM,
+                   variant: int = VARIANT_AUTO, stream=None) -> None:
+    """Scan every row of a (rows, cols) container on its own."""
+    _check(_L().skel_scan_rows(_h(inp), _h(out), kind, op, variant,
+                               C.c_void_p(_stream(stream))), "skel_scan_rows")
+
+
 def skel_reduce_segments(op: int, inp: Container, offsets: Container, out: Container,
                          variant: int = VARIANT_AUTO, stream=None) -> None:
     """out[s] = op over inp[offsets[s]:offsets[s+1]] for every segment s."""
@@ -633,7 +645,12 @@ def _shutdown():
     _shutting_down = True
 
 
-# Load eagerly when built, so a broken library fails at import; when it is not
-# built yet (e.g. while running build_lib), every call raises ImportError.
+# Load eagerly when built, so a broken library fails at import.  When it is not
+# built, or was built from older sources, the package still imports (build_lib
+# lives in it) and every call raises ImportError until it is rebuilt.
 if os.path.exists(LIB_PATH):
-    load_library()
+    try:
+        load_library()
+    except ImportError as _e:
+        if "older than the sources" not in str(_e):
+            raise

@@ -12,6 +12,7 @@ the reverse-mode adjoints declared in include/skel.h:
     mapoverlap1d_fn    transposed neighbourhood map (clamped reads
     mapoverlap2d_fn    accumulate onto the edge elements)
     scan_sum_fn        reverse scan of the upstream gradient
+    scan_rows_sum_fn   reverse scan of each row of the upstream gradient
 
 All tensors are float32 CUDA tensors.  Stencil weights are constants (no
 gradient); Map parameters get a gradient when given as a tensor that
@@ -28,7 +29,7 @@ from . import (EDGE_CLAMP, EXCLUSIVE, INCLUSIVE, MAP_AFFINE, MAP_AFFINE_TANH, MA
                MAP_IDENTITY, MAP_MUL, REVERSE_EXCLUSIVE, REVERSE_INCLUSIVE, SUM, skel_map,
                skel_map_backward, skel_mapoverlap1d, skel_mapoverlap1d_backward,
                skel_mapoverlap2d, skel_mapoverlap2d_backward, skel_mapreduce, skel_reduce,
-               skel_scan, wrap_tensor)
+               skel_scan, skel_scan_rows, wrap_tensor)
 
 _TWO_INPUTS = {MAP_AXPY, MAP_MUL}
 _NPARAMS = {MAP_AXPY: 1, MAP_AFFINE: 2, MAP_AFFINE_TANH: 2}
@@ -246,5 +247,37 @@ def scan_sum_fn(x, kind: int = INCLUSIVE):
     return _ScanSumFn.apply(_f32(x, "x").reshape(-1), int(kind))
 
 
+_REVERSE = {INCLUSIVE: REVERSE_INCLUSIVE, EXCLUSIVE: REVERSE_EXCLUSIVE,
+            REVERSE_INCLUSIVE: INCLUSIVE, REVERSE_EXCLUSIVE: EXCLUSIVE}
+
+
+class _ScanRowsSumFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, x, kind):
+        out = torch.empty_like(x)
+        with _wrapped(x, out) as (cx, co):
+            skel_scan_rows(cx, co, kind, SUM)
+        ctx.kind = kind
+        return out
+
+    @staticmethod
+    def backward(ctx, g):
+        g = _f32(g, "grad")
+        dx = torch.empty_like(g)
+        with _wrapped(g, dx) as (cg, cdx):
+            skel_scan_rows(cg, cdx, _REVERSE[ctx.kind], SUM)
+        return dx, None
+
+
+def scan_rows_sum_fn(x, kind: int = INCLUSIVE):
+    """Prefix (or suffix) sums along the last axis of a float32 tensor,
+    differentiable; leading axes are rows."""
+    x = _f32(x, "x")
+    if x.dim() < 2:
+        raise ValueError("x needs at least 2 dimensions")
+    shape = x.shape
+    return _ScanRowsSumFn.apply(x.reshape(-1, shape[-1]), int(kind)).reshape(shape)
+
+
 __all__ = ["map_fn", "reduce_sum_fn", "mapreduce_sum_fn", "mapoverlap1d_fn",
-           "mapoverlap2d_fn", "scan_sum_fn"]
+           "mapoverlap2d_fn", "scan_sum_fn", "scan_rows_sum_fn"]

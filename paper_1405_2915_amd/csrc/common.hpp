@@ -28,6 +28,12 @@ inline size_t dtype_size(skel_dtype t) {
     return 0;
 }
 inline bool dtype_valid(int t) { return t >= SKEL_F32 && t <= SKEL_I64; }
+
+// every row of a matrix with `cols` columns starts 16-byte aligned in both an
+// input of type a and an output of type b (the matrices themselves are)
+inline bool rows_aligned(skel_dtype a, skel_dtype b, int64_t cols) {
+    return (cols * (int64_t)dtype_size(a)) % 16 == 0 && (cols * (int64_t)dtype_size(b)) % 16 == 0;
+}
 const char* dtype_name(skel_dtype t);
 
 // Everything the container protocol needs from the device runtime.  The HIP

@@ -24,12 +24,27 @@ const char* const kScan[] = {"S0_single_wg", "S1_reduce_then_scan",
                              "S2_decoupled_lookback", "S3_persistent_lookback"};
 
 const char* const kSegments[] = {"B0_per_segment", "B1_persistent"};
+const char* const kScanRows[] = {"SR0_per_row", "SR1_wave_per_row"};
 const char* const kAdjoint[] = {"A0_gather", "A1_flipped_forward"};
 
 const char* const kSkeletonNames[] = {"MAP",          "REDUCE", "MAPREDUCE",
                                       "MAPOVERLAP1D", "MAPOVERLAP2D", "SCAN",
                                       "REDUCE_SEGMENTS", "MAPOVERLAP1D_BACKWARD",
-                                      "MAPOVERLAP2D_BACKWARD"};
+                                      "MAPOVERLAP2D_BACKWARD", "SCAN_ROWS"};
+static_assert(sizeof kSkeletonNames / sizeof kSkeletonNames[0] == SKEL_SK_COUNT,
+              "one name per skeleton id");
+#define SKEL_NAMES_MATCH(table, count) \
+    static_assert(sizeof table / sizeof table[0] == count, "one name per variant of " #table)
+SKEL_NAMES_MATCH(kMap, MAP_NVAR);
+SKEL_NAMES_MATCH(kReduce, REDUCE_NVAR);
+SKEL_NAMES_MATCH(kMapReduce, MAPREDUCE_NVAR);
+SKEL_NAMES_MATCH(kOverlap1D, OVERLAP1D_NVAR);
+SKEL_NAMES_MATCH(kOverlap2D, OVERLAP2D_NVAR);
+SKEL_NAMES_MATCH(kScan, SCAN_NVAR);
+SKEL_NAMES_MATCH(kSegments, SEGMENTS_NVAR);
+SKEL_NAMES_MATCH(kScanRows, SCANROWS_NVAR);
+SKEL_NAMES_MATCH(kAdjoint, ADJOINT_NVAR);
+#undef SKEL_NAMES_MATCH
 
 struct TableEntry {
     int skeleton;
@@ -67,6 +82,11 @@ int static_rule(const CallContext& c) {
     case SKEL_SK_SCAN:
         return c.n <= (INT64_C(1) << 15) && !c.reverse ? S0_SINGLE_WG : S3_PERSISTENT_LOOKBACK;
     case SKEL_SK_REDUCE_SEGMENTS: return B1_PERSISTENT;
+    case SKEL_SK_SCAN_ROWS:
+        // a few long rows: one single-pass scan per row fills the device;
+        // otherwise one wavefront per row
+        return c.rows_aligned && c.rows < 64 && c.cols >= (INT64_C(1) << 20) ? SR0_PER_ROW
+                                                                              : SR1_WAVE_PER_ROW;
     case SKEL_SK_MAPOVERLAP1D_BACKWARD:
     case SKEL_SK_MAPOVERLAP2D_BACKWARD: return A1_FLIPPED_FORWARD;
     }
@@ -108,6 +128,7 @@ int variant_count(int skeleton) {
     case SKEL_SK_MAPOVERLAP2D: return OVERLAP2D_NVAR;
     case SKEL_SK_SCAN: return SCAN_NVAR;
     case SKEL_SK_REDUCE_SEGMENTS: return SEGMENTS_NVAR;
+    case SKEL_SK_SCAN_ROWS: return SCANROWS_NVAR;
     case SKEL_SK_MAPOVERLAP1D_BACKWARD:
     case SKEL_SK_MAPOVERLAP2D_BACKWARD: return ADJOINT_NVAR;
     }
@@ -124,6 +145,7 @@ const char* variant_name(int skeleton, int v) {
     case SKEL_SK_MAPOVERLAP2D: return kOverlap2D[v];
     case SKEL_SK_SCAN: return kScan[v];
     case SKEL_SK_REDUCE_SEGMENTS: return kSegments[v];
+    case SKEL_SK_SCAN_ROWS: return kScanRows[v];
     case SKEL_SK_MAPOVERLAP1D_BACKWARD:
     case SKEL_SK_MAPOVERLAP2D_BACKWARD: return kAdjoint[v];
     }
@@ -179,6 +201,12 @@ bool selectable(int v, const CallContext& c, const char** why) {
     case SKEL_SK_SCAN:
         if (c.reverse && v != S2_LOOKBACK && v != S3_PERSISTENT_LOOKBACK) {
             *why = "reverse scans run in the single-pass variants only";
+            return false;
+        }
+        return true;
+    case SKEL_SK_SCAN_ROWS:
+        if (v == SR0_PER_ROW && !c.rows_aligned) {
+            *why = "per-row single-pass scans need 16-byte aligned row starts";
             return false;
         }
         return true;
@@ -304,7 +332,10 @@ int skel_select_variant(int skeleton, skel_dtype dtype, int64_t n, int64_t rows,
     if (skeleton == SKEL_SK_MAPOVERLAP1D || skeleton == SKEL_SK_MAPOVERLAP1D_BACKWARD)
         c.radius = aux;
     else if (skeleton == SKEL_SK_SCAN) c.reverse = aux;
-    else c.separable = aux;
+    else if (skeleton == SKEL_SK_SCAN_ROWS) {
+        c.reverse = aux;
+        c.rows_aligned = skel::rows_aligned(dtype, dtype, cols);
+    } else c.separable = aux;
     skel_status st;
     return skel::choose_variant(SKEL_VARIANT_AUTO, c, &st);
 }

@@ -24,6 +24,7 @@ enum Overlap2DVariant { O2A_DIRECT = 0, O2B_LDS_TILE = 1, O2C_LDS_SEPARABLE = 2,
 enum ScanVariant { S0_SINGLE_WG = 0, S1_REDUCE_THEN_SCAN = 1, S2_LOOKBACK = 2,
                    S3_PERSISTENT_LOOKBACK = 3, SCAN_NVAR };
 enum SegmentsVariant { B0_PER_SEGMENT = 0, B1_PERSISTENT = 1, SEGMENTS_NVAR };
+enum ScanRowsVariant { SR0_PER_ROW = 0, SR1_WAVE_PER_ROW = 1, SCANROWS_NVAR };
 // MapOverlap adjoints (1D and 2D share the names)
 enum AdjointVariant { A0_GATHER = 0, A1_FLIPPED_FORWARD = 1, ADJOINT_NVAR };
 
@@ -37,6 +38,7 @@ struct CallContext {
     int separable = 0;  // MapOverlap2D: weights given as factors
     int radius = 0;     // MapOverlap1D radius
     int reverse = 0;    // Scan: a reverse (suffix) kind
+    int rows_aligned = 0;  // row-wise Scan: every row starts 16-byte aligned
 };
 
 int variant_count(int skeleton);

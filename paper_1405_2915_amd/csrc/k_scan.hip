@@ -130,10 +130,12 @@ __device__ __forceinline__ void keep_raw_only(Raw<P>& raw) {
 // Scan the wavefront's slice given its exclusive prefix, and store it.  REV:
 // the slice is combined from its last element down (the prefix then holds
 // everything after the slice).
+// Returns prefix op (the slice's elements below n).
 template <class P, bool FULL, bool REV = false>
-__device__ __forceinline__ void tile_scan_store(typename P::out_t* out, int64_t n, int64_t tile,
-                                                const Raw<P>& raw, typename P::acc_t prefix,
-                                                bool exclusive) {
+__device__ __forceinline__ typename P::acc_t tile_scan_store(typename P::out_t* out, int64_t n,
+                                                             int64_t tile, const Raw<P>& raw,
+                                                             typename P::acc_t prefix,
+                                                             bool exclusive) {
     using acc_t = typename P::acc_t;
     using out_t = typename P::out_t;
     using C = typename P::C;
@@ -183,6 +185,7 @@ __device__ __forceinline__ void tile_scan_store(typename P::out_t* out, int64_t 
         // (interleaving rows would spill at 1024 lanes per workgroup)
         __builtin_amdgcn_sched_barrier(0);
     }
+    return running;
 }
 
 // Wavefront totals -> LDS; returns (exclusive prefix of this wavefront within
@@ -477,6 +480,71 @@ __global__ __launch_bounds__(P::kBlock) void scan_single(const typename P::in_t*
     }
 }
 
+// ----------------------------------------------------------- row-wise scans
+// Every row of a rows x cols matrix scanned on its own (a batch of Scan
+// instances of one length).  SR1: one wavefront per row, walking it in chunks
+// of 2048 elements laid out like one wavefront's slice of a tile and carrying
+// the running prefix from chunk to chunk (REV: from the row's end).  Rows
+// whose starts are not 16-byte aligned take 64-element chunks of single-element
+// accesses instead.
+template <int DIN, int DOUT, int OP>
+struct SPW : SP<DIN, DOUT, OP> {
+    static constexpr int NW = 1;
+    static constexpr int kBlock = kWave;
+    static constexpr int64_t kTile = SP<DIN, DOUT, OP>::kWaveElems;
+};
+
+template <class P, bool REV>
+__global__ __launch_bounds__(kWave) void scan_rows_vec(const typename P::in_t* in,
+                                                       typename P::out_t* out, int64_t rows,
+                                                       int64_t cols, int exclusive) {
+    using acc_t = typename P::acc_t;
+    const int64_t nch = (cols + P::kTile - 1) / P::kTile;
+    for (int64_t row = blockIdx.x; row < rows; row += gridDim.x) {
+        const typename P::in_t* src = in + row * cols;
+        typename P::out_t* dst = out + row * cols;
+        acc_t carry = P::C::id();
+        for (int64_t q = 0; q < nch; ++q) {
+            const int64_t ch = REV ? nch - 1 - q : q;
+            Raw<P> raw;
+            if ((ch + 1) * P::kTile <= cols) {
+                tile_load<P, true, true>(src, cols, ch, raw);
+                keep_raw_only<P>(raw);
+                carry = tile_scan_store<P, true, REV>(dst, cols, ch, raw, carry, exclusive != 0);
+            } else {
+                tile_load<P, false, true>(src, cols, ch, raw);
+                keep_raw_only<P>(raw);
+                carry = tile_scan_store<P, false, REV>(dst, cols, ch, raw, carry, exclusive != 0);
+            }
+        }
+    }
+}
+
+template <class P, bool REV>
+__global__ __launch_bounds__(kWave) void scan_rows_scalar(const typename P::in_t* in,
+                                                          typename P::out_t* out, int64_t rows,
+                                                          int64_t cols, int exclusive) {
+    using acc_t = typename P::acc_t;
+    using C = typename P::C;
+    const int l = lane();
+    const int64_t nch = (cols + kWave - 1) / kWave;
+    for (int64_t row = blockIdx.x; row < rows; row += gridDim.x) {
+        const typename P::in_t* src = in + row * cols;
+        typename P::out_t* dst = out + row * cols;
+        acc_t carry = C::id();
+        for (int64_t q = 0; q < nch; ++q) {
+            const int64_t i = (REV ? nch - 1 - q : q) * kWave + l;
+            const acc_t x = i < cols ? widen<acc_t>(src[i]) : C::id();
+            const acc_t incl = REV ? wave_inclusive_suffix_scan<C>(x) : wave_inclusive_scan<C>(x);
+            const acc_t nb = REV ? __shfl_down(incl, 1) : __shfl_up(incl, 1);
+            const bool first = REV ? l == kWave - 1 : l == 0;
+            const acc_t v = C::op(carry, exclusive ? (first ? C::id() : nb) : incl);
+            if (i < cols) dst[i] = (typename P::out_t)v;
+            carry = C::op(carry, __shfl(incl, REV ? 0 : kWave - 1));
+        }
+    }
+}
+
 // --------------------------------------------------------------- launchers
 template <int DIN, int DOUT, int OP>
 skel_status scan_typed(int v, int kind, const void* x, void* y, int64_t n, LaunchCtx& lc) {
@@ -534,6 +602,36 @@ skel_status scan_typed(int v, int kind, const void* x, void* y, int64_t n, Launc
     }
 }
 
+template <int DIN, int DOUT, int OP>
+skel_status scan_rows_typed(int kind, const void* x, void* y, int64_t rows, int64_t cols,
+                            bool vec, LaunchCtx& lc) {
+    using P = SPW<DIN, DOUT, OP>;
+    const auto* in = static_cast<const typename P::in_t*>(x);
+    auto* out = static_cast<typename P::out_t*>(y);
+    const bool rev = kind == SKEL_REVERSE_INCLUSIVE || kind == SKEL_REVERSE_EXCLUSIVE;
+    const int excl = (kind == SKEL_EXCLUSIVE || kind == SKEL_REVERSE_EXCLUSIVE) ? 1 : 0;
+    const unsigned grid = (unsigned)std::min<int64_t>(rows, INT64_C(1) << 20);
+    hipStream_t st = lc.stream;
+    if (vec) {
+        if (rev) scan_rows_vec<P, true><<<grid, kWave, 0, st>>>(in, out, rows, cols, excl);
+        else scan_rows_vec<P, false><<<grid, kWave, 0, st>>>(in, out, rows, cols, excl);
+        return launch_check("scan_rows_vec");
+    }
+    if (rev) scan_rows_scalar<P, true><<<grid, kWave, 0, st>>>(in, out, rows, cols, excl);
+    else scan_rows_scalar<P, false><<<grid, kWave, 0, st>>>(in, out, rows, cols, excl);
+    return launch_check("scan_rows_scalar");
+}
+
+template <int DIN, int DOUT>
+skel_status scan_rows_op(int kind, int op, const void* x, void* y, int64_t rows, int64_t cols,
+                         bool vec, LaunchCtx& lc) {
+    switch (op) {
+    case SKEL_SUM: return scan_rows_typed<DIN, DOUT, SKEL_SUM>(kind, x, y, rows, cols, vec, lc);
+    case SKEL_MIN: return scan_rows_typed<DIN, DOUT, SKEL_MIN>(kind, x, y, rows, cols, vec, lc);
+    default: return scan_rows_typed<DIN, DOUT, SKEL_MAX>(kind, x, y, rows, cols, vec, lc);
+    }
+}
+
 template <int DIN, int DOUT>
 skel_status scan_op(int v, int kind, int op, const void* x, void* y, int64_t n,
                     LaunchCtx& lc) {
@@ -545,6 +643,15 @@ skel_status scan_op(int v, int kind, int op, const void* x, void* y, int64_t n,
 }
 
 }  // namespace
+
+skel_status launch_scan_rows(int kind, int op, skel_dtype din, skel_dtype dout, const void* x,
+                             void* y, int64_t rows, int64_t cols, bool vec, LaunchCtx& lc) {
+    if (din == SKEL_I32 && dout == SKEL_I32)
+        return scan_rows_op<SKEL_I32, SKEL_I32>(kind, op, x, y, rows, cols, vec, lc);
+    if (din == SKEL_I32) return scan_rows_op<SKEL_I32, SKEL_I64>(kind, op, x, y, rows, cols, vec, lc);
+    if (din == SKEL_I64) return scan_rows_op<SKEL_I64, SKEL_I64>(kind, op, x, y, rows, cols, vec, lc);
+    return scan_rows_op<SKEL_F32, SKEL_F32>(kind, op, x, y, rows, cols, vec, lc);
+}
 
 skel_status launch_scan(int v, int kind, int op, skel_dtype din, skel_dtype dout,
                         const void* x, void* y, int64_t n, LaunchCtx& lc) {

@@ -101,6 +101,10 @@ skel_status launch_reduce_segments(int variant, int op, const float* x, int64_t 
 skel_status launch_scan(int variant, int kind, int op, skel_dtype din,
                         skel_dtype dout, const void* x, void* out, int64_t n,
                         LaunchCtx& lc);
+// every row of a rows x cols matrix scanned on its own, one wavefront per row;
+// vec: row starts are 16-byte aligned for both types (16-byte accesses)
+skel_status launch_scan_rows(int kind, int op, skel_dtype din, skel_dtype dout, const void* x,
+                             void* y, int64_t rows, int64_t cols, bool vec, LaunchCtx& lc);
 // adjoints (k_grad.hip); g_broadcast: g holds one value for every element
 skel_status launch_map_backward(int op, float p0, float p1, const float* x, const float* y,
                                 const float* g, bool g_broadcast, float* dx, float* dy,

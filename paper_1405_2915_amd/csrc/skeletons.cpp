@@ -407,6 +407,65 @@ skel_status skel_scan(skel_container* in, skel_container* out, skel_scan_kind ki
     });
 }
 
+skel_status skel_scan_rows(skel_container* in, skel_container* out, skel_scan_kind kind,
+                           skel_reduce_op op, int variant, void* stream) {
+    LaunchCtx lc;
+    skel_status st = begin(stream, &lc);
+    if (st != SKEL_OK) return st;
+    if (!in || !out) return fail(SKEL_E_INVAL, "null container");
+    if (kind < SKEL_INCLUSIVE || kind > SKEL_REVERSE_EXCLUSIVE)
+        return fail(SKEL_E_INVAL, "unknown scan kind %d", (int)kind);
+    if (!reduce_op_valid(op)) return fail(SKEL_E_INVAL, "unknown scan op %d", (int)op);
+    const skel_dtype a = in->dtype, b = out->dtype;
+    bool ok = (a == SKEL_I32 && (b == SKEL_I32 || b == SKEL_I64)) ||
+              (a == SKEL_I64 && b == SKEL_I64) || (a == SKEL_F32 && b == SKEL_F32);
+    if (!ok)
+        return fail(SKEL_E_DTYPE, "Scan %s -> %s not supported", dtype_name(a),
+                    dtype_name(b));
+    if (in->rows != out->rows || in->cols != out->cols)
+        return fail(SKEL_E_SHAPE, "row-wise Scan operand shapes differ");
+    CallContext cc;
+    cc.skeleton = SKEL_SK_SCAN_ROWS;
+    cc.din = a;
+    cc.dout = b;
+    cc.n = in->n;
+    cc.rows = in->rows;
+    cc.cols = in->cols;
+    cc.op = op;
+    cc.reverse = kind == SKEL_REVERSE_INCLUSIVE || kind == SKEL_REVERSE_EXCLUSIVE;
+    cc.rows_aligned = rows_aligned(a, b, in->cols);
+    int v = choose_variant(variant, cc, &st);
+    if (v < 0) return st;
+    int flat = -1;
+    if (v == SR0_PER_ROW && in->n > 0) {
+        // each row runs the flat Scan variant the plan picks for its length
+        CallContext fc = cc;
+        fc.skeleton = SKEL_SK_SCAN;
+        fc.n = in->cols;
+        fc.rows = fc.cols = 0;
+        flat = choose_variant(SKEL_VARIANT_AUTO, fc, &st);
+        if (flat < 0) return st;
+    }
+    Operands ops;
+    ops.add(in, SKEL_READ);
+    ops.add(out, SKEL_WRITE);
+    return run(ops, stream, lc, [&]() -> skel_status {
+        if (in->n == 0) return SKEL_OK;
+        if (v == SR1_WAVE_PER_ROW)
+            return launch_scan_rows(kind, op, a, b, ops.ptr(in), ops.ptr(out), in->rows,
+                                    in->cols, cc.rows_aligned != 0, lc);
+        const size_t sa = dtype_size(a), sb = dtype_size(b);
+        const char* x = static_cast<const char*>(ops.ptr(in));
+        char* y = static_cast<char*>(ops.ptr(out));
+        for (int64_t r = 0; r < in->rows; ++r) {
+            const skel_status e = launch_scan(flat, kind, op, a, b, x + r * in->cols * sa,
+                                              y + r * in->cols * sb, in->cols, lc);
+            if (e != SKEL_OK) return e;
+        }
+        return SKEL_OK;
+    });
+}
+
 skel_status skel_map_backward(skel_map_op op, const double* params, int nparams,
                               skel_container* const* in, int nin, skel_container* g,
                               skel_container* const* grad_in, skel_container* grad_params,

@@ -304,7 +304,8 @@ def test_create_validation(rt):
 
 # ------------------------------------------------------------ execution plan
 
-SK_MAP, SK_REDUCE, SK_MAPREDUCE, SK_OV1, SK_OV2, SK_SCAN, SK_SEG, SK_OV1B, SK_OV2B = range(9)
+SK_MAP, SK_REDUCE, SK_MAPREDUCE, SK_OV1, SK_OV2, SK_SCAN, SK_SEG, SK_OV1B, SK_OV2B, \
+    SK_SCANROWS = range(10)
 
 
 def name_of(lib, sk, v):
@@ -314,7 +315,7 @@ def name_of(lib, sk, v):
 
 def test_variant_registry(rt):
     want = {SK_MAP: 3, SK_REDUCE: 5, SK_MAPREDUCE: 5, SK_OV1: 3, SK_OV2: 4, SK_SCAN: 4,
-            SK_SEG: 2, SK_OV1B: 2, SK_OV2B: 2}
+            SK_SEG: 2, SK_OV1B: 2, SK_OV2B: 2, SK_SCANROWS: 2}
     for sk, k in want.items():
         assert rt.skel_variant_count(sk) == k
         names = [name_of(rt, sk, v) for v in range(k)]
@@ -429,6 +430,17 @@ def test_wrap_device_rejects_bad_arguments(rt):
     # an empty wrapped container needs no memory
     assert rt.skel_container_wrap_device(F32, 1, 0, None, None, C.byref(h)) == OK
     assert rt.skel_container_destroy(h) == OK
+
+
+def test_scan_rows_plan(rt):
+    sel = lambda rows, cols, dt=I32, rev=0: name_of(
+        rt, SK_SCANROWS, rt.skel_select_variant(SK_SCANROWS, dt, rows * cols, rows, cols, rev))
+    assert sel(64 * 2048, 2048) == "SR1_wave_per_row"       # many rows: one launch
+    assert sel(4, 1 << 24) == "SR0_per_row"                 # few long rows
+    assert sel(4, (1 << 24) + 2) == "SR1_wave_per_row"      # rows not 16-byte aligned
+    assert sel(4, (1 << 24) + 2, I64) == "SR0_per_row"      # 8-byte elements: aligned
+    assert sel(4, 1 << 24, I32, 1) == "SR0_per_row"         # reverse kinds too
+    assert rt.skel_variant_name(SK_SCANROWS, 2) is None
 
 
 def test_reverse_scan_plan(rt):

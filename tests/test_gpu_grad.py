@@ -261,6 +261,22 @@ def test_autograd_functions(skel, oracle_mod):
     ref, mag = oracle_mod.scan(gh, "reverse_exclusive")
     assert np.all(np.abs(x.grad.cpu().numpy() - ref) <= 1e-5 * mag + 1e-30)
 
+    # scan along the last axis of a batch of fields (3 x 40 x 2048, and an odd
+    # width): each row's gradient is its own suffix sum
+    for shape in [(3, 40, 2048), (5, 37)]:
+        nel = int(np.prod(shape))
+        fh = si.normal_f32(nel, 10, 6).reshape(shape)
+        gf = si.normal_f32(nel, 10, 7).reshape(shape)
+        f = t(fh).requires_grad_()
+        sr = ag.scan_rows_sum_fn(f, skel.INCLUSIVE)
+        ref, mag = oracle_mod.scan_rows(fh.reshape(-1, shape[-1]), "inclusive")
+        got = sr.detach().cpu().numpy().reshape(ref.shape)
+        assert np.all(np.abs(got - ref) <= 1e-5 * mag + 1e-30), shape
+        (sr * t(gf)).sum().backward()
+        ref, mag = oracle_mod.scan_rows(gf.reshape(-1, shape[-1]), "reverse_inclusive")
+        got = f.grad.cpu().numpy().reshape(ref.shape)
+        assert np.all(np.abs(got - ref) <= 1e-5 * mag + 1e-30), shape
+
 
 def test_wrap_tensor_round_trip(skel, oracle_mod):
     import torch

@@ -522,6 +522,29 @@ def test_reverse_scan_f32_and_widening(oracle_mod):
     assert narrow.tolist() == [((int(v) + 2 ** 31) % 2 ** 32) - 2 ** 31 for v in exact]
 
 
+def test_scan_rows_library_forms(oracle_mod):
+    # a row-wise scan is numpy's cumsum along the last axis (exact in int64;
+    # the float32 case against a float64 cumsum of the stored values)
+    g = si.rng(5, 7)
+    x = g.integers(-1000, 1000, (7, 301), dtype=np.int64).astype(np.int32)
+    c = np.cumsum(x.astype(np.int64), axis=1)
+    assert np.array_equal(oracle_mod.scan_rows(x, "inclusive", "sum", np.int64), c)
+    assert np.array_equal(oracle_mod.scan_rows(x, "exclusive", "sum", np.int64), c - x)
+    rc = np.cumsum(x[:, ::-1].astype(np.int64), axis=1)[:, ::-1]
+    assert np.array_equal(oracle_mod.scan_rows(x, "reverse_inclusive", "sum", np.int64), rc)
+    assert np.array_equal(oracle_mod.scan_rows(x, "reverse_exclusive", "sum", np.int64), rc - x)
+    assert np.array_equal(oracle_mod.scan_rows(x, "inclusive", "max"),
+                          np.maximum.accumulate(x, axis=1))
+    xf = si.normal_f32(5 * 64, 0, 13).reshape(5, 64)
+    out, mag = oracle_mod.scan_rows(xf, "inclusive")
+    assert np.array_equal(out, np.cumsum(xf.astype(np.float64), axis=1))
+    assert np.array_equal(mag, np.cumsum(np.abs(xf.astype(np.float64)), axis=1))
+    # rows do not leak into each other: a row of ones after a row of large values
+    y = np.array([[10 ** 6] * 5, [1] * 5], np.int32)
+    assert oracle_mod.scan_rows(y, "inclusive", "sum").tolist()[1] == [1, 2, 3, 4, 5]
+    assert oracle_mod.scan_rows(np.zeros((3, 0), np.int32)).shape == (3, 0)
+
+
 def _dense_1d(oracle_mod, n, w, r, edge):
     """The forward map as a dense matrix, column j = forward(e_j) (pad 0)."""
     a = np.zeros((n, n))
