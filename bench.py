@@ -310,6 +310,74 @@ def backward_kernels(skel, torch, wl):
     return res
 
 
+FIELDS, FIELD_H, FIELD_W = 64, 2048, 2048  # the batched layer: 2^28 f32 per tensor
+
+
+def field_layer(skel, torch, reps=5):
+    """The differentiable layer on a batch of fields (64 x 2048 x 2048 f32,
+    N(0, 1) from torch's seeded generator on the device): a 5-point stencil on
+    every field (clamped borders), then prefix sums along every field row.
+    Forward: one batched-field stencil call and one row-wise Scan; backward
+    from an upstream gradient: one reverse row-wise Scan and one batched-field
+    stencil transpose.  Each part is captured once into a HIP graph and
+    replayed (HIP events on the replay stream); every part moves 8 algorithmic
+    bytes per element (f32 in, f32 out)."""
+    import synth_inputs as si
+    dev = torch.device("cuda", 0)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(si.BASE_SEED + 1000 * 4)
+    shape = (FIELDS, FIELD_H, FIELD_W)
+    x = torch.randn(shape, generator=gen, device=dev)
+    gz = torch.randn(shape, generator=gen, device=dev)
+    y, z, gy, gx = (torch.empty_like(x) for _ in range(4))
+    w5 = si.five_point_weights()
+    stream = torch.cuda.Stream()
+    res, made = {}, []
+    with torch.cuda.stream(stream):
+        def wrap(t):
+            made.append(skel.wrap_tensor(t, stream))
+            return made[-1]
+        rows = lambda t: wrap(t.view(-1, FIELD_W))
+        cx, cy, cz, cgz, cgy, cgx = (rows(t) for t in (x, y, z, gz, gy, gx))
+        parts = {
+            "forward_stencil": lambda: skel.skel_mapoverlap2d_fields(
+                cx, cy, FIELDS, w2d=w5, edge=skel.EDGE_CLAMP),
+            "forward_scan_rows": lambda: skel.skel_scan_rows(cy, cz, skel.INCLUSIVE, skel.SUM),
+            "backward_scan_rows": lambda: skel.skel_scan_rows(cgz, cgy, skel.REVERSE_INCLUSIVE,
+                                                              skel.SUM),
+            "backward_stencil": lambda: skel.skel_mapoverlap2d_fields_backward(
+                cgy, cgx, FIELDS, w2d=w5, edge=skel.EDGE_CLAMP),
+        }
+        for fn in parts.values():  # sizes the stream's workspace outside the captures
+            fn()
+        torch.cuda.synchronize()
+        graphs = {}
+        for name, fn in parts.items():
+            graphs[name] = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(graphs[name], stream=stream):
+                fn()
+        torch.cuda.synchronize()
+        nbytes = 8 * x.numel()
+        for name, g in graphs.items():
+            g.replay()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            for _ in range(reps):
+                g.replay()
+            b.record(stream)
+            b.synchronize()
+            ms = a.elapsed_time(b) / reps
+            res[name] = {"us": round(ms * 1e3, 1), "GBps": round(nbytes / (ms * 1e-3) / 1e9, 1)}
+    skel.skel_sync(stream)
+    for c in made:
+        c.destroy()
+    for p in ("forward", "backward"):
+        us = sum(v["us"] for k, v in res.items() if k.startswith(p))
+        res[p] = {"us": round(us, 1), "GBps": round(2 * 8 * x.numel() / (us * 1e-6) / 1e9, 1)}
+    res["fields"] = [FIELDS, FIELD_H, FIELD_W]
+    return res
+
+
 def dispatch_overhead(skel, torch):
     """Host cost of the execution plan and of a whole skeleton call (argument
     checks, plan, container protocol, launch), from Python through the C ABI,
@@ -543,6 +611,8 @@ def main():
         out["next_rows"] = nxt
         log("backward kernels")
         nxt["backward"] = backward_kernels(skel, torch, wl)
+        log("batched field layer, 64 x 2048^2: forward and backward")
+        nxt["field_layer"] = field_layer(skel, torch)
         log("small configuration, 2^20")
         out["small_config"] = small_config(skel, torch)
         out["small_config"]["dispatch"] = dispatch_overhead(skel, torch)

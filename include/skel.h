@@ -279,6 +279,18 @@ skel_status skel_mapoverlap2d(skel_container *in, skel_container *out,
                               const float *wx, int ry, int rx, skel_edge edge,
                               float pad, int variant, void *stream);
 
+/* MapOverlap 2D over a batch of equally shaped images (fields) stored back to
+ * back: in and out are (fields * H) x W containers, and every H x W field is
+ * mapped on its own, exactly as skel_mapoverlap2d maps one image (its own
+ * borders; no field reads another).  fields must divide the row count
+ * (SKEL_E_SHAPE otherwise).  One launch covers many fields, which keeps the
+ * device full for small fields.  skel_mapoverlap2d is the case fields = 1. */
+skel_status skel_mapoverlap2d_fields(skel_container *in, skel_container *out,
+                                     int64_t fields, const float *w2d,
+                                     const float *wy, const float *wx, int ry,
+                                     int rx, skel_edge edge, float pad,
+                                     int variant, void *stream);
+
 /* Scan (Section III): inclusive out[i] = in[0] op ... op in[i]; exclusive
  * out[0] = identity, out[i] = in[0] op ... op in[i-1]; reverse inclusive
  * out[i] = in[i] op ... op in[n-1]; reverse exclusive out[n-1] = identity,
@@ -370,6 +382,16 @@ skel_status skel_mapoverlap2d_backward(skel_container *g, skel_container *grad_i
                                        const float *w2d, const float *wy,
                                        const float *wx, int ry, int rx, skel_edge edge,
                                        int variant, void *stream);
+
+/* MapOverlap 2D backward over a batch of fields, as skel_mapoverlap2d_fields:
+ * every field's transpose on its own.  skel_mapoverlap2d_backward is the case
+ * fields = 1. */
+skel_status skel_mapoverlap2d_fields_backward(skel_container *g,
+                                              skel_container *grad_in,
+                                              int64_t fields, const float *w2d,
+                                              const float *wy, const float *wx,
+                                              int ry, int rx, skel_edge edge,
+                                              int variant, void *stream);
 
 /* ------------------------------------------- variants and selection ---- */
 

@@ -121,6 +121,8 @@ def load_library(path: str = LIB_PATH):
         "skel_map_backward": (st, [i, dp, i, C.POINTER(vp), i, vp, C.POINTER(vp), vp, vp]),
         "skel_mapoverlap1d_backward": (st, [vp, vp, fp, i, i, i, vp]),
         "skel_mapoverlap2d_backward": (st, [vp, vp, fp, fp, fp, i, i, i, i, vp]),
+        "skel_mapoverlap2d_fields": (st, [vp, vp, i64, fp, fp, fp, i, i, i, C.c_float, i, vp]),
+        "skel_mapoverlap2d_fields_backward": (st, [vp, vp, i64, fp, fp, fp, i, i, i, i, vp]),
         "skel_variant_count": (i, [i]),
         "skel_variant_name": (C.c_char_p, [i, i]),
         "skel_select_variant": (i, [i, i, i64, i64, i64, i]),
@@ -508,10 +510,9 @@ def skel_mapoverlap1d(inp: Container, out: Container, w, radius: int,
                                   C.c_void_p(_stream(stream))), "skel_mapoverlap1d")
 
 
-def skel_mapoverlap2d(inp: Container, out: Container, w2d=None, wy=None, wx=None,
-                      ry: int | None = None, rx: int | None = None,
-                      edge: int = EDGE_CLAMP, pad: float = 0.0,
-                      variant: int = VARIANT_AUTO, stream=None) -> None:
+def _weights_2d(w2d, wy, wx, ry, rx):
+    """ctypes pointers for the 2D weights (and the arrays they point into,
+    which the caller keeps alive for the call) and the radii."""
     a2, p2 = _floats(w2d)
     ay, py = _floats(wy)
     ax, px = _floats(wx)
@@ -528,8 +529,28 @@ def skel_mapoverlap2d(inp: Container, out: Container, w2d=None, wy=None, wx=None
         rx = (ax.size - 1) // 2 if rx is None else rx
         if ay.size != 2 * ry + 1 or ax.size != 2 * rx + 1:
             raise ValueError("wy / wx sizes must be 2r+1")
+    return (p2, py, px), (a2, ay, ax), ry, rx
+
+
+def skel_mapoverlap2d(inp: Container, out: Container, w2d=None, wy=None, wx=None,
+                      ry: int | None = None, rx: int | None = None,
+                      edge: int = EDGE_CLAMP, pad: float = 0.0,
+                      variant: int = VARIANT_AUTO, stream=None) -> None:
+    (p2, py, px), keep, ry, rx = _weights_2d(w2d, wy, wx, ry, rx)
     _check(_L().skel_mapoverlap2d(_h(inp), _h(out), p2, py, px, ry, rx, edge, pad, variant,
                                   C.c_void_p(_stream(stream))), "skel_mapoverlap2d")
+
+
+def skel_mapoverlap2d_fields(inp: Container, out: Container, fields: int, w2d=None, wy=None,
+                             wx=None, ry: int | None = None, rx: int | None = None,
+                             edge: int = EDGE_CLAMP, pad: float = 0.0,
+                             variant: int = VARIANT_AUTO, stream=None) -> None:
+    """The 2D map on each of `fields` equally shaped images stored back to back
+    in (fields * H, W) containers."""
+    (p2, py, px), keep, ry, rx = _weights_2d(w2d, wy, wx, ry, rx)
+    _check(_L().skel_mapoverlap2d_fields(_h(inp), _h(out), fields, p2, py, px, ry, rx, edge,
+                                         pad, variant, C.c_void_p(_stream(stream))),
+           "skel_mapoverlap2d_fields")
 
 
 def skel_scan(inp: Container, out: Container, kind: int = INCLUSIVE, op: int = SUM,
@@ -582,19 +603,22 @@ def skel_mapoverlap2d_backward(g: Container, grad_in: Container, w2d=None, wy=No
                                ry: int | None = None, rx: int | None = None,
                                edge: int = EDGE_CLAMP, variant: int = VARIANT_AUTO,
                                stream=None) -> None:
-    a2, p2 = _floats(w2d)
-    ay, py = _floats(wy)
-    ax, px = _floats(wx)
-    if w2d is not None:
-        shp = np.shape(w2d)
-        ry = (shp[0] - 1) // 2 if ry is None else ry
-        rx = (shp[1] - 1) // 2 if rx is None else rx
-    else:
-        ry = (ay.size - 1) // 2 if ry is None else ry
-        rx = (ax.size - 1) // 2 if rx is None else rx
+    (p2, py, px), keep, ry, rx = _weights_2d(w2d, wy, wx, ry, rx)
     _check(_L().skel_mapoverlap2d_backward(_h(g), _h(grad_in), p2, py, px, ry, rx, edge,
                                            variant, C.c_void_p(_stream(stream))),
            "skel_mapoverlap2d_backward")
+
+
+def skel_mapoverlap2d_fields_backward(g: Container, grad_in: Container, fields: int, w2d=None,
+                                      wy=None, wx=None, ry: int | None = None,
+                                      rx: int | None = None, edge: int = EDGE_CLAMP,
+                                      variant: int = VARIANT_AUTO, stream=None) -> None:
+    """The 2D transpose on each of `fields` equally shaped images."""
+    (p2, py, px), keep, ry, rx = _weights_2d(w2d, wy, wx, ry, rx)
+    _check(_L().skel_mapoverlap2d_fields_backward(_h(g), _h(grad_in), fields, p2, py, px, ry,
+                                                  rx, edge, variant,
+                                                  C.c_void_p(_stream(stream))),
+           "skel_mapoverlap2d_fields_backward")
 
 
 def skel_variant_count(skeleton: int) -> int:

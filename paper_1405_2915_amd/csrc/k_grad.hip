@@ -254,6 +254,9 @@ __device__ __forceinline__ float adj2_at(const float* g, int64_t rows, int64_t c
 __global__ __launch_bounds__(kBlock) void ov2_adjoint(const float* g, float* dx, int64_t rows,
                                                       int64_t cols, WA2 w, int ry, int rx,
                                                       int edge) {
+    // blockIdx.y: one of several equally shaped images stored back to back
+    g += (int64_t)blockIdx.y * rows * cols;
+    dx += (int64_t)blockIdx.y * rows * cols;
     const int64_t total = rows * cols;
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     for (int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x; p < total; p += stride) {
@@ -264,32 +267,42 @@ __global__ __launch_bounds__(kBlock) void ov2_adjoint(const float* g, float* dx,
 
 // the first and last rows and columns only (the pixels that clamped reads
 // land on), in order: row 0, row rows-1, then column 0 and column cols-1 of
-// the rows in between.  One wavefront per pixel: the lanes share the taps
-// (a, b), each gathering its taps' row and column ranges, and the lane sums
-// are combined by a fixed butterfly.
+// the rows in between.  A group of G lanes per pixel (G the power of two
+// covering the taps, at most a wavefront: 16 for 3 x 3 weights, 64 for 9 x 9)
+// shares the taps (a, b), each lane gathering its taps' row and column
+// ranges, and the lane sums are combined by a fixed butterfly within the group.
 __global__ __launch_bounds__(kBlock) void ov2_adjoint_border(const float* g, float* dx,
                                                              int64_t rows, int64_t cols, WA2 w,
-                                                             int ry, int rx, int edge) {
+                                                             int ry, int rx, int edge, int G) {
+    // blockIdx.y: one of several equally shaped images stored back to back
+    g += (int64_t)blockIdx.y * rows * cols;
+    dx += (int64_t)blockIdx.y * rows * cols;
     const int64_t nrow = rows > 1 ? 2 : 1;
     const int64_t ncol = cols > 1 ? 2 : 1;
     const int64_t mid = rows > 2 ? rows - 2 : 0;
     const int64_t total = nrow * cols + ncol * mid;
-    const int l = dev::lane();
+    const int lg = (int)threadIdx.x % G;  // lane within the pixel's group
     const int nx = 2 * rx + 1, taps = (2 * ry + 1) * nx;
-    const int64_t waves = (int64_t)gridDim.x * (kBlock / dev::kWave);
-    for (int64_t p = (int64_t)blockIdx.x * (kBlock / dev::kWave) + threadIdx.x / dev::kWave;
-         p < total; p += waves) {
+    const int64_t groups = (int64_t)gridDim.x * (kBlock / G);
+    // every lane runs the same number of iterations (the butterfly below needs
+    // whole wavefronts): pixels past the end are computed on pixel 0 and not
+    // stored
+    const int64_t iters = (total + groups - 1) / groups;
+    for (int64_t it = 0; it < iters; ++it) {
+        const int64_t p = it * groups + (int64_t)blockIdx.x * (kBlock / G) + threadIdx.x / G;
+        const bool live = p < total;
+        const int64_t pp = live ? p : 0;
         int64_t s, t;
-        if (p < nrow * cols) {
-            s = p < cols ? 0 : rows - 1;
-            t = p < cols ? p : p - cols;
+        if (pp < nrow * cols) {
+            s = pp < cols ? 0 : rows - 1;
+            t = pp < cols ? pp : pp - cols;
         } else {
-            const int64_t q = p - nrow * cols;
+            const int64_t q = pp - nrow * cols;
             s = 1 + q / ncol;
             t = (q % ncol) == 0 ? 0 : cols - 1;
         }
         float acc = 0.0f;
-        for (int q = l; q < taps; q += dev::kWave) {
+        for (int q = lg; q < taps; q += G) {
             const int a = q / nx, b = q - a * nx;
             int64_t ilo, ihi, jlo, jhi;
             tap_range(s, a, ry, rows, edge, &ilo, &ihi);
@@ -298,8 +311,8 @@ __global__ __launch_bounds__(kBlock) void ov2_adjoint_border(const float* g, flo
             for (int64_t i = ilo; i <= ihi; ++i)
                 for (int64_t j = jlo; j <= jhi; ++j) acc = __builtin_fmaf(wab, g[i * cols + j], acc);
         }
-        acc = dev::wave_reduce<dev::Comb<float, SKEL_SUM>>(acc);
-        if (l == 0) dx[s * cols + t] = acc;
+        for (int o = G >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+        if (live && lg == 0) dx[s * cols + t] = acc;
     }
 }
 
@@ -383,17 +396,23 @@ skel_status launch_overlap1d_adjoint(int v, const float* g, float* dx, int64_t n
 }
 
 skel_status launch_overlap2d_adjoint(int v, const float* g, float* dx, int64_t rows,
-                                     int64_t cols, const float* w2d, const float* wy,
-                                     const float* wx, int ry, int rx, int edge,
+                                     int64_t cols, int64_t fields, const float* w2d,
+                                     const float* wy, const float* wx, int ry, int rx, int edge,
                                      LaunchCtx& lc) {
     WA2 wk{};
     const int ny = 2 * ry + 1, nx = 2 * rx + 1;
     for (int a = 0; a < ny; ++a)
         for (int b = 0; b < nx; ++b) wk.w[a * nx + b] = w2d ? w2d[a * nx + b] : wy[a] * wx[b];
+    const int64_t img = rows * cols;
     if (v == A0_GATHER) {
-        ov2_adjoint<<<grid_for(rows * cols, *lc.dev), kBlock, 0, lc.stream>>>(g, dx, rows, cols,
-                                                                             wk, ry, rx, edge);
-        return launch_check("ov2_adjoint");
+        for (int64_t f0 = 0; f0 < fields; f0 += kMaxFieldsPerLaunch) {
+            const unsigned nf = (unsigned)std::min<int64_t>(fields - f0, kMaxFieldsPerLaunch);
+            ov2_adjoint<<<dim3(grid_for(img, *lc.dev), nf), kBlock, 0, lc.stream>>>(
+                g + f0 * img, dx + f0 * img, rows, cols, wk, ry, rx, edge);
+            const skel_status e = launch_check("ov2_adjoint");
+            if (e != SKEL_OK) return e;
+        }
+        return SKEL_OK;
     }
     const int fe = edge == SKEL_EDGE_CYCLIC ? SKEL_EDGE_CYCLIC : SKEL_EDGE_CONST;
     skel_status e;
@@ -401,20 +420,28 @@ skel_status launch_overlap2d_adjoint(int v, const float* g, float* dx, int64_t r
         float wf[(2 * SKEL_MAX_RADIUS_2D + 1) * (2 * SKEL_MAX_RADIUS_2D + 1)];
         for (int a = 0; a < ny; ++a)
             for (int b = 0; b < nx; ++b) wf[a * nx + b] = w2d[(ny - 1 - a) * nx + (nx - 1 - b)];
-        e = launch_overlap2d(O2B_LDS_TILE, g, dx, rows, cols, wf, nullptr, nullptr, ry, rx, fe,
-                             0.0f, lc);
+        e = launch_overlap2d(O2B_LDS_TILE, g, dx, rows, cols, fields, wf, nullptr, nullptr, ry,
+                             rx, fe, 0.0f, lc);
     } else {
         float fy[2 * SKEL_MAX_RADIUS_2D + 1], fx[2 * SKEL_MAX_RADIUS_2D + 1];
         for (int a = 0; a < ny; ++a) fy[a] = wy[ny - 1 - a];
         for (int b = 0; b < nx; ++b) fx[b] = wx[nx - 1 - b];
-        e = launch_overlap2d(O2D_SEPARABLE_L1, g, dx, rows, cols, nullptr, fy, fx, ry, rx, fe,
-                             0.0f, lc);
+        e = launch_overlap2d(O2D_SEPARABLE_L1, g, dx, rows, cols, fields, nullptr, fy, fx, ry,
+                             rx, fe, 0.0f, lc);
     }
     if (e != SKEL_OK || edge != SKEL_EDGE_CLAMP) return e;
-    const int64_t border = 2 * cols + 2 * rows;  // one wavefront per border pixel
-    ov2_adjoint_border<<<grid_for(border * dev::kWave, *lc.dev), kBlock, 0, lc.stream>>>(
-        g, dx, rows, cols, wk, ry, rx, edge);
-    return launch_check("ov2_adjoint_border");
+    const int taps = ny * nx;
+    int G = 4;  // lanes per border pixel: the power of two covering the taps
+    while (G < taps && G < dev::kWave) G *= 2;
+    const int64_t border = 2 * cols + 2 * rows;
+    for (int64_t f0 = 0; f0 < fields; f0 += kMaxFieldsPerLaunch) {
+        const unsigned nf = (unsigned)std::min<int64_t>(fields - f0, kMaxFieldsPerLaunch);
+        ov2_adjoint_border<<<dim3(grid_for(border * G, *lc.dev), nf), kBlock, 0, lc.stream>>>(
+            g + f0 * img, dx + f0 * img, rows, cols, wk, ry, rx, edge, G);
+        e = launch_check("ov2_adjoint_border");
+        if (e != SKEL_OK) return e;
+    }
+    return SKEL_OK;
 }
 
 }  // namespace skel

@@ -269,6 +269,9 @@ template <int RY, int RX>
 __global__ __launch_bounds__(kBlock) void ov2_direct(const float* x, float* out, int64_t rows,
                                                      int64_t cols, W2 w, int ry_, int rx_,
                                                      int edge, float pad, int64_t nbx) {
+    // blockIdx.y: one of several equally shaped images stored back to back
+    x += (int64_t)blockIdx.y * rows * cols;
+    out += (int64_t)blockIdx.y * rows * cols;
     using RD = Rad<RY, RX>;
     const int ry = RD::dyn ? ry_ : RY, rx = RD::dyn ? rx_ : RX;
     const int wx = 2 * rx + 1;
@@ -311,6 +314,9 @@ template <int RY, int RX>
 __global__ __launch_bounds__(kBlock) void ov2_lds(const float* x, float* out, int64_t rows,
                                                   int64_t cols, W2 w, int ry_, int rx_, int edge,
                                                   float pad, int64_t nbx, int64_t nb) {
+    // blockIdx.y: one of several equally shaped images stored back to back
+    x += (int64_t)blockIdx.y * rows * cols;
+    out += (int64_t)blockIdx.y * rows * cols;
     using RD = Rad<RY, RX>;
     constexpr int LW = RD::LW, HX = RD::HX, MY = RD::MY, MX = RD::MX;
     const int ry = RD::dyn ? ry_ : RY, rx = RD::dyn ? rx_ : RX;
@@ -358,6 +364,9 @@ template <int RY, int RX>
 __global__ __launch_bounds__(kBlock) void ov2_sep(const float* x, float* out, int64_t rows,
                                                   int64_t cols, W2 w, int ry_, int rx_, int edge,
                                                   float pad, int64_t nbx, int64_t nb) {
+    // blockIdx.y: one of several equally shaped images stored back to back
+    x += (int64_t)blockIdx.y * rows * cols;
+    out += (int64_t)blockIdx.y * rows * cols;
     using RD = Rad<RY, RX>;
     constexpr int LW = RD::LW, HX = RD::HX, MY = RD::MY, MX = RD::MX;
     constexpr int HW = kTX + 4;  // row-pass buffer stride (padded)
@@ -429,6 +438,9 @@ __global__ __launch_bounds__(kBlock) void ov2_sep_l1(const float* x, float* out,
                                                      int64_t cols, W2 w, int ry_, int rx_,
                                                      int edge, float pad, int64_t nbx,
                                                      int64_t nb) {
+    // blockIdx.y: one of several equally shaped images stored back to back
+    x += (int64_t)blockIdx.y * rows * cols;
+    out += (int64_t)blockIdx.y * rows * cols;
     using RD = Rad<RY, RX>;
     constexpr int MY = RD::MY, MX = RD::MX, HX = RD::HX;
     constexpr int HW = kTX + 4;              // row-pass buffer stride (padded)
@@ -528,29 +540,44 @@ skel_status run1d(int v, const float* x, float* out, int64_t n, const W1& w, int
 }
 
 template <int RY, int RX>
-skel_status run2d(int v, const float* x, float* out, int64_t rows, int64_t cols, const W2& w,
-                  int ry, int rx, int edge, float pad, hipStream_t st) {
+skel_status run2d(int v, const float* x, float* out, int64_t rows, int64_t cols,
+                  unsigned fields, const W2& w, int ry, int rx, int edge, float pad,
+                  hipStream_t st) {
     if (v == O2A_DIRECT) {
         const int64_t nbx = div_up(cols, 64), nby = div_up(rows, 4);
-        ov2_direct<RY, RX><<<(unsigned)(nbx * nby), kBlock, 0, st>>>(x, out, rows, cols, w, ry,
-                                                                      rx, edge, pad, nbx);
+        ov2_direct<RY, RX><<<dim3((unsigned)(nbx * nby), fields), kBlock, 0, st>>>(
+            x, out, rows, cols, w, ry, rx, edge, pad, nbx);
         return launch_check("overlap2d_direct");
     }
     if (v == O2D_SEPARABLE_L1) {
         const int64_t nbx = div_up(cols, kTX), nb = nbx * div_up(rows, kTY2);
-        ov2_sep_l1<RY, RX><<<(unsigned)nb, kBlock, 0, st>>>(x, out, rows, cols, w, ry, rx, edge,
-                                                            pad, nbx, nb);
+        ov2_sep_l1<RY, RX><<<dim3((unsigned)nb, fields), kBlock, 0, st>>>(
+            x, out, rows, cols, w, ry, rx, edge, pad, nbx, nb);
         return launch_check("overlap2d_separable_l1");
     }
     const int64_t nbx = div_up(cols, kTX), nby = div_up(rows, kTY), nb = nbx * nby;
     if (v == O2B_LDS_TILE) {
-        ov2_lds<RY, RX><<<(unsigned)nb, kBlock, 0, st>>>(x, out, rows, cols, w, ry, rx, edge,
-                                                         pad, nbx, nb);
+        ov2_lds<RY, RX><<<dim3((unsigned)nb, fields), kBlock, 0, st>>>(
+            x, out, rows, cols, w, ry, rx, edge, pad, nbx, nb);
         return launch_check("overlap2d_lds");
     }
-    ov2_sep<RY, RX><<<(unsigned)nb, kBlock, 0, st>>>(x, out, rows, cols, w, ry, rx, edge, pad,
-                                                     nbx, nb);
+    ov2_sep<RY, RX><<<dim3((unsigned)nb, fields), kBlock, 0, st>>>(x, out, rows, cols, w, ry,
+                                                                   rx, edge, pad, nbx, nb);
     return launch_check("overlap2d_separable");
+}
+
+template <int RY, int RX>
+skel_status run2d_fields(int v, const float* x, float* out, int64_t rows, int64_t cols,
+                         int64_t fields, const W2& w, int ry, int rx, int edge, float pad,
+                         hipStream_t st) {
+    const int64_t img = rows * cols;
+    for (int64_t f0 = 0; f0 < fields; f0 += kMaxFieldsPerLaunch) {
+        const unsigned nf = (unsigned)std::min<int64_t>(fields - f0, kMaxFieldsPerLaunch);
+        const skel_status e = run2d<RY, RX>(v, x + f0 * img, out + f0 * img, rows, cols, nf, w,
+                                            ry, rx, edge, pad, st);
+        if (e != SKEL_OK) return e;
+    }
+    return SKEL_OK;
 }
 
 }  // namespace
@@ -568,8 +595,8 @@ skel_status launch_overlap1d(int v, const float* x, float* out, int64_t n, const
 }
 
 skel_status launch_overlap2d(int v, const float* x, float* out, int64_t rows, int64_t cols,
-                             const float* w2d, const float* wy, const float* wx, int ry, int rx,
-                             int edge, float pad, LaunchCtx& lc) {
+                             int64_t fields, const float* w2d, const float* wy, const float* wx,
+                             int ry, int rx, int edge, float pad, LaunchCtx& lc) {
     W2 wk{};
     const int ny = 2 * ry + 1, nx = 2 * rx + 1;
     for (int a = 0; a < ny; ++a)
@@ -580,12 +607,12 @@ skel_status launch_overlap2d(int v, const float* x, float* out, int64_t rows, in
         for (int b = 0; b < nx; ++b) wk.wx[b] = wx[b];
     }
     if (ry == 4 && rx == 4)
-        return run2d<4, 4>(v, x, out, rows, cols, wk, ry, rx, edge, pad, lc.stream);
+        return run2d_fields<4, 4>(v, x, out, rows, cols, fields, wk, ry, rx, edge, pad, lc.stream);
     if (ry == 1 && rx == 1)
-        return run2d<1, 1>(v, x, out, rows, cols, wk, ry, rx, edge, pad, lc.stream);
+        return run2d_fields<1, 1>(v, x, out, rows, cols, fields, wk, ry, rx, edge, pad, lc.stream);
     if (ry == 2 && rx == 2)
-        return run2d<2, 2>(v, x, out, rows, cols, wk, ry, rx, edge, pad, lc.stream);
-    return run2d<-1, -1>(v, x, out, rows, cols, wk, ry, rx, edge, pad, lc.stream);
+        return run2d_fields<2, 2>(v, x, out, rows, cols, fields, wk, ry, rx, edge, pad, lc.stream);
+    return run2d_fields<-1, -1>(v, x, out, rows, cols, fields, wk, ry, rx, edge, pad, lc.stream);
 }
 
 }  // namespace skel

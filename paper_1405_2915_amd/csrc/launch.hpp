@@ -91,8 +91,11 @@ skel_status launch_mapreduce(int variant, int map_op, float p0, float p1,
 skel_status launch_overlap1d(int variant, const float* x, float* out, int64_t n,
                              const float* w, int r, int edge, float pad,
                              LaunchCtx& lc);
+// `fields` images of rows x cols stored back to back, each mapped on its own
+// (its own borders); one launch covers up to kMaxFieldsPerLaunch of them
+constexpr int64_t kMaxFieldsPerLaunch = 65535;
 skel_status launch_overlap2d(int variant, const float* x, float* out,
-                             int64_t rows, int64_t cols, const float* w2d,
+                             int64_t rows, int64_t cols, int64_t fields, const float* w2d,
                              const float* wy, const float* wx, int ry, int rx,
                              int edge, float pad, LaunchCtx& lc);
 skel_status launch_reduce_segments(int variant, int op, const float* x, int64_t n,
@@ -112,7 +115,8 @@ skel_status launch_map_backward(int op, float p0, float p1, const float* x, cons
 skel_status launch_overlap1d_adjoint(int variant, const float* g, float* dx, int64_t n,
                                      const float* w, int r, int edge, LaunchCtx& lc);
 skel_status launch_overlap2d_adjoint(int variant, const float* g, float* dx, int64_t rows,
-                                     int64_t cols, const float* w2d, const float* wy,
-                                     const float* wx, int ry, int rx, int edge, LaunchCtx& lc);
+                                     int64_t cols, int64_t fields, const float* w2d,
+                                     const float* wy, const float* wx, int ry, int rx,
+                                     int edge, LaunchCtx& lc);
 
 }  // namespace skel

@@ -286,9 +286,10 @@ skel_status skel_mapoverlap1d(skel_container* in, skel_container* out, const flo
     });
 }
 
-skel_status skel_mapoverlap2d(skel_container* in, skel_container* out, const float* w2d,
-                              const float* wy, const float* wx, int ry, int rx,
-                              skel_edge edge, float pad, int variant, void* stream) {
+skel_status skel_mapoverlap2d_fields(skel_container* in, skel_container* out, int64_t fields,
+                                     const float* w2d, const float* wy, const float* wx, int ry,
+                                     int rx, skel_edge edge, float pad, int variant,
+                                     void* stream) {
     LaunchCtx lc;
     skel_status st = begin(stream, &lc);
     if (st != SKEL_OK) return st;
@@ -305,10 +306,14 @@ skel_status skel_mapoverlap2d(skel_container* in, skel_container* out, const flo
         return fail(SKEL_E_DTYPE, "MapOverlap operands must be f32");
     if (in->rows != out->rows || in->cols != out->cols)
         return fail(SKEL_E_SHAPE, "MapOverlap operand shapes differ");
+    if (fields < 1 || in->rows % fields != 0)
+        return fail(SKEL_E_SHAPE, "%lld rows do not split into %lld fields",
+                    (long long)in->rows, (long long)fields);
+    const int64_t frows = in->rows / fields;
     CallContext cc;
     cc.skeleton = SKEL_SK_MAPOVERLAP2D;
     cc.n = in->n;
-    cc.rows = in->rows;
+    cc.rows = frows;
     cc.cols = in->cols;
     cc.separable = w2d ? 0 : 1;
     int v = choose_variant(variant, cc, &st);
@@ -318,10 +323,16 @@ skel_status skel_mapoverlap2d(skel_container* in, skel_container* out, const flo
     ops.add(out, SKEL_WRITE);
     return run(ops, stream, lc, [&]() -> skel_status {
         if (in->n == 0) return SKEL_OK;
-        return launch_overlap2d(v, (const float*)ops.ptr(in), (float*)ops.ptr(out),
-                                in->rows, in->cols, w2d, w2d ? nullptr : wy,
-                                w2d ? nullptr : wx, ry, rx, edge, pad, lc);
+        return launch_overlap2d(v, (const float*)ops.ptr(in), (float*)ops.ptr(out), frows,
+                                in->cols, fields, w2d, w2d ? nullptr : wy, w2d ? nullptr : wx,
+                                ry, rx, edge, pad, lc);
     });
+}
+
+skel_status skel_mapoverlap2d(skel_container* in, skel_container* out, const float* w2d,
+                              const float* wy, const float* wx, int ry, int rx,
+                              skel_edge edge, float pad, int variant, void* stream) {
+    return skel_mapoverlap2d_fields(in, out, 1, w2d, wy, wx, ry, rx, edge, pad, variant, stream);
 }
 
 skel_status skel_reduce_segments(skel_reduce_op op, skel_container* in,
@@ -551,10 +562,10 @@ skel_status skel_mapoverlap1d_backward(skel_container* g, skel_container* grad_i
     });
 }
 
-skel_status skel_mapoverlap2d_backward(skel_container* g, skel_container* grad_in,
-                                       const float* w2d, const float* wy, const float* wx,
-                                       int ry, int rx, skel_edge edge, int variant,
-                                       void* stream) {
+skel_status skel_mapoverlap2d_fields_backward(skel_container* g, skel_container* grad_in,
+                                              int64_t fields, const float* w2d, const float* wy,
+                                              const float* wx, int ry, int rx, skel_edge edge,
+                                              int variant, void* stream) {
     LaunchCtx lc;
     skel_status st = begin(stream, &lc);
     if (st != SKEL_OK) return st;
@@ -570,10 +581,14 @@ skel_status skel_mapoverlap2d_backward(skel_container* g, skel_container* grad_i
         return fail(SKEL_E_DTYPE, "MapOverlap backward operands must be f32");
     if (g->rows != grad_in->rows || g->cols != grad_in->cols)
         return fail(SKEL_E_SHAPE, "MapOverlap backward shapes differ");
+    if (fields < 1 || g->rows % fields != 0)
+        return fail(SKEL_E_SHAPE, "%lld rows do not split into %lld fields",
+                    (long long)g->rows, (long long)fields);
+    const int64_t frows = g->rows / fields;
     CallContext cc;
     cc.skeleton = SKEL_SK_MAPOVERLAP2D_BACKWARD;
     cc.n = g->n;
-    cc.rows = g->rows;
+    cc.rows = frows;
     cc.cols = g->cols;
     cc.separable = w2d ? 0 : 1;
     int v = choose_variant(variant, cc, &st);
@@ -584,8 +599,16 @@ skel_status skel_mapoverlap2d_backward(skel_container* g, skel_container* grad_i
     return run(ops, stream, lc, [&]() -> skel_status {
         if (g->n == 0) return SKEL_OK;
         return launch_overlap2d_adjoint(v, (const float*)ops.ptr(g), (float*)ops.ptr(grad_in),
-                                        g->rows, g->cols, w2d, wy, wx, ry, rx, edge, lc);
+                                        frows, g->cols, fields, w2d, wy, wx, ry, rx, edge, lc);
     });
+}
+
+skel_status skel_mapoverlap2d_backward(skel_container* g, skel_container* grad_in,
+                                       const float* w2d, const float* wy, const float* wx,
+                                       int ry, int rx, skel_edge edge, int variant,
+                                       void* stream) {
+    return skel_mapoverlap2d_fields_backward(g, grad_in, 1, w2d, wy, wx, ry, rx, edge, variant,
+                                             stream);
 }
 
 }  // extern "C"
