@@ -172,21 +172,12 @@ __global__ __launch_bounds__(kBlock) void ov1_shfl(const float* x, float* out, i
             // adjacent row's end lane (or the extra halo vectors)
             const f32x4 prev = k > 0 ? c[k - 1] : edge_l;
             const f32x4 next = k + 1 < U ? c[k + 1] : edge_r;
-            f32x4 lt, rt;
-            lt.x = __shfl_up(c[k].x, 1);
-            lt.y = __shfl_up(c[k].y, 1);
-            lt.z = __shfl_up(c[k].z, 1);
-            lt.w = __shfl_up(c[k].w, 1);
-            rt.x = __shfl_down(c[k].x, 1);
-            rt.y = __shfl_down(c[k].y, 1);
-            rt.z = __shfl_down(c[k].z, 1);
-            rt.w = __shfl_down(c[k].w, 1);
-            const f32x4 pl = {__shfl(prev.x, dev::kWave - 1), __shfl(prev.y, dev::kWave - 1),
-                              __shfl(prev.z, dev::kWave - 1), __shfl(prev.w, dev::kWave - 1)};
-            const f32x4 nf = {__shfl(next.x, 0), __shfl(next.y, 0), __shfl(next.z, 0),
-                              __shfl(next.w, 0)};
-            if (l == 0) lt = k > 0 ? pl : edge_l;
-            if (l == dev::kWave - 1) rt = k + 1 < U ? nf : edge_r;
+            // register-only moves: lane 0 takes the previous row's last vector
+            // (or the halo), lane 63 the next row's first (or the halo)
+            const f32x4 lt = dev::wave_shift_up(
+                c[k], k > 0 ? dev::lane_value(prev, dev::kWave - 1) : edge_l);
+            const f32x4 rt = dev::wave_shift_down(c[k], k + 1 < U ? dev::lane_value(next, 0)
+                                                                  : edge_r);
             const float v[12] = {lt.x, lt.y, lt.z, lt.w, c[k].x, c[k].y, c[k].z, c[k].w,
                                  rt.x, rt.y, rt.z, rt.w};
             float acc[4] = {0.f, 0.f, 0.f, 0.f};

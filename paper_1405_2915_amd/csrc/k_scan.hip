@@ -157,8 +157,8 @@ __device__ __forceinline__ typename P::acc_t tile_scan_store(typename P::out_t* 
             loc[e] = t;
         }
         const acc_t incl = REV ? wave_inclusive_suffix_scan<C>(t) : wave_inclusive_scan<C>(t);
-        const acc_t tot = __shfl(incl, REV ? 0 : kWave - 1);
-        const acc_t ex = REV ? __shfl_down(incl, 1) : __shfl_up(incl, 1);
+        const acc_t tot = lane_value(incl, REV ? 0 : kWave - 1);
+        const acc_t ex = REV ? wave_shift_down(incl, C::id()) : wave_shift_up(incl, C::id());
         const bool first = REV ? l == kWave - 1 : l == 0;
         const acc_t base = C::op(running, first ? C::id() : ex);
         out_t o[E];
@@ -417,8 +417,7 @@ __global__ __launch_bounds__(1024) void scan_tile_offsets(typename P::acc_t* sum
             if (k < w) wex = C::op(wex, lds[k]);
             total = C::op(total, lds[k]);
         }
-        acc_t lex = __shfl_up(incl, 1);
-        if (l == 0) lex = C::id();
+        const acc_t lex = wave_shift_up(incl, C::id());
         if (i < ntiles) sums[i] = C::op(carry, C::op(wex, lex));
         carry = C::op(carry, total);
         __syncthreads();
@@ -536,11 +535,11 @@ __global__ __launch_bounds__(kWave) void scan_rows_scalar(const typename P::in_t
             const int64_t i = (REV ? nch - 1 - q : q) * kWave + l;
             const acc_t x = i < cols ? widen<acc_t>(src[i]) : C::id();
             const acc_t incl = REV ? wave_inclusive_suffix_scan<C>(x) : wave_inclusive_scan<C>(x);
-            const acc_t nb = REV ? __shfl_down(incl, 1) : __shfl_up(incl, 1);
+            const acc_t nb = REV ? wave_shift_down(incl, C::id()) : wave_shift_up(incl, C::id());
             const bool first = REV ? l == kWave - 1 : l == 0;
             const acc_t v = C::op(carry, exclusive ? (first ? C::id() : nb) : incl);
             if (i < cols) dst[i] = (typename P::out_t)v;
-            carry = C::op(carry, __shfl(incl, REV ? 0 : kWave - 1));
+            carry = C::op(carry, lane_value(incl, REV ? 0 : kWave - 1));
         }
     }
 }

@@ -117,29 +117,98 @@ __device__ __forceinline__ T wave_reduce(T v) {
     return v;
 }
 
-// Inclusive scan over the 64 lanes (Hillis-Steele with lane shifts).
+// ------------------------------------------- register-only cross-lane moves
+// DPP (data-parallel primitive) moves and v_readlane pass values between the
+// lanes of a wavefront inside the register file; __shfl* go through the LDS
+// crossbar (ds_bpermute), which costs LDS bandwidth and a round trip per
+// move.  Controls (gfx9 encoding): row_shl:k 0x100+k and row_shr:k 0x110+k
+// move within rows of 16 lanes; wave_shl:1 0x130 and wave_shr:1 0x138 move
+// across the whole wavefront.  "shr" moves data to higher lanes (lane i reads
+// lane i - k).
+enum : int {
+    kDppRowShl = 0x100,
+    kDppRowShr = 0x110,
+    kDppWaveShl1 = 0x130,
+    kDppWaveShr1 = 0x138
+};
+
+// dpp<CTRL>(fill, v): every lane receives v of the lane CTRL names; a lane
+// whose source lies outside its row (row controls) or outside the wavefront
+// (wave controls) receives its own `fill`.
+template <int CTRL, class T>
+__device__ __forceinline__ T dpp(T fill, T v) {
+    static_assert(sizeof(T) % 4 == 0, "DPP moves 32-bit words");
+    constexpr int W = sizeof(T) / 4;
+    int f[W], x[W], r[W];
+    __builtin_memcpy(f, &fill, sizeof(T));
+    __builtin_memcpy(x, &v, sizeof(T));
+#pragma unroll
+    for (int k = 0; k < W; ++k)
+        r[k] = __builtin_amdgcn_update_dpp(f[k], x[k], CTRL, 0xf, 0xf, false);
+    T out;
+    __builtin_memcpy(&out, r, sizeof(T));
+    return out;
+}
+
+// v of lane `src` (a constant), in every lane
+template <class T>
+__device__ __forceinline__ T lane_value(T v, int src) {
+    static_assert(sizeof(T) % 4 == 0, "v_readlane moves 32-bit words");
+    constexpr int W = sizeof(T) / 4;
+    int x[W], r[W];
+    __builtin_memcpy(x, &v, sizeof(T));
+#pragma unroll
+    for (int k = 0; k < W; ++k) r[k] = __builtin_amdgcn_readlane(x[k], src);
+    T out;
+    __builtin_memcpy(&out, r, sizeof(T));
+    return out;
+}
+
+// lane l receives v of lane l - 1; lane 0 receives its own fill
+template <class T>
+__device__ __forceinline__ T wave_shift_up(T v, T fill) {
+    return dpp<kDppWaveShr1>(fill, v);
+}
+
+// lane l receives v of lane l + 1; lane 63 receives its own fill
+template <class T>
+__device__ __forceinline__ T wave_shift_down(T v, T fill) {
+    return dpp<kDppWaveShl1>(fill, v);
+}
+
+// Inclusive scan over the 64 lanes: Hillis-Steele steps of 1, 2, 4 and 8
+// lanes inside each row of 16 (DPP row shifts, the identity entering at the
+// row start), then each row adds the totals of the rows before it, read from
+// lanes 15, 31 and 47.  Needs every lane of the wavefront active.
 template <class C, class T>
 __device__ __forceinline__ T wave_inclusive_scan(T v) {
-    const int l = lane();
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        T u = __shfl_up(v, d);
-        if (l >= d) v = C::op(u, v);
-    }
-    return v;
+    const T id = C::id();
+    v = C::op(dpp<kDppRowShr + 1>(id, v), v);
+    v = C::op(dpp<kDppRowShr + 2>(id, v), v);
+    v = C::op(dpp<kDppRowShr + 4>(id, v), v);
+    v = C::op(dpp<kDppRowShr + 8>(id, v), v);
+    const T t0 = lane_value(v, 15), t1 = lane_value(v, 31), t2 = lane_value(v, 47);
+    const T b2 = C::op(t0, t1), b3 = C::op(b2, t2);
+    const int row = lane() >> 4;
+    const T before = row == 0 ? id : row == 1 ? t0 : row == 2 ? b2 : b3;
+    return C::op(before, v);
 }
 
 // Inclusive suffix scan over the 64 lanes: lane l ends with v[l] op ... op
-// v[63] (lane shifts downwards).
+// v[63] (DPP row shifts downwards, then the totals of the rows after, read
+// from lanes 16, 32 and 48).  Needs every lane of the wavefront active.
 template <class C, class T>
 __device__ __forceinline__ T wave_inclusive_suffix_scan(T v) {
-    const int l = lane();
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        T u = __shfl_down(v, d);
-        if (l + d < kWave) v = C::op(v, u);
-    }
-    return v;
+    const T id = C::id();
+    v = C::op(v, dpp<kDppRowShl + 1>(id, v));
+    v = C::op(v, dpp<kDppRowShl + 2>(id, v));
+    v = C::op(v, dpp<kDppRowShl + 4>(id, v));
+    v = C::op(v, dpp<kDppRowShl + 8>(id, v));
+    const T t1 = lane_value(v, 16), t2 = lane_value(v, 32), t3 = lane_value(v, 48);
+    const T a1 = C::op(t2, t3), a0 = C::op(t1, a1);
+    const int row = lane() >> 4;
+    const T after = row == 3 ? id : row == 2 ? t3 : row == 1 ? a1 : a0;
+    return C::op(v, after);
 }
 
 // Block reduction for blocks of up to 1024 threads.  `lds` holds one T per
