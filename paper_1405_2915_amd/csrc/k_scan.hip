@@ -28,10 +28,11 @@
 //       Tiles are numbered by an atomic counter in start order, so every tile
 //       waited on is already resident: the wait always ends.
 //   S3  S2's tile step run by persistent workgroups (one per resident slot)
-//       that loop over tile ids; a workgroup takes its next id while it
-//       stores, so neither a workgroup launch nor the counter's round trip
-//       sits between one tile's stores and the next tile's loads
-//       (2^27 i32 -> i64 exclusive: 321 us against 337 us for S2 on MI355X).
+//       that loop over tile ids; a workgroup takes its next id once its
+//       stores are issued, so no workgroup launch sits between one tile's
+//       stores and the next tile's loads, and the counter's round trip
+//       overlaps the stores' drain (2^27 i32 -> i64 exclusive: 310 us against
+//       337 us for S2 on MI355X).
 //
 // Tile descriptors are self-validating tagged words (two per tile), written
 // and read with single-copy-atomic device-scope accesses, so no fences and no
@@ -269,8 +270,8 @@ __device__ typename P::acc_t lookback(u64* status, int64_t tile, typename P::acc
 // `seq` is the tile's position in scan order (descriptor index), `tile` the
 // data tile it covers (they differ for the reverse kinds)
 // s_next (persistent form only): thread 0 takes the workgroup's next tile id
-// once this tile's prefix is known, so the counter's round trip overlaps the
-// stores
+// after issuing this tile's stores, so the counter's round trip overlaps their
+// drain
 template <class P, bool FULL, bool REV>
 __device__ __forceinline__ void lookback_tile(const typename P::in_t* in,
                                               typename P::out_t* out, int64_t n, int64_t seq,
@@ -289,11 +290,13 @@ __device__ __forceinline__ void lookback_tile(const typename P::in_t* in,
         if (threadIdx.x == 0) s_prefix = e;
     }
     __syncthreads();
-    u64 next = 0;
-    if (s_next != nullptr && threadIdx.x == 0) next = atomicAdd(&sync[SYNC_TILE_COUNTER], 1ull);
     keep_raw_only<P>(raw);
     tile_scan_store<P, FULL, REV>(out, n, tile, raw, P::C::op(s_prefix, wex), exclusive != 0);
-    if (s_next != nullptr && threadIdx.x == 0) *s_next = (int64_t)next;
+    // the next id is taken only once this tile's stores are issued: an id held
+    // longer delays the tiles after it, which wait on its descriptor (taking
+    // it before the stores measured 3% slower, a whole tile ahead 34%)
+    if (s_next != nullptr && threadIdx.x == 0)
+        *s_next = (int64_t)atomicAdd(&sync[SYNC_TILE_COUNTER], 1ull);
 }
 
 template <class P, bool REV>
