@@ -57,6 +57,27 @@ def test_fields_forward_and_backward(skel, oracle_mod, edge, sep, r):
     skel.skel_sync()
 
 
+def test_fields_beyond_one_launch(skel, oracle_mod):
+    # more fields than one launch's grid holds (65535): the launcher splits them
+    f, h, wd = 70001, 2, 4
+    x = si.uniform_f32(f * h * wd, -1.0, 1.0, 22, 99).reshape(f * h, wd)
+    w = si.five_point_weights(0.5, 0.1, 0.2, 0.05, 0.15)
+    cx = skel.Container.from_numpy(x)
+    out = skel.Container.empty(skel.F32, f * h, wd)
+    skel.skel_mapoverlap2d_fields(cx, out, f, w2d=w, edge=skel.EDGE_CLAMP)
+    got = out.to_numpy().reshape(f, h, wd)
+    back = skel.Container.empty(skel.F32, f * h, wd)
+    skel.skel_mapoverlap2d_fields_backward(cx, back, f, w2d=w, edge=skel.EDGE_CLAMP)
+    gb = back.to_numpy().reshape(f, h, wd)
+    for k in (0, 1, 65534, 65535, 65536, f - 1):
+        xf = x[k * h:(k + 1) * h]
+        ref, mag = oracle_mod.mapoverlap2d(xf, 1, 1, w2d=w, edge="clamp")
+        assert np.all(np.abs(got[k] - ref) <= 1e-6 * mag + 1e-30), k
+        ref, mag = oracle_mod.mapoverlap2d_adjoint(xf, 1, 1, w2d=w, edge="clamp")
+        assert np.all(np.abs(gb[k] - ref) <= 1e-6 * mag + 1e-30), k
+    skel.skel_sync()
+
+
 def test_fields_shape_errors(skel):
     x = skel.Container.from_numpy(np.zeros((10, 8), np.float32))
     out = skel.Container.empty(skel.F32, 10, 8)

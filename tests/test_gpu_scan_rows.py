@@ -100,3 +100,20 @@ def test_scan_rows_many_rows(skel, oracle_mod):
             skel.skel_scan_rows(cx, out, KINDS[kind], skel.SUM, variant=v)
             assert np.array_equal(out.to_numpy().reshape(shape), ref), (kind, v)
     skel.skel_sync()
+
+
+def test_scan_rows_more_rows_than_one_grid(skel, oracle_mod):
+    # the kernels step over rows in a grid of at most 2^20 workgroups; sampled
+    # rows around that stride are checked against the oracle one by one
+    for cols in (3, 4):  # element accesses, then 16-byte vectors
+        rows = (1 << 20) + 5
+        x = si.int_uniform_i32(rows * cols, 1000, 21, 5 + cols).reshape(rows, cols)
+        out = skel.Container.empty(skel.I64, rows, cols)
+        skel.skel_scan_rows(skel.Container.from_numpy(x), out, skel.EXCLUSIVE, skel.SUM,
+                            variant=SR1)
+        got = out.to_numpy().reshape(rows, cols)
+        for r in (0, 1, (1 << 20) - 1, 1 << 20, (1 << 20) + 1, rows - 1):
+            assert np.array_equal(got[r], oracle_mod.scan(x[r], "exclusive", "sum", np.int64)), \
+                (cols, r)
+    skel.skel_sync()
+
