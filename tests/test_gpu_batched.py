@@ -133,3 +133,74 @@ def test_graph_capture_replays(skel, oracle_mod):
         assert np.array_equal(tmp.to_numpy(), oracle_mod.scan(ik, "inclusive", "sum",
                                                               np.int64)), rep
     skel.skel_sync(stream)
+
+
+def test_graph_replays_batched_layer_and_persistent_scan(skel, oracle_mod):
+    """The batched forms and the persistent scan captured once (a batched-field
+    stencil, a row-wise scan, its reverse, the batched transpose, and an S3
+    scan whose workgroups share a tile counter reset on the device) and
+    replayed with new inputs and eager calls of the same kinds in between;
+    every replay is checked against the oracle."""
+    import torch
+    dev = torch.device("cuda", 0)
+    F, H, W = 6, 96, 136
+    n = (1 << 18) + 77
+    w5 = si.five_point_weights(0.5, 0.1, 0.2, 0.05, 0.15)
+    x = torch.empty(F * H, W, device=dev)
+    y, z, gz, gy, gx = (torch.empty_like(x) for _ in range(5))
+    si_t = torch.empty(n, dtype=torch.int32, device=dev)
+    so_t = torch.empty(n, dtype=torch.int64, device=dev)
+    stream = torch.cuda.Stream()
+    cs = [skel.wrap_tensor(t, stream) for t in (x, y, z, gz, gy, gx, si_t, so_t)]
+    cx, cy, cz, cgz, cgy, cgx, csi, cso = cs
+
+    def chain():
+        skel.skel_mapoverlap2d_fields(cx, cy, F, w2d=w5, stream=stream)
+        skel.skel_scan_rows(cy, cz, skel.INCLUSIVE, skel.SUM, stream=stream)
+        skel.skel_scan_rows(cgz, cgy, skel.REVERSE_INCLUSIVE, skel.SUM, stream=stream)
+        skel.skel_mapoverlap2d_fields_backward(cgy, cgx, F, w2d=w5, stream=stream)
+        skel.skel_scan(csi, cso, skel.EXCLUSIVE, skel.SUM, variant=3, stream=stream)
+
+    with torch.cuda.stream(stream):
+        chain()  # outside capture: sizes workspaces
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=stream):
+            chain()
+    torch.cuda.synchronize()
+    tmp = torch.empty(n, dtype=torch.int64, device=dev)
+    ctmp = skel.wrap_tensor(tmp, stream)
+    for rep in range(4):
+        xh = si.normal_f32(F * H * W, 7, rep).reshape(F * H, W)
+        gh = si.normal_f32(F * H * W, 7, 10 + rep).reshape(F * H, W)
+        ih = si.int_uniform_i32(n, 1000, 7, 20 + rep)
+        with torch.cuda.stream(stream):
+            x.copy_(torch.from_numpy(xh))
+            gz.copy_(torch.from_numpy(gh))
+            si_t.copy_(torch.from_numpy(ih))
+            # eager calls of the same kinds between replays
+            skel.skel_scan(csi, ctmp, skel.INCLUSIVE, skel.SUM, variant=3, stream=stream)
+            skel.skel_scan_rows(cgz, cgx, skel.INCLUSIVE, skel.SUM, stream=stream)
+            g.replay()
+        stream.synchronize()
+        zr = z.cpu().numpy()
+        gxr = gx.cpu().numpy()
+        for f in range(F):
+            blk = slice(f * H, (f + 1) * H)
+            yref, ymag = oracle_mod.mapoverlap2d(xh[blk], 1, 1, w2d=w5, edge="clamp")
+            zref = np.cumsum(yref, axis=1)
+            assert np.all(np.abs(zr[blk] - zref) <= 1e-5 * np.cumsum(ymag, axis=1) + 1e-30), \
+                (rep, f)
+            gyref, gymag = oracle_mod.scan_rows(gh[blk], "reverse_inclusive")
+            dref, _ = oracle_mod.mapoverlap2d_adjoint(gyref.astype(np.float32), 1, 1, w2d=w5,
+                                                      edge="clamp")
+            _, dmag = oracle_mod.mapoverlap2d_adjoint(gymag.astype(np.float32), 1, 1,
+                                                      w2d=np.abs(w5), edge="clamp")
+            assert np.all(np.abs(gxr[blk] - dref) <= 1e-5 * dmag + 1e-30), (rep, f)
+        assert np.array_equal(so_t.cpu().numpy(), oracle_mod.scan(ih, "exclusive", "sum",
+                                                                 np.int64)), rep
+        assert np.array_equal(tmp.cpu().numpy(), oracle_mod.scan(ih, "inclusive", "sum",
+                                                                np.int64)), rep
+    skel.skel_sync(stream)
+    for c in cs + [ctmp]:
+        c.destroy()
