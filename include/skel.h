@@ -312,7 +312,9 @@ skel_status skel_scan(skel_container *in, skel_container *out,
  * aligned, i.e. cols * element size is a multiple of 16 for both types); 1
  * runs one wavefront per row in a single launch, with 16-byte accesses when
  * the rows are so aligned and element accesses otherwise.  The static rule
- * takes 0 for fewer than 64 aligned rows of at least 2^20 elements, else 1. */
+ * takes 0 for fewer than 64 aligned rows of at least 2^20 elements, else 1
+ * (a few long rows that are not 16-byte aligned therefore run at one
+ * wavefront per row, far below the device's bandwidth). */
 skel_status skel_scan_rows(skel_container *in, skel_container *out,
                            skel_scan_kind kind, skel_reduce_op op, int variant,
                            void *stream);
