@@ -189,7 +189,10 @@ skel_status skel_container_wrap_device(skel_dtype dtype, int64_t rows, int64_t c
 
 /* Destroy a container with no outstanding acquire; device memory is released
  * stream-ordered after the last device access (wrapped device memory is left
- * to its owner). */
+ * to its owner).  Destroying waits for the container's pending device work
+ * (unless it wraps device memory and has no host copy) and frees its pinned
+ * host copy, so it must not run while a stream is being captured into a
+ * graph: those calls would invalidate the capture. */
 skel_status skel_container_destroy(skel_container *c);
 
 /* Section IV coherence protocol.  Make the copy at `place` usable for

@@ -79,6 +79,10 @@ class _Allocator(C.Structure):
 _lib = None
 _live = weakref.WeakSet()
 _keepalive = []
+# handles of containers collected while a graph capture was running on the
+# current stream: destroying one may wait for the device and frees pinned host
+# memory, which would invalidate the capture, so they are destroyed afterwards
+_deferred = []
 _shutting_down = False
 _device = 0
 
@@ -224,7 +228,21 @@ def skel_finalize() -> None:
     _check(load_library().skel_finalize(), "skel_finalize")
 
 
+def _capturing() -> bool:
+    return (torch is not None and torch.cuda.is_initialized()
+            and torch.cuda.is_current_stream_capturing())
+
+
+def _destroy_deferred() -> None:
+    if _deferred and _lib is not None and not _capturing():
+        handles = _deferred[:]
+        del _deferred[:]
+        for h in handles:
+            _lib.skel_container_destroy(C.c_void_p(h))
+
+
 def skel_sync(stream=None) -> None:
+    _destroy_deferred()
     _check(load_library().skel_sync(C.c_void_p(_stream(stream))), "skel_sync")
 
 
@@ -239,6 +257,7 @@ class Container:
     with lazy coherence.  Wraps the opaque skel_container handle."""
 
     def __init__(self, handle: int, dtype: int, rows: int, cols: int):
+        _destroy_deferred()
         self.handle = handle
         self.dtype = dtype
         self.rows = rows
@@ -340,6 +359,10 @@ class Container:
 
     def __del__(self):
         if self.handle and not _shutting_down and _lib is not None:
+            if _capturing():  # collected during a graph capture: destroy it afterwards
+                _deferred.append(self.handle)
+                self.handle = None
+                return
             try:
                 self.destroy()
             except Exception:
@@ -662,6 +685,9 @@ def _shutdown():
             c.destroy()
         except Exception:
             pass
+    for h in _deferred:
+        _lib.skel_container_destroy(C.c_void_p(h))
+    del _deferred[:]
     try:
         _L().skel_finalize()
     except Exception:

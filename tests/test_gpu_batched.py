@@ -204,3 +204,33 @@ def test_graph_replays_batched_layer_and_persistent_scan(skel, oracle_mod):
     skel.skel_sync(stream)
     for c in cs + [ctmp]:
         c.destroy()
+
+
+def test_containers_collected_during_capture_are_destroyed_after(skel):
+    """A container that Python collects while a graph is being captured is not
+    destroyed then (that would wait for the device and free pinned memory,
+    invalidating the capture): it is destroyed after the capture."""
+    import gc
+    import torch
+    n = 1 << 16
+    x = torch.ones(n, device="cuda")
+    y = torch.empty_like(x)
+    stream = torch.cuda.Stream()
+    cx, cy = skel.wrap_tensor(x, stream), skel.wrap_tensor(y, stream)
+    garbage = [skel.Container.from_numpy(np.ones(1000, np.float32)) for _ in range(4)]
+    for c in garbage:  # device copies with pending work, pinned host copies
+        skel.skel_map(skel.MAP_AFFINE, [2.0, 0.0], [c], c, stream=stream)
+    with torch.cuda.stream(stream):
+        skel.skel_map(skel.MAP_AFFINE, [2.0, 1.0], [cx], cy, stream=stream)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=stream):
+            del garbage
+            gc.collect()  # collected inside the capture
+            skel.skel_map(skel.MAP_AFFINE, [2.0, 1.0], [cx], cy, stream=stream)
+        g.replay()
+    stream.synchronize()
+    assert torch.all(y == 3.0)
+    skel.skel_sync(stream)  # the deferred containers are destroyed here
+    cx.destroy()
+    cy.destroy()
