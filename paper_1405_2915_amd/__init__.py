@@ -243,7 +243,7 @@ def _destroy_deferred() -> None:
 
 def skel_sync(stream=None) -> None:
     _destroy_deferred()
-    _check(load_library().skel_sync(C.c_void_p(_stream(stream))), "skel_sync")
+    _check(load_library().skel_sync(_stream(stream)), "skel_sync")
 
 
 def skel_last_error() -> str:
@@ -372,9 +372,10 @@ class Container:
 def _h(c):
     if c is None:
         return None
-    if not isinstance(c, Container) or not c.handle:
-        raise TypeError("expected a live Container")
-    return C.c_void_p(c.handle)
+    if c.__class__ is not Container or not c.handle:
+        if not isinstance(c, Container) or not c.handle:
+            raise TypeError("expected a live Container")
+    return c.handle
 
 
 def skel_container_create(dtype: int, rows: int, cols: int, host_src=None) -> Container:
@@ -401,7 +402,7 @@ def skel_container_wrap_device(dtype: int, rows: int, cols: int, dev_ptr: int,
     the library never frees it."""
     out = C.c_void_p()
     _check(load_library().skel_container_wrap_device(dtype, rows, cols, C.c_void_p(dev_ptr),
-                                                     C.c_void_p(_stream(stream)),
+                                                     _stream(stream),
                                                      C.byref(out)),
            "skel_container_wrap_device")
     return Container(out.value, dtype, rows, cols)
@@ -428,7 +429,7 @@ def wrap_tensor(t, stream=None) -> Container:
 
 def skel_container_acquire(c: Container, place: int, access: int, stream=None) -> int:
     ptr = C.c_void_p()
-    _check(_L().skel_container_acquire(_h(c), place, access, C.c_void_p(_stream(stream)),
+    _check(_L().skel_container_acquire(_h(c), place, access, _stream(stream),
                                        C.byref(ptr)), "skel_container_acquire")
     return ptr.value or 0
 
@@ -439,7 +440,7 @@ def skel_container_acquire_range(c: Container, place: int, access: int, first: i
     element `first` of the copy at `place`."""
     ptr = C.c_void_p()
     _check(_L().skel_container_acquire_range(_h(c), place, access, int(first), int(count),
-                                             C.c_void_p(_stream(stream)), C.byref(ptr)),
+                                             _stream(stream), C.byref(ptr)),
            "skel_container_acquire_range")
     return ptr.value or 0
 
@@ -456,7 +457,7 @@ def skel_container_valid_ranges(c: Container, place: int):
 
 
 def skel_container_release(c: Container, place: int, stream=None) -> None:
-    _check(_L().skel_container_release(_h(c), place, C.c_void_p(_stream(stream))),
+    _check(_L().skel_container_release(_h(c), place, _stream(stream)),
            "skel_container_release")
 
 
@@ -474,18 +475,35 @@ def skel_container_info(c: Container):
 
 
 # --------------------------------------------------------------- skeletons
+_PARAM_ARRAYS = {}  # parameter lists of plain Python numbers -> their ctypes arrays
+
+
 def _params(params):
     """(keep-alive object, pointer argument, count) for a parameter list."""
     if params is None or len(params) == 0:
         return None, None, 0
-    vals = [float(v) for v in params]
+    key = tuple(params)
+    hit = _PARAM_ARRAYS.get(key)
+    if hit is not None:
+        return hit
+    vals = [float(v) for v in key]
     arr = (C.c_double * len(vals))(*vals)
-    return arr, arr, len(vals)
+    hit = (arr, arr, len(vals))
+    # only plain numbers are keys (a tensor would hash by identity, not value);
+    # the library copies the values at call time, so a shared array is safe
+    if len(_PARAM_ARRAYS) < 256 and all(v.__class__ in (int, float) for v in key):
+        _PARAM_ARRAYS[key] = hit
+    return hit
+
+
+_HANDLE_ARRAYS = {k: C.c_void_p * k for k in range(1, 9)}
 
 
 def _handles(cs):
-    arr = (C.c_void_p * len(cs))(*[c.handle for c in cs])
-    return arr, len(cs)
+    hs = [_h(c) for c in cs]
+    k = len(hs)
+    arr = (_HANDLE_ARRAYS.get(k) or (C.c_void_p * k))(*hs)
+    return arr, k
 
 
 def _floats(w):
@@ -498,29 +516,24 @@ def _floats(w):
 def skel_map(op: int, params, ins, out: Container, variant: int = VARIANT_AUTO,
              stream=None) -> None:
     """Map: out[i] = f(ins[0][i], ins[1][i])."""
-    for c in ins:
-        _h(c)
-    _h(out)
-    p, pp, np_ = _params(params)
     arr, nin = _handles(ins)
-    _check(_L().skel_map(op, pp, np_, arr, nin, _h(out), variant,
-                         C.c_void_p(_stream(stream))), "skel_map")
+    ho = _h(out)
+    p, pp, np_ = _params(params)
+    _check(_L().skel_map(op, pp, np_, arr, nin, ho, variant, _stream(stream)), "skel_map")
 
 
 def skel_reduce(op: int, inp: Container, out1: Container, variant: int = VARIANT_AUTO,
                 stream=None) -> None:
-    _check(_L().skel_reduce(op, _h(inp), _h(out1), variant, C.c_void_p(_stream(stream))),
+    _check(_L().skel_reduce(op, _h(inp), _h(out1), variant, _stream(stream)),
            "skel_reduce")
 
 
 def skel_mapreduce(map_op: int, params, ins, op: int, out1: Container,
                    variant: int = VARIANT_AUTO, stream=None) -> None:
-    for c in ins:
-        _h(c)
-    p, pp, np_ = _params(params)
     arr, nin = _handles(ins)
+    p, pp, np_ = _params(params)
     _check(_L().skel_mapreduce(map_op, pp, np_, arr, nin, op, _h(out1), variant,
-                               C.c_void_p(_stream(stream))), "skel_mapreduce")
+                               _stream(stream)), "skel_mapreduce")
 
 
 def skel_mapoverlap1d(inp: Container, out: Container, w, radius: int,
@@ -530,7 +543,7 @@ def skel_mapoverlap1d(inp: Container, out: Container, w, radius: int,
     if wa is None or wa.size != 2 * radius + 1:
         raise ValueError("w must hold 2*radius+1 weights")
     _check(_L().skel_mapoverlap1d(_h(inp), _h(out), wp, radius, edge, pad, variant,
-                                  C.c_void_p(_stream(stream))), "skel_mapoverlap1d")
+                                  _stream(stream)), "skel_mapoverlap1d")
 
 
 def _weights_2d(w2d, wy, wx, ry, rx):
@@ -561,7 +574,7 @@ def skel_mapoverlap2d(inp: Container, out: Container, w2d=None, wy=None, wx=None
                       variant: int = VARIANT_AUTO, stream=None) -> None:
     (p2, py, px), keep, ry, rx = _weights_2d(w2d, wy, wx, ry, rx)
     _check(_L().skel_mapoverlap2d(_h(inp), _h(out), p2, py, px, ry, rx, edge, pad, variant,
-                                  C.c_void_p(_stream(stream))), "skel_mapoverlap2d")
+                                  _stream(stream)), "skel_mapoverlap2d")
 
 
 def skel_mapoverlap2d_fields(inp: Container, out: Container, fields: int, w2d=None, wy=None,
@@ -572,13 +585,13 @@ def skel_mapoverlap2d_fields(inp: Container, out: Container, fields: int, w2d=No
     in (fields * H, W) containers."""
     (p2, py, px), keep, ry, rx = _weights_2d(w2d, wy, wx, ry, rx)
     _check(_L().skel_mapoverlap2d_fields(_h(inp), _h(out), fields, p2, py, px, ry, rx, edge,
-                                         pad, variant, C.c_void_p(_stream(stream))),
+                                         pad, variant, _stream(stream)),
            "skel_mapoverlap2d_fields")
 
 
 def skel_scan(inp: Container, out: Container, kind: int = INCLUSIVE, op: int = SUM,
               variant: int = VARIANT_AUTO, stream=None) -> None:
-    _check(_L().skel_scan(_h(inp), _h(out), kind, op, variant, C.c_void_p(_stream(stream))),
+    _check(_L().skel_scan(_h(inp), _h(out), kind, op, variant, _stream(stream)),
            "skel_scan")
 
 
@@ -586,29 +599,27 @@ def skel_scan_rows(inp: Container, out: Container, kind: int = INCLUSIVE, op: in
                    variant: int = VARIANT_AUTO, stream=None) -> None:
     """Scan every row of a (rows, cols) container on its own."""
     _check(_L().skel_scan_rows(_h(inp), _h(out), kind, op, variant,
-                               C.c_void_p(_stream(stream))), "skel_scan_rows")
+                               _stream(stream)), "skel_scan_rows")
 
 
 def skel_reduce_segments(op: int, inp: Container, offsets: Container, out: Container,
                          variant: int = VARIANT_AUTO, stream=None) -> None:
     """out[s] = op over inp[offsets[s]:offsets[s+1]] for every segment s."""
     _check(_L().skel_reduce_segments(op, _h(inp), _h(offsets), _h(out), variant,
-                                     C.c_void_p(_stream(stream))), "skel_reduce_segments")
+                                     _stream(stream)), "skel_reduce_segments")
 
 
 def skel_map_backward(map_op: int, params, ins, g: Container, grad_ins,
                       grad_params: Container | None = None, stream=None) -> None:
     """grad_ins[k] = g * df/d(input k); grad_params[k] = sum_i g df/dp_k.
     g has n elements or one (broadcast)."""
-    for c in list(ins) + list(grad_ins):
-        _h(c)
-    p, pp, np_ = _params(params)
     arr, nin = _handles(ins)
     garr, ng = _handles(grad_ins)
+    p, pp, np_ = _params(params)
     if ng != nin:
         raise ValueError("one gradient output per input")
     _check(_L().skel_map_backward(map_op, pp, np_, arr, nin, _h(g), garr, _h(grad_params),
-                                  C.c_void_p(_stream(stream))), "skel_map_backward")
+                                  _stream(stream)), "skel_map_backward")
 
 
 def skel_mapoverlap1d_backward(g: Container, grad_in: Container, w, radius: int,
@@ -618,7 +629,7 @@ def skel_mapoverlap1d_backward(g: Container, grad_in: Container, w, radius: int,
     if wa is None or wa.size != 2 * radius + 1:
         raise ValueError("w must hold 2*radius+1 weights")
     _check(_L().skel_mapoverlap1d_backward(_h(g), _h(grad_in), wp, radius, edge, variant,
-                                           C.c_void_p(_stream(stream))),
+                                           _stream(stream)),
            "skel_mapoverlap1d_backward")
 
 
@@ -628,7 +639,7 @@ def skel_mapoverlap2d_backward(g: Container, grad_in: Container, w2d=None, wy=No
                                stream=None) -> None:
     (p2, py, px), keep, ry, rx = _weights_2d(w2d, wy, wx, ry, rx)
     _check(_L().skel_mapoverlap2d_backward(_h(g), _h(grad_in), p2, py, px, ry, rx, edge,
-                                           variant, C.c_void_p(_stream(stream))),
+                                           variant, _stream(stream)),
            "skel_mapoverlap2d_backward")
 
 
@@ -640,7 +651,7 @@ def skel_mapoverlap2d_fields_backward(g: Container, grad_in: Container, fields: 
     (p2, py, px), keep, ry, rx = _weights_2d(w2d, wy, wx, ry, rx)
     _check(_L().skel_mapoverlap2d_fields_backward(_h(g), _h(grad_in), fields, p2, py, px, ry,
                                                   rx, edge, variant,
-                                                  C.c_void_p(_stream(stream))),
+                                                  _stream(stream)),
            "skel_mapoverlap2d_fields_backward")
 
 
