@@ -502,6 +502,34 @@ def small_config(skel, torch):
     for name, (nbytes, fn) in calls.items():
         ms = time_call(torch, fn, 50)
         res[name] = {"us": round(ms * 1e3, 2), "GBps": round(nbytes / (ms * 1e-3) / 1e9, 1)}
+    # the four calls as one step, issued call by call and replayed as a
+    # captured HIP graph (launch-bound work is where the graph pays)
+    stream = torch.cuda.Stream()
+    reps = 200
+    with torch.cuda.stream(stream):
+        for _, fn in calls.values():  # sizes this stream's workspace outside the capture
+            fn()
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=stream):
+            for _, fn in calls.values():
+                fn()
+        torch.cuda.synchronize()
+
+        def per_step(body):
+            body()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            for _ in range(reps):
+                body()
+            b.record(stream)
+            b.synchronize()
+            return a.elapsed_time(b) / reps * 1e3
+
+        eager = per_step(lambda: [fn() for _, fn in calls.values()])
+        graph = per_step(g.replay)
+    skel.skel_sync(stream)
+    res["step_of_four"] = {"eager_us": round(eager, 2), "graph_us": round(graph, 2)}
     for c in (x, y, s, so, z, o, r):
         c.destroy()
     return res
