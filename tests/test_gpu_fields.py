@@ -91,3 +91,29 @@ def test_fields_shape_errors(skel):
         assert e.value.status == skel.E_SHAPE
     skel.skel_mapoverlap2d_fields(x, out, 10, w2d=w)  # ten 1 x 8 fields
     skel.skel_sync()
+
+
+from hypothesis import HealthCheck, given, settings, strategies as st  # noqa: E402
+
+
+@settings(max_examples=60, deadline=None, suppress_health_check=list(HealthCheck))
+@given(f=st.integers(1, 5), h=st.integers(1, 40), wd=st.integers(1, 40), ry=st.integers(0, 3),
+       rx=st.integers(0, 3), edge=st.sampled_from(list(EDGES)), sep=st.booleans(),
+       seed=st.integers(0, 1000))
+def test_fields_drawn_shapes(skel, oracle_mod, f, h, wd, ry, rx, edge, sep, seed):
+    x = si.uniform_f32(f * h * wd, -1.0, 1.0, 24, seed).reshape(f * h, wd)
+    wy = si.uniform_f32(2 * ry + 1, -1.0, 1.0, 24, 2000 + seed)
+    wx = si.uniform_f32(2 * rx + 1, -1.0, 1.0, 24, 3000 + seed)
+    w = {"wy": wy, "wx": wx} if sep else {"w2d": np.outer(wy, wx).astype(np.float32)}
+    cx = skel.Container.from_numpy(x)
+    out = skel.Container.empty(skel.F32, f * h, wd)
+    skel.skel_mapoverlap2d_fields(cx, out, f, edge=EDGES[edge], pad=0.5, **w)
+    back = skel.Container.empty(skel.F32, f * h, wd)
+    skel.skel_mapoverlap2d_fields_backward(cx, back, f, edge=EDGES[edge], **w)
+    got, gb = out.to_numpy().reshape(f, h, wd), back.to_numpy().reshape(f, h, wd)
+    for k in range(f):
+        xf = x[k * h:(k + 1) * h]
+        ref, mag = oracle_mod.mapoverlap2d(xf, ry, rx, edge=edge, pad=0.5, **w)
+        assert np.all(np.abs(got[k] - ref) <= 1e-6 * mag + 1e-30), k
+        ref, mag = oracle_mod.mapoverlap2d_adjoint(xf, ry, rx, edge=edge, **w)
+        assert np.all(np.abs(gb[k] - ref) <= 1e-6 * mag + 1e-30), k

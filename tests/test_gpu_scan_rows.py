@@ -117,3 +117,25 @@ def test_scan_rows_more_rows_than_one_grid(skel, oracle_mod):
                 (cols, r)
     skel.skel_sync()
 
+
+
+from hypothesis import HealthCheck, given, settings, strategies as st  # noqa: E402
+
+
+@settings(max_examples=60, deadline=None, suppress_health_check=list(HealthCheck))
+@given(rows=st.integers(1, 40), cols=st.integers(1, 5000),
+       pair=st.sampled_from(["i32_i32", "i32_i64", "i64_i64"]),
+       kind=st.sampled_from(list(KINDS)), op=st.sampled_from(list(RED_OPS)),
+       variant=st.sampled_from([SR0, SR1]), seed=st.integers(0, 1000))
+def test_scan_rows_drawn_shapes(skel, oracle_mod, rows, cols, pair, kind, op, variant, seed):
+    din, dout, sk_out = {"i32_i32": (np.int32, np.int32, skel.I32),
+                         "i32_i64": (np.int32, np.int64, skel.I64),
+                         "i64_i64": (np.int64, np.int64, skel.I64)}[pair]
+    if variant == SR0 and not aligned(cols, np.dtype(din).itemsize, np.dtype(dout).itemsize):
+        variant = SR1
+    x = ints(si.rng(23, seed), (rows, cols), din)
+    out = skel.Container.empty(sk_out, rows, cols)
+    skel.skel_scan_rows(skel.Container.from_numpy(x), out, KINDS[kind], RED_OPS[op],
+                        variant=variant)
+    assert np.array_equal(out.to_numpy().reshape(rows, cols),
+                          oracle_mod.scan_rows(x, kind, op, dout))
