@@ -11,6 +11,7 @@ the reverse-mode adjoints declared in include/skel.h:
     mapreduce_sum_fn   Map backward with the broadcast upstream gradient
     mapoverlap1d_fn    transposed neighbourhood map (clamped reads
     mapoverlap2d_fn    accumulate onto the edge elements)
+    mapoverlap2d_fields_fn  the same over a batch of fields, one launch
     scan_sum_fn        reverse scan of the upstream gradient
     scan_rows_sum_fn   reverse scan of each row of the upstream gradient
 
@@ -28,8 +29,9 @@ import torch
 from . import (EDGE_CLAMP, EXCLUSIVE, INCLUSIVE, MAP_AFFINE, MAP_AFFINE_TANH, MAP_AXPY,
                MAP_IDENTITY, MAP_MUL, REVERSE_EXCLUSIVE, REVERSE_INCLUSIVE, SUM, skel_map,
                skel_map_backward, skel_mapoverlap1d, skel_mapoverlap1d_backward,
-               skel_mapoverlap2d, skel_mapoverlap2d_backward, skel_mapreduce, skel_reduce,
-               skel_scan, skel_scan_rows, wrap_tensor)
+               skel_mapoverlap2d, skel_mapoverlap2d_backward, skel_mapoverlap2d_fields,
+               skel_mapoverlap2d_fields_backward, skel_mapreduce, skel_reduce, skel_scan,
+               skel_scan_rows, wrap_tensor)
 
 _TWO_INPUTS = {MAP_AXPY, MAP_MUL}
 _NPARAMS = {MAP_AXPY: 1, MAP_AFFINE: 2, MAP_AFFINE_TANH: 2}
@@ -222,6 +224,39 @@ def mapoverlap2d_fn(x, w2d=None, wy=None, wx=None, edge: int = EDGE_CLAMP, pad: 
     return _Overlap2DFn.apply(x, cv(w2d), cv(wy), cv(wx), int(edge), float(pad))
 
 
+class _Overlap2DFieldsFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, x, fields, w2d, wy, wx, edge, pad):
+        out = torch.empty_like(x)
+        with _wrapped(x, out) as (cx, co):
+            skel_mapoverlap2d_fields(cx, co, fields, w2d=w2d, wy=wy, wx=wx, edge=edge, pad=pad)
+        ctx.fields, ctx.w2d, ctx.wy, ctx.wx, ctx.edge = fields, w2d, wy, wx, edge
+        return out
+
+    @staticmethod
+    def backward(ctx, g):
+        g = _f32(g, "grad")
+        dx = torch.empty_like(g)
+        with _wrapped(g, dx) as (cg, cdx):
+            skel_mapoverlap2d_fields_backward(cg, cdx, ctx.fields, w2d=ctx.w2d, wy=ctx.wy,
+                                              wx=ctx.wx, edge=ctx.edge)
+        return dx, None, None, None, None, None, None
+
+
+def mapoverlap2d_fields_fn(x, w2d=None, wy=None, wx=None, edge: int = EDGE_CLAMP,
+                           pad: float = 0.0):
+    """2D neighbourhood map over every (H, W) field of a (fields, H, W) tensor
+    (each with its own borders), in one launch; differentiable in x."""
+    x = _f32(x, "x")
+    if x.dim() != 3:
+        raise ValueError("x must be (fields, H, W)")
+    f, h, w = x.shape
+    cv = lambda a: None if a is None else np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+    out = _Overlap2DFieldsFn.apply(x.reshape(f * h, w), int(f), cv(w2d), cv(wy), cv(wx),
+                                   int(edge), float(pad))
+    return out.reshape(f, h, w)
+
+
 class _ScanSumFn(torch.autograd.Function):
     @staticmethod
     def forward(ctx, x, kind):
@@ -280,4 +315,4 @@ def scan_rows_sum_fn(x, kind: int = INCLUSIVE):
 
 
 __all__ = ["map_fn", "reduce_sum_fn", "mapreduce_sum_fn", "mapoverlap1d_fn",
-           "mapoverlap2d_fn", "scan_sum_fn", "scan_rows_sum_fn"]
+           "mapoverlap2d_fn", "mapoverlap2d_fields_fn", "scan_sum_fn", "scan_rows_sum_fn"]

@@ -261,6 +261,28 @@ def test_autograd_functions(skel, oracle_mod):
     ref, mag = oracle_mod.scan(gh, "reverse_exclusive")
     assert np.all(np.abs(x.grad.cpu().numpy() - ref) <= 1e-5 * mag + 1e-30)
 
+    # the layer of the batched fields: stencil on every field, then prefix sums
+    # along the rows; the gradient is the stencil's transpose of the rows'
+    # suffix sums of the upstream gradient
+    F_, H_, W_ = 3, 33, 70
+    w5 = si.five_point_weights(0.5, 0.1, 0.2, 0.05, 0.15)
+    xf = si.normal_f32(F_ * H_ * W_, 10, 8).reshape(F_, H_, W_)
+    gf = si.normal_f32(F_ * H_ * W_, 10, 9).reshape(F_, H_, W_)
+    xt = t(xf).requires_grad_()
+    zt = ag.scan_rows_sum_fn(ag.mapoverlap2d_fields_fn(xt, w2d=w5))
+    (zt * t(gf)).sum().backward()
+    for k in range(F_):
+        yref, ymag = oracle_mod.mapoverlap2d(xf[k], 1, 1, w2d=w5, edge="clamp")
+        got = zt.detach()[k].cpu().numpy()
+        assert np.all(np.abs(got - np.cumsum(yref, axis=1))
+                      <= 1e-5 * np.cumsum(ymag, axis=1) + 1e-30), k
+        gy, gmag = oracle_mod.scan_rows(gf[k], "reverse_inclusive")
+        dref, _ = oracle_mod.mapoverlap2d_adjoint(gy.astype(np.float32), 1, 1, w2d=w5,
+                                                  edge="clamp")
+        _, dmag = oracle_mod.mapoverlap2d_adjoint(gmag.astype(np.float32), 1, 1,
+                                                  w2d=np.abs(w5), edge="clamp")
+        assert np.all(np.abs(xt.grad[k].cpu().numpy() - dref) <= 1e-5 * dmag + 1e-30), k
+
     # scan along the last axis of a batch of fields (3 x 40 x 2048, and an odd
     # width): each row's gradient is its own suffix sum
     for shape in [(3, 40, 2048), (5, 37)]:
