@@ -406,9 +406,9 @@ const char *skel_variant_name(int skeleton, int variant); /* NULL if out of rang
 /* The execution plan's choice (Section III) for a call context, without
  * running anything: returns the variant index, or -1 if none is selectable.
  * n is the element count (rows*cols for 2D); dtype is the input element type;
- * `aux` is the radius for SKEL_SK_MAPOVERLAP1D(_BACKWARD), 1 when the 2D
- * weights are given as separable factors for SKEL_SK_MAPOVERLAP2D(_BACKWARD),
- * 1 for the reverse kinds of SKEL_SK_SCAN and SKEL_SK_SCAN_ROWS, and ignored
+ * `aux` is the radius for SKEL_SK_MAPOVERLAP1D(_BACKWARD); for
+ * SKEL_SK_MAPOVERLAP2D(_BACKWARD), separable + 2 * max(ry, rx), where separable
+ * is 1 when the weights are given as factors wy, wx; 1 for the reverse kinds of SKEL_SK_SCAN and SKEL_SK_SCAN_ROWS, and ignored
  * otherwise (for SKEL_SK_SCAN_ROWS, rows and cols give the matrix shape and
  * dtype serves as both types). */
 int skel_select_variant(int skeleton, skel_dtype dtype, int64_t n,

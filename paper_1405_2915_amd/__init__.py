@@ -96,7 +96,12 @@ def load_library(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise ImportError(f"{path} is not built; run `python -m paper_1405_2915_amd.build_lib`"
                           " (the HIP library is required, there is no fallback)")
-    lib = C.CDLL(path)
+    try:
+        lib = C.CDLL(path)
+    except OSError as e:  # e.g. an undefined symbol: linked from sources of different ages
+        raise ImportError(f"{path} cannot be loaded ({e}): it is older than the sources or "
+                          "half rebuilt; rebuild it with "
+                          "`python -m paper_1405_2915_amd.build_lib`") from e
     st, vp, i64, i = C.c_int, C.c_void_p, C.c_int64, C.c_int
     dp = C.POINTER(C.c_double)
     fp = C.POINTER(C.c_float)
@@ -666,7 +671,8 @@ def skel_variant_name(skeleton: int, variant: int):
 
 def skel_select_variant(skeleton: int, dtype: int, n: int, rows: int = 1, cols: int | None = None,
                         aux: int = 0) -> int:
-    """aux: the radius for MapOverlap1D, 1 for separable MapOverlap2D weights."""
+    """aux: the radius for MapOverlap1D; for MapOverlap2D, separable + 2 * max(ry, rx)
+    (separable: 1 when the weights are given as factors); 1 for reverse scans."""
     return load_library().skel_select_variant(skeleton, dtype, n, rows,
                                               n if cols is None else cols, aux)
 

@@ -9,6 +9,10 @@
 
 namespace skel {
 
+int overlap2d_dense_variant(int64_t n, int radius) {
+    return radius <= 4 && n >= (INT64_C(1) << 20) ? O2E_MARCH : O2B_LDS_TILE;
+}
+
 namespace {
 
 const char* const kMap[] = {"M0_scalar", "M1_vec4", "M2_vec4x4_nt"};
@@ -19,7 +23,7 @@ const char* const kMapReduce[] = {"MR0_unfused", "MR1_fused_two_pass",
                                   "MR4_compensated"};
 const char* const kOverlap1D[] = {"O1a_direct", "O1b_lds_tile", "O1c_shuffle"};
 const char* const kOverlap2D[] = {"O2a_direct", "O2b_lds_tile", "O2c_lds_separable",
-                                  "O2d_separable_l1"};
+                                  "O2d_separable_l1", "O2e_march"};
 const char* const kScan[] = {"S0_single_wg", "S1_reduce_then_scan",
                              "S2_decoupled_lookback", "S3_persistent_lookback"};
 
@@ -78,7 +82,8 @@ int static_rule(const CallContext& c) {
     case SKEL_SK_MAPREDUCE:
         return c.n <= (INT64_C(1) << 15) ? MR3_FUSED_SINGLE_WG : MR2_FUSED_TICKET;
     case SKEL_SK_MAPOVERLAP1D: return c.radius <= 4 ? O1C_SHUFFLE : O1B_LDS_TILE;
-    case SKEL_SK_MAPOVERLAP2D: return c.separable ? O2D_SEPARABLE_L1 : O2B_LDS_TILE;
+    case SKEL_SK_MAPOVERLAP2D:
+        return c.separable ? O2D_SEPARABLE_L1 : overlap2d_dense_variant(c.n, c.radius);
     case SKEL_SK_SCAN:
         return c.n <= (INT64_C(1) << 15) && !c.reverse ? S0_SINGLE_WG : S3_PERSISTENT_LOOKBACK;
     case SKEL_SK_REDUCE_SEGMENTS: return B1_PERSISTENT;
@@ -195,6 +200,10 @@ bool selectable(int v, const CallContext& c, const char** why) {
     case SKEL_SK_MAPOVERLAP2D:
         if ((v == O2C_LDS_SEPARABLE || v == O2D_SEPARABLE_L1) && !c.separable) {
             *why = "separable variants need the weights as factors wy, wx";
+            return false;
+        }
+        if (v == O2E_MARCH && c.radius > 4) {
+            *why = "marching variant reaches at most 4 neighbours per side";
             return false;
         }
         return true;
@@ -335,7 +344,10 @@ int skel_select_variant(int skeleton, skel_dtype dtype, int64_t n, int64_t rows,
     else if (skeleton == SKEL_SK_SCAN_ROWS) {
         c.reverse = aux;
         c.rows_aligned = skel::rows_aligned(dtype, dtype, cols);
-    } else c.separable = aux;
+    } else if (skeleton == SKEL_SK_MAPOVERLAP2D || skeleton == SKEL_SK_MAPOVERLAP2D_BACKWARD) {
+        c.separable = aux & 1;
+        c.radius = aux >> 1;
+    }
     skel_status st;
     return skel::choose_variant(SKEL_VARIANT_AUTO, c, &st);
 }

@@ -420,8 +420,8 @@ skel_status launch_overlap2d_adjoint(int v, const float* g, float* dx, int64_t r
         float wf[(2 * SKEL_MAX_RADIUS_2D + 1) * (2 * SKEL_MAX_RADIUS_2D + 1)];
         for (int a = 0; a < ny; ++a)
             for (int b = 0; b < nx; ++b) wf[a * nx + b] = w2d[(ny - 1 - a) * nx + (nx - 1 - b)];
-        e = launch_overlap2d(O2B_LDS_TILE, g, dx, rows, cols, fields, wf, nullptr, nullptr, ry,
-                             rx, fe, 0.0f, lc);
+        e = launch_overlap2d(overlap2d_dense_variant(fields * img, ry > rx ? ry : rx), g, dx,
+                             rows, cols, fields, wf, nullptr, nullptr, ry, rx, fe, 0.0f, lc);
     } else {
         float fy[2 * SKEL_MAX_RADIUS_2D + 1], fx[2 * SKEL_MAX_RADIUS_2D + 1];
         for (int a = 0; a < ny; ++a) fy[a] = wy[ny - 1 - a];

@@ -21,6 +21,11 @@
 //        (2r+1)^2 multiply-adds per output
 //   O2d  2D separable with the row pass read from global memory through L1
 //        and only its result staged in LDS (64x32 tiles, full occupancy)
+//   O2e  2D marching window (ry, rx <= 4): each wavefront walks down a strip
+//        of 256 columns, loading every input row once; horizontal neighbours
+//        come from the adjacent lanes by DPP moves and the 2ry+1 output rows
+//        a loaded row feeds are kept in a ring of registers.  No LDS, no
+//        barrier.
 // 2D tiles are visited in an XCD-aware order: consecutive workgroups go to
 // different XCDs round-robin, so tile ids are remapped to give each XCD a
 // contiguous band of tiles whose shared halo rows stay in that XCD's L2.
@@ -511,6 +516,169 @@ __global__ __launch_bounds__(kBlock) void ov2_sep_l1(const float* x, float* out,
     for (int o = 0; o < RO; ++o) store4(out, rows, cols, y0 + RO * rg + o, x0 + 4 * cg, acc[o]);
 }
 
+// O2e.  A workgroup's four wavefronts take four vertically stacked strips,
+// so the ry halo rows that one strip shares with the next are read from
+// cache.  Input row m of a strip (row i0 - ry + m of the image) feeds output
+// rows m - a of the strip with weight row a; output row o accumulates in ring
+// slot o mod (2ry+1), which is stored and cleared once row o + 2ry is in.
+// What bounds it is how many rows a wavefront has in flight: all rows of a
+// chunk are loaded before the first is used.  Measured (5-point stencil on
+// 64 fields of 2048^2; strip rows / chunk rows): 32/9 394 us, 16/9 378,
+// 64/9 397, 32/18 433, 16/18 (the whole strip) 358, O2b 428; on 4096^2
+// 16/18 takes 24 us against 28 for O2b.  A dense 9 x 9 needs 24 rows for a
+// 16-row strip, more than the registers hold: there 64-row strips in chunks
+// of 18 rows measured best (67 us on 4096^2, 16-row strips 90).
+constexpr int kMarchCols = 4 * dev::kWave;    // columns per strip
+constexpr int kMarchMaxR = 4;                 // radius reach of one neighbour lane
+// With a run-time column radius (radii other than 1, 2 or 4 in both
+// directions) the tap loop is longer, and whole-strip chunks spill; those
+// instances load about eight rows at a time.
+template <int RY, bool DYN>
+struct March {
+    static constexpr int NW = 2 * RY + 1;                       // ring slots
+    static constexpr int rows = RY <= 2 ? 16 : 64;              // output rows per strip
+    static constexpr int chunk = DYN ? NW * ((8 + NW - 1) / NW)  // rows loaded at once
+                               : RY <= 2 ? rows + 2 * RY : 2 * NW;
+    static_assert(chunk % NW == 0 && (rows + 2 * RY) % chunk == 0, "whole chunks per strip");
+};
+
+// four consecutive columns starting at j of row rp, through the column rule
+__device__ __forceinline__ f32x4 fetch_row4(const float* rp, int64_t cols, int64_t j,
+                                            bool aligned, int edge, float pad) {
+    if (aligned && j >= 0 && j + 4 <= cols) return *reinterpret_cast<const f32x4*>(rp + j);
+    float v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        int64_t c;
+        v[q] = border(j + q, cols, edge, c) ? rp[c] : pad;
+    }
+    return f32x4{v[0], v[1], v[2], v[3]};
+}
+
+// Add loaded row m of a strip (held in ring position t = m mod (2ry+1)) into
+// the output rows it feeds, then store output row m - 2ry, now complete, and
+// clear its slot for row m + 1.  c: this lane's four columns; e: the chunk
+// beyond the strip's end read by lanes 0 (left) and 63 (right).
+template <int RY, int MX>
+__device__ __forceinline__ void march_row(float (&acc)[2 * RY + 1][4], int t, int m, f32x4 c,
+                                          f32x4 e, const W2& w, int rx, float* out,
+                                          int64_t i0, int64_t j, int64_t cols, bool vec_store) {
+    constexpr int NW = 2 * RY + 1;
+    const int nx = 2 * rx + 1;
+    const f32x4 lt = dev::wave_shift_up(c, e), rt = dev::wave_shift_down(c, e);
+    const float v[12] = {lt.x, lt.y, lt.z, lt.w, c.x, c.y, c.z, c.w, rt.x, rt.y, rt.z, rt.w};
+#pragma unroll
+    for (int a = 0; a < NW; ++a) {
+        const int s = ((t - a) % NW + NW) % NW;
+#pragma unroll
+        for (int d = -MX; d <= MX; ++d) {
+            if (d < -rx || d > rx) continue;
+            const float wab = w.w[a * nx + d + rx];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[s][q] = __builtin_fmaf(wab, v[4 + q + d], acc[s][q]);
+        }
+    }
+    const int sd = (t + 1) % NW;
+    if (m >= 2 * RY) {
+        float* op = out + (i0 + m - 2 * RY) * cols;
+        if (vec_store) {
+            dev::store_vec_nt(f32x4{acc[sd][0], acc[sd][1], acc[sd][2], acc[sd][3]},
+                              reinterpret_cast<f32x4*>(op + j));
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (j + q < cols) op[j + q] = acc[sd][q];
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[sd][q] = 0.0f;
+}
+
+template <int RY, int RX>
+__global__ __launch_bounds__(kBlock) void ov2_march(const float* x, float* out, int64_t rows,
+                                                    int64_t cols, W2 w, int rx_, int edge,
+                                                    float pad, int64_t nbx, int64_t nb) {
+    // blockIdx.y: one of several equally shaped images stored back to back
+    x += (int64_t)blockIdx.y * rows * cols;
+    out += (int64_t)blockIdx.y * rows * cols;
+    using M = March<RY, (RX < 0)>;
+    constexpr int NW = M::NW, CH = M::chunk, kMarchRows = M::rows;
+    constexpr int MX = RX >= 0 ? RX : kMarchMaxR;
+    const int rx = RX >= 0 ? RX : rx_;
+    const int l = dev::lane();
+    const int64_t bx = (int64_t)blockIdx.x % nbx, by = (int64_t)blockIdx.x / nbx;
+    const int64_t j0 = bx * kMarchCols;
+    const int64_t i0 = (by * (kBlock / dev::kWave) + threadIdx.x / dev::kWave) * kMarchRows;
+    if (i0 >= rows) return;  // whole wavefronts; no barrier follows
+    const int64_t j = j0 + 4 * l;
+    const bool aligned = (cols & 3) == 0;
+    const int nout = (int)(rows - i0 < kMarchRows ? rows - i0 : kMarchRows);
+    const int nin = nout + 2 * RY;
+    // the chunk the edge lanes read beyond the strip: left of it for lane 0,
+    // right of it for lane 63 (other lanes re-read their own chunk)
+    const int64_t je = l == 0 ? j0 - 4 : l == dev::kWave - 1 ? j0 + kMarchCols : j;
+    float acc[NW][4];
+#pragma unroll
+    for (int s = 0; s < NW; ++s)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[s][q] = 0.0f;
+    int m0 = 0;
+    // fast path: the strip lies inside the row, so every row is two
+    // unconditional 16-byte loads per lane.  Rows beyond the image ends (at
+    // most ry <= rows away) and the edge chunks beyond the row ends map by the
+    // edge rule without branches: cyclic reads the chunk at the other end,
+    // clamp repeats the row's end value, const takes the pad.
+    if (aligned && j0 + kMarchCols <= cols && rows >= kMarchMaxR) {
+        const bool lo = l == 0 && j0 == 0, hi = l == dev::kWave - 1 && j0 + kMarchCols == cols;
+        const bool efix = (lo || hi) && edge != SKEL_EDGE_CYCLIC;
+        const int64_t jf = lo ? cols - 4 : hi ? 0 : je;
+        const int64_t jr = efix ? j : jf;
+        for (; m0 + CH <= nin; m0 += CH) {
+            f32x4 c[CH], e[CH];
+            bool in[CH];
+#pragma unroll
+            for (int t = 0; t < CH; ++t) {
+                const int64_t k = i0 - RY + m0 + t;
+                in[t] = k >= 0 && k < rows;
+                const int64_t kk = in[t] ? k
+                                 : edge == SKEL_EDGE_CYCLIC ? (k < 0 ? k + rows : k - rows)
+                                 : (k < 0 ? 0 : rows - 1);
+                c[t] = *reinterpret_cast<const f32x4*>(x + kk * cols + j);
+                e[t] = *reinterpret_cast<const f32x4*>(x + kk * cols + jr);
+            }
+#pragma unroll
+            for (int t = 0; t < CH; ++t) {
+                if (edge == SKEL_EDGE_CONST && !in[t]) {
+                    c[t] = f32x4{pad, pad, pad, pad};
+                    e[t] = c[t];
+                }
+                if (efix) {
+                    const float b = edge == SKEL_EDGE_CONST ? pad : lo ? c[t].x : c[t].w;
+                    e[t] = f32x4{b, b, b, b};
+                }
+                march_row<RY, MX>(acc, t % NW, m0 + t, c[t], e[t], w, rx, out, i0, j, cols,
+                                  true);
+            }
+        }
+    }
+    // general path: the remaining rows, strips at the row ends, ragged widths
+    for (; m0 < nin; m0 += NW) {
+#pragma unroll
+        for (int t = 0; t < NW; ++t) {
+            const int m = m0 + t;
+            if (m >= nin) break;
+            int64_t kk;
+            f32x4 c = {pad, pad, pad, pad}, e = {pad, pad, pad, pad};
+            if (border(i0 - RY + m, rows, edge, kk)) {
+                const float* rp = x + kk * cols;
+                c = fetch_row4(rp, cols, j, aligned, edge, pad);
+                if (l == 0 || l == dev::kWave - 1) e = fetch_row4(rp, cols, je, aligned, edge, pad);
+            }
+            march_row<RY, MX>(acc, t, m, c, e, w, rx, out, i0, j, cols, aligned && j + 4 <= cols);
+        }
+    }
+}
+
 // --------------------------------------------------------------- launchers
 int64_t div_up(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
@@ -539,6 +707,33 @@ skel_status run2d(int v, const float* x, float* out, int64_t rows, int64_t cols,
         ov2_direct<RY, RX><<<dim3((unsigned)(nbx * nby), fields), kBlock, 0, st>>>(
             x, out, rows, cols, w, ry, rx, edge, pad, nbx);
         return launch_check("overlap2d_direct");
+    }
+    if (v == O2E_MARCH) {  // selectable for ry, rx <= 4 only
+        const int64_t nbx = div_up(cols, kMarchCols);
+        constexpr int64_t kWaves = kBlock / dev::kWave;
+        if constexpr (RY >= 0) {
+            const int64_t nb = nbx * div_up(rows, March<RY, (RX < 0)>::rows * kWaves);
+            ov2_march<RY, RX><<<dim3((unsigned)nb, fields), kBlock, 0, st>>>(
+                x, out, rows, cols, w, rx, edge, pad, nbx, nb);
+        } else {
+            switch (ry) {
+#define SKEL_O2E_CASE(R)                                                                      \
+    case R: {                                                                                 \
+        const int64_t nb = nbx * div_up(rows, March<R, true>::rows * kWaves);                 \
+        ov2_march<R, -1><<<dim3((unsigned)nb, fields), kBlock, 0, st>>>(x, out, rows, cols, w, \
+                                                                        rx, edge, pad, nbx, nb); \
+        break;                                                                                \
+    }
+                SKEL_O2E_CASE(0)
+                SKEL_O2E_CASE(1)
+                SKEL_O2E_CASE(2)
+                SKEL_O2E_CASE(3)
+                SKEL_O2E_CASE(4)
+#undef SKEL_O2E_CASE
+            default: return SKEL_E_UNSUPPORTED;
+            }
+        }
+        return launch_check("overlap2d_march");
     }
     if (v == O2D_SEPARABLE_L1) {
         const int64_t nbx = div_up(cols, kTX), nb = nbx * div_up(rows, kTY2);

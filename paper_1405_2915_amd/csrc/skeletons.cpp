@@ -316,6 +316,7 @@ skel_status skel_mapoverlap2d_fields(skel_container* in, skel_container* out, in
     cc.rows = frows;
     cc.cols = in->cols;
     cc.separable = w2d ? 0 : 1;
+    cc.radius = ry > rx ? ry : rx;
     int v = choose_variant(variant, cc, &st);
     if (v < 0) return st;
     Operands ops;

@@ -314,7 +314,7 @@ def name_of(lib, sk, v):
 
 
 def test_variant_registry(rt):
-    want = {SK_MAP: 3, SK_REDUCE: 5, SK_MAPREDUCE: 5, SK_OV1: 3, SK_OV2: 4, SK_SCAN: 4,
+    want = {SK_MAP: 3, SK_REDUCE: 5, SK_MAPREDUCE: 5, SK_OV1: 3, SK_OV2: 5, SK_SCAN: 4,
             SK_SEG: 2, SK_OV1B: 2, SK_OV2B: 2, SK_SCANROWS: 2}
     for sk, k in want.items():
         assert rt.skel_variant_count(sk) == k
@@ -332,7 +332,14 @@ def test_static_plan(rt):
     assert sel(SK_SCAN, 100, I32) == "S0_single_wg"
     assert sel(SK_SCAN, 1 << 27, I32) == "S3_persistent_lookback"
     assert sel(SK_OV2, 1 << 24, F32, 1) == "O2d_separable_l1"
-    assert sel(SK_OV2, 1 << 24, F32, 0) == "O2b_lds_tile"  # separable not selectable
+    # dense weights: aux = 2 * radius; the marching window up to radius 4 on
+    # large images, else the LDS tile (separable variants not selectable)
+    assert sel(SK_OV2, 1 << 24, F32, 2 * 1) == "O2e_march"
+    assert sel(SK_OV2, 1 << 28, F32, 2 * 2) == "O2e_march"
+    assert sel(SK_OV2, 1 << 24, F32, 2 * 4) == "O2e_march"
+    assert sel(SK_OV2, 1 << 24, F32, 2 * 5) == "O2b_lds_tile"
+    assert sel(SK_OV2, 1 << 18, F32, 2 * 1) == "O2b_lds_tile"
+    assert sel(SK_OV2, 1 << 24, F32, 1 + 2 * 4) == "O2d_separable_l1"
     assert sel(SK_OV1, 1 << 20, F32, 2) == "O1c_shuffle"   # aux = radius
     assert sel(SK_OV1, 1 << 20, F32, 7) == "O1b_lds_tile"  # beyond 4 neighbours
     assert sel(SK_MAP, 1 << 20) == "M2_vec4x4_nt"
@@ -355,7 +362,7 @@ def test_plan_table(rt, tmp_path):
     assert sel(SK_SCAN, 1 << 20, I32) == "S1_reduce_then_scan"
     assert sel(SK_SCAN, 1 << 20, I64) == "S3_persistent_lookback"  # no entry: static
     # table entry not selectable for this call: static rule instead
-    assert sel(SK_OV2, 1 << 20, F32, 0) == "O2b_lds_tile"
+    assert sel(SK_OV2, 1 << 20, F32, 0) == "O2e_march"
     # a bad file is rejected whole and the old table stays
     bad = tmp_path / "bad.txt"
     bad.write_text("REDUCE f32 10 R1_two_pass\nREDUCE f99 4 nope\n")
