@@ -83,7 +83,12 @@ int static_rule(const CallContext& c) {
         return c.n <= (INT64_C(1) << 15) ? MR3_FUSED_SINGLE_WG : MR2_FUSED_TICKET;
     case SKEL_SK_MAPOVERLAP1D: return c.radius <= 4 ? O1C_SHUFFLE : O1B_LDS_TILE;
     case SKEL_SK_MAPOVERLAP2D:
-        return c.separable ? O2D_SEPARABLE_L1 : overlap2d_dense_variant(c.n, c.radius);
+        // the marching window takes either weight form (separable: level with
+        // O2d on a 9 x 9 Gaussian over 4096^2, 30.8 / 30.5 us; 3 x 3 over 64
+        // fields of 2048^2 355 / 393 us); beyond its reach the separable L1
+        // variant or the LDS tile
+        if (!c.separable) return overlap2d_dense_variant(c.n, c.radius);
+        return c.radius <= 4 && c.n >= (INT64_C(1) << 20) ? O2E_MARCH : O2D_SEPARABLE_L1;
     case SKEL_SK_SCAN:
         return c.n <= (INT64_C(1) << 15) && !c.reverse ? S0_SINGLE_WG : S3_PERSISTENT_LOOKBACK;
     case SKEL_SK_REDUCE_SEGMENTS: return B1_PERSISTENT;

@@ -558,8 +558,10 @@ __device__ __forceinline__ f32x4 fetch_row4(const float* rp, int64_t cols, int64
 // Add loaded row m of a strip (held in ring position t = m mod (2ry+1)) into
 // the output rows it feeds, then store output row m - 2ry, now complete, and
 // clear its slot for row m + 1.  c: this lane's four columns; e: the chunk
-// beyond the strip's end read by lanes 0 (left) and 63 (right).
-template <int RY, int MX>
+// beyond the strip's end read by lanes 0 (left) and 63 (right).  SEP: the
+// weights are factors, so the row is filtered once with wx and the result
+// added with wy[a] (the LDS separable variants' order of operations).
+template <int RY, int MX, bool SEP>
 __device__ __forceinline__ void march_row(float (&acc)[2 * RY + 1][4], int t, int m, f32x4 c,
                                           f32x4 e, const W2& w, int rx, float* out,
                                           int64_t i0, int64_t j, int64_t cols, bool vec_store) {
@@ -567,15 +569,32 @@ __device__ __forceinline__ void march_row(float (&acc)[2 * RY + 1][4], int t, in
     const int nx = 2 * rx + 1;
     const f32x4 lt = dev::wave_shift_up(c, e), rt = dev::wave_shift_down(c, e);
     const float v[12] = {lt.x, lt.y, lt.z, lt.w, c.x, c.y, c.z, c.w, rt.x, rt.y, rt.z, rt.w};
-#pragma unroll
-    for (int a = 0; a < NW; ++a) {
-        const int s = ((t - a) % NW + NW) % NW;
+    if constexpr (SEP) {
+        float h[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int d = -MX; d <= MX; ++d) {
             if (d < -rx || d > rx) continue;
-            const float wab = w.w[a * nx + d + rx];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) acc[s][q] = __builtin_fmaf(wab, v[4 + q + d], acc[s][q]);
+            for (int q = 0; q < 4; ++q) h[q] = __builtin_fmaf(w.wx[d + rx], v[4 + q + d], h[q]);
+        }
+#pragma unroll
+        for (int a = 0; a < NW; ++a) {
+            const int s = ((t - a) % NW + NW) % NW;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[s][q] = __builtin_fmaf(w.wy[a], h[q], acc[s][q]);
+        }
+    } else {
+#pragma unroll
+        for (int a = 0; a < NW; ++a) {
+            const int s = ((t - a) % NW + NW) % NW;
+#pragma unroll
+            for (int d = -MX; d <= MX; ++d) {
+                if (d < -rx || d > rx) continue;
+                const float wab = w.w[a * nx + d + rx];
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    acc[s][q] = __builtin_fmaf(wab, v[4 + q + d], acc[s][q]);
+            }
         }
     }
     const int sd = (t + 1) % NW;
@@ -594,7 +613,7 @@ __device__ __forceinline__ void march_row(float (&acc)[2 * RY + 1][4], int t, in
     for (int q = 0; q < 4; ++q) acc[sd][q] = 0.0f;
 }
 
-template <int RY, int RX>
+template <int RY, int RX, bool SEP>
 __global__ __launch_bounds__(kBlock) void ov2_march(const float* x, float* out, int64_t rows,
                                                     int64_t cols, W2 w, int rx_, int edge,
                                                     float pad, int64_t nbx, int64_t nb) {
@@ -656,7 +675,7 @@ __global__ __launch_bounds__(kBlock) void ov2_march(const float* x, float* out, 
                     const float b = edge == SKEL_EDGE_CONST ? pad : lo ? c[t].x : c[t].w;
                     e[t] = f32x4{b, b, b, b};
                 }
-                march_row<RY, MX>(acc, t % NW, m0 + t, c[t], e[t], w, rx, out, i0, j, cols,
+                march_row<RY, MX, SEP>(acc, t % NW, m0 + t, c[t], e[t], w, rx, out, i0, j, cols,
                                   true);
             }
         }
@@ -674,7 +693,7 @@ __global__ __launch_bounds__(kBlock) void ov2_march(const float* x, float* out, 
                 c = fetch_row4(rp, cols, j, aligned, edge, pad);
                 if (l == 0 || l == dev::kWave - 1) e = fetch_row4(rp, cols, je, aligned, edge, pad);
             }
-            march_row<RY, MX>(acc, t, m, c, e, w, rx, out, i0, j, cols, aligned && j + 4 <= cols);
+            march_row<RY, MX, SEP>(acc, t, m, c, e, w, rx, out, i0, j, cols, aligned && j + 4 <= cols);
         }
     }
 }
@@ -698,9 +717,39 @@ skel_status run1d(int v, const float* x, float* out, int64_t n, const W1& w, int
     return launch_check("overlap1d_lds");
 }
 
+template <int RY, int RX, bool SEP>
+skel_status run2d_march(const float* x, float* out, int64_t rows, int64_t cols, unsigned fields,
+                        const W2& w, int ry, int rx, int edge, float pad, hipStream_t st) {
+    const int64_t nbx = div_up(cols, kMarchCols);
+    constexpr int64_t kWaves = kBlock / dev::kWave;
+    if constexpr (RY >= 0) {
+        const int64_t nb = nbx * div_up(rows, March<RY, (RX < 0)>::rows * kWaves);
+        ov2_march<RY, RX, SEP><<<dim3((unsigned)nb, fields), kBlock, 0, st>>>(
+            x, out, rows, cols, w, rx, edge, pad, nbx, nb);
+    } else {
+        switch (ry) {
+#define SKEL_O2E_CASE(R)                                                                       \
+    case R: {                                                                                  \
+        const int64_t nb = nbx * div_up(rows, March<R, true>::rows * kWaves);                  \
+        ov2_march<R, -1, SEP><<<dim3((unsigned)nb, fields), kBlock, 0, st>>>(                  \
+            x, out, rows, cols, w, rx, edge, pad, nbx, nb);                                    \
+        break;                                                                                 \
+    }
+            SKEL_O2E_CASE(0)
+            SKEL_O2E_CASE(1)
+            SKEL_O2E_CASE(2)
+            SKEL_O2E_CASE(3)
+            SKEL_O2E_CASE(4)
+#undef SKEL_O2E_CASE
+        default: return SKEL_E_UNSUPPORTED;
+        }
+    }
+    return launch_check("overlap2d_march");
+}
+
 template <int RY, int RX>
 skel_status run2d(int v, const float* x, float* out, int64_t rows, int64_t cols,
-                  unsigned fields, const W2& w, int ry, int rx, int edge, float pad,
+                  unsigned fields, const W2& w, bool sep, int ry, int rx, int edge, float pad,
                   hipStream_t st) {
     if (v == O2A_DIRECT) {
         const int64_t nbx = div_up(cols, 64), nby = div_up(rows, 4);
@@ -708,33 +757,10 @@ skel_status run2d(int v, const float* x, float* out, int64_t rows, int64_t cols,
             x, out, rows, cols, w, ry, rx, edge, pad, nbx);
         return launch_check("overlap2d_direct");
     }
-    if (v == O2E_MARCH) {  // selectable for ry, rx <= 4 only
-        const int64_t nbx = div_up(cols, kMarchCols);
-        constexpr int64_t kWaves = kBlock / dev::kWave;
-        if constexpr (RY >= 0) {
-            const int64_t nb = nbx * div_up(rows, March<RY, (RX < 0)>::rows * kWaves);
-            ov2_march<RY, RX><<<dim3((unsigned)nb, fields), kBlock, 0, st>>>(
-                x, out, rows, cols, w, rx, edge, pad, nbx, nb);
-        } else {
-            switch (ry) {
-#define SKEL_O2E_CASE(R)                                                                      \
-    case R: {                                                                                 \
-        const int64_t nb = nbx * div_up(rows, March<R, true>::rows * kWaves);                 \
-        ov2_march<R, -1><<<dim3((unsigned)nb, fields), kBlock, 0, st>>>(x, out, rows, cols, w, \
-                                                                        rx, edge, pad, nbx, nb); \
-        break;                                                                                \
-    }
-                SKEL_O2E_CASE(0)
-                SKEL_O2E_CASE(1)
-                SKEL_O2E_CASE(2)
-                SKEL_O2E_CASE(3)
-                SKEL_O2E_CASE(4)
-#undef SKEL_O2E_CASE
-            default: return SKEL_E_UNSUPPORTED;
-            }
-        }
-        return launch_check("overlap2d_march");
-    }
+    if (v == O2E_MARCH)  // selectable for ry, rx <= 4 only
+        return sep ? run2d_march<RY, RX, true>(x, out, rows, cols, fields, w, ry, rx, edge, pad, st)
+                   : run2d_march<RY, RX, false>(x, out, rows, cols, fields, w, ry, rx, edge, pad,
+                                                st);
     if (v == O2D_SEPARABLE_L1) {
         const int64_t nbx = div_up(cols, kTX), nb = nbx * div_up(rows, kTY2);
         ov2_sep_l1<RY, RX><<<dim3((unsigned)nb, fields), kBlock, 0, st>>>(
@@ -754,13 +780,13 @@ skel_status run2d(int v, const float* x, float* out, int64_t rows, int64_t cols,
 
 template <int RY, int RX>
 skel_status run2d_fields(int v, const float* x, float* out, int64_t rows, int64_t cols,
-                         int64_t fields, const W2& w, int ry, int rx, int edge, float pad,
-                         hipStream_t st) {
+                         int64_t fields, const W2& w, bool sep, int ry, int rx, int edge,
+                         float pad, hipStream_t st) {
     const int64_t img = rows * cols;
     for (int64_t f0 = 0; f0 < fields; f0 += kMaxFieldsPerLaunch) {
         const unsigned nf = (unsigned)std::min<int64_t>(fields - f0, kMaxFieldsPerLaunch);
         const skel_status e = run2d<RY, RX>(v, x + f0 * img, out + f0 * img, rows, cols, nf, w,
-                                            ry, rx, edge, pad, st);
+                                            sep, ry, rx, edge, pad, st);
         if (e != SKEL_OK) return e;
     }
     return SKEL_OK;
@@ -793,12 +819,12 @@ skel_status launch_overlap2d(int v, const float* x, float* out, int64_t rows, in
         for (int b = 0; b < nx; ++b) wk.wx[b] = wx[b];
     }
     if (ry == 4 && rx == 4)
-        return run2d_fields<4, 4>(v, x, out, rows, cols, fields, wk, ry, rx, edge, pad, lc.stream);
+        return run2d_fields<4, 4>(v, x, out, rows, cols, fields, wk, !w2d, ry, rx, edge, pad, lc.stream);
     if (ry == 1 && rx == 1)
-        return run2d_fields<1, 1>(v, x, out, rows, cols, fields, wk, ry, rx, edge, pad, lc.stream);
+        return run2d_fields<1, 1>(v, x, out, rows, cols, fields, wk, !w2d, ry, rx, edge, pad, lc.stream);
     if (ry == 2 && rx == 2)
-        return run2d_fields<2, 2>(v, x, out, rows, cols, fields, wk, ry, rx, edge, pad, lc.stream);
-    return run2d_fields<-1, -1>(v, x, out, rows, cols, fields, wk, ry, rx, edge, pad, lc.stream);
+        return run2d_fields<2, 2>(v, x, out, rows, cols, fields, wk, !w2d, ry, rx, edge, pad, lc.stream);
+    return run2d_fields<-1, -1>(v, x, out, rows, cols, fields, wk, !w2d, ry, rx, edge, pad, lc.stream);
 }
 
 }  // namespace skel
