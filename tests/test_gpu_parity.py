@@ -290,6 +290,36 @@ def test_mapoverlap2d(skel, oracle_mod, edge, ry, rx):
                 assert not bad.any(), (edge, ry, rx, shape, sep, v, np.argwhere(bad)[:5])
 
 
+# The marching-window variant's straight-line path runs for whole 256-column
+# strips of images with at least 4 rows: rows beyond the image ends and the
+# chunks beyond a row's two ends are mapped by the edge rule without branches.
+# These shapes put strips at both row ends (widths that are multiples of 256),
+# a ragged last strip (260, 772), images of 4 and 5 rows (rows wrapped or
+# clamped up to 4 away) and strips that end mid-strip in height.
+MARCH_SHAPES = [(4, 256), (5, 512), (37, 768), (70, 1024), (20, 260), (9, 772)]
+MARCH_RADII = [(1, 1), (2, 2), (4, 4), (3, 1), (0, 2), (4, 0)]
+
+
+@pytest.mark.parametrize("edge", list(EDGES))
+@pytest.mark.parametrize("ry,rx", MARCH_RADII)
+def test_mapoverlap2d_march_paths(skel, oracle_mod, edge, ry, rx):
+    v = skel.variant_index(skel.SK_MAPOVERLAP2D, "O2e_march")
+    wy = si.uniform_f32(2 * ry + 1, -1.0, 1.0, 41, 10 + ry)
+    wx = si.uniform_f32(2 * rx + 1, -1.0, 1.0, 41, 20 + rx)
+    w2d = si.uniform_f32((2 * ry + 1) * (2 * rx + 1), -1.0, 1.0, 41, 30).reshape(
+        2 * ry + 1, 2 * rx + 1)
+    for shape in MARCH_SHAPES:
+        x = si.uniform_f32(shape[0] * shape[1], -1.0, 1.0, 42, shape[1]).reshape(shape)
+        for kw in (dict(w2d=w2d), dict(wy=wy, wx=wx)):
+            ref, mag = oracle_mod.mapoverlap2d(x, ry, rx, edge=edge, pad=0.625, **kw)
+            out = skel.Container.empty(skel.F32, shape[0], shape[1])
+            skel.skel_mapoverlap2d(cont(skel, x), out, ry=ry, rx=rx, edge=EDGES[edge],
+                                   pad=0.625, variant=v, **kw)
+            got = out.to_numpy().reshape(shape).astype(np.float64)
+            bad = np.abs(got - ref) > 1e-6 * mag + 1e-30
+            assert not bad.any(), (edge, ry, rx, shape, list(kw), np.argwhere(bad)[:5])
+
+
 def test_mapoverlap_constant_field_and_impulse(skel):
     g = si.gaussian_weights(4, 2.0)
     sw = math.fsum(float(v) for v in g)
@@ -391,6 +421,27 @@ def test_scan_repeated_calls_reuse_descriptors(skel, oracle_mod):
 
 # ------------------------------------------- drawn tiny shapes (hypothesis)
 from hypothesis import HealthCheck, given, settings, strategies as st  # noqa: E402
+
+
+@settings(max_examples=40, deadline=None, suppress_health_check=list(HealthCheck))
+@given(rows=st.integers(1, 90), cols=st.sampled_from([252, 255, 256, 257, 260, 512, 516, 768]),
+       ry=st.integers(0, 4), rx=st.integers(0, 4), edge=st.sampled_from(list(EDGES)),
+       sep=st.booleans(), seed=st.integers(0, 1000))
+def test_mapoverlap2d_march_drawn_shapes(skel, oracle_mod, rows, cols, ry, rx, edge, sep, seed):
+    # widths around whole 256-column strips, where the marching window
+    # switches between its straight-line and general paths
+    img = si.uniform_f32(rows * cols, -1.0, 1.0, 43, seed).reshape(rows, cols)
+    wy = si.uniform_f32(2 * ry + 1, -1.0, 1.0, 43, 2000 + seed)
+    wx = si.uniform_f32(2 * rx + 1, -1.0, 1.0, 43, 3000 + seed)
+    kw = {"wy": wy, "wx": wx} if sep else {
+        "w2d": (wy.astype(np.float64)[:, None] * wx.astype(np.float64)[None, :]).astype(
+            np.float32)}
+    ref, mag = oracle_mod.mapoverlap2d(img, ry, rx, edge=edge, pad=-0.5, **kw)
+    out = skel.Container.empty(skel.F32, rows, cols)
+    skel.skel_mapoverlap2d(cont(skel, img), out, ry=ry, rx=rx, edge=EDGES[edge], pad=-0.5,
+                           variant=skel.variant_index(skel.SK_MAPOVERLAP2D, "O2e_march"), **kw)
+    got = out.to_numpy().reshape(rows, cols).astype(np.float64)
+    assert np.all(np.abs(got - ref) <= 1e-6 * mag + 1e-30), (rows, cols, ry, rx, edge, sep)
 
 
 @settings(max_examples=60, deadline=None, suppress_health_check=list(HealthCheck))
