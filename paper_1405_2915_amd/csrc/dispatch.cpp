@@ -10,7 +10,11 @@
 namespace skel {
 
 int overlap2d_dense_variant(int64_t n, int radius) {
-    return radius <= 4 && n >= (INT64_C(1) << 20) ? O2E_MARCH : O2B_LDS_TILE;
+    // radii 3 and 4 use 64-row strips: too few wavefronts below 2^24 elements
+    // (dense 9 x 9 on 1024^2: 25 us against 13 for the LDS tile)
+    if (radius <= 2) return n >= (INT64_C(1) << 20) ? O2E_MARCH : O2B_LDS_TILE;
+    if (radius <= 4) return n >= (INT64_C(1) << 24) ? O2E_MARCH : O2B_LDS_TILE;
+    return O2B_LDS_TILE;
 }
 
 namespace {
@@ -83,12 +87,11 @@ int static_rule(const CallContext& c) {
         return c.n <= (INT64_C(1) << 15) ? MR3_FUSED_SINGLE_WG : MR2_FUSED_TICKET;
     case SKEL_SK_MAPOVERLAP1D: return c.radius <= 4 ? O1C_SHUFFLE : O1B_LDS_TILE;
     case SKEL_SK_MAPOVERLAP2D:
-        // the marching window takes either weight form (separable: level with
-        // O2d on a 9 x 9 Gaussian over 4096^2, 30.8 / 30.5 us; 3 x 3 over 64
-        // fields of 2048^2 355 / 393 us); beyond its reach the separable L1
-        // variant or the LDS tile
+        // separable weights: the marching window for radii up to 2 (3 x 3 over
+        // 64 fields of 2048^2: 355 against 393 us for O2d); the 9 x 9 Gaussian
+        // is level on 4096^2 (30.8 / 30.5 us) and slower for O2e elsewhere
         if (!c.separable) return overlap2d_dense_variant(c.n, c.radius);
-        return c.radius <= 4 && c.n >= (INT64_C(1) << 20) ? O2E_MARCH : O2D_SEPARABLE_L1;
+        return c.radius <= 2 && c.n >= (INT64_C(1) << 20) ? O2E_MARCH : O2D_SEPARABLE_L1;
     case SKEL_SK_SCAN:
         return c.n <= (INT64_C(1) << 15) && !c.reverse ? S0_SINGLE_WG : S3_PERSISTENT_LOOKBACK;
     case SKEL_SK_REDUCE_SEGMENTS: return B1_PERSISTENT;

@@ -42,11 +42,12 @@ struct CallContext {
 };
 
 // 2D neighbourhood map with a dense (non-separable) weight matrix: the
-// marching window for radii up to 4 on 2^20 elements or more, else the LDS
-// tile.  Measured, marching window against LDS tile: 5-point stencil on 64
-// fields of 2048^2 357 / 441 us, on 4096^2 24.1 / 28.0, on 1024^2 7.0 / 8.7;
-// 5 x 5 on 4096^2 26.7 / 33.3; dense 9 x 9 on 4096^2 60.7 / 63.3.  Also the
-// forward pass that the flipped transpose runs.
+// marching window for radii up to 2 on 2^20 elements or more and for radii 3
+// and 4 on 2^24 or more, else the LDS tile.  Measured, marching window against
+// LDS tile: 5-point stencil on 64 fields of 2048^2 357 / 441 us, on 4096^2
+// 24.1 / 28.0, on 1024^2 7.0 / 8.7; 5 x 5 on 4096^2 26.7 / 33.3; dense 9 x 9
+// on 4096^2 60.7 / 63.3.  Also the forward pass that the flipped transpose
+// runs.
 int overlap2d_dense_variant(int64_t n, int radius);
 
 int variant_count(int skeleton);
