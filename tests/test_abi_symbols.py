@@ -60,3 +60,23 @@ def test_calls_without_init_fail_cleanly():
     assert st == skel.E_NOINIT
     assert b"skel_init" in lib.skel_last_error()
     assert lib.skel_reduce(0, None, None, -1, None) == skel.E_NOINIT
+
+
+def test_unloadable_library_raises_import_error(tmp_path):
+    """A library the dynamic loader refuses (here: an undefined symbol, as a
+    half-finished rebuild leaves it) turns into ImportError, which the package
+    import tolerates so that the build step inside it can still run."""
+    import paper_1405_2915_amd as skel
+    src = tmp_path / "stale.c"
+    src.write_text("extern int symbol_from_elsewhere(void);\n"
+                   "int skel_init(void) { return symbol_from_elsewhere(); }\n")
+    so = tmp_path / "libstale.so"
+    subprocess.run(["gcc", "-shared", "-fPIC", "-Wl,-z,now", "-o", str(so), str(src)],
+                   check=True)
+    saved = skel._lib
+    skel._lib = None
+    try:
+        with pytest.raises(ImportError, match="older than the sources"):
+            skel.load_library(str(so))
+    finally:
+        skel._lib = saved
