@@ -17,6 +17,10 @@ int overlap2d_dense_variant(int64_t n, int radius) {
     return O2B_LDS_TILE;
 }
 
+int overlap2d_separable_variant(int64_t n, int radius) {
+    return radius <= 2 && n >= (INT64_C(1) << 20) ? O2E_MARCH : O2D_SEPARABLE_L1;
+}
+
 namespace {
 
 const char* const kMap[] = {"M0_scalar", "M1_vec4", "M2_vec4x4_nt"};
@@ -87,11 +91,8 @@ int static_rule(const CallContext& c) {
         return c.n <= (INT64_C(1) << 15) ? MR3_FUSED_SINGLE_WG : MR2_FUSED_TICKET;
     case SKEL_SK_MAPOVERLAP1D: return c.radius <= 4 ? O1C_SHUFFLE : O1B_LDS_TILE;
     case SKEL_SK_MAPOVERLAP2D:
-        // separable weights: the marching window for radii up to 2 (3 x 3 over
-        // 64 fields of 2048^2: 355 against 393 us for O2d); the 9 x 9 Gaussian
-        // is level on 4096^2 (30.8 / 30.5 us) and slower for O2e elsewhere
-        if (!c.separable) return overlap2d_dense_variant(c.n, c.radius);
-        return c.radius <= 2 && c.n >= (INT64_C(1) << 20) ? O2E_MARCH : O2D_SEPARABLE_L1;
+        return c.separable ? overlap2d_separable_variant(c.n, c.radius)
+                           : overlap2d_dense_variant(c.n, c.radius);
     case SKEL_SK_SCAN:
         return c.n <= (INT64_C(1) << 15) && !c.reverse ? S0_SINGLE_WG : S3_PERSISTENT_LOOKBACK;
     case SKEL_SK_REDUCE_SEGMENTS: return B1_PERSISTENT;

@@ -426,8 +426,8 @@ skel_status launch_overlap2d_adjoint(int v, const float* g, float* dx, int64_t r
         float fy[2 * SKEL_MAX_RADIUS_2D + 1], fx[2 * SKEL_MAX_RADIUS_2D + 1];
         for (int a = 0; a < ny; ++a) fy[a] = wy[ny - 1 - a];
         for (int b = 0; b < nx; ++b) fx[b] = wx[nx - 1 - b];
-        e = launch_overlap2d(O2D_SEPARABLE_L1, g, dx, rows, cols, fields, nullptr, fy, fx, ry,
-                             rx, fe, 0.0f, lc);
+        e = launch_overlap2d(overlap2d_separable_variant(fields * img, ry > rx ? ry : rx), g, dx,
+                             rows, cols, fields, nullptr, fy, fx, ry, rx, fe, 0.0f, lc);
     }
     if (e != SKEL_OK || edge != SKEL_EDGE_CLAMP) return e;
     const int taps = ny * nx;

@@ -199,6 +199,27 @@ def test_mapoverlap2d_backward(skel, oracle_mod, edge, ry, rx):
                                        np.argwhere(bad)[:5])
 
 
+@pytest.mark.parametrize("edge", list(EDGES))
+@pytest.mark.parametrize("ry,rx", [(1, 1), (2, 2), (0, 2)])
+def test_mapoverlap2d_backward_large(skel, oracle_mod, edge, ry, rx):
+    # 2^20 elements and more: the flipped transpose runs the marching-window
+    # forward kernel (radius <= 2) for either weight form
+    w2d = si.uniform_f32((2 * ry + 1) * (2 * rx + 1), -1.0, 1.0, 19, 20).reshape(
+        2 * ry + 1, 2 * rx + 1)
+    wy = si.uniform_f32(2 * ry + 1, 0.0, 1.0, 19, 21)
+    wx = si.uniform_f32(2 * rx + 1, -1.0, 1.0, 19, 22)
+    for rows, cols in [(1024, 1024), (1040, 1032)]:
+        g = si.uniform_f32(rows * cols, -1.0, 1.0, 19, cols).reshape(rows, cols)
+        for kw in ({"w2d": w2d}, {"wy": wy, "wx": wx}):
+            ref, mag = oracle_mod.mapoverlap2d_adjoint(g, ry, rx, edge=edge, **kw)
+            out = skel.Container.empty(skel.F32, rows, cols)
+            skel.skel_mapoverlap2d_backward(cont(skel, g), out, ry=ry, rx=rx, edge=EDGES[edge],
+                                            **kw)
+            bad = np.abs(out.to_numpy().reshape(rows, cols).astype(np.float64) - ref) \
+                > 1e-6 * mag + 1e-30
+            assert not bad.any(), (edge, ry, rx, rows, cols, list(kw), np.argwhere(bad)[:5])
+
+
 # ----------------------------------------------------------- autograd layer
 def test_autograd_functions(skel, oracle_mod):
     import torch
