@@ -321,7 +321,9 @@ def field_layer(skel, torch, reps=5):
     from an upstream gradient: one reverse row-wise Scan and one batched-field
     stencil transpose.  Each part is captured once into a HIP graph and
     replayed (HIP events on the replay stream); every part moves 8 algorithmic
-    bytes per element (f32 in, f32 out)."""
+    bytes per element (f32 in, f32 out).  For comparison, the forward stencil
+    is also timed with the LDS-tile variant forced (`compare_*`, not part of
+    the pass totals)."""
     import synth_inputs as si
     dev = torch.device("cuda", 0)
     gen = torch.Generator(device=dev)
@@ -347,6 +349,9 @@ def field_layer(skel, torch, reps=5):
                                                               skel.SUM),
             "backward_stencil": lambda: skel.skel_mapoverlap2d_fields_backward(
                 cgy, cgx, FIELDS, w2d=w5, edge=skel.EDGE_CLAMP),
+            "compare_forward_stencil_O2b_lds_tile": lambda: skel.skel_mapoverlap2d_fields(
+                cx, cy, FIELDS, w2d=w5, edge=skel.EDGE_CLAMP,
+                variant=skel.variant_index(skel.SK_MAPOVERLAP2D, "O2b_lds_tile")),
         }
         for fn in parts.values():  # sizes the stream's workspace outside the captures
             fn()
@@ -375,6 +380,10 @@ def field_layer(skel, torch, reps=5):
         us = sum(v["us"] for k, v in res.items() if k.startswith(p))
         res[p] = {"us": round(us, 1), "GBps": round(2 * 8 * x.numel() / (us * 1e-6) / 1e9, 1)}
     res["fields"] = [FIELDS, FIELD_H, FIELD_W]
+    n = x.numel()
+    res["forward_stencil_variant"] = skel.skel_variant_name(
+        skel.SK_MAPOVERLAP2D, skel.skel_select_variant(skel.SK_MAPOVERLAP2D, skel.F32, n,
+                                                       FIELD_H, FIELD_W, aux=2 * 1))
     return res
 
 
