@@ -532,13 +532,14 @@ constexpr int kMarchCols = 4 * dev::kWave;    // columns per strip
 constexpr int kMarchMaxR = 4;                 // radius reach of one neighbour lane
 // With a run-time column radius (radii other than 1, 2 or 4 in both
 // directions) the tap loop is longer, and whole-strip chunks spill; those
-// instances load about eight rows at a time.
+// instances load about eight rows at a time (one ring of 7 for radius 3,
+// where two rings spill).
 template <int RY, bool DYN>
 struct March {
     static constexpr int NW = 2 * RY + 1;                       // ring slots
     static constexpr int rows = RY <= 2 ? 16 : 64;              // output rows per strip
-    static constexpr int chunk = DYN ? NW * ((8 + NW - 1) / NW)  // rows loaded at once
-                               : RY <= 2 ? rows + 2 * RY : 2 * NW;
+    static constexpr int chunk = DYN ? (RY == 3 ? NW : NW * ((8 + NW - 1) / NW))
+                               : RY <= 2 ? rows + 2 * RY : 2 * NW;  // rows loaded at once
     static_assert(chunk % NW == 0 && (rows + 2 * RY) % chunk == 0, "whole chunks per strip");
 };
 
@@ -679,8 +680,56 @@ __global__ __launch_bounds__(kBlock) void ov2_march(const float* x, float* out, 
                                   true);
             }
         }
+    } else if (rows >= kMarchMaxR) {
+        // a strip past a ragged row end, or rows not 16-byte aligned: the
+        // column rule is the same for every row, so each lane maps its four
+        // columns and the edge chunk once; rows are then straight-line element
+        // loads from valid addresses, with the pad selected afterwards
+        int64_t ci[4], ei[4];
+        bool cp[4], ep[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            int64_t cc;
+            cp[q] = !border(j + q, cols, edge, cc);
+            ci[q] = cp[q] ? 0 : cc;
+            ep[q] = !border(je + q, cols, edge, cc);
+            ei[q] = ep[q] ? 0 : cc;
+        }
+        const bool vec_store = aligned && j + 4 <= cols;
+        for (; m0 + CH <= nin; m0 += CH) {
+            float cv[CH][4], ev[CH][4];
+            bool in[CH];
+#pragma unroll
+            for (int t = 0; t < CH; ++t) {
+                const int64_t k = i0 - RY + m0 + t;
+                in[t] = k >= 0 && k < rows;
+                const int64_t kk = in[t] ? k
+                                 : edge == SKEL_EDGE_CYCLIC ? (k < 0 ? k + rows : k - rows)
+                                 : (k < 0 ? 0 : rows - 1);
+                const float* rp = x + kk * cols;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    cv[t][q] = rp[ci[q]];
+                    ev[t][q] = rp[ei[q]];
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < CH; ++t) {
+                const bool padrow = edge == SKEL_EDGE_CONST && !in[t];
+                float c[4], e[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    c[q] = padrow || cp[q] ? pad : cv[t][q];
+                    e[q] = padrow || ep[q] ? pad : ev[t][q];
+                }
+                march_row<RY, MX, SEP>(acc, t % NW, m0 + t, f32x4{c[0], c[1], c[2], c[3]},
+                                       f32x4{e[0], e[1], e[2], e[3]}, w, rx, out, i0, j, cols,
+                                       vec_store);
+            }
+        }
     }
-    // general path: the remaining rows, strips at the row ends, ragged widths
+    // general path: the last strip of an image whose height is not a whole
+    // number of strips, and images of fewer than four rows
     for (; m0 < nin; m0 += NW) {
 #pragma unroll
         for (int t = 0; t < NW; ++t) {
