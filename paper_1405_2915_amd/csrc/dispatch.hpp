@@ -42,17 +42,18 @@ struct CallContext {
 };
 
 // 2D neighbourhood map with a dense (non-separable) weight matrix: the
-// marching window for radii up to 2 on 2^20 elements or more and for radii 3
-// and 4 on 2^24 or more, else the LDS tile.  Measured, marching window against
-// LDS tile: 5-point stencil on 64 fields of 2048^2 357 / 441 us, on 4096^2
-// 24.1 / 28.0, on 1024^2 7.0 / 8.7; 5 x 5 on 4096^2 26.7 / 33.3; dense 9 x 9
-// on 4096^2 60.7 / 63.3.  Also the forward pass that the flipped transpose
+// marching window for radii up to 2 on 2^20 elements or more, else the LDS
+// tile.  Measured with the Infinity Cache evicted before each call, marching
+// window against LDS tile: 5-point stencil on 64 fields of 2048^2 357 / 426
+// us, on 16384^2 360 / 443, on 2048^2 8.6 / 13.0 (on 8192^2 96 / 84); 5 x 5
+// on 16384^2 379 / 452.  Dense 9 x 9 loses (4096^2: 96 / 68 us; its 64-row
+// strips or shorter ones).  Also the forward pass that the flipped transpose
 // runs.
 int overlap2d_dense_variant(int64_t n, int radius);
 // The same with the weights given as factors: the marching window for radii up
-// to 2 on 2^20 elements or more (3 x 3 over 64 fields of 2048^2: 355 against
-// 393 us), else the separable L1 variant (the 9 x 9 Gaussian is level on
-// 4096^2, 30.8 / 30.5 us, and slower for the marching window elsewhere).
+// to 2 on 2^20 elements or more (3 x 3 over 64 fields of 2048^2: 357 against
+// 388 us, caches evicted), else the separable L1 variant (the 9 x 9 Gaussian:
+// level on 4096^2, slower for the marching window elsewhere).
 int overlap2d_separable_variant(int64_t n, int radius);
 
 int variant_count(int skeleton);

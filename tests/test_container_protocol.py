@@ -332,16 +332,15 @@ def test_static_plan(rt):
     assert sel(SK_SCAN, 100, I32) == "S0_single_wg"
     assert sel(SK_SCAN, 1 << 27, I32) == "S3_persistent_lookback"
     # aux = separable + 2 * radius: the marching window up to radius 2 on large
-    # images (either weight form) and for dense radii 3 and 4 from 2^24, else
-    # the separable L1 variant or, for dense weights, the LDS tile (separable
-    # variants not selectable)
+    # images (either weight form), else the separable L1 variant or, for dense
+    # weights, the LDS tile (separable variants not selectable)
     assert sel(SK_OV2, 1 << 24, F32, 1) == "O2e_march"
     assert sel(SK_OV2, 1 << 24, F32, 1 + 2 * 5) == "O2d_separable_l1"
     assert sel(SK_OV2, 1 << 18, F32, 1 + 2 * 4) == "O2d_separable_l1"
     assert sel(SK_OV2, 1 << 24, F32, 2 * 1) == "O2e_march"
     assert sel(SK_OV2, 1 << 28, F32, 2 * 2) == "O2e_march"
-    assert sel(SK_OV2, 1 << 24, F32, 2 * 4) == "O2e_march"
-    assert sel(SK_OV2, 1 << 22, F32, 2 * 4) == "O2b_lds_tile"
+    assert sel(SK_OV2, 1 << 24, F32, 2 * 4) == "O2b_lds_tile"
+    assert sel(SK_OV2, 1 << 22, F32, 2 * 3) == "O2b_lds_tile"
     assert sel(SK_OV2, 1 << 20, F32, 2 * 2) == "O2e_march"
     assert sel(SK_OV2, 1 << 24, F32, 2 * 5) == "O2b_lds_tile"
     assert sel(SK_OV2, 1 << 18, F32, 2 * 1) == "O2b_lds_tile"
