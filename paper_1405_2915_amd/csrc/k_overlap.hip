@@ -524,10 +524,11 @@ __global__ __launch_bounds__(kBlock) void ov2_sep_l1(const float* x, float* out,
 // What bounds it is how many rows a wavefront has in flight: all rows of a
 // chunk are loaded before the first is used.  Measured (5-point stencil on
 // 64 fields of 2048^2; strip rows / chunk rows): 32/9 394 us, 16/9 378,
-// 64/9 397, 32/18 433, 16/18 (the whole strip) 358, O2b 428; on 4096^2
-// 16/18 takes 24 us against 28 for O2b.  A dense 9 x 9 needs 24 rows for a
-// 16-row strip, more than the registers hold: there 64-row strips in chunks
-// of 18 rows measured best (67 us on 4096^2, 16-row strips 90).
+// 64/9 397, 32/18 433, 16/18 (the whole strip) 358, O2b 428.  A dense 9 x 9
+// needs 24 rows for a 16-row strip, more than the registers hold: 64-row
+// strips in chunks of 18 rows are used there (on 4096^2, back to back with
+// the image in the Infinity Cache: 67 us, 16-row strips 90; evicted, all of
+// them lose to O2b, which the plan therefore keeps for radii above 2).
 constexpr int kMarchCols = 4 * dev::kWave;    // columns per strip
 constexpr int kMarchMaxR = 4;                 // radius reach of one neighbour lane
 // With a run-time column radius (radii other than 1, 2 or 4 in both
