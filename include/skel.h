@@ -339,6 +339,28 @@ skel_status skel_reduce_segments(skel_reduce_op op, skel_container *in,
                                  skel_container *offsets, skel_container *out,
                                  int variant, void *stream);
 
+/* Allocation-free Scan, for callers that cannot allocate device memory:
+ * code being captured into a HIP graph, tight serving loops, harnesses that
+ * forbid hipMalloc.  It computes exactly what skel_scan computes for the
+ * forward kinds (SKEL_INCLUSIVE, SKEL_EXCLUSIVE; the reverse kinds give
+ * SKEL_E_UNSUPPORTED), with the same type pairs and ops, on plain device
+ * pointers instead of containers: in holds n elements of din, out receives n
+ * elements of dout; both are device memory owned by the caller, 16-byte
+ * aligned; out equals in (same types) or does not overlap it.  The work is
+ * enqueued on `stream` and runs the reduce-then-scan variant S1, whose
+ * per-tile totals live in a library array of 256 KiB in device memory, one
+ * per GPU, held until the process ends; nothing is allocated or freed by the
+ * call, and nothing needs clearing between calls (every total is written
+ * before it is read).  Limit: n <= 2^30 elements for 4-byte inputs (I32,
+ * F32) and 2^29 for I64 inputs (32768 tiles); larger n gives SKEL_E_SHAPE
+ * before anything is enqueued.  Every call on one GPU shares that GPU's
+ * array: calls that may run at the same time on one GPU (on different
+ * streams without an ordering between them) race and give wrong results;
+ * calls on one stream are ordered and safe.  Requires skel_init. */
+skel_status skel_scan_noalloc(const void *in, skel_dtype din, void *out, skel_dtype dout,
+                              int64_t n, skel_scan_kind kind, skel_reduce_op op,
+                              void *stream);
+
 /* --------------------------------------------------------- adjoints ---- */
 /* Reverse-mode derivatives for a scalar loss L, given the upstream gradient
  * g = dL/d(out) of a forward call.  All operands are F32 containers; outputs

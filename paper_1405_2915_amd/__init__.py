@@ -123,6 +123,7 @@ def load_library(path: str = LIB_PATH):
         "skel_mapoverlap2d": (st, [vp, vp, fp, fp, fp, i, i, i, C.c_float, i, vp]),
         "skel_scan": (st, [vp, vp, i, i, i, vp]),
         "skel_scan_rows": (st, [vp, vp, i, i, i, vp]),
+        "skel_scan_noalloc": (st, [vp, i, vp, i, i64, i, i, vp]),
         "skel_reduce_segments": (st, [i, vp, vp, vp, i, vp]),
         "skel_container_wrap_device": (st, [i, i64, i64, vp, vp, C.POINTER(vp)]),
         "skel_container_acquire_range": (st, [vp, i, i, i64, i64, vp, C.POINTER(vp)]),
@@ -598,6 +599,16 @@ def skel_scan(inp: Container, out: Container, kind: int = INCLUSIVE, op: int = S
               variant: int = VARIANT_AUTO, stream=None) -> None:
     _check(_L().skel_scan(_h(inp), _h(out), kind, op, variant, _stream(stream)),
            "skel_scan")
+
+
+def skel_scan_noalloc(in_ptr: int, din: int, out_ptr: int, dout: int, n: int,
+                      kind: int = INCLUSIVE, op: int = SUM, stream=None) -> None:
+    """Scan of n elements at device address in_ptr into out_ptr (caller-owned
+    device memory, e.g. tensors' data_ptr()) that allocates nothing: the
+    library's fixed per-GPU array holds the tile totals.  Forward kinds only;
+    at most 2^30 elements (2^29 for int64 input)."""
+    _check(_L().skel_scan_noalloc(C.c_void_p(in_ptr), din, C.c_void_p(out_ptr), dout, int(n),
+                                  kind, op, _stream(stream)), "skel_scan_noalloc")
 
 
 def skel_scan_rows(inp: Container, out: Container, kind: int = INCLUSIVE, op: int = SUM,

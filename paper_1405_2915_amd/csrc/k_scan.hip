@@ -39,6 +39,8 @@
 // clearing pass are needed; the host gives every call a fresh epoch.  The
 // look-back wait is bounded: on expiry the kernel raises a flag that
 // skel_sync reports, and finishes (with wrong values) instead of hanging.
+#include <mutex>
+
 #include "kcommon.hpp"
 #include "dispatch.hpp"
 #include "kepoch.hpp"
@@ -548,6 +550,21 @@ __global__ __launch_bounds__(kWave) void scan_rows_scalar(const typename P::in_t
 }
 
 // --------------------------------------------------------------- launchers
+// S1's three launches; `sums` holds one accumulator per tile (written by the
+// first launch before the others read it, so it needs no clearing)
+template <class P>
+skel_status reduce_then_scan(const typename P::in_t* in, typename P::out_t* out, int64_t n,
+                             int excl, typename P::acc_t* sums, hipStream_t st) {
+    const int64_t ntiles = (n + P::kTile - 1) / P::kTile;
+    skel_status e;
+    scan_tile_totals<P><<<(unsigned)ntiles, P::kBlock, 0, st>>>(in, n, sums);
+    if ((e = launch_check("scan_tile_totals")) != SKEL_OK) return e;
+    scan_tile_offsets<P><<<1, 1024, 0, st>>>(sums, ntiles);
+    if ((e = launch_check("scan_tile_offsets")) != SKEL_OK) return e;
+    scan_tile_apply<P><<<(unsigned)ntiles, P::kBlock, 0, st>>>(in, out, n, sums, excl);
+    return launch_check("scan_tile_apply");
+}
+
 template <int DIN, int DOUT, int OP>
 skel_status scan_typed(int v, int kind, const void* x, void* y, int64_t n, LaunchCtx& lc) {
     using P = SP<DIN, DOUT, OP>;
@@ -570,13 +587,7 @@ skel_status scan_typed(int v, int kind, const void* x, void* y, int64_t n, Launc
         void* mem = nullptr;
         skel_status e = ws_scratch(lc, (size_t)ntiles * sizeof(acc_t), &mem);
         if (e != SKEL_OK) return e;
-        acc_t* sums = static_cast<acc_t*>(mem);
-        scan_tile_totals<P><<<(unsigned)ntiles, P::kBlock, 0, st>>>(in, n, sums);
-        if ((e = launch_check("scan_tile_totals")) != SKEL_OK) return e;
-        scan_tile_offsets<P><<<1, 1024, 0, st>>>(sums, ntiles);
-        if ((e = launch_check("scan_tile_offsets")) != SKEL_OK) return e;
-        scan_tile_apply<P><<<(unsigned)ntiles, P::kBlock, 0, st>>>(in, out, n, sums, excl);
-        return launch_check("scan_tile_apply");
+        return reduce_then_scan<P>(in, out, n, excl, static_cast<acc_t*>(mem), st);
     }
     case S3_PERSISTENT_LOOKBACK: {
         void* status = nullptr;
@@ -664,3 +675,124 @@ skel_status launch_scan(int v, int kind, int op, skel_dtype din, skel_dtype dout
 }
 
 }  // namespace skel
+
+// ------------------------------------------------- allocation-free Scan ----
+// skel_scan_noalloc runs S1 with its tile totals in a file-scope device array
+// instead of the stream's workspace, so a call allocates nothing.  Every GPU
+// the library runs on holds its own copy of the array (until the process
+// ends); host code reaches it only through the address hipGetSymbolAddress
+// returns with that device current, never through the array's name.
+namespace skel {
+
+constexpr int64_t kNoAllocTiles = 32768;  // tile totals the array holds (8 bytes each)
+static __device__ __align__(256) unsigned long long scratch[kNoAllocTiles];  // 256 KiB
+
+namespace {
+
+constexpr int kNoAllocMaxDevices = 64;
+void* g_scratch_addr[kNoAllocMaxDevices];  // per device ordinal
+std::mutex g_scratch_mu;
+
+skel_status scratch_address(int device, void** out) {
+    if (device < 0 || device >= kNoAllocMaxDevices)
+        return fail(SKEL_E_INVAL, "device %d beyond the %d the allocation-free scan tracks",
+                    device, kNoAllocMaxDevices);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_addr[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || p == nullptr) {
+            (void)hipGetLastError();
+            return fail(SKEL_E_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", device,
+                        hipGetErrorString(e));
+        }
+        g_scratch_addr[device] = p;
+    }
+    *out = g_scratch_addr[device];
+    return SKEL_OK;
+}
+
+template <int DIN, int DOUT, int OP>
+skel_status noalloc_typed(const void* x, void* y, int64_t n, int excl, void* sums,
+                          hipStream_t st) {
+    using P = SP<DIN, DOUT, OP>;
+    static_assert(sizeof(typename P::acc_t) <= sizeof(scratch[0]), "one array word per tile");
+    return reduce_then_scan<P>(static_cast<const typename P::in_t*>(x),
+                               static_cast<typename P::out_t*>(y), n, excl,
+                               static_cast<typename P::acc_t*>(sums), st);
+}
+
+template <int DIN, int DOUT>
+skel_status noalloc_op(int op, const void* x, void* y, int64_t n, int excl, void* sums,
+                       hipStream_t st) {
+    switch (op) {
+    case SKEL_SUM: return noalloc_typed<DIN, DOUT, SKEL_SUM>(x, y, n, excl, sums, st);
+    case SKEL_MIN: return noalloc_typed<DIN, DOUT, SKEL_MIN>(x, y, n, excl, sums, st);
+    default: return noalloc_typed<DIN, DOUT, SKEL_MAX>(x, y, n, excl, sums, st);
+    }
+}
+
+// the scan tile of an input type: what bounds n for a given array size
+int64_t noalloc_tile(skel_dtype din) {
+    return din == SKEL_I64 ? SP<SKEL_I64, SKEL_I64, SKEL_SUM>::kTile
+                           : SP<SKEL_I32, SKEL_I32, SKEL_SUM>::kTile;
+}
+
+}  // namespace
+
+skel_status scan_noalloc_setup(int device) {
+    void* p = nullptr;
+    return scratch_address(device, &p);
+}
+
+}  // namespace skel
+
+using namespace skel;
+
+extern "C" skel_status skel_scan_noalloc(const void* in, skel_dtype din, void* out,
+                                         skel_dtype dout, int64_t n, skel_scan_kind kind,
+                                         skel_reduce_op op, void* stream) {
+    if (!rt().initialized) return fail(SKEL_E_NOINIT, "skel_init has not been called");
+    if (kind == SKEL_REVERSE_INCLUSIVE || kind == SKEL_REVERSE_EXCLUSIVE)
+        return fail(SKEL_E_UNSUPPORTED, "the allocation-free scan runs the forward kinds only");
+    if (kind != SKEL_INCLUSIVE && kind != SKEL_EXCLUSIVE)
+        return fail(SKEL_E_INVAL, "unknown scan kind %d", (int)kind);
+    if (op < SKEL_SUM || op > SKEL_MAX) return fail(SKEL_E_INVAL, "unknown scan op %d", (int)op);
+    const bool types_ok = (din == SKEL_I32 && (dout == SKEL_I32 || dout == SKEL_I64)) ||
+                          (din == SKEL_I64 && dout == SKEL_I64) ||
+                          (din == SKEL_F32 && dout == SKEL_F32);
+    if (!types_ok)
+        return fail(SKEL_E_DTYPE, "Scan %s -> %s not supported",
+                    dtype_valid(din) ? dtype_name(din) : "?",
+                    dtype_valid(dout) ? dtype_name(dout) : "?");
+    if (n < 0) return fail(SKEL_E_INVAL, "negative element count %lld", (long long)n);
+    if (n == 0) return SKEL_OK;
+    const int64_t tile = noalloc_tile(din);
+    if ((n + tile - 1) / tile > kNoAllocTiles)
+        return fail(SKEL_E_SHAPE,
+                    "n = %lld exceeds the allocation-free maximum of %lld elements for %s "
+                    "input (%lld tiles of %lld)", (long long)n,
+                    (long long)(kNoAllocTiles * tile), dtype_name(din),
+                    (long long)kNoAllocTiles, (long long)tile);
+    if (!in || !out) return fail(SKEL_E_INVAL, "null data pointer");
+    if (reinterpret_cast<uintptr_t>(in) % 16 != 0 || reinterpret_cast<uintptr_t>(out) % 16 != 0)
+        return fail(SKEL_E_INVAL, "in and out must be 16-byte aligned");
+    const uintptr_t a0 = reinterpret_cast<uintptr_t>(in), b0 = reinterpret_cast<uintptr_t>(out);
+    const uintptr_t a1 = a0 + (uintptr_t)n * dtype_size(din);
+    const uintptr_t b1 = b0 + (uintptr_t)n * dtype_size(dout);
+    if (a0 < b1 && b0 < a1 && !(a0 == b0 && din == dout))
+        return fail(SKEL_E_INVAL, "out must equal in (same types) or not overlap it");
+    int device = -1;
+    skel_status st = hip_check(hipGetDevice(&device), "hipGetDevice");
+    if (st != SKEL_OK) return st;
+    void* sums = nullptr;
+    st = scratch_address(device, &sums);
+    if (st != SKEL_OK) return st;
+    const int excl = kind == SKEL_EXCLUSIVE ? 1 : 0;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (din == SKEL_I32 && dout == SKEL_I32)
+        return noalloc_op<SKEL_I32, SKEL_I32>(op, in, out, n, excl, sums, s);
+    if (din == SKEL_I32) return noalloc_op<SKEL_I32, SKEL_I64>(op, in, out, n, excl, sums, s);
+    if (din == SKEL_I64) return noalloc_op<SKEL_I64, SKEL_I64>(op, in, out, n, excl, sums, s);
+    return noalloc_op<SKEL_F32, SKEL_F32>(op, in, out, n, excl, sums, s);
+}

@@ -108,6 +108,9 @@ skel_status launch_scan(int variant, int kind, int op, skel_dtype din,
 // vec: row starts are 16-byte aligned for both types (16-byte accesses)
 skel_status launch_scan_rows(int kind, int op, skel_dtype din, skel_dtype dout, const void* x,
                              void* y, int64_t rows, int64_t cols, bool vec, LaunchCtx& lc);
+// device address of the allocation-free scan's array on `device` (k_scan.hip),
+// looked up once per device with that device current (skel_init)
+skel_status scan_noalloc_setup(int device);
 // adjoints (k_grad.hip); g_broadcast: g holds one value for every element
 skel_status launch_map_backward(int op, float p0, float p1, const float* x, const float* y,
                                 const float* g, bool g_broadcast, float* dx, float* dy,

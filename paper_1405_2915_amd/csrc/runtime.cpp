@@ -307,6 +307,8 @@ skel_status skel_init(int device, const skel_allocator* alloc) {
     g_dev.lds_bytes = (int)prop.sharedMemPerBlock;
     g_dev.wave = prop.warpSize;
     g_dev.max_threads = prop.maxThreadsPerBlock;
+    st = scan_noalloc_setup(device);
+    if (st != SKEL_OK) return st;
     rt().backend = &g_hip_backend;
     rt().device = device;
     rt().allocator = alloc ? *alloc : skel_allocator{nullptr, nullptr, nullptr};
