@@ -101,6 +101,14 @@ def _load():
         fn = getattr(lib, nm)
         fn.argtypes = [tin, I64, C.c_int, C.c_int, tout]
         fn.restype = C.c_int
+    lib.oracle_chain_f32.argtypes = [C.c_int, vp, C.c_int, f32p, I64, I64, I64, vp, vp, vp,
+                                     C.c_int, C.c_int, C.c_int, C.c_float,
+                                     C.POINTER(C.c_double)]
+    lib.oracle_chain_f32.restype = C.c_double
+    lib.oracle_chain_grad_f32.argtypes = [C.c_int, vp, C.c_int, f32p, I64, I64, I64, vp, vp,
+                                          vp, C.c_int, C.c_int, C.c_int, C.c_double, f64p,
+                                          vp, vp, vp]
+    lib.oracle_chain_grad_f32.restype = C.c_int
     lib.oracle_scan_f32.argtypes = [f32p, I64, C.c_int, C.c_int, f64p, vp]
     lib.oracle_scan_f32.restype = C.c_int
     _lib = lib
@@ -367,3 +375,48 @@ def scan_rows(x, kind: str = "inclusive", op: str = "sum", out_dtype=None):
     if not res:
         return np.empty(x.shape, dtype=np.int64 if out_dtype is not None else x.dtype)
     return np.stack(res).reshape(x.shape)
+
+
+def chain(map_op: str, params, x, ry: int, rx: int, w2d=None, wy=None, wx=None,
+          edge: str = "clamp", pad: float = 0.0):
+    """(loss, mag) of the call chain Map -> MapOverlap 2D -> Reduce SUM over
+    x of shape (fields, rows, cols) (or (rows, cols): one field), binary64."""
+    lib = _load()
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    if x.ndim == 2:
+        x = x.reshape(1, *x.shape)
+    assert x.ndim == 3
+    w2d, wy, wx = _weights2d(w2d, wy, wx, ry, rx)
+    p, np_ = _params(params)
+    mag = C.c_double(0.0)
+    v = lib.oracle_chain_f32(MAP_OPS[map_op], _ptr(p), np_, x.reshape(-1), x.shape[0],
+                             x.shape[1], x.shape[2], _ptr(w2d), _ptr(wy), _ptr(wx), ry, rx,
+                             EDGES[edge], pad, C.byref(mag))
+    if np.isnan(v) and not np.isnan(x).any():
+        raise ValueError("oracle chain: bad arguments")
+    return float(v), float(mag.value)
+
+
+def chain_grad(map_op: str, params, x, ry: int, rx: int, g1: float = 1.0, w2d=None, wy=None,
+               wx=None, edge: str = "clamp"):
+    """Reverse mode through the chain: (dx, dx_mag, dparams, dparams_mag),
+    binary64, dx shaped like x."""
+    lib = _load()
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    shape = x.shape
+    if x.ndim == 2:
+        x = x.reshape(1, *x.shape)
+    assert x.ndim == 3
+    w2d, wy, wx = _weights2d(w2d, wy, wx, ry, rx)
+    p, np_ = _params(params)
+    dx = np.empty(x.size, dtype=np.float64)
+    dxm = np.empty(x.size, dtype=np.float64)
+    dp = np.zeros(max(np_, 1), dtype=np.float64)
+    dpm = np.zeros(max(np_, 1), dtype=np.float64)
+    rc = lib.oracle_chain_grad_f32(MAP_OPS[map_op], _ptr(p), np_, x.reshape(-1), x.shape[0],
+                                   x.shape[1], x.shape[2], _ptr(w2d), _ptr(wy), _ptr(wx), ry,
+                                   rx, EDGES[edge], float(g1), dx, _ptr(dxm), _ptr(dp),
+                                   _ptr(dpm))
+    if rc != 0:
+        raise ValueError("oracle chain_grad: bad arguments")
+    return dx.reshape(shape), dxm.reshape(shape), dp[:np_], dpm[:np_]

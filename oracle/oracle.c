@@ -14,6 +14,7 @@
 
 #include <math.h>
 #include <stddef.h>
+#include <stdlib.h>
 #include <stdint.h>
 #include <string.h>
 
@@ -543,5 +544,127 @@ int oracle_mapoverlap2d_adjoint_f32(const float *g, int64_t rows, int64_t cols,
             }
         }
     }
+    return 0;
+}
+
+/* -------------------------------------------------- call chain ---- */
+
+/* The call chain Map -> MapOverlap 2D -> Reduce SUM (a composition of three
+ * skeleton calls, Section V; each step as defined above, Section III), over
+ * `fields` images of rows x cols stored back to back, each mapped with its own
+ * borders:
+ *     t = f(x)                       element by element, binary64
+ *     s[f][i][j] = sum_ab W[a][b] * t[f][e(i+a-ry)][e(j+b-rx)]  (pad outside)
+ *     loss = sum over f, i, j of s[f][i][j]          sequential, index order
+ * No rounding between the steps.  *mag receives sum |W[a][b] * read value|
+ * over every term, the magnitude the result's error is measured against. */
+double oracle_chain_f32(int map_op, const double *params, int nparams, const float *x,
+                        int64_t fields, int64_t rows, int64_t cols, const float *w2d,
+                        const float *wy, const float *wx, int ry, int rx, int edge,
+                        float pad, double *mag)
+{
+    double probe;
+    if (elem_fn(map_op, params, nparams, 0.0, 0.0, &probe) != 0 || needs_y(map_op))
+        return NAN;
+    if (ry < 0 || rx < 0 || (w2d == NULL && (wy == NULL || wx == NULL))) return NAN;
+    if (edge != ORC_EDGE_CLAMP && edge != ORC_EDGE_CONST && edge != ORC_EDGE_CYCLIC)
+        return NAN;
+    const int64_t img = rows * cols, n = fields * img;
+    double *t = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+    if (!t) return NAN;
+    for (int64_t i = 0; i < n; ++i)
+        elem_fn(map_op, params, nparams, (double)x[i], 0.0, &t[i]);
+    double loss = 0.0, m = 0.0;
+    for (int64_t f = 0; f < fields; ++f) {
+        const double *tf = t + f * img;
+        for (int64_t i = 0; i < rows; ++i) {
+            for (int64_t j = 0; j < cols; ++j) {
+                double s = 0.0;
+                for (int a = 0; a <= 2 * ry; ++a) {
+                    for (int b = 0; b <= 2 * rx; ++b) {
+                        int64_t si, sj;
+                        int in_r = border_index(i + a - ry, rows, edge, &si);
+                        int in_c = border_index(j + b - rx, cols, edge, &sj);
+                        double v = (in_r && in_c) ? tf[si * cols + sj] : (double)pad;
+                        double term = weight2d(w2d, wy, wx, rx, a, b) * v;
+                        s = s + term;
+                        m = m + fabs(term);
+                    }
+                }
+                loss = loss + s;
+            }
+        }
+    }
+    free(t);
+    if (mag) *mag = m;
+    return loss;
+}
+
+/* Reverse mode through the same chain for the upstream gradient g1 of the
+ * loss: the Reduce adjoint broadcasts g1 to every s; the MapOverlap adjoint
+ * sends W[a][b] * g1 from every output back to the element its tap read
+ * (nothing for pad reads); the Map adjoint multiplies by f's partials:
+ *     dx[k] = gt[k] * df/dx(x[k]),   dparams[p] = sum_k gt[k] * df/dp_p(x[k]).
+ * dx_mag[k] = |df/dx(x[k])| * sum |W[a][b] * g1| over the taps that reached k;
+ * dparams_mag[p] the matching sums of absolute terms.  Any output pointer
+ * but dx may be NULL. */
+int oracle_chain_grad_f32(int map_op, const double *params, int nparams, const float *x,
+                          int64_t fields, int64_t rows, int64_t cols, const float *w2d,
+                          const float *wy, const float *wx, int ry, int rx, int edge,
+                          double g1, double *dx, double *dx_mag, double *dparams,
+                          double *dparams_mag)
+{
+    double probe;
+    if (elem_fn(map_op, params, nparams, 0.0, 0.0, &probe) != 0 || needs_y(map_op))
+        return -1;
+    if (ry < 0 || rx < 0 || (w2d == NULL && (wy == NULL || wx == NULL))) return -1;
+    if (edge != ORC_EDGE_CLAMP && edge != ORC_EDGE_CONST && edge != ORC_EDGE_CYCLIC)
+        return -1;
+    const int64_t img = rows * cols, n = fields * img;
+    double *gt = (double *)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+    double *gm = (double *)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+    if (!gt || !gm) {
+        free(gt);
+        free(gm);
+        return -1;
+    }
+    for (int64_t f = 0; f < fields; ++f) {
+        double *gtf = gt + f * img, *gmf = gm + f * img;
+        for (int64_t i = 0; i < rows; ++i) {
+            for (int64_t j = 0; j < cols; ++j) {
+                for (int a = 0; a <= 2 * ry; ++a) {
+                    for (int b = 0; b <= 2 * rx; ++b) {
+                        int64_t si, sj;
+                        if (!border_index(i + a - ry, rows, edge, &si)) continue;
+                        if (!border_index(j + b - rx, cols, edge, &sj)) continue;
+                        double term = weight2d(w2d, wy, wx, rx, a, b) * g1;
+                        gtf[si * cols + sj] = gtf[si * cols + sj] + term;
+                        gmf[si * cols + sj] = gmf[si * cols + sj] + fabs(term);
+                    }
+                }
+            }
+        }
+    }
+    double s0 = 0.0, s1 = 0.0, m0 = 0.0, m1 = 0.0;
+    for (int64_t k = 0; k < n; ++k) {
+        double fx, fy, fp0, fp1;
+        elem_partials(map_op, params, (double)x[k], 0.0, &fx, &fy, &fp0, &fp1);
+        dx[k] = gt[k] * fx;
+        if (dx_mag) dx_mag[k] = gm[k] * fabs(fx);
+        s0 = s0 + gt[k] * fp0;
+        s1 = s1 + gt[k] * fp1;
+        m0 = m0 + fabs(gt[k] * fp0);
+        m1 = m1 + fabs(gt[k] * fp1);
+    }
+    if (dparams) {
+        if (nparams > 0) dparams[0] = s0;
+        if (nparams > 1) dparams[1] = s1;
+    }
+    if (dparams_mag) {
+        if (nparams > 0) dparams_mag[0] = m0;
+        if (nparams > 1) dparams_mag[1] = m1;
+    }
+    free(gt);
+    free(gm);
     return 0;
 }

@@ -158,6 +158,28 @@ int oracle_mapoverlap2d_adjoint_f32(const float *g, int64_t rows, int64_t cols,
                                     const float *wx, int ry, int rx, int edge,
                                     double *dx, double *mag);
 
+/* The call chain Map -> MapOverlap 2D -> Reduce SUM over `fields` images of
+ * rows x cols stored back to back (a composition of skeleton calls, Section V):
+ *   loss = sum_{f,i,j} sum_{a,b} W[a][b] * t_f[e(i+a-ry)][e(j+b-rx)],
+ *   t = f(x; params) (one-input element functions only), pad outside for CONST.
+ * Binary64 throughout, no rounding between the steps.  *mag (may be NULL)
+ * receives the sum of |W[a][b] * read value| over every term.  Returns NaN for
+ * bad arguments. */
+double oracle_chain_f32(int map_op, const double *params, int nparams, const float *x,
+                        int64_t fields, int64_t rows, int64_t cols, const float *w2d,
+                        const float *wy, const float *wx, int ry, int rx, int edge,
+                        float pad, double *mag);
+
+/* Reverse mode through that chain for the loss's upstream gradient g1:
+ *   gt = MapOverlap adjoint of (g1 everywhere);  dx = gt * df/dx;
+ *   dparams[p] = sum_k gt[k] * df/dp_p (index order).
+ * dx_mag, dparams, dparams_mag may be NULL.  Returns 0, or -1. */
+int oracle_chain_grad_f32(int map_op, const double *params, int nparams, const float *x,
+                          int64_t fields, int64_t rows, int64_t cols, const float *w2d,
+                          const float *wy, const float *wx, int ry, int rx, int edge,
+                          double g1, double *dx, double *dx_mag, double *dparams,
+                          double *dparams_mag);
+
 #ifdef __cplusplus
 }
 #endif

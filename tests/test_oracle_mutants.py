@@ -63,6 +63,24 @@ MUTANTS = [
      "if (op == ORC_MIN) acc = v > acc ? v : acc;", 0),
     ("fsum_drops_low_parts", "if (lo != 0.0) m->p[i++] = lo;", "(void)lo;", 0),
     ("fsum_no_halfway_fix", "if (y == x - hi) hi = x;", "(void)x;", 0),
+    ("chain_skips_map", "elem_fn(map_op, params, nparams, (double)x[i], 0.0, &t[i]);",
+     "t[i] = (double)x[i];", 0),
+    ("chain_rows_mirrored", "int in_r = border_index(i + a - ry, rows, edge, &si);",
+     "int in_r = border_index(i - a + ry, rows, edge, &si);", 1),
+    ("chain_pad_ignored", "double v = (in_r && in_c) ? tf[si * cols + sj] : (double)pad;",
+     "double v = (in_r && in_c) ? tf[si * cols + sj] : 0.0;", 0),
+    ("chain_grad_cols_mirrored",
+     "if (!border_index(j + b - rx, cols, edge, &sj)) continue;",
+     "if (!border_index(j - b + rx, cols, edge, &sj)) continue;", 1),
+    ("chain_grad_pad_reads_count",
+     "if (!border_index(i + a - ry, rows, edge, &si)) continue;\n"
+     "                        if (!border_index(j + b - rx, cols, edge, &sj)) continue;\n"
+     "                        double term = weight2d(w2d, wy, wx, rx, a, b) * g1;",
+     "if (!border_index(i + a - ry, rows, edge, &si)) si = i;\n"
+     "                        if (!border_index(j + b - rx, cols, edge, &sj)) sj = j;\n"
+     "                        double term = weight2d(w2d, wy, wx, rx, a, b) * g1;", 0),
+    ("chain_grad_ignores_adjoint", "dx[k] = gt[k] * fx;", "dx[k] = g1 * fx;", 0),
+    ("chain_grad_param_swapped", "s0 = s0 + gt[k] * fp0;", "s0 = s0 + gt[k] * fp1;", 0),
     ("segments_drop_last", "out[s] = oracle_reduce_f32(op, x + off[s], off[s + 1] - off[s]);",
      "out[s] = oracle_reduce_f32(op, x + off[s], off[s + 1] - off[s] - (off[s + 1] > off[s]));",
      0),

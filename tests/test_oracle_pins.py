@@ -674,3 +674,123 @@ def test_oracle_threads_do_not_change_results(oracle_mod):
             assert np.array_equal(a, b)
     finally:
         oracle_mod.set_threads(before)
+
+
+# --------------------------------------------------------------- call chain --
+# Map -> MapOverlap 2D -> Reduce SUM (a composition of skeleton calls)
+
+CHAIN_MAPS = {"identity": ([], lambda x, p: x),
+              "affine_tanh": ([0.75, -0.25], lambda x, p: np.tanh(p[0] * x + p[1])),
+              "square": ([], lambda x, p: x * x)}
+
+
+def _asym5():
+    """asymmetric 5-point weights (C .5, N .1, S .2, W .05, E .15): a flipped
+    or transposed tap changes the result"""
+    return si.five_point_weights(0.5, 0.1, 0.2, 0.05, 0.15)
+
+
+@pytest.mark.parametrize("edge,mode", [("clamp", "nearest"), ("const", "constant"),
+                                       ("cyclic", "wrap")])
+@pytest.mark.parametrize("shape,ry,rx", [((1, 1, 1), 1, 1), ((2, 3, 4), 1, 1),
+                                         ((2, 16, 16), 1, 1), ((1, 7, 5), 2, 3),
+                                         ((3, 4, 9), 0, 2)])
+@pytest.mark.parametrize("op", sorted(CHAIN_MAPS))
+def test_chain_scipy(oracle_mod, edge, mode, shape, ry, rx, op):
+    """The chain equals scipy's correlation of the mapped fields, summed."""
+    params, fn = CHAIN_MAPS[op]
+    x = si.normal_f32(int(np.prod(shape)), 6, 70).reshape(shape)
+    if (ry, rx) == (1, 1):
+        w2d = _asym5()
+    else:
+        w2d = si.uniform_f32((2 * ry + 1) * (2 * rx + 1), -1.0, 1.0, 6, 71).reshape(
+            2 * ry + 1, 2 * rx + 1)
+    pad = 0.375
+    t = fn(x.astype(np.float64), params)
+    ref = math.fsum(ndi.correlate(t[f], w2d.astype(np.float64), mode=mode, cval=pad).sum()
+                    for f in range(shape[0]))
+    got, mag = oracle_mod.chain(op, params, x, ry, rx, w2d=w2d, edge=edge, pad=pad)
+    assert abs(got - ref) <= 1e-12 * mag
+
+
+@pytest.mark.parametrize("op", sorted(CHAIN_MAPS))
+def test_chain_closed_forms(oracle_mod, op):
+    params, fn = CHAIN_MAPS[op]
+    w5 = _asym5()
+    wsum = math.fsum(w5.astype(np.float64).reshape(-1))
+    x = si.normal_f32(3 * 11 * 13, 6, 72).reshape(3, 11, 13)
+    # cyclic borders: every mapped element is read once per tap
+    got, mag = oracle_mod.chain(op, params, x, 1, 1, w2d=w5, edge="cyclic")
+    want = wsum * math.fsum(fn(x.astype(np.float64), params).reshape(-1))
+    assert abs(got - want) <= 1e-12 * mag
+    # a constant field stays constant under clamped borders
+    c = np.full((2, 5, 6), 0.625, np.float32)
+    got, mag = oracle_mod.chain(op, params, c, 1, 1, w2d=w5, edge="clamp")
+    want = 2 * 5 * 6 * wsum * float(fn(np.float64(0.625), params))
+    assert abs(got - want) <= 1e-12 * mag
+    # separable factors act as their exact (binary64) outer product
+    wy, wx = si.gaussian_weights(2, 1.0), si.binomial5_weights()
+    got, mag = oracle_mod.chain(op, params, x, 2, 2, wy=wy, wx=wx, edge="clamp")
+    outer = wy.astype(np.float64)[:, None] * wx.astype(np.float64)[None, :]
+    t = fn(x.astype(np.float64), params)
+    want = math.fsum(ndi.correlate(t[f], outer, mode="nearest").sum() for f in range(3))
+    assert abs(got - want) <= 1e-12 * mag
+    # identity map: the chain is the fsum of the MapOverlap oracle's outputs
+    if op == "identity":
+        for edge in ("clamp", "const", "cyclic"):
+            got, mag = oracle_mod.chain(op, params, x, 1, 1, w2d=w5, edge=edge, pad=0.5)
+            parts = [oracle_mod.mapoverlap2d(x[f], 1, 1, w2d=w5, edge=edge, pad=0.5)[0]
+                     for f in range(3)]
+            assert abs(got - math.fsum(np.concatenate([p.reshape(-1) for p in parts]))) \
+                <= 1e-12 * mag
+
+
+@pytest.mark.parametrize("edge", ["clamp", "const", "cyclic"])
+def test_chain_grad_finite_differences_16x16(oracle_mod, edge):
+    """Central differences of the chain's binary64 forward at 16 x 16 (the
+    size the differentiation workload checks at): every element of dx at the
+    corners, edges and inside, and both parameters."""
+    params = [0.75, -0.25]
+    w5 = _asym5()
+    rng = si.rng(6, 73)
+    # inputs on a 2^-8 grid so that x +- 2^-12 is exact in binary32
+    x = (rng.integers(-512, 512, (2, 16, 16)) / 256.0).astype(np.float32)
+    g1 = 1.5
+    dx, dxm, dp, dpm = oracle_mod.chain_grad("affine_tanh", params, x, 1, 1, g1, w2d=w5,
+                                             edge=edge)
+    h = 2.0 ** -12
+    for f, i, j in [(0, 0, 0), (0, 0, 15), (1, 15, 0), (1, 15, 15), (0, 0, 7), (1, 9, 0),
+                    (0, 15, 4), (1, 6, 15), (0, 7, 8), (1, 1, 1), (0, 14, 13)]:
+        xp, xm = x.copy(), x.copy()
+        xp[f, i, j] += np.float32(h)
+        xm[f, i, j] -= np.float32(h)
+        lp, _ = oracle_mod.chain("affine_tanh", params, xp, 1, 1, w2d=w5, edge=edge)
+        lm, _ = oracle_mod.chain("affine_tanh", params, xm, 1, 1, w2d=w5, edge=edge)
+        fd = g1 * (lp - lm) / (2 * h)
+        assert abs(dx[f, i, j] - fd) <= 1e-6 * max(1.0, abs(fd)), (f, i, j, dx[f, i, j], fd)
+    hp = 1e-6
+    for k in range(2):
+        pp, pm = list(params), list(params)
+        pp[k] += hp
+        pm[k] -= hp
+        lp, _ = oracle_mod.chain("affine_tanh", pp, x, 1, 1, w2d=w5, edge=edge)
+        lm, _ = oracle_mod.chain("affine_tanh", pm, x, 1, 1, w2d=w5, edge=edge)
+        fd = g1 * (lp - lm) / (2 * hp)
+        assert abs(dp[k] - fd) <= 1e-6 * max(1.0, dpm[k]), (k, dp[k], fd)
+
+
+@pytest.mark.parametrize("edge", ["clamp", "const", "cyclic"])
+def test_chain_grad_composes_the_pinned_adjoints(oracle_mod, edge):
+    """The chain's gradient is the MapOverlap adjoint of the broadcast upstream
+    gradient, pushed through the Map adjoint (both pinned above)."""
+    w5 = _asym5()
+    x = si.normal_f32(2 * 9 * 7, 6, 74).reshape(2, 9, 7)
+    g1 = -0.75
+    for op, params in (("identity", []), ("affine_tanh", [0.75, -0.25])):
+        dx, _, dp, _ = oracle_mod.chain_grad(op, params, x, 1, 1, g1, w2d=w5, edge=edge)
+        for f in range(2):
+            gt, _ = oracle_mod.mapoverlap2d_adjoint(np.full((9, 7), g1, np.float32), 1, 1,
+                                                    w2d=w5, edge=edge)
+            # the Map adjoint oracle takes g in binary32: gt rounded once (2^-24)
+            want, _, _, _ = oracle_mod.map_grad(op, params, x[f], gt.astype(np.float32))
+            np.testing.assert_allclose(dx[f].reshape(-1), want, rtol=2e-7, atol=1e-12)
