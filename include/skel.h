@@ -117,7 +117,8 @@ typedef enum skel_skeleton {
     SKEL_SK_MAPOVERLAP1D_BACKWARD = 7,
     SKEL_SK_MAPOVERLAP2D_BACKWARD = 8,
     SKEL_SK_SCAN_ROWS = 9,
-    SKEL_SK_COUNT = 10
+    SKEL_SK_MAP_OVERLAP2D_REDUCE = 10,
+    SKEL_SK_COUNT = 11
 } skel_skeleton;
 
 #define SKEL_VARIANT_AUTO (-1)
@@ -321,6 +322,49 @@ skel_status skel_scan(skel_container *in, skel_container *out,
 skel_status skel_scan_rows(skel_container *in, skel_container *out,
                            skel_scan_kind kind, skel_reduce_op op, int variant,
                            void *stream);
+
+/* The call chain Map -> MapOverlap 2D -> Reduce SUM as one skeleton call
+ * (Section V: a chain of skeleton calls composed, here optimised as a whole;
+ * Section III: the three skeletons):
+ *     out1[0] = sum over fields f, pixels (i, j) of
+ *               sum_{a,b} W[a][b] * t_f[e(i+a-ry)][e(j+b-rx)],   t = f(in)
+ * in is a (fields * H) x W F32 container of `fields` images stored back to
+ * back, each mapped with its own borders exactly as skel_mapoverlap2d_fields
+ * maps it; map_op is a one-input element function (IDENTITY, AFFINE, TANH,
+ * AFFINE_TANH or SQUARE; others give SKEL_E_INVAL) with its parameters;
+ * weights, radii, edge and pad as skel_mapoverlap2d; out1 is one F32 element.
+ * Variants (SKEL_SK_MAP_OVERLAP2D_REDUCE): 0 composed, the three skeletons'
+ * kernels in turn with the mapped fields and the stencil output stored in the
+ * stream's scratch memory; 1 fused, one pass that reads `in` once, weighing
+ * f(in) by how often the neighbourhood map reads each element (the sum of a
+ * linear map's outputs), plus the pad reads for CONST.  Both sum in binary32 in
+ * a fixed order (deterministic).  fields must divide the row count
+ * (SKEL_E_SHAPE).  n = 0 gives 0. */
+skel_status skel_map_overlap2d_reduce(skel_map_op map_op, const double *params, int nparams,
+                                      skel_container *in, int64_t fields, const float *w2d,
+                                      const float *wy, const float *wx, int ry, int rx,
+                                      skel_edge edge, float pad, skel_container *out1,
+                                      int variant, void *stream);
+
+/* Reverse mode through that chain, given g1 = dL/d(out1[0]) (one F32 element
+ * on the device):
+ *     grad_in = g1 * f'(in) * A^T 1   (A^T 1: how often, weighted, each
+ *               element is read by the neighbourhood map of its field;
+ *               CLAMP reads past an edge count on the edge element, CONST
+ *               pad reads on none)
+ *     grad_params[k] = g1 * sum_i (A^T 1)_i * df/dp_k(in_i)
+ * grad_in: F32, shaped like in, overwritten; grad_params: 2 F32 elements for
+ * AFFINE and AFFINE_TANH (NULL to skip), summed in a fixed order.  Same
+ * variants as the forward: 0 composes the Reduce adjoint (broadcast of g1),
+ * the MapOverlap adjoint and the Map adjoint through stored intermediates; 1
+ * reads in once and writes grad_in once. */
+skel_status skel_map_overlap2d_reduce_backward(skel_map_op map_op, const double *params,
+                                               int nparams, skel_container *in, int64_t fields,
+                                               const float *w2d, const float *wy,
+                                               const float *wx, int ry, int rx, skel_edge edge,
+                                               skel_container *g1, skel_container *grad_in,
+                                               skel_container *grad_params, int variant,
+                                               void *stream);
 
 /* Segmented Reduce: the Reduce skeleton applied to many vectors of uneven
  * length at once (a batch of operands of one skeleton instance, Section III),

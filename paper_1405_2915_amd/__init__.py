@@ -47,7 +47,8 @@ INCLUSIVE, EXCLUSIVE, REVERSE_INCLUSIVE, REVERSE_EXCLUSIVE = 0, 1, 2, 3
 SUM, MIN, MAX = 0, 1, 2
 MAP_IDENTITY, MAP_AXPY, MAP_AFFINE, MAP_TANH, MAP_AFFINE_TANH, MAP_MUL, MAP_SQUARE = range(7)
 SK_MAP, SK_REDUCE, SK_MAPREDUCE, SK_MAPOVERLAP1D, SK_MAPOVERLAP2D, SK_SCAN, \
-    SK_REDUCE_SEGMENTS, SK_MAPOVERLAP1D_BACKWARD, SK_MAPOVERLAP2D_BACKWARD, SK_SCAN_ROWS = range(10)
+    SK_REDUCE_SEGMENTS, SK_MAPOVERLAP1D_BACKWARD, SK_MAPOVERLAP2D_BACKWARD, SK_SCAN_ROWS, \
+    SK_MAP_OVERLAP2D_REDUCE = range(11)
 VARIANT_AUTO = -1
 MAX_RADIUS_1D, MAX_RADIUS_2D = 64, 8
 
@@ -133,6 +134,10 @@ def load_library(path: str = LIB_PATH):
         "skel_mapoverlap2d_backward": (st, [vp, vp, fp, fp, fp, i, i, i, i, vp]),
         "skel_mapoverlap2d_fields": (st, [vp, vp, i64, fp, fp, fp, i, i, i, C.c_float, i, vp]),
         "skel_mapoverlap2d_fields_backward": (st, [vp, vp, i64, fp, fp, fp, i, i, i, i, vp]),
+        "skel_map_overlap2d_reduce": (st, [i, dp, i, vp, i64, fp, fp, fp, i, i, i, C.c_float,
+                                           vp, i, vp]),
+        "skel_map_overlap2d_reduce_backward": (st, [i, dp, i, vp, i64, fp, fp, fp, i, i, i, vp,
+                                                    vp, vp, i, vp]),
         "skel_variant_count": (i, [i]),
         "skel_variant_name": (C.c_char_p, [i, i]),
         "skel_select_variant": (i, [i, i, i64, i64, i64, i]),
@@ -669,6 +674,34 @@ def skel_mapoverlap2d_fields_backward(g: Container, grad_in: Container, fields: 
                                                   rx, edge, variant,
                                                   _stream(stream)),
            "skel_mapoverlap2d_fields_backward")
+
+
+def skel_map_overlap2d_reduce(map_op: int, params, inp: Container, fields: int, out1: Container,
+                              w2d=None, wy=None, wx=None, ry: int | None = None,
+                              rx: int | None = None, edge: int = EDGE_CLAMP, pad: float = 0.0,
+                              variant: int = VARIANT_AUTO, stream=None) -> None:
+    """out1[0] = sum of the 2D neighbourhood map of f(inp) over every field (the
+    chain Map -> MapOverlap 2D -> Reduce SUM as one call)."""
+    (p2, py, px), keep, ry, rx = _weights_2d(w2d, wy, wx, ry, rx)
+    p, pp, np_ = _params(params)
+    _check(_L().skel_map_overlap2d_reduce(map_op, pp, np_, _h(inp), fields, p2, py, px, ry, rx,
+                                          edge, pad, _h(out1), variant, _stream(stream)),
+           "skel_map_overlap2d_reduce")
+
+
+def skel_map_overlap2d_reduce_backward(map_op: int, params, inp: Container, fields: int,
+                                       g1: Container, grad_in: Container,
+                                       grad_params: Container | None = None, w2d=None, wy=None,
+                                       wx=None, ry: int | None = None, rx: int | None = None,
+                                       edge: int = EDGE_CLAMP, variant: int = VARIANT_AUTO,
+                                       stream=None) -> None:
+    """grad_in = g1 * d(chain)/d(inp), grad_params = g1 * d(chain)/d(params)."""
+    (p2, py, px), keep, ry, rx = _weights_2d(w2d, wy, wx, ry, rx)
+    p, pp, np_ = _params(params)
+    _check(_L().skel_map_overlap2d_reduce_backward(map_op, pp, np_, _h(inp), fields, p2, py, px,
+                                                   ry, rx, edge, _h(g1), _h(grad_in),
+                                                   _h(grad_params), variant, _stream(stream)),
+           "skel_map_overlap2d_reduce_backward")
 
 
 def skel_variant_count(skeleton: int) -> int:

@@ -12,6 +12,9 @@ the reverse-mode adjoints declared in include/skel.h:
     mapoverlap1d_fn    transposed neighbourhood map (clamped reads
     mapoverlap2d_fn    accumulate onto the edge elements)
     mapoverlap2d_fields_fn  the same over a batch of fields, one launch
+    map_overlap2d_reduce_fn  the call chain Map -> MapOverlap 2D -> Reduce SUM
+                       as one call (fused: reads x once), and its adjoint in
+                       one pass (dx and the parameter gradients)
     scan_sum_fn        reverse scan of the upstream gradient
     scan_rows_sum_fn   reverse scan of each row of the upstream gradient
 
@@ -31,7 +34,8 @@ from . import (EDGE_CLAMP, EXCLUSIVE, INCLUSIVE, MAP_AFFINE, MAP_AFFINE_TANH, MA
                skel_map_backward, skel_mapoverlap1d, skel_mapoverlap1d_backward,
                skel_mapoverlap2d, skel_mapoverlap2d_backward, skel_mapoverlap2d_fields,
                skel_mapoverlap2d_fields_backward, skel_mapreduce, skel_reduce, skel_scan,
-               skel_scan_rows, wrap_tensor)
+               skel_scan_rows, wrap_tensor, skel_map_overlap2d_reduce,
+               skel_map_overlap2d_reduce_backward, VARIANT_AUTO)
 
 _TWO_INPUTS = {MAP_AXPY, MAP_MUL}
 _NPARAMS = {MAP_AXPY: 1, MAP_AFFINE: 2, MAP_AFFINE_TANH: 2}
@@ -257,6 +261,53 @@ def mapoverlap2d_fields_fn(x, w2d=None, wy=None, wx=None, edge: int = EDGE_CLAMP
     return out.reshape(f, h, w)
 
 
+class _MapOverlapReduceFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, op, pvals, ptensor, x, fields, w2d, wy, wx, edge, pad, variant):
+        out = torch.empty(1, dtype=torch.float32, device=x.device)
+        with _wrapped(x, out) as (cx, co):
+            skel_map_overlap2d_reduce(op, pvals, cx, fields, co, w2d=w2d, wy=wy, wx=wx,
+                                      edge=edge, pad=pad, variant=variant)
+        ctx.op, ctx.pvals, ctx.fields = op, pvals, fields
+        ctx.w2d, ctx.wy, ctx.wx, ctx.edge, ctx.variant = w2d, wy, wx, edge, variant
+        ctx.has_pt = ptensor is not None
+        ctx.save_for_backward(x, ptensor)
+        return out.reshape(())
+
+    @staticmethod
+    def backward(ctx, g):
+        x, ptensor = ctx.saved_tensors
+        g1 = _f32(g.reshape(1), "grad")
+        dx = torch.empty_like(x)
+        np_ = _NPARAMS.get(ctx.op, 0)
+        want_p = ctx.has_pt and ctx.needs_input_grad[2] and np_ > 0
+        dp = torch.empty(np_, dtype=torch.float32, device=x.device) if want_p else None
+        with _wrapped(x, g1, dx, dp) as (cx, cg, cdx, cdp):
+            skel_map_overlap2d_reduce_backward(ctx.op, ctx.pvals, cx, ctx.fields, cg, cdx, cdp,
+                                               w2d=ctx.w2d, wy=ctx.wy, wx=ctx.wx, edge=ctx.edge,
+                                               variant=ctx.variant)
+        gp = dp.reshape(ptensor.shape).to(ptensor.device) if want_p else None
+        return None, None, gp, dx, None, None, None, None, None, None, None
+
+
+def map_overlap2d_reduce_fn(op: int, x, params=None, w2d=None, wy=None, wx=None,
+                            edge: int = EDGE_CLAMP, pad: float = 0.0,
+                            variant: int = VARIANT_AUTO):
+    """sum over every field of the 2D neighbourhood map of f(x; params), for x
+    of shape (fields, H, W) or (H, W): the chain Map -> MapOverlap 2D ->
+    Reduce SUM in one call, differentiable in x and in params (a tensor)."""
+    x = _f32(x, "x")
+    if x.dim() == 2:
+        x = x.unsqueeze(0)
+    if x.dim() != 3:
+        raise ValueError("x must be (fields, H, W) or (H, W)")
+    f, h, w = x.shape
+    pvals, pt = _param_values(params)
+    cv = lambda a: None if a is None else np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+    return _MapOverlapReduceFn.apply(op, pvals, pt, x.reshape(f * h, w), int(f), cv(w2d),
+                                     cv(wy), cv(wx), int(edge), float(pad), int(variant))
+
+
 class _ScanSumFn(torch.autograd.Function):
     @staticmethod
     def forward(ctx, x, kind):
@@ -315,4 +366,5 @@ def scan_rows_sum_fn(x, kind: int = INCLUSIVE):
 
 
 __all__ = ["map_fn", "reduce_sum_fn", "mapreduce_sum_fn", "mapoverlap1d_fn",
-           "mapoverlap2d_fn", "mapoverlap2d_fields_fn", "scan_sum_fn", "scan_rows_sum_fn"]
+           "mapoverlap2d_fn", "mapoverlap2d_fields_fn", "map_overlap2d_reduce_fn", "scan_sum_fn",
+           "scan_rows_sum_fn"]

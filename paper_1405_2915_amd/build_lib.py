@@ -23,10 +23,10 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libskel.so")
 HOSTTEST_LIB = os.path.join(PKG, "libskel_hosttest.so")
 
-HIP_SOURCES = ["common.cpp", "container.cpp", "dispatch.cpp", "runtime.cpp",
+HIP_SOURCES = ["common.cpp", "container.cpp", "dispatch.cpp", "runtime.cpp", "chain_table.cpp",
                "skeletons.cpp", "k_map.hip", "k_reduce.hip", "k_scan.hip",
-               "k_overlap.hip", "k_segments.hip", "k_grad.hip"]
-HOST_SOURCES = ["common.cpp", "container.cpp", "dispatch.cpp"]
+               "k_overlap.hip", "k_segments.hip", "k_grad.hip", "k_chain.hip"]
+HOST_SOURCES = ["common.cpp", "container.cpp", "dispatch.cpp", "chain_table.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -34,11 +34,13 @@ const char* const kScan[] = {"S0_single_wg", "S1_reduce_then_scan",
 const char* const kSegments[] = {"B0_per_segment", "B1_persistent"};
 const char* const kScanRows[] = {"SR0_per_row", "SR1_wave_per_row"};
 const char* const kAdjoint[] = {"A0_gather", "A1_flipped_forward"};
+const char* const kChain[] = {"C0_composed", "C1_fused"};
 
 const char* const kSkeletonNames[] = {"MAP",          "REDUCE", "MAPREDUCE",
                                       "MAPOVERLAP1D", "MAPOVERLAP2D", "SCAN",
                                       "REDUCE_SEGMENTS", "MAPOVERLAP1D_BACKWARD",
-                                      "MAPOVERLAP2D_BACKWARD", "SCAN_ROWS"};
+                                      "MAPOVERLAP2D_BACKWARD", "SCAN_ROWS",
+                                      "MAP_OVERLAP2D_REDUCE"};
 static_assert(sizeof kSkeletonNames / sizeof kSkeletonNames[0] == SKEL_SK_COUNT,
               "one name per skeleton id");
 #define SKEL_NAMES_MATCH(table, count) \
@@ -52,6 +54,7 @@ SKEL_NAMES_MATCH(kScan, SCAN_NVAR);
 SKEL_NAMES_MATCH(kSegments, SEGMENTS_NVAR);
 SKEL_NAMES_MATCH(kScanRows, SCANROWS_NVAR);
 SKEL_NAMES_MATCH(kAdjoint, ADJOINT_NVAR);
+SKEL_NAMES_MATCH(kChain, CHAIN_NVAR);
 #undef SKEL_NAMES_MATCH
 
 struct TableEntry {
@@ -99,6 +102,7 @@ int static_rule(const CallContext& c) {
                                                                               : SR1_WAVE_PER_ROW;
     case SKEL_SK_MAPOVERLAP1D_BACKWARD:
     case SKEL_SK_MAPOVERLAP2D_BACKWARD: return A1_FLIPPED_FORWARD;
+    case SKEL_SK_MAP_OVERLAP2D_REDUCE: return C1_FUSED;
     }
     return -1;
 }
@@ -141,6 +145,7 @@ int variant_count(int skeleton) {
     case SKEL_SK_SCAN_ROWS: return SCANROWS_NVAR;
     case SKEL_SK_MAPOVERLAP1D_BACKWARD:
     case SKEL_SK_MAPOVERLAP2D_BACKWARD: return ADJOINT_NVAR;
+    case SKEL_SK_MAP_OVERLAP2D_REDUCE: return CHAIN_NVAR;
     }
     return 0;
 }
@@ -158,6 +163,7 @@ const char* variant_name(int skeleton, int v) {
     case SKEL_SK_SCAN_ROWS: return kScanRows[v];
     case SKEL_SK_MAPOVERLAP1D_BACKWARD:
     case SKEL_SK_MAPOVERLAP2D_BACKWARD: return kAdjoint[v];
+    case SKEL_SK_MAP_OVERLAP2D_REDUCE: return kChain[v];
     }
     return nullptr;
 }

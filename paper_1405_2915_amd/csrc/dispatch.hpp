@@ -25,6 +25,8 @@ enum ScanVariant { S0_SINGLE_WG = 0, S1_REDUCE_THEN_SCAN = 1, S2_LOOKBACK = 2,
                    S3_PERSISTENT_LOOKBACK = 3, SCAN_NVAR };
 enum SegmentsVariant { B0_PER_SEGMENT = 0, B1_PERSISTENT = 1, SEGMENTS_NVAR };
 enum ScanRowsVariant { SR0_PER_ROW = 0, SR1_WAVE_PER_ROW = 1, SCANROWS_NVAR };
+// the call chain Map -> MapOverlap 2D -> Reduce SUM (forward and backward)
+enum ChainVariant { C0_COMPOSED = 0, C1_FUSED = 1, CHAIN_NVAR };
 // MapOverlap adjoints (1D and 2D share the names)
 enum AdjointVariant { A0_GATHER = 0, A1_FLIPPED_FORWARD = 1, ADJOINT_NVAR };
 

@@ -17,6 +17,7 @@
 // All are HBM streams (map_grad: 12 to 20 bytes per element; adjoints: 8
 // bytes per element plus the cached neighbourhood reads).
 #include "kcommon.hpp"
+#include "kelem.hpp"
 #include "dispatch.hpp"
 #include "launch.hpp"
 
@@ -28,45 +29,10 @@ using dev::f32x4;
 constexpr int kBlock = 256;
 
 template <int OP>
-constexpr bool grad_two_inputs() { return OP == SKEL_MAP_AXPY || OP == SKEL_MAP_MUL; }
+constexpr bool grad_two_inputs() { return dev::two_inputs<OP>(); }
 template <int OP>
-constexpr int grad_nparams() {
-    return OP == SKEL_MAP_AXPY ? 1 : (OP == SKEL_MAP_AFFINE || OP == SKEL_MAP_AFFINE_TANH) ? 2 : 0;
-}
-
-// g * partial derivatives of f at (x, y): dx, dy and the parameter terms
-template <int OP>
-__device__ __forceinline__ void elem_grad(float x, float y, float g, float p0, float p1,
-                                          float& dx, float& dy, float& s0, float& s1) {
-    dy = 0.0f;
-    s0 = 0.0f;
-    s1 = 0.0f;
-    if constexpr (OP == SKEL_MAP_IDENTITY) {
-        dx = g;
-    } else if constexpr (OP == SKEL_MAP_AXPY) {
-        dx = p0 * g;
-        dy = g;
-        s0 = g * x;
-    } else if constexpr (OP == SKEL_MAP_AFFINE) {
-        dx = p0 * g;
-        s0 = g * x;
-        s1 = g;
-    } else if constexpr (OP == SKEL_MAP_TANH) {
-        const float t = tanhf(x);
-        dx = g * (1.0f - t * t);
-    } else if constexpr (OP == SKEL_MAP_AFFINE_TANH) {
-        const float t = tanhf(__builtin_fmaf(p0, x, p1));
-        const float gd = g * (1.0f - t * t);  // g * tanh' at the pre-activation
-        dx = gd * p0;
-        s0 = gd * x;
-        s1 = gd;
-    } else if constexpr (OP == SKEL_MAP_MUL) {
-        dx = g * y;
-        dy = g * x;
-    } else {  // SQUARE
-        dx = 2.0f * g * x;
-    }
-}
+constexpr int grad_nparams() { return dev::map_nparams<OP>(); }
+using dev::elem_grad;
 
 template <int OP, bool BCAST>
 __global__ __launch_bounds__(kBlock) void map_grad(const float* x, const float* y,

@@ -11,6 +11,7 @@
 //       2^26 floats: 128 us, against 145-161 us with plain loads or stores).
 // All three are HBM-bound streams: 8 or 12 bytes per element, 1-2 flops.
 #include "kcommon.hpp"
+#include "kelem.hpp"
 #include "launch.hpp"
 
 namespace skel {
@@ -18,19 +19,8 @@ namespace {
 
 using dev::f32x4;
 
-template <int OP>
-__device__ __forceinline__ float fmap(float x, float y, float p0, float p1) {
-    if constexpr (OP == SKEL_MAP_IDENTITY) return x;
-    else if constexpr (OP == SKEL_MAP_AXPY) return __builtin_fmaf(p0, x, y);
-    else if constexpr (OP == SKEL_MAP_AFFINE) return __builtin_fmaf(p0, x, p1);
-    else if constexpr (OP == SKEL_MAP_TANH) return tanhf(x);
-    else if constexpr (OP == SKEL_MAP_AFFINE_TANH) return tanhf(__builtin_fmaf(p0, x, p1));
-    else if constexpr (OP == SKEL_MAP_MUL) return x * y;
-    else return x * x;
-}
-
-template <int OP>
-constexpr bool two_inputs() { return OP == SKEL_MAP_AXPY || OP == SKEL_MAP_MUL; }
+using dev::fmap;
+using dev::two_inputs;
 
 template <int OP>
 __device__ __forceinline__ f32x4 fmap4(f32x4 a, f32x4 b, float p0, float p1) {

@@ -21,6 +21,7 @@
 #include <type_traits>
 
 #include "kcommon.hpp"
+#include "kelem.hpp"
 #include "dispatch.hpp"
 #include "kepoch.hpp"
 #include "launch.hpp"
@@ -62,18 +63,8 @@ struct PlainSrc {
     __device__ __forceinline__ acc_t at(int64_t i) const { return widen<acc_t>(x[i]); }
 };
 
-template <int MOP>
-__device__ __forceinline__ float fmap(float x, float y, float p0, float p1) {
-    if constexpr (MOP == SKEL_MAP_IDENTITY) return x;
-    else if constexpr (MOP == SKEL_MAP_AXPY) return __builtin_fmaf(p0, x, y);
-    else if constexpr (MOP == SKEL_MAP_AFFINE) return __builtin_fmaf(p0, x, p1);
-    else if constexpr (MOP == SKEL_MAP_TANH) return tanhf(x);
-    else if constexpr (MOP == SKEL_MAP_AFFINE_TANH) return tanhf(__builtin_fmaf(p0, x, p1));
-    else if constexpr (MOP == SKEL_MAP_MUL) return x * y;
-    else return x * x;
-}
-template <int MOP>
-constexpr bool two_inputs() { return MOP == SKEL_MAP_AXPY || MOP == SKEL_MAP_MUL; }
+using dev::fmap;
+using dev::two_inputs;
 
 // f(x[i], y[i]) accumulated in binary32; inputs f32 or bf16 bit patterns
 template <class P, int MOP>

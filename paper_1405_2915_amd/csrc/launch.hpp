@@ -108,6 +108,17 @@ skel_status launch_scan(int variant, int kind, int op, skel_dtype din,
 // vec: row starts are 16-byte aligned for both types (16-byte accesses)
 skel_status launch_scan_rows(int kind, int op, skel_dtype din, skel_dtype dout, const void* x,
                              void* y, int64_t rows, int64_t cols, bool vec, LaunchCtx& lc);
+// the call chain Map -> MapOverlap 2D -> Reduce SUM over `fields` images of
+// rows x cols (k_chain.hip): out[0] = the sum; the backward pass writes
+// dx = d(sum)/dx * g1[0] and, if dparams is not NULL, the parameter gradients
+skel_status launch_chain(int variant, int map_op, float p0, float p1, const float* x,
+                         int64_t rows, int64_t cols, int64_t fields, const float* w2d,
+                         const float* wy, const float* wx, int ry, int rx, int edge, float pad,
+                         float* out, LaunchCtx& lc);
+skel_status launch_chain_backward(int variant, int map_op, float p0, float p1, const float* x,
+                                  int64_t rows, int64_t cols, int64_t fields, const float* w2d,
+                                  const float* wy, const float* wx, int ry, int rx, int edge,
+                                  const float* g1, float* dx, float* dparams, LaunchCtx& lc);
 // device address of the allocation-free scan's array on `device` (k_scan.hip),
 // looked up once per device with that device current (skel_init)
 skel_status scan_noalloc_setup(int device);

@@ -612,4 +612,136 @@ skel_status skel_mapoverlap2d_backward(skel_container* g, skel_container* grad_i
                                              stream);
 }
 
+// the chain's Map step: a one-input element function
+static bool chain_map_op_valid(int op) {
+    return op == SKEL_MAP_IDENTITY || op == SKEL_MAP_AFFINE || op == SKEL_MAP_TANH ||
+           op == SKEL_MAP_AFFINE_TANH || op == SKEL_MAP_SQUARE;
+}
+
+// arguments common to the chain's forward and backward calls
+static skel_status check_chain_args(skel_map_op map_op, const double* params, int nparams,
+                                    skel_container* in, int64_t fields, const float* w2d,
+                                    const float* wy, const float* wx, int ry, int rx,
+                                    skel_edge edge, float* p0, float* p1, int64_t* frows) {
+    if (!chain_map_op_valid(map_op))
+        return fail(SKEL_E_INVAL, "the chain's Map takes a one-input element function, not %d",
+                    (int)map_op);
+    skel_status st = check_map_args(map_op, params, nparams, &in, 1, p0, p1);
+    if (st != SKEL_OK) return st;
+    if (!w2d && (!wy || !wx))
+        return fail(SKEL_E_INVAL, "need w2d or both separable factors wy, wx");
+    if (ry < 0 || rx < 0 || ry > SKEL_MAX_RADIUS_2D || rx > SKEL_MAX_RADIUS_2D)
+        return fail(SKEL_E_INVAL, "radii (%d, %d) outside 0..%d", ry, rx, SKEL_MAX_RADIUS_2D);
+    if (edge < SKEL_EDGE_CLAMP || edge > SKEL_EDGE_CYCLIC)
+        return fail(SKEL_E_INVAL, "unknown edge rule %d", (int)edge);
+    if (in->dtype != SKEL_F32) return fail(SKEL_E_DTYPE, "the chain's input must be f32");
+    if (fields < 1 || in->rows % fields != 0)
+        return fail(SKEL_E_SHAPE, "%lld rows do not split into %lld fields",
+                    (long long)in->rows, (long long)fields);
+    *frows = in->rows / fields;
+    return SKEL_OK;
+}
+
+skel_status skel_map_overlap2d_reduce(skel_map_op map_op, const double* params, int nparams,
+                                      skel_container* in, int64_t fields, const float* w2d,
+                                      const float* wy, const float* wx, int ry, int rx,
+                                      skel_edge edge, float pad, skel_container* out1,
+                                      int variant, void* stream) {
+    LaunchCtx lc;
+    skel_status st = begin(stream, &lc);
+    if (st != SKEL_OK) return st;
+    if (!in || !out1) return fail(SKEL_E_INVAL, "null container");
+    float p0, p1;
+    int64_t frows = 0;
+    st = check_chain_args(map_op, params, nparams, in, fields, w2d, wy, wx, ry, rx, edge, &p0,
+                          &p1, &frows);
+    if (st != SKEL_OK) return st;
+    if (out1 == in) return fail(SKEL_E_INVAL, "the chain's output aliases its input");
+    if (out1->n != 1 || out1->dtype != SKEL_F32)
+        return fail(SKEL_E_SHAPE, "the chain's output must be one f32 element");
+    CallContext cc;
+    cc.skeleton = SKEL_SK_MAP_OVERLAP2D_REDUCE;
+    cc.n = in->n;
+    cc.rows = frows;
+    cc.cols = in->cols;
+    cc.op = map_op;
+    cc.separable = w2d ? 0 : 1;
+    cc.radius = ry > rx ? ry : rx;
+    int v = choose_variant(variant, cc, &st);
+    if (v < 0) return st;
+    Operands ops;
+    ops.add(in, SKEL_READ);
+    ops.add(out1, SKEL_WRITE);
+    return run(ops, stream, lc, [&]() -> skel_status {
+        if (in->n == 0)  // no pixels, no terms: the empty sum
+            return launch_reduce(R0_SINGLE_WG, SKEL_SUM, SKEL_F32, SKEL_F32, nullptr, 0,
+                                 ops.ptr(out1), lc);
+        return launch_chain(v, map_op, p0, p1, (const float*)ops.ptr(in), frows, in->cols, fields,
+                            w2d, w2d ? nullptr : wy, w2d ? nullptr : wx, ry, rx, edge, pad,
+                            (float*)ops.ptr(out1), lc);
+    });
+}
+
+skel_status skel_map_overlap2d_reduce_backward(skel_map_op map_op, const double* params,
+                                               int nparams, skel_container* in, int64_t fields,
+                                               const float* w2d, const float* wy,
+                                               const float* wx, int ry, int rx, skel_edge edge,
+                                               skel_container* g1, skel_container* grad_in,
+                                               skel_container* grad_params, int variant,
+                                               void* stream) {
+    LaunchCtx lc;
+    skel_status st = begin(stream, &lc);
+    if (st != SKEL_OK) return st;
+    if (!in || !g1 || !grad_in) return fail(SKEL_E_INVAL, "null container");
+    float p0, p1;
+    int64_t frows = 0;
+    st = check_chain_args(map_op, params, nparams, in, fields, w2d, wy, wx, ry, rx, edge, &p0,
+                          &p1, &frows);
+    if (st != SKEL_OK) return st;
+    if (g1->n != 1 || g1->dtype != SKEL_F32)
+        return fail(SKEL_E_SHAPE, "g1 must be one f32 element");
+    if (grad_in->dtype != SKEL_F32 || grad_in->rows != in->rows || grad_in->cols != in->cols)
+        return fail(SKEL_E_SHAPE, "grad_in must be an f32 container shaped like in");
+    if (grad_in == in || grad_in == g1 || g1 == in)
+        return fail(SKEL_E_INVAL, "the chain's backward operands must be distinct containers");
+    const int np = map_op == SKEL_MAP_AFFINE || map_op == SKEL_MAP_AFFINE_TANH ? 2 : 0;
+    if (grad_params) {
+        if (grad_params->dtype != SKEL_F32) return fail(SKEL_E_DTYPE, "grad_params must be f32");
+        if (grad_params->n != np)
+            return fail(SKEL_E_SHAPE, "grad_params has %lld elements, the op has %d parameter(s)",
+                        (long long)grad_params->n, np);
+        if (grad_params == in || grad_params == g1 || grad_params == grad_in)
+            return fail(SKEL_E_INVAL, "grad_params aliases another operand");
+    }
+    CallContext cc;
+    cc.skeleton = SKEL_SK_MAP_OVERLAP2D_REDUCE;
+    cc.n = in->n;
+    cc.rows = frows;
+    cc.cols = in->cols;
+    cc.op = map_op;
+    cc.separable = w2d ? 0 : 1;
+    cc.radius = ry > rx ? ry : rx;
+    int v = choose_variant(variant, cc, &st);
+    if (v < 0) return st;
+    Operands ops;
+    ops.add(in, SKEL_READ);
+    ops.add(g1, SKEL_READ);
+    ops.add(grad_in, SKEL_WRITE);
+    if (grad_params && np > 0) ops.add(grad_params, SKEL_WRITE);
+    return run(ops, stream, lc, [&]() -> skel_status {
+        float* dp = grad_params && np > 0 ? (float*)ops.ptr(grad_params) : nullptr;
+        if (in->n == 0) {
+            // an empty chain: the sum is 0 whatever the parameters
+            return dp ? launch_map_backward(SKEL_MAP_AFFINE, 0.0f, 0.0f, nullptr, nullptr,
+                                            (const float*)ops.ptr(g1), true, nullptr, nullptr, 0,
+                                            dp, lc)
+                      : SKEL_OK;
+        }
+        return launch_chain_backward(v, map_op, p0, p1, (const float*)ops.ptr(in), frows,
+                                     in->cols, fields, w2d, w2d ? nullptr : wy,
+                                     w2d ? nullptr : wx, ry, rx, edge, (const float*)ops.ptr(g1),
+                                     (float*)ops.ptr(grad_in), dp, lc);
+    });
+}
+
 }  // extern "C"

@@ -8,6 +8,7 @@
 #include <cstring>
 #include <vector>
 
+#include "chain_table.hpp"
 #include "common.hpp"
 
 namespace {
@@ -114,6 +115,21 @@ void skel_hosttest_fail_copy(int k) { g_fail_copy = k; }
 // event_records, stream_waits, event_syncs, stream_syncs
 void skel_hosttest_counts(unsigned long long* out11) {
     std::memcpy(out11, &g_counts, sizeof g_counts);
+}
+
+// The fused chain's weight of every element of one rows x cols field, as the
+// kernels look it up (row class x column class of the host table), into
+// out[rows * cols]; *pad_total receives the table's constant pad term.
+void skel_hosttest_chain_weights(int64_t rows, int64_t cols, int64_t fields, const float* w2d,
+                                 const float* wy, const float* wx, int ry, int rx, int edge,
+                                 float pad, float* out, double* pad_total) {
+    skel::ChainTable t;
+    skel::chain_table(rows, cols, fields, w2d, wy, wx, ry, rx, edge, pad, &t);
+    for (int64_t r = 0; r < rows; ++r)
+        for (int64_t c = 0; c < cols; ++c)
+            out[r * cols + c] =
+                t.tab[skel::chain_row_class(t, r) * t.ncc + skel::chain_col_class(t, c)];
+    *pad_total = t.pad_total;
 }
 
 int skel_hosttest_wait_count_on(void* stream) {

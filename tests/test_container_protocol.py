@@ -305,7 +305,7 @@ def test_create_validation(rt):
 # ------------------------------------------------------------ execution plan
 
 SK_MAP, SK_REDUCE, SK_MAPREDUCE, SK_OV1, SK_OV2, SK_SCAN, SK_SEG, SK_OV1B, SK_OV2B, \
-    SK_SCANROWS = range(10)
+    SK_SCANROWS, SK_CHAIN = range(11)
 
 
 def name_of(lib, sk, v):
@@ -315,7 +315,7 @@ def name_of(lib, sk, v):
 
 def test_variant_registry(rt):
     want = {SK_MAP: 3, SK_REDUCE: 5, SK_MAPREDUCE: 5, SK_OV1: 3, SK_OV2: 5, SK_SCAN: 4,
-            SK_SEG: 2, SK_OV1B: 2, SK_OV2B: 2, SK_SCANROWS: 2}
+            SK_SEG: 2, SK_OV1B: 2, SK_OV2B: 2, SK_SCANROWS: 2, SK_CHAIN: 2}
     for sk, k in want.items():
         assert rt.skel_variant_count(sk) == k
         names = [name_of(rt, sk, v) for v in range(k)]

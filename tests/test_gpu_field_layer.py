@@ -50,9 +50,11 @@ def test_field_layer_full_size(skel, oracle_mod):
     for f, r in SAMPLES:
         xb, k = block(x[f].cpu().numpy(), r)
         yb, mag = oracle_mod.mapoverlap2d(xb, 1, 1, w2d=w5, edge="clamp")
-        # the scan of the exact stencil row in binary64, and its magnitude bound
-        zref = np.cumsum(yb[k])
-        bound = 1e-5 * np.cumsum(mag[k]) + 1e-30
+        # the oracle's scan of the stencil row (rounded once to binary32: at
+        # most 2^-24 of each |term| sum, far inside the bar), and the prefix
+        # sums of the term magnitudes as the bound
+        zref, _ = oracle_mod.scan(yb[k].astype(np.float32), "inclusive", "sum")
+        bound = 1e-5 * oracle_mod.scan(mag[k].astype(np.float32), "inclusive", "sum")[0] + 1e-30
         got = z[f, r].cpu().numpy().astype(np.float64)
         assert np.all(np.abs(got - zref) <= bound), ("forward", f, r)
         gb, k = block(gz[f].cpu().numpy(), r)
