@@ -134,7 +134,7 @@ class Workload:
             "scan_excl_i32_i64": sk.skel_select_variant(sk.SK_SCAN, sk.I32, N_SCAN),
             "mapreduce_dot": sk.skel_select_variant(sk.SK_MAPREDUCE, sk.F32, N_VEC),
             "mapoverlap2d_9x9": sk.skel_select_variant(sk.SK_MAPOVERLAP2D, sk.F32, IMG * IMG,
-                                                       IMG, IMG, aux=1),
+                                                       IMG, IMG, aux=1 + 2 * 4),
             "reduce_sum": sk.skel_select_variant(sk.SK_REDUCE, sk.F32, N_VEC),
         }
 
@@ -249,29 +249,56 @@ def batched_reduce(skel, torch):
     return res
 
 
-def bf16_sums(skel, torch):
+def bf16_sums(skel, torch, with_errors=True):
     """2^28 bfloat16 values, |x| log-uniform in [1e-3, 1e3] with random signs:
-    plain (R2 / MR2) against compensated (R4 / MR4) Reduce and dot.  Accuracy
-    against exactly rounded sums is checked by the GPU precision tests."""
+    plain (R2 / MR2) against compensated (R4 / MR4) and pairwise (R5 / MR5)
+    Reduce and dot.  Each result's error is stated against the exactly rounded
+    sum of the same stored values (the oracle, on the host, after the timing),
+    with the bars the precision tests hold it to: 1e-5 sum|x| for every
+    variant, 2u|s| + 2^-36 sum|x| for the compensated ones, 64u sum|x| (65u for
+    the dot) for the pairwise ones (u = 2^-24)."""
     import synth_inputs as si
     n = 1 << 28
-    xb = skel.Container.from_numpy(si.log_uniform_signed_bf16(n, config=5, index=0), skel.BF16)
-    yb = skel.Container.from_numpy(si.log_uniform_signed_bf16(n, config=5, index=1), skel.BF16)
+    xh = si.log_uniform_signed_bf16(n, config=5, index=0)
+    yh = si.log_uniform_signed_bf16(n, config=5, index=1)
+    xb = skel.Container.from_numpy(xh, skel.BF16)
+    yb = skel.Container.from_numpy(yh, skel.BF16)
     out = skel.Container.empty(skel.F32, 1)
     res = {"elements": n}
-    for name in ("R2_ticket", "R4_compensated"):
+    got = {}
+    for name in ("R2_ticket", "R4_compensated", "R5_pairwise"):
         v = skel.variant_index(skel.SK_REDUCE, name)
         ms = time_call(torch, lambda: skel.skel_reduce(skel.SUM, xb, out, variant=v), 10)
+        got["reduce_" + name] = float(out.to_numpy()[0])
         res["reduce_" + name] = {"us": round(ms * 1e3, 1),
                                  "GBps": round(2 * n / (ms * 1e-3) / 1e9, 1)}
-    for name in ("MR2_fused_ticket", "MR4_compensated"):
+    for name in ("MR2_fused_ticket", "MR4_compensated", "MR5_pairwise"):
         v = skel.variant_index(skel.SK_MAPREDUCE, name)
         ms = time_call(torch, lambda: skel.skel_mapreduce(skel.MAP_MUL, None, [xb, yb],
                                                           skel.SUM, out, variant=v), 10)
+        got["dot_" + name] = float(out.to_numpy()[0])
         res["dot_" + name] = {"us": round(ms * 1e3, 1),
                               "GBps": round(4 * n / (ms * 1e-3) / 1e9, 1)}
     for c in (xb, yb, out):
         c.destroy()
+    if with_errors:
+        import oracle
+        log("exact bf16 sums on the host (oracle)")
+        xf, yf = si.bf16_bits_to_f32(xh), si.bf16_bits_to_f32(yh)
+        ref = {"reduce": (oracle.sum_bf16_exact(xh), oracle.abs_sum(xf)),
+               "dot": (oracle.dot_bf16_exact(xh, yh), oracle.abs_sum(xf * yf))}
+        u = 2.0 ** -24
+        for key, val in got.items():
+            kind = key.split("_")[0]
+            exact, mag = ref[kind]
+            err = abs(val - exact)
+            bar = (2 * u * abs(exact) + 2.0 ** -36 * mag if "compensated" in key
+                   else (64 + (kind == "dot")) * u * mag if "pairwise" in key else 1e-5 * mag)
+            res[key].update({"result": val, "abs_err": float(f"{err:.4g}"),
+                             "rel_err": float(f"{err / abs(exact):.4g}"),
+                             "err_over_abs_sum": float(f"{err / mag:.4g}"),
+                             "bar": float(f"{bar:.4g}"), "within_bar": bool(err <= bar)})
+        res["exact"] = {k: {"sum": v[0], "abs_sum": v[1]} for k, v in ref.items()}
     return res
 
 
@@ -384,6 +411,55 @@ def field_layer(skel, torch, reps=5):
     res["forward_stencil_variant"] = skel.skel_variant_name(
         skel.SK_MAPOVERLAP2D, skel.skel_select_variant(skel.SK_MAPOVERLAP2D, skel.F32, n,
                                                        FIELD_H, FIELD_W, aux=2 * 1))
+    return res
+
+
+def chain_layer(skel, torch, reps=5):
+    """The differentiation workload's loss as one call: loss = sum over 64
+    fields of 2048 x 2048 (N(0, 1) from torch's seeded generator on the
+    device) of the 5-point MapOverlap2D (clamped) of tanh(w x + b), w = 0.75,
+    b = -0.25, and its backward (dx, dw, db) from dL/dloss = 1.  Fused (C1:
+    one pass reading x; the backward reads x and writes dx) against composed
+    (C0: Map, batched-field stencil and Reduce with stored intermediates; the
+    backward broadcasts, transposes the stencil and runs the Map adjoint).
+    Algorithmic bytes: 4 per element forward, 8 backward."""
+    import synth_inputs as si
+    dev = torch.device("cuda", 0)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(si.BASE_SEED + 1000 * 4)
+    x = torch.randn((FIELDS, FIELD_H, FIELD_W), generator=gen, device=dev)
+    dx = torch.empty_like(x)
+    w5 = si.five_point_weights()
+    params = [0.75, -0.25]
+    cx = skel.wrap_tensor(x.view(-1, FIELD_W))
+    cdx = skel.wrap_tensor(dx.view(-1, FIELD_W))
+    out = skel.Container.empty(skel.F32, 1)
+    g1 = skel.Container.from_numpy(np.ones(1, np.float32))
+    dp = skel.Container.empty(skel.F32, 2)
+    n = x.numel()
+    res = {"fields": [FIELDS, FIELD_H, FIELD_W], "map": "tanh(0.75 x - 0.25)",
+           "stencil": "5-point, C 0.5, N S W E 0.125, clamp"}
+    for v in range(skel.skel_variant_count(skel.SK_MAP_OVERLAP2D_REDUCE)):
+        name = skel.skel_variant_name(skel.SK_MAP_OVERLAP2D_REDUCE, v)
+        fwd = time_call(torch, lambda: skel.skel_map_overlap2d_reduce(
+            skel.MAP_AFFINE_TANH, params, cx, FIELDS, out, w2d=w5, variant=v), reps)
+        loss = float(out.to_numpy()[0])
+        bwd = time_call(torch, lambda: skel.skel_map_overlap2d_reduce_backward(
+            skel.MAP_AFFINE_TANH, params, cx, FIELDS, g1, cdx, dp, w2d=w5, variant=v), reps)
+        res[name] = {
+            "forward_us": round(fwd * 1e3, 1),
+            "forward_GBps": round(4 * n / (fwd * 1e-3) / 1e9, 1),
+            "forward_frac_hbm": round(4 * n / (fwd * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "backward_us": round(bwd * 1e3, 1),
+            "backward_GBps": round(8 * n / (bwd * 1e-3) / 1e9, 1),
+            "backward_frac_hbm": round(8 * n / (bwd * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "loss": loss, "dparams": [float(v_) for v_ in dp.to_numpy()]}
+    fused, comp = res["C1_fused"], res["C0_composed"]
+    res["speedup_fused_vs_composed"] = {
+        "forward": round(comp["forward_us"] / fused["forward_us"], 2),
+        "backward": round(comp["backward_us"] / fused["backward_us"], 2)}
+    for c in (cx, cdx, out, g1, dp):
+        c.destroy()
     return res
 
 
@@ -643,13 +719,15 @@ def main():
         nxt = {"graph_step": graph_replay(skel, torch, wl, max(args.steps, 5))}
         log("batched Reduce over 4096 uneven vectors")
         nxt["batched_reduce"] = batched_reduce(skel, torch)
-        log("bf16 plain vs compensated sums, 2^28")
+        log("bf16 plain, compensated and pairwise sums, 2^28")
         nxt["bf16_sums"] = bf16_sums(skel, torch)
         out["next_rows"] = nxt
         log("backward kernels")
         nxt["backward"] = backward_kernels(skel, torch, wl)
         log("batched field layer, 64 x 2048^2: forward and backward")
         nxt["field_layer"] = field_layer(skel, torch)
+        log("loss chain Map -> MapOverlap2D -> Reduce, 64 x 2048^2: fused and composed")
+        nxt["chain_loss"] = chain_layer(skel, torch)
         log("small configuration, 2^20")
         out["small_config"] = small_config(skel, torch)
         out["small_config"]["dispatch"] = dispatch_overhead(skel, torch)

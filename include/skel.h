@@ -169,7 +169,9 @@ const char *skel_last_error(void);
 
 /* ---------------------------------------------------------- containers --- */
 
-/* Create a rows x cols container of `dtype` (rows >= 1, cols >= 0).  If
+/* Create a smart container (Section IV: the operand data is wrapped in a
+ * container that owns it and tracks where valid copies are) of rows x cols
+ * elements of `dtype` (rows >= 1, cols >= 0).  If
  * host_src is non-NULL, rows*cols elements are copied from it (the caller may
  * free it on return) and the host copy is the valid one; otherwise the
  * container is uninitialised and must be written before it is read. */
@@ -188,7 +190,8 @@ skel_status skel_container_wrap_device(skel_dtype dtype, int64_t rows, int64_t c
                                        void *dev_ptr, void *stream,
                                        skel_container **out);
 
-/* Destroy a container with no outstanding acquire; device memory is released
+/* Destroy a container (Section IV: the container owns its copies, so it
+ * frees them) with no outstanding acquire; device memory is released
  * stream-ordered after the last device access (wrapped device memory is left
  * to its owner).  Destroying waits for the container's pending device work
  * (unless it wraps device memory and has no host copy) and frees its pinned
@@ -230,8 +233,9 @@ skel_status skel_container_acquire_range(skel_container *c, skel_place place,
 skel_status skel_container_valid_ranges(const skel_container *c, skel_place place,
                                         int64_t *pairs, int64_t max_pairs, int64_t *count);
 
-/* End the access begun by the matching acquire at `place`; a device release
- * records the container's last-access event on `stream`. */
+/* End the access begun by the matching acquire at `place` (Section IV
+ * coherence protocol; Section V: a device release records the container's
+ * last-access event on `stream`, the dependence later calls order after). */
 skel_status skel_container_release(skel_container *c, skel_place place,
                                    void *stream);
 
@@ -259,13 +263,17 @@ skel_status skel_reduce(skel_reduce_op op, skel_container *in,
                         skel_container *out1, int variant, void *stream);
 
 /* MapReduce: out1[0] = op over i of f(in[0][i], in[1][i]) with no stored
- * intermediate.  Inputs F32 (or BF16 for IDENTITY/MUL/SQUARE), out1 F32. */
+ * intermediate.  The paper names MapReduce only as another framework's
+ * programming model (Section II); the reading taken here is the map-then-
+ * reduce composition of the Section III map and reduce skeletons, fused.  Inputs F32 (or BF16 for IDENTITY/MUL/SQUARE), out1 F32. */
 skel_status skel_mapreduce(skel_map_op map_op, const double *params,
                            int nparams, skel_container *const *in, int nin,
                            skel_reduce_op op, skel_container *out1,
                            int variant, void *stream);
 
-/* MapOverlap 1D: out[i] = sum_{k=0}^{2r} w[k] * in[e(i + k - r)] over a
+/* MapOverlap 1D (Section III names mapoverlap among SkePU's data-parallel
+ * skeletons; the linear neighbourhood weighting is the reading taken here):
+ * out[i] = sum_{k=0}^{2r} w[k] * in[e(i + k - r)] over a
  * vector of n F32 elements (correlation orientation: w[0] weighs the lowest
  * index).  e() applies `edge` (pad is the CONST value).  w holds 2r+1 floats
  * (copied at call time); 0 <= r <= SKEL_MAX_RADIUS_1D.  out != in. */
@@ -273,7 +281,7 @@ skel_status skel_mapoverlap1d(skel_container *in, skel_container *out,
                               const float *w, int radius, skel_edge edge,
                               float pad, int variant, void *stream);
 
-/* MapOverlap 2D on a rows x cols F32 matrix:
+/* MapOverlap 2D (Section III, as MapOverlap 1D) on a rows x cols F32 matrix:
  *   out[i][j] = sum_{a=0}^{2ry} sum_{b=0}^{2rx} W[a][b] * in[e(i+a-ry)][e(j+b-rx)]
  * W is w2d ((2ry+1) x (2rx+1) row-major) when non-NULL, else the separable
  * outer product wy[a] * wx[b].  0 <= ry, rx <= SKEL_MAX_RADIUS_2D.  Weights
@@ -484,11 +492,15 @@ int skel_select_variant(int skeleton, skel_dtype dtype, int64_t n,
  * a precomputed dispatch structure for fast run-time lookup; Section III:
  * execution plans built off-line per target system).  Text, one entry per
  * line, '#' starts a comment:
- *     <SKELETON> <dtype> <log2 n> <variant name or index>
- * e.g. "REDUCE f32 20 R2_ticket".  A call of size n uses the entry with the
- * largest log2 n <= ceil(log2 n) for its skeleton and input dtype (sizes
- * beyond the table extrapolate from its last entry, sizes below use its
- * first).  An entry that is not selectable for a call falls back to the
+ *     <SKELETON> <dtype> <log2 n> <variant name or index> [<class>]
+ * e.g. "REDUCE f32 20 R2_ticket".  MapOverlap entries (and only they) end with
+ * the stencil class they were tuned on, as skel_select_variant's aux encodes
+ * it (the radius in 1D; separable + 2 * max(ry, rx) in 2D, e.g.
+ * "MAPOVERLAP2D f32 22 O2c_lds_separable 9" for 9 x 9 factors), and apply
+ * only to calls of that class; other classes use the static rules.  A call of
+ * size n uses the entry with the largest log2 n <= ceil(log2 n) for its
+ * skeleton, input dtype (and class) (sizes beyond the table extrapolate from
+ * its last entry, sizes below use its first).  An entry that is not selectable for a call falls back to the
  * static rules.  The whole file is validated before it replaces the current
  * table; on error the old table stays.  SKEL_VARIANT_<SKELETON>=<name> in the
  * environment overrides both. */

@@ -434,7 +434,9 @@ def wrap_tensor(t, stream=None) -> Container:
         raise ValueError("wrap_tensor needs a contiguous CUDA tensor")
     if t.dtype not in _TORCH_DTYPE:
         raise TypeError(f"unsupported tensor dtype {t.dtype}")
-    rows, cols = (1, t.numel()) if t.dim() <= 1 else (t.shape[0], t.numel() // t.shape[0])
+    # leading axis = rows; an empty tensor (any shape) is a 1 x 0 container
+    rows, cols = ((1, t.numel()) if t.dim() <= 1 or t.numel() == 0
+                  else (t.shape[0], t.numel() // t.shape[0]))
     return skel_container_wrap_device(_TORCH_DTYPE[t.dtype], rows, cols, t.data_ptr(), stream)
 
 

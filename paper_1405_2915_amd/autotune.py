@@ -118,11 +118,15 @@ def tune(lo=10, hi=28, reps=7, log=print, allow_order_dependent=False):
             c.destroy()
     report["dtypes"] = {"REDUCE": "f32", "MAPREDUCE": "f32", "SCAN": "i32", "MAP": "f32",
                         "MAPOVERLAP1D": "f32", "MAPOVERLAP2D": "f32"}
+    # the stencil class each MapOverlap entry was tuned on: radius 2 (the
+    # 5-point binomial) in 1D, separable 9 x 9 (1 + 2 * 4) in 2D
+    report["classes"] = {"MAPOVERLAP1D": 2, "MAPOVERLAP2D": 1 + 2 * 4}
     return plan_from_report(report, allow_order_dependent=allow_order_dependent), report
 
 
 def plan_from_report(report, tol=0.05, allow_order_dependent=False):
-    """Plan entries (skeleton, dtype, log2 n, variant) from measured times.
+    """Plan entries (skeleton, dtype, log2 n, variant, stencil class or None)
+    from measured times.
 
     Sizes are visited in increasing order and the previous size's choice is
     kept while it stays within `tol` of the fastest variant, so timing noise
@@ -130,6 +134,7 @@ def plan_from_report(report, tol=0.05, allow_order_dependent=False):
     table = []
     for name, per_k in report["results"].items():
         dt = report.get("dtypes", {}).get(name, "f32")
+        cls = report.get("classes", {}).get(name)
         prev = None
         for k in sorted(per_k, key=int):
             res = {a: b for a, b in per_k[k].items()
@@ -137,7 +142,7 @@ def plan_from_report(report, tol=0.05, allow_order_dependent=False):
             best = min(res, key=res.get)
             if prev in res and res[prev] <= (1 + tol) * res[best]:
                 best = prev
-            table.append((name, dt, int(k), best))
+            table.append((name, dt, int(k), best, cls))
             prev = best
     return table
 
@@ -145,15 +150,16 @@ def plan_from_report(report, tol=0.05, allow_order_dependent=False):
 def write_plan(table, path, header):
     os.makedirs(os.path.dirname(path), exist_ok=True)
     with open(path, "w") as f:
-        f.write("# execution plan: fastest variant per (skeleton, dtype, log2 n)\n")
+        f.write("# execution plan: fastest variant per (skeleton, dtype, log2 n[, stencil "
+                "class])\n")
         for line in header:
             f.write(f"# {line}\n")
         # keep only the sizes where the choice changes (nearest lower key rules)
         last = {}
-        for name, dt, k, v in table:
-            if last.get((name, dt)) != v:
-                f.write(f"{name} {dt} {k} {v}\n")
-                last[(name, dt)] = v
+        for name, dt, k, v, cls in table:
+            if last.get((name, dt, cls)) != v:
+                f.write(f"{name} {dt} {k} {v}" + ("" if cls is None else f" {cls}") + "\n")
+                last[(name, dt, cls)] = v
 
 
 def main():

@@ -21,10 +21,10 @@ namespace {
 
 const char* const kMap[] = {"M0_scalar", "M1_vec4", "M2_vec4x4_nt"};
 const char* const kReduce[] = {"R0_single_wg", "R1_two_pass", "R2_ticket",
-                               "R3_atomic", "R4_compensated"};
+                               "R3_atomic", "R4_compensated", "R5_pairwise"};
 const char* const kMapReduce[] = {"MR0_unfused", "MR1_fused_two_pass",
                                   "MR2_fused_ticket", "MR3_fused_single_wg",
-                                  "MR4_compensated"};
+                                  "MR4_compensated", "MR5_pairwise"};
 const char* const kOverlap1D[] = {"O1a_direct", "O1b_lds_tile", "O1c_shuffle"};
 const char* const kOverlap2D[] = {"O2a_direct", "O2b_lds_tile", "O2c_lds_separable",
                                   "O2d_separable_l1", "O2e_march"};
@@ -62,7 +62,25 @@ struct TableEntry {
     int dtype;
     int log2n;
     int variant;
+    int cls;  // stencil class the entry was tuned on (stencil skeletons), else -1
 };
+
+bool is_stencil(int skeleton) {
+    return skeleton == SKEL_SK_MAPOVERLAP1D || skeleton == SKEL_SK_MAPOVERLAP2D ||
+           skeleton == SKEL_SK_MAPOVERLAP1D_BACKWARD || skeleton == SKEL_SK_MAPOVERLAP2D_BACKWARD;
+}
+
+// The stencil class of a call: the radius in 1D; separable + 2 * max(ry, rx)
+// in 2D (the encoding of skel_select_variant's aux).  Variants rank
+// differently for different radii and weight forms, so a table entry applies
+// only to calls of the class it was tuned on.
+int stencil_class(const CallContext& c) {
+    if (c.skeleton == SKEL_SK_MAPOVERLAP1D || c.skeleton == SKEL_SK_MAPOVERLAP1D_BACKWARD)
+        return c.radius;
+    if (c.skeleton == SKEL_SK_MAPOVERLAP2D || c.skeleton == SKEL_SK_MAPOVERLAP2D_BACKWARD)
+        return c.separable + 2 * c.radius;
+    return -1;
+}
 std::vector<TableEntry> g_table;
 std::mutex g_table_mu;
 
@@ -111,9 +129,10 @@ int table_rule(const CallContext& c) {
     std::lock_guard<std::mutex> lk(g_table_mu);
     if (g_table.empty()) return -1;
     int key = ceil_log2(c.n < 1 ? 1 : c.n);
+    const int cls = stencil_class(c);
     int best = -1, best_k = -1, lowest = -1, lowest_k = 1 << 30;
     for (const auto& e : g_table) {
-        if (e.skeleton != c.skeleton || e.dtype != (int)c.din) continue;
+        if (e.skeleton != c.skeleton || e.dtype != (int)c.din || e.cls != cls) continue;
         if (e.log2n <= key && e.log2n > best_k) {
             best = e.variant;
             best_k = e.log2n;
@@ -185,9 +204,9 @@ bool selectable(int v, const CallContext& c, const char** why) {
             *why = "atomic finish supports floating-point SUM only";
             return false;
         }
-        if (v == R4_COMPENSATED &&
+        if ((v == R4_COMPENSATED || v == R5_PAIRWISE) &&
             (c.op != SKEL_SUM || (c.din != SKEL_F32 && c.din != SKEL_BF16))) {
-            *why = "compensated summation applies to floating-point SUM only";
+            *why = "compensated and pairwise summation apply to floating-point SUM only";
             return false;
         }
         return true;
@@ -197,8 +216,8 @@ bool selectable(int v, const CallContext& c, const char** why) {
             *why = "unfused form needs F32 inputs (Map is F32)";
             return false;
         }
-        if (v == MR4_COMPENSATED && c.op != SKEL_SUM) {
-            *why = "compensated summation applies to SUM only";
+        if ((v == MR4_COMPENSATED || v == MR5_PAIRWISE) && c.op != SKEL_SUM) {
+            *why = "compensated and pairwise summation apply to SUM only";
             return false;
         }
         return true;
@@ -294,11 +313,13 @@ skel_status load_plan_table(const char* path) {
         while (std::isspace((unsigned char)*p)) ++p;
         if (*p == '#' || *p == '\0') continue;
         char sk[32], dt[16], vn[64];
-        int lg;
-        if (std::sscanf(p, "%31s %15s %d %63s", sk, dt, &lg, vn) != 4) {
+        int lg, cls = -1;
+        const int got = std::sscanf(p, "%31s %15s %d %63s %d", sk, dt, &lg, vn, &cls);
+        if (got != 4 && got != 5) {
             std::fclose(f);
-            return fail(SKEL_E_INVAL, "%s:%d: expected <skeleton> <dtype> <log2n> <variant>",
-                        path, lineno);
+            return fail(SKEL_E_INVAL,
+                        "%s:%d: expected <skeleton> <dtype> <log2n> <variant> [<class>]", path,
+                        lineno);
         }
         int s = -1, d = -1;
         for (int k = 0; k < SKEL_SK_COUNT; ++k)
@@ -311,7 +332,14 @@ skel_status load_plan_table(const char* path) {
             return fail(SKEL_E_INVAL, "%s:%d: unknown skeleton, dtype or variant", path,
                         lineno);
         }
-        t.push_back({s, d, lg, v});
+        if (is_stencil(s) != (got == 5) || (got == 5 && cls < 0)) {
+            std::fclose(f);
+            return fail(SKEL_E_INVAL,
+                        "%s:%d: MapOverlap entries carry the stencil class they were tuned on "
+                        "(radius in 1D, separable + 2 * radius in 2D); other entries do not",
+                        path, lineno);
+        }
+        t.push_back({s, d, lg, v, cls});
     }
     std::fclose(f);
     std::lock_guard<std::mutex> lk(g_table_mu);

@@ -15,9 +15,10 @@ namespace skel {
 // variant indices (stable: they are the values of the `variant` argument)
 enum MapVariant { M0_SCALAR = 0, M1_VEC4 = 1, M2_VEC4X4_NT = 2, MAP_NVAR };
 enum ReduceVariant { R0_SINGLE_WG = 0, R1_TWO_PASS = 1, R2_TICKET = 2, R3_ATOMIC = 3,
-                     R4_COMPENSATED = 4, REDUCE_NVAR };
+                     R4_COMPENSATED = 4, R5_PAIRWISE = 5, REDUCE_NVAR };
 enum MapReduceVariant { MR0_UNFUSED = 0, MR1_FUSED_TWO_PASS = 1, MR2_FUSED_TICKET = 2,
-                        MR3_FUSED_SINGLE_WG = 3, MR4_COMPENSATED = 4, MAPREDUCE_NVAR };
+                        MR3_FUSED_SINGLE_WG = 3, MR4_COMPENSATED = 4, MR5_PAIRWISE = 5,
+                        MAPREDUCE_NVAR };
 enum Overlap1DVariant { O1A_DIRECT = 0, O1B_LDS_TILE = 1, O1C_SHUFFLE = 2, OVERLAP1D_NVAR };
 enum Overlap2DVariant { O2A_DIRECT = 0, O2B_LDS_TILE = 1, O2C_LDS_SEPARABLE = 2,
                         O2D_SEPARABLE_L1 = 3, O2E_MARCH = 4, OVERLAP2D_NVAR };

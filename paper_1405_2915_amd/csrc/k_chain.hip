@@ -32,72 +32,91 @@ namespace {
 using namespace dev;
 
 constexpr int kBlock = 256;
-constexpr int kUnroll = 4;
+#ifndef SKEL_CHAIN_UNROLL
+#define SKEL_CHAIN_UNROLL 4
+#endif
+constexpr int kUnroll = SKEL_CHAIN_UNROLL;  // 16-byte loads in flight per lane and chunk
 constexpr int kMaxClasses = kChainMaxClasses;
 
 // Unsigned division by a divisor fixed for the whole launch, as a multiply-high
 // and shifts (Granlund and Montgomery, "Division by invariant integers using
 // multiplication", 1994, unsigned case): l = ceil(log2 d),
-// m = floor(2^64 (2^l - d) / d) + 1, q = (t + ((n - t) >> min(l, 1))) >> max(l - 1, 0)
-// with t = mulhi(m, n).  Exact for every 64-bit n and 1 <= d < 2^63.
-struct DivU64 {
-    uint64_t m;
+// m = floor(2^W (2^l - d) / d) + 1, q = (t + ((n - t) >> min(l, 1))) >> max(l - 1, 0)
+// with t = mulhi(m, n).  Exact for every W-bit n and 1 <= d < 2^(W-1).
+template <class T>
+struct DivU {
+    T m;
     int s1, s2;
-    __device__ __forceinline__ uint64_t div(uint64_t n) const {
-        const uint64_t t = __umul64hi(m, n);
+    __device__ __forceinline__ T div(T n) const {
+        T t;
+        if constexpr (sizeof(T) == 4) t = __umulhi(m, n);
+        else t = __umul64hi(m, n);
         return (t + ((n - t) >> s1)) >> s2;
     }
 };
 
-DivU64 make_div(uint64_t d) {
+template <class T>
+DivU<T> make_div(uint64_t d) {
+    constexpr int W = 8 * sizeof(T);
     int l = 0;
-    while (l < 63 && (UINT64_C(1) << l) < d) ++l;
-    const unsigned __int128 num = (unsigned __int128)((UINT64_C(1) << l) - d) << 64;
-    DivU64 r;
-    r.m = (uint64_t)(num / d) + 1;
+    while (l < W - 1 && (UINT64_C(1) << l) < d) ++l;
+    const unsigned __int128 num = (unsigned __int128)((UINT64_C(1) << l) - d) << W;
+    DivU<T> r;
+    r.m = (T)(num / d + 1);
     r.s1 = l < 1 ? l : 1;
     r.s2 = l > 1 ? l - 1 : 0;
     return r;
 }
 
 // What the kernels need to weigh an element: the field shape, the dividers
-// that locate a flat index in its field, and the (A^T 1) table of
+// that locate a flat index in its field (T: 32-bit indices when the array
+// has fewer than 2^32 elements, else 64-bit), and the (A^T 1) table of
 // chain_table.hpp (row classes, column classes, the interior entry).
+template <class T>
 struct ChainGeom {
-    int64_t rows, cols;
-    DivU64 by_cols, by_rows;  // element index -> row; row -> field
+    T rows, cols;
+    DivU<T> by_cols, by_rows;  // element index -> row; row -> field
     int ry, rx;
-    int small_r, small_c;     // fewer than 2r + 1 rows / columns
-    int ncc;                  // column classes (table row length)
-    float interior;           // the table's interior entry (the weight sum)
+    int inner_ok;              // the field has interior rows and columns
+    int small_r, small_c;      // fewer than 2r + 1 rows / columns
+    int ncc;                   // column classes (table row length)
+    float interior;            // the table's interior entry (the weight sum)
     float tab[kMaxClasses * kMaxClasses];
 };
 
-__device__ __forceinline__ int row_class(const ChainGeom& g, int64_t r) {
-    if (g.small_r) return (int)r;
-    if (r < g.ry) return (int)r;
+template <class T>
+__device__ __forceinline__ int row_class(const ChainGeom<T>& g, T r) {
+    if (g.small_r || r < (T)g.ry) return (int)r;
     if (r >= g.rows - g.ry) return 2 * g.ry - (int)(g.rows - 1 - r);
     return g.ry;
 }
-__device__ __forceinline__ int col_class(const ChainGeom& g, int64_t c) {
-    if (g.small_c) return (int)c;
-    if (c < g.rx) return (int)c;
+template <class T>
+__device__ __forceinline__ int col_class(const ChainGeom<T>& g, T c) {
+    if (g.small_c || c < (T)g.rx) return (int)c;
     if (c >= g.cols - g.rx) return 2 * g.rx - (int)(g.cols - 1 - c);
     return g.rx;
 }
 
-// (A^T 1) of the four consecutive elements from flat index e0 (they may
-// straddle row and field ends); tab is the workgroup's LDS copy of the table
-__device__ __forceinline__ void coef4(const ChainGeom& g, const float* tab, int64_t e0,
-                                      float (&c)[4]) {
-    const uint64_t row = g.by_cols.div((uint64_t)e0);
-    int64_t col = e0 - (int64_t)row * g.cols;
-    int64_t rl = (int64_t)(row - g.by_rows.div(row) * (uint64_t)g.rows);
+// (A^T 1) of the four consecutive elements from flat index e0.  Inside a
+// field (the common case) all four take the interior entry; a vector that
+// touches a border band, or straddles a row or field end, looks each element
+// up in the workgroup's LDS copy of the table.
+template <class T>
+__device__ __forceinline__ void coef4(const ChainGeom<T>& g, const float (&tab)[kMaxClasses * kMaxClasses],
+                                      T e0, float (&c)[4]) {
+    const T row = g.by_cols.div(e0);
+    T col = e0 - row * g.cols;
+    T rl = row - g.by_rows.div(row) * g.rows;
+    const bool inner = g.inner_ok && rl >= (T)g.ry && rl < g.rows - g.ry && col >= (T)g.rx &&
+                       col + 3 + g.rx < g.cols;
+    if (inner) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) c[e] = g.interior;
+        return;
+    }
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-        const bool in_r = !g.small_r && rl >= g.ry && rl < g.rows - g.ry;
-        const bool in_c = !g.small_c && col >= g.rx && col < g.cols - g.rx;
-        c[e] = (in_r && in_c) ? g.interior : tab[row_class(g, rl) * g.ncc + col_class(g, col)];
+        c[e] = tab[row_class(g, rl) * g.ncc + col_class(g, col)];
         if (++col == g.cols) {
             col = 0;
             if (++rl == g.rows) rl = 0;
@@ -105,48 +124,111 @@ __device__ __forceinline__ void coef4(const ChainGeom& g, const float* tab, int6
     }
 }
 
-__device__ __forceinline__ void load_table(const ChainGeom& g, float* tab) {
+template <class T>
+__device__ __forceinline__ void load_table(const ChainGeom<T>& g,
+                                           float (&tab)[kMaxClasses * kMaxClasses]) {
     for (int k = threadIdx.x; k < kMaxClasses * kMaxClasses; k += kBlock) tab[k] = g.tab[k];
     __syncthreads();
 }
 
+// tanh from the identity tanh(a) = (1 - e^-2a) / (1 + e^-2a) for a = |y| with
+// the hardware base-2 exponential and reciprocal, and the odd Taylor series
+// y - y^3/3 + 2y^5/15 below |y| = 1/16 (truncation under 2^-27 relative
+// there, where the quotient would lose digits to cancellation); absolute
+// error about 1e-7 everywhere, saturating to +-1 without overflow
+__device__ __forceinline__ float tanh_fast(float y) {
+    const float a = __builtin_fabsf(y);
+    const float e = __builtin_amdgcn_exp2f(-2.8853900817779268f * a);  // e^-2a, 2 log2(e) a
+    const float q = (1.0f - e) * __builtin_amdgcn_rcpf(1.0f + e);
+    const float y2 = y * y;
+    const float p = y * __builtin_fmaf(y2, __builtin_fmaf(y2, 0.13333333333f, -0.33333333333f), 1.0f);
+    return a < 0.0625f ? p : __builtin_copysignf(q, y);
+}
+
+// the chain's element function (one input), tanh by tanh_fast
+template <int MOP>
+__device__ __forceinline__ float chain_f(float x, float p0, float p1) {
+    if constexpr (MOP == SKEL_MAP_TANH) return tanh_fast(x);
+    else if constexpr (MOP == SKEL_MAP_AFFINE_TANH) return tanh_fast(__builtin_fmaf(p0, x, p1));
+    else return fmap<MOP>(x, 0.0f, p0, p1);
+}
+
+// g * (df/dx, df/dp0, df/dp1) of the chain's element function
+template <int MOP>
+__device__ __forceinline__ void chain_grad(float x, float g, float p0, float p1, float& dx,
+                                           float& s0, float& s1) {
+    s0 = 0.0f;
+    s1 = 0.0f;
+    if constexpr (MOP == SKEL_MAP_TANH) {
+        const float t = tanh_fast(x);
+        dx = g * (1.0f - t * t);
+    } else if constexpr (MOP == SKEL_MAP_AFFINE_TANH) {
+        const float t = tanh_fast(__builtin_fmaf(p0, x, p1));
+        const float gd = g * (1.0f - t * t);
+        dx = gd * p0;
+        s0 = gd * x;
+        s1 = gd;
+    } else {
+        float dy;
+        elem_grad<MOP>(x, 0.0f, g, p0, p1, dx, dy, s0, s1);
+    }
+}
+
+// the kUnroll vectors of one lane in the chunk at vector index `base`
+template <class T>
+__device__ __forceinline__ void load_chunk(const f32x4* xv, T nv, T base, f32x4 (&v)[kUnroll]) {
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+        const T i = base + u * kBlock + threadIdx.x;
+        v[u] = i < nv ? __builtin_nontemporal_load(&xv[i]) : f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+}
+
 // C1 forward: per-workgroup partial sums of f(x) * (A^T 1); every lane keeps
 // kUnroll 16-byte loads in flight, workgroups sweep consecutive chunks
-template <int MOP>
-__global__ __launch_bounds__(kBlock) void chain_fwd(const float* x, int64_t n, ChainGeom g,
+template <int MOP, class T>
+__global__ __launch_bounds__(kBlock) void chain_fwd(const float* x, T n, ChainGeom<T> g,
                                                     float p0, float p1, float* partials) {
     __shared__ float tab[kMaxClasses * kMaxClasses];
     __shared__ float lds[kBlock / kWave];
     load_table(g, tab);
-    float acc[kUnroll] = {0.0f, 0.0f, 0.0f, 0.0f};
+    float acc[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) acc[u] = 0.0f;
     const f32x4* xv = reinterpret_cast<const f32x4*>(x);
-    const int64_t nv = n / 4;
-    constexpr int64_t CH = (int64_t)kBlock * kUnroll;
-    for (int64_t base = (int64_t)blockIdx.x * CH; base < nv; base += (int64_t)gridDim.x * CH) {
-        f32x4 v[kUnroll];
+    const T nv = n / 4;
+    constexpr T CH = (T)kBlock * kUnroll;
+    const T stride = (T)gridDim.x * CH;
+    // the next chunk's loads are issued before this chunk's arithmetic, so
+    // the memory system stays busy while the lanes compute
+    f32x4 v[kUnroll];
+    load_chunk(xv, nv, (T)blockIdx.x * CH, v);
+    for (T base = (T)blockIdx.x * CH; base < nv; base += stride) {
+        f32x4 cur[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) cur[u] = v[u];
+        if (base + stride < nv) load_chunk(xv, nv, base + stride, v);
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
-            const int64_t i = base + u * kBlock + threadIdx.x;
-            v[u] = i < nv ? __builtin_nontemporal_load(&xv[i]) : f32x4{0.f, 0.f, 0.f, 0.f};
-        }
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-            const int64_t i = base + u * kBlock + threadIdx.x;
+            const T i = base + u * kBlock + threadIdx.x;
             if (i >= nv) break;
             float c[4];
             coef4(g, tab, 4 * i, c);
 #pragma unroll
-            for (int e = 0; e < 4; ++e) acc[u] = __builtin_fmaf(fmap<MOP>(v[u][e], 0.0f, p0, p1), c[e], acc[u]);
+            for (int e = 0; e < 4; ++e)
+                acc[u] = __builtin_fmaf(chain_f<MOP>(cur[u][e], p0, p1), c[e], acc[u]);
         }
     }
     // the n % 4 tail: one element per low lane of workgroup 0
-    const int64_t t = nv * 4 + threadIdx.x;
+    const T t = nv * 4 + threadIdx.x;
     if (blockIdx.x == 0 && t < n) {
         float c[4];
         coef4(g, tab, t, c);
-        acc[0] = __builtin_fmaf(fmap<MOP>(x[t], 0.0f, p0, p1), c[0], acc[0]);
+        acc[0] = __builtin_fmaf(chain_f<MOP>(x[t], p0, p1), c[0], acc[0]);
     }
-    float a = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+    float a = 0.0f;
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) a += acc[u];
     a = block_reduce<Comb<float, SKEL_SUM>>(a, lds);
     if (threadIdx.x == 0) partials[blockIdx.x] = a;
 }
@@ -167,8 +249,8 @@ __global__ __launch_bounds__(kBlock) void chain_finish(const float* partials, in
 
 // C1 backward: dx = g1 * (A^T 1) * df/dx, and per-workgroup partials of
 // g1 * (A^T 1) * df/dp_k (NP arrays of gridDim.x values)
-template <int MOP>
-__global__ __launch_bounds__(kBlock) void chain_bwd(const float* x, int64_t n, ChainGeom g,
+template <int MOP, class T>
+__global__ __launch_bounds__(kBlock) void chain_bwd(const float* x, T n, ChainGeom<T> g,
                                                     float p0, float p1, const float* g1,
                                                     float* dx, float* partials) {
     constexpr int NP = map_nparams<MOP>();
@@ -179,40 +261,41 @@ __global__ __launch_bounds__(kBlock) void chain_bwd(const float* x, int64_t n, C
     float a0 = 0.0f, a1 = 0.0f;
     const f32x4* xv = reinterpret_cast<const f32x4*>(x);
     f32x4* dv = reinterpret_cast<f32x4*>(dx);
-    const int64_t nv = n / 4;
-    constexpr int64_t CH = (int64_t)kBlock * kUnroll;
-    for (int64_t base = (int64_t)blockIdx.x * CH; base < nv; base += (int64_t)gridDim.x * CH) {
-        f32x4 v[kUnroll];
+    const T nv = n / 4;
+    constexpr T CH = (T)kBlock * kUnroll;
+    const T stride = (T)gridDim.x * CH;
+    f32x4 v[kUnroll];
+    load_chunk(xv, nv, (T)blockIdx.x * CH, v);
+    for (T base = (T)blockIdx.x * CH; base < nv; base += stride) {
+        f32x4 cur[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) cur[u] = v[u];
+        if (base + stride < nv) load_chunk(xv, nv, base + stride, v);
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
-            const int64_t i = base + u * kBlock + threadIdx.x;
-            v[u] = i < nv ? __builtin_nontemporal_load(&xv[i]) : f32x4{0.f, 0.f, 0.f, 0.f};
-        }
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-            const int64_t i = base + u * kBlock + threadIdx.x;
+            const T i = base + u * kBlock + threadIdx.x;
             if (i >= nv) break;
             float c[4];
             coef4(g, tab, 4 * i, c);
             f32x4 o;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                float ddx, ddy, s0, s1;
-                elem_grad<MOP>(v[u][e], 0.0f, gv * c[e], p0, p1, ddx, ddy, s0, s1);
-                o[e] = ddx;
+                float d, s0, s1;
+                chain_grad<MOP>(cur[u][e], gv * c[e], p0, p1, d, s0, s1);
+                o[e] = d;
                 a0 += s0;
                 a1 += s1;
             }
             store_vec_nt(o, &dv[i]);
         }
     }
-    const int64_t t = nv * 4 + threadIdx.x;
+    const T t = nv * 4 + threadIdx.x;
     if (blockIdx.x == 0 && t < n) {
         float c[4];
         coef4(g, tab, t, c);
-        float ddx, ddy, s0, s1;
-        elem_grad<MOP>(x[t], 0.0f, gv * c[0], p0, p1, ddx, ddy, s0, s1);
-        dx[t] = ddx;
+        float o, s0, s1;
+        chain_grad<MOP>(x[t], gv * c[0], p0, p1, o, s0, s1);
+        dx[t] = o;
         a0 += s0;
         a1 += s1;
     }
@@ -227,45 +310,54 @@ __global__ __launch_bounds__(kBlock) void chain_bwd(const float* x, int64_t n, C
     }
 }
 
+#ifndef SKEL_CHAIN_GROUPS_PER_CU
+#define SKEL_CHAIN_GROUPS_PER_CU 16
+#endif
+
+// one chunk of kBlock * kUnroll vectors per workgroup at least, at most
+// SKEL_CHAIN_GROUPS_PER_CU workgroups per CU (the element function's
+// arithmetic needs more waves in flight than a plain reduction)
 int grid_for(int64_t n, const DevInfo& d) {
     int64_t g = (n / 4 + (int64_t)kBlock * kUnroll - 1) / ((int64_t)kBlock * kUnroll);
-    const int64_t cap = (int64_t)d.cus * 4;
+    const int64_t cap = (int64_t)d.cus * SKEL_CHAIN_GROUPS_PER_CU;
     if (g > cap) g = cap;
     return g < 1 ? 1 : (int)g;
 }
 
-ChainGeom geometry(const ChainTable& t) {
-    ChainGeom g;
-    g.rows = t.rows;
-    g.cols = t.cols;
-    g.by_cols = make_div((uint64_t)t.cols);
-    g.by_rows = make_div((uint64_t)t.rows);
+template <class T>
+ChainGeom<T> geometry(const ChainTable& t) {
+    ChainGeom<T> g;
+    g.rows = (T)t.rows;
+    g.cols = (T)t.cols;
+    g.by_cols = make_div<T>((uint64_t)t.cols);
+    g.by_rows = make_div<T>((uint64_t)t.rows);
     g.ry = t.ry;
     g.rx = t.rx;
     g.small_r = t.small_r;
     g.small_c = t.small_c;
+    g.inner_ok = !t.small_r && !t.small_c;
     g.ncc = t.ncc;
     g.interior = t.interior;
     for (int k = 0; k < kMaxClasses * kMaxClasses; ++k) g.tab[k] = t.tab[k];
     return g;
 }
 
-template <int MOP>
-skel_status fused_forward(const float* x, int64_t n, const ChainGeom& g, float p0, float p1,
-                          float add, float* out, LaunchCtx& lc) {
+template <int MOP, class T>
+skel_status fused_forward(const float* x, int64_t n, const ChainTable& tb, float p0, float p1,
+                          float* out, LaunchCtx& lc) {
     const int groups = grid_for(n, *lc.dev);
     void* mem = nullptr;
     skel_status e = ws_scratch(lc, (size_t)groups * sizeof(float), &mem);
     if (e != SKEL_OK) return e;
     float* part = static_cast<float*>(mem);
-    chain_fwd<MOP><<<groups, kBlock, 0, lc.stream>>>(x, n, g, p0, p1, part);
+    chain_fwd<MOP, T><<<groups, kBlock, 0, lc.stream>>>(x, (T)n, geometry<T>(tb), p0, p1, part);
     if ((e = launch_check("chain_fwd")) != SKEL_OK) return e;
-    chain_finish<<<1, kBlock, 0, lc.stream>>>(part, groups, 1, add, out);
+    chain_finish<<<1, kBlock, 0, lc.stream>>>(part, groups, 1, (float)tb.pad_total, out);
     return launch_check("chain_finish");
 }
 
-template <int MOP>
-skel_status fused_backward(const float* x, int64_t n, const ChainGeom& g, float p0, float p1,
+template <int MOP, class T>
+skel_status fused_backward(const float* x, int64_t n, const ChainTable& tb, float p0, float p1,
                            const float* g1, float* dx, float* dparams, LaunchCtx& lc) {
     constexpr int NP = map_nparams<MOP>();
     const int groups = grid_for(n, *lc.dev);
@@ -273,11 +365,30 @@ skel_status fused_backward(const float* x, int64_t n, const ChainGeom& g, float 
     skel_status e = ws_scratch(lc, (size_t)groups * 2 * sizeof(float), &mem);
     if (e != SKEL_OK) return e;
     float* part = static_cast<float*>(mem);
-    chain_bwd<MOP><<<groups, kBlock, 0, lc.stream>>>(x, n, g, p0, p1, g1, dx, part);
+    chain_bwd<MOP, T><<<groups, kBlock, 0, lc.stream>>>(x, (T)n, geometry<T>(tb), p0, p1, g1, dx,
+                                                       part);
     if ((e = launch_check("chain_bwd")) != SKEL_OK) return e;
     if (NP == 0 || !dparams) return SKEL_OK;
     chain_finish<<<1, kBlock, 0, lc.stream>>>(part, groups, NP, 0.0f, dparams);
     return launch_check("chain_finish");
+}
+
+// 32-bit index arithmetic when every flat index fits
+template <int MOP>
+skel_status fused_forward_any(const float* x, int64_t n, const ChainTable& tb, float p0, float p1,
+                              float* out, LaunchCtx& lc) {
+    if (n < (INT64_C(1) << 32) - 4)
+        return fused_forward<MOP, uint32_t>(x, n, tb, p0, p1, out, lc);
+    return fused_forward<MOP, uint64_t>(x, n, tb, p0, p1, out, lc);
+}
+
+template <int MOP>
+skel_status fused_backward_any(const float* x, int64_t n, const ChainTable& tb, float p0,
+                               float p1, const float* g1, float* dx, float* dparams,
+                               LaunchCtx& lc) {
+    if (n < (INT64_C(1) << 32) - 4)
+        return fused_backward<MOP, uint32_t>(x, n, tb, p0, p1, g1, dx, dparams, lc);
+    return fused_backward<MOP, uint64_t>(x, n, tb, p0, p1, g1, dx, dparams, lc);
 }
 
 // The composed form keeps its two intermediates in the stream's scratch
@@ -297,16 +408,14 @@ skel_status launch_chain(int variant, int map_op, float p0, float p1, const floa
     if (variant == C1_FUSED) {
         ChainTable tb;
         chain_table(rows, cols, fields, w2d, wy, wx, ry, rx, edge, pad, &tb);
-        const ChainGeom g = geometry(tb);
-        const float add = (float)tb.pad_total;
         switch (map_op) {
         case SKEL_MAP_IDENTITY:
-            return fused_forward<SKEL_MAP_IDENTITY>(x, n, g, p0, p1, add, out, lc);
-        case SKEL_MAP_AFFINE: return fused_forward<SKEL_MAP_AFFINE>(x, n, g, p0, p1, add, out, lc);
-        case SKEL_MAP_TANH: return fused_forward<SKEL_MAP_TANH>(x, n, g, p0, p1, add, out, lc);
+            return fused_forward_any<SKEL_MAP_IDENTITY>(x, n, tb, p0, p1, out, lc);
+        case SKEL_MAP_AFFINE: return fused_forward_any<SKEL_MAP_AFFINE>(x, n, tb, p0, p1, out, lc);
+        case SKEL_MAP_TANH: return fused_forward_any<SKEL_MAP_TANH>(x, n, tb, p0, p1, out, lc);
         case SKEL_MAP_AFFINE_TANH:
-            return fused_forward<SKEL_MAP_AFFINE_TANH>(x, n, g, p0, p1, add, out, lc);
-        default: return fused_forward<SKEL_MAP_SQUARE>(x, n, g, p0, p1, add, out, lc);
+            return fused_forward_any<SKEL_MAP_AFFINE_TANH>(x, n, tb, p0, p1, out, lc);
+        default: return fused_forward_any<SKEL_MAP_SQUARE>(x, n, tb, p0, p1, out, lc);
         }
     }
     // C0: Map into t, the neighbourhood map of every field into s, Reduce s,
@@ -352,17 +461,17 @@ skel_status launch_chain_backward(int variant, int map_op, float p0, float p1, c
     if (variant == C1_FUSED) {
         ChainTable tb;
         chain_table(rows, cols, fields, w2d, wy, wx, ry, rx, edge, 0.0f, &tb);
-        const ChainGeom g = geometry(tb);
         switch (map_op) {
         case SKEL_MAP_IDENTITY:
-            return fused_backward<SKEL_MAP_IDENTITY>(x, n, g, p0, p1, g1, dx, dparams, lc);
+            return fused_backward_any<SKEL_MAP_IDENTITY>(x, n, tb, p0, p1, g1, dx, dparams, lc);
         case SKEL_MAP_AFFINE:
-            return fused_backward<SKEL_MAP_AFFINE>(x, n, g, p0, p1, g1, dx, dparams, lc);
+            return fused_backward_any<SKEL_MAP_AFFINE>(x, n, tb, p0, p1, g1, dx, dparams, lc);
         case SKEL_MAP_TANH:
-            return fused_backward<SKEL_MAP_TANH>(x, n, g, p0, p1, g1, dx, dparams, lc);
+            return fused_backward_any<SKEL_MAP_TANH>(x, n, tb, p0, p1, g1, dx, dparams, lc);
         case SKEL_MAP_AFFINE_TANH:
-            return fused_backward<SKEL_MAP_AFFINE_TANH>(x, n, g, p0, p1, g1, dx, dparams, lc);
-        default: return fused_backward<SKEL_MAP_SQUARE>(x, n, g, p0, p1, g1, dx, dparams, lc);
+            return fused_backward_any<SKEL_MAP_AFFINE_TANH>(x, n, tb, p0, p1, g1, dx, dparams, lc);
+        default:
+            return fused_backward_any<SKEL_MAP_SQUARE>(x, n, tb, p0, p1, g1, dx, dparams, lc);
         }
     }
     // C0: the Reduce adjoint (g1 broadcast, as the Map adjoint of the identity),

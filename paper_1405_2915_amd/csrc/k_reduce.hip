@@ -14,6 +14,12 @@
 //   R4 / MR4  the R2 pass with compensated (TwoSum / TwoProduct) binary32
 //             accumulation: accuracy of a doubled working precision for the
 //             same HBM traffic, for long sums of bf16 or f32 data
+//   R5 / MR5  the R2 pass with pairwise (cascade) summation in every lane:
+//             each chunk's values are added as a balanced tree, and the chunk
+//             sums are folded into a binary counter of partial sums, so a
+//             lane's additions form a balanced tree over its whole share
+//             (error growing with log n instead of n per lane), for the same
+//             HBM traffic
 //   MR0       the composed plain form: Map into a temporary, then R1
 // Every lane streams 16-byte vectors with four loads in flight and keeps four
 // independent accumulators; partials are combined by 64-lane butterflies and
@@ -207,6 +213,114 @@ struct CompMapSrc {
     }
 };
 
+// ----------------------------------------------------------- pairwise sums
+// R5 / MR5 sources: the same loads as PlainSrc / MapSrc, and `vals`, the E
+// (mapped) values of one vector for the pairwise tree
+template <class P>
+struct PairSrc : PlainSrc<P> {
+    static constexpr bool kPairwise = true;
+    __device__ __forceinline__ void vals(const typename PlainSrc<P>::Vec& v,
+                                         float (&o)[P::E]) const {
+#pragma unroll
+        for (int e = 0; e < P::E; ++e) o[e] = widen<float>(v.a[e]);
+    }
+};
+
+template <class P, int MOP>
+struct PairMapSrc : MapSrc<P, MOP> {
+    static constexpr bool kPairwise = true;
+    __device__ __forceinline__ void vals(const typename MapSrc<P, MOP>::Vec& v,
+                                         float (&o)[P::E]) const {
+#pragma unroll
+        for (int e = 0; e < P::E; ++e)
+            o[e] = fmap<MOP>(widen<float>(v.a[e]), two_inputs<MOP>() ? widen<float>(v.b[e]) : 0.0f,
+                             this->p0, this->p1);
+    }
+};
+
+template <class S, class = void>
+struct IsPairwise { static constexpr bool value = false; };
+template <class S>
+struct IsPairwise<S, decltype((void)S::kPairwise)> { static constexpr bool value = S::kPairwise; };
+
+// balanced tree over K values (K a power of two), in place
+template <int K>
+__device__ __forceinline__ float tree_sum(float (&v)[K]) {
+#pragma unroll
+    for (int w = K / 2; w >= 1; w /= 2)
+#pragma unroll
+        for (int i = 0; i < w; ++i) v[i] = v[i] + v[i + w];
+    return v[0];
+}
+
+// Insert chunk sum `c` (the k-th of this lane, counting from 0) into the
+// binary counter of partial sums: level l holds the sum of 2^l consecutive
+// chunks while bit l of k is set.  Adding chunk k carries through the set low
+// bits like an increment, so every addition combines two equal-sized sums.
+// The top level absorbs whatever would carry beyond it.
+constexpr int kPairLevels = 16;
+__device__ __forceinline__ void cascade_insert(float (&lvl)[kPairLevels], float c, uint32_t k) {
+    bool going = true;
+#pragma unroll
+    for (int l = 0; l < kPairLevels - 1; ++l) {
+        const bool bit = ((k >> l) & 1u) != 0;
+        const float merged = lvl[l] + c;
+        if (going) {
+            if (bit) {
+                c = merged;
+                lvl[l] = 0.0f;
+            } else {
+                lvl[l] = c;
+                going = false;
+            }
+        }
+    }
+    if (going) lvl[kPairLevels - 1] += c;
+}
+
+// pairwise form of thread_acc (below): same chunks and tails
+template <class P, int NT, class Src>
+__device__ __forceinline__ float thread_acc_pairwise(const Src& s, int64_t n, int64_t blk,
+                                                     int64_t nblk) {
+    constexpr int E = P::E;
+    constexpr int64_t CH = (int64_t)NT * kUnroll;
+    float lvl[kPairLevels];
+#pragma unroll
+    for (int l = 0; l < kPairLevels; ++l) lvl[l] = 0.0f;
+    const int64_t nv = n / E;
+    const int64_t nch = nv / CH;
+    uint32_t k = 0;
+    for (int64_t c = blk; c < nch; c += nblk, ++k) {
+        const int64_t b = c * CH + threadIdx.x;
+        typename Src::Vec v[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) s.load(b + u * NT, v[u]);
+        float t[kUnroll * E];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            float o[E];
+            s.vals(v[u], o);
+#pragma unroll
+            for (int e = 0; e < E; ++e) t[u * E + e] = o[e];
+        }
+        cascade_insert(lvl, tree_sum<kUnroll * E>(t), k);
+    }
+    // the levels in increasing order, then the tails (fewer than one chunk)
+    float total = 0.0f;
+#pragma unroll
+    for (int l = 0; l < kPairLevels; ++l) total += lvl[l];
+    for (int64_t i = nch * CH + blk * NT + threadIdx.x; i < nv; i += nblk * NT) {
+        typename Src::Vec v;
+        s.load(i, v);
+        float o[E];
+        s.vals(v, o);
+        total += tree_sum<E>(o);
+    }
+    const int64_t t = nv * E + blk * NT + threadIdx.x;
+    if (t < n) total += s.at(t);
+    return total;
+}
+
 // One lane's share of workgroup `blk` of `nblk`: the workgroup walks chunks of
 // NT * kUnroll consecutive 16-byte vectors (chunk blk, blk + nblk, ...), every
 // lane with kUnroll loads in flight; then the vectors after the last whole
@@ -217,6 +331,7 @@ template <class P, int NT, class Src>
 __device__ __forceinline__ typename P::acc_t thread_acc(const Src& s, int64_t n, int64_t blk,
                                                         int64_t nblk) {
     using acc_t = typename P::acc_t;
+    if constexpr (IsPairwise<Src>::value) return thread_acc_pairwise<P, NT>(s, n, blk, nblk);
     constexpr int E = P::E;
     constexpr int64_t CH = (int64_t)NT * kUnroll;
     acc_t a[kUnroll];
@@ -460,6 +575,11 @@ skel_status reduce_typed(int v, const void* x, int64_t n, void* out, LaunchCtx& 
         CompSrc<PC> cs{static_cast<const typename PC::in_t*>(x)};
         return launch_ticket<PC>(cs, n, static_cast<float*>(out), lc);
     }
+    if constexpr (DOUT == SKEL_F32 && OP == SKEL_SUM) if (v == R5_PAIRWISE) {
+        PairSrc<P> ps;
+        ps.x = static_cast<const typename P::in_t*>(x);
+        return launch_ticket<P>(ps, n, static_cast<float*>(out), lc);
+    }
     void* part = nullptr;
     skel_status e = ws_scratch(lc, partial_bytes(*lc.dev), &part);
     if (e != SKEL_OK) return e;
@@ -486,6 +606,14 @@ skel_status mapreduce_typed(int v, float p0, float p1, const void* x, const void
         using PC = RPC<DIN>;
         CompMapSrc<PC, MOP> cs{static_cast<const in_t*>(x), static_cast<const in_t*>(y), p0, p1};
         return launch_ticket<PC>(cs, n, out, lc);
+    }
+    if constexpr (OP == SKEL_SUM) if (v == MR5_PAIRWISE) {
+        PairMapSrc<P, MOP> ps;
+        ps.x = static_cast<const in_t*>(x);
+        ps.y = static_cast<const in_t*>(y);
+        ps.p0 = p0;
+        ps.p1 = p1;
+        return launch_ticket<P>(ps, n, out, lc);
     }
     if constexpr (DIN == SKEL_F32) if (v == MR0_UNFUSED) {
         // Map into a temporary with the Map skeleton's vector kernel, then the

@@ -74,6 +74,11 @@ skel_status ws_counters(LaunchCtx& lc, size_t bytes, void** p);
 // epoch; fails with SKEL_E_STATE if the array would have to grow (or be
 // cleared) while the stream is being captured into a graph
 skel_status ws_status(LaunchCtx& lc, size_t bytes, void** p);
+// SKEL_E_STATE, before anything is enqueued, if `calls` calls that each take a
+// descriptor array (of `bytes`; 0: the size is checked by the first call
+// itself) would have to enlarge or reset it while the stream is captured
+// (outside a capture they may: nothing to check)
+skel_status ws_status_ready(LaunchCtx& lc, size_t bytes, int64_t calls);
 skel_status hip_check(hipError_t e, const char* what);
 skel_status launch_check(const char* kernel);
 // workgroups of `block` threads of `kernel` that the device holds at once

@@ -278,6 +278,22 @@ skel_status ws_status(LaunchCtx& lc, size_t bytes, void** p) {
     return SKEL_OK;
 }
 
+skel_status ws_status_ready(LaunchCtx& lc, size_t bytes, int64_t calls) {
+    if (calls <= 0) return SKEL_OK;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(lc.stream, &cs) != hipSuccess) {
+        (void)hipGetLastError();
+        cs = hipStreamCaptureStatusNone;
+    }
+    if (cs == hipStreamCaptureStatusNone) return SKEL_OK;
+    const Workspace* w = lc.ws;
+    if (w->status_bytes < bytes || w->epoch_calls + (uint64_t)calls >= (uint64_t)kEpochMax - 1)
+        return fail(SKEL_E_STATE,
+                    "the descriptor workspace would have to be enlarged or reset while the "
+                    "stream is captured; run the same call once before capture");
+    return SKEL_OK;
+}
+
 }  // namespace skel
 
 using namespace skel;

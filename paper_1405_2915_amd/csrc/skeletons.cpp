@@ -29,7 +29,12 @@ class Operands {
                 count_eager(c, a);
                 return SKEL_OK;
             }
-        ops_[n_++] = {c, a, nullptr, false};
+        ops_[n_] = Op();
+        ops_[n_].c = c;
+        ops_[n_].access = a;
+        ops_[n_].ptr = nullptr;
+        ops_[n_].held = false;
+        ++n_;
         count_eager(c, a);
         return SKEL_OK;
     }
@@ -40,17 +45,38 @@ class Operands {
         }
         return SKEL_OK;
     }
+    // Acquire every operand on the device.  The validity of each written
+    // operand is remembered first, so that a call failing before its kernels
+    // are enqueued (an acquire, or a workspace that cannot grow) can put it
+    // back: a failed call has no side effect on the coherence state.
     skel_status acquire_all(void* stream) {
+        for (int i = 0; i < n_; ++i)
+            if (ops_[i].access & SKEL_WRITE) {
+                ops_[i].saved_host = ops_[i].c->valid_host;
+                ops_[i].saved_dev = ops_[i].c->valid_dev;
+            }
         for (int i = 0; i < n_; ++i) {
             skel_status st = acquire(ops_[i].c, SKEL_DEVICE, ops_[i].access, stream,
                                      &ops_[i].ptr);
             if (st != SKEL_OK) {
                 release_all(stream);
+                restore_written();
                 return st;
             }
             ops_[i].held = true;
+            ops_[i].acquired = true;
         }
         return SKEL_OK;
+    }
+    // Undo the validity changes of the written operands (the call enqueued
+    // nothing that writes them).
+    void restore_written() {
+        for (int i = 0; i < n_; ++i)
+            if (ops_[i].acquired && (ops_[i].access & SKEL_WRITE)) {
+                ops_[i].c->valid_host = ops_[i].saved_host;
+                ops_[i].c->valid_dev = ops_[i].saved_dev;
+                ops_[i].acquired = false;
+            }
     }
     void release_all(void* stream) {
         for (int i = 0; i < n_; ++i)
@@ -76,6 +102,8 @@ class Operands {
         skel_access access;
         void* ptr;
         bool held;
+        bool acquired = false;
+        skel_ranges saved_host, saved_dev;  // validity before the call (written operands)
     };
     struct Pending {
         skel_container* c;
@@ -109,7 +137,13 @@ skel_status run(Operands& ops, void* stream, LaunchCtx& lc, F&& launch) {
     if (st != SKEL_OK) return st;
     st = launch();
     ops.release_all(stream);
-    if (st == SKEL_OK) ops.commit_eager();
+    if (st == SKEL_OK) {
+        ops.commit_eager();
+    } else if (st == SKEL_E_STATE || st == SKEL_E_NOMEM) {
+        // the launchers take their workspace before enqueuing any kernel, so
+        // these failures leave the operands' data as it was
+        ops.restore_written();
+    }
     return st;
 }
 
@@ -466,6 +500,14 @@ skel_status skel_scan_rows(skel_container* in, skel_container* out, skel_scan_ki
         if (v == SR1_WAVE_PER_ROW)
             return launch_scan_rows(kind, op, a, b, ops.ptr(in), ops.ptr(out), in->rows,
                                     in->cols, cc.rows_aligned != 0, lc);
+        // every row's single-pass scan takes the same descriptor array and
+        // advances the epoch once: the first row's call sizes the array
+        // before it enqueues anything; that no later row has to reset it
+        // inside a capture is checked here, before the first row
+        if (flat == S2_LOOKBACK || flat == S3_PERSISTENT_LOOKBACK) {
+            const skel_status ready = ws_status_ready(lc, 0, in->rows);
+            if (ready != SKEL_OK) return ready;
+        }
         const size_t sa = dtype_size(a), sb = dtype_size(b);
         const char* x = static_cast<const char*>(ops.ptr(in));
         char* y = static_cast<char*>(ops.ptr(out));

@@ -314,7 +314,7 @@ def name_of(lib, sk, v):
 
 
 def test_variant_registry(rt):
-    want = {SK_MAP: 3, SK_REDUCE: 5, SK_MAPREDUCE: 5, SK_OV1: 3, SK_OV2: 5, SK_SCAN: 4,
+    want = {SK_MAP: 3, SK_REDUCE: 6, SK_MAPREDUCE: 6, SK_OV1: 3, SK_OV2: 5, SK_SCAN: 4,
             SK_SEG: 2, SK_OV1B: 2, SK_OV2B: 2, SK_SCANROWS: 2, SK_CHAIN: 2}
     for sk, k in want.items():
         assert rt.skel_variant_count(sk) == k
@@ -357,7 +357,7 @@ def test_static_plan(rt):
 def test_plan_table(rt, tmp_path):
     p = tmp_path / "plan.txt"
     p.write_text("# tuned\nREDUCE f32 10 R1_two_pass\nREDUCE f32 20 R3_atomic\n"
-                 "SCAN i32 12 S1_reduce_then_scan\nMAPOVERLAP2D f32 10 O2c_lds_separable\n")
+                 "SCAN i32 12 S1_reduce_then_scan\nMAPOVERLAP2D f32 10 O2c_lds_separable 0\n")
     assert rt.skel_load_plan(str(p).encode()) == OK
     sel = lambda sk, n, dt=F32, sep=0: name_of(
         rt, sk, rt.skel_select_variant(sk, dt, n, 1, n, sep))
@@ -376,6 +376,33 @@ def test_plan_table(rt, tmp_path):
     assert sel(SK_REDUCE, 1 << 15) == "R1_two_pass"
     assert rt.skel_clear_plan() == OK
     assert sel(SK_REDUCE, 1 << 15) == "R0_single_wg"
+    # MapOverlap entries must name their stencil class; other entries must not
+    for text in ("MAPOVERLAP2D f32 10 O2c_lds_separable\n", "MAPOVERLAP1D f32 10 O1a_direct\n",
+                 "REDUCE f32 10 R1_two_pass 3\n", "MAPOVERLAP2D f32 10 O2a_direct -1\n"):
+        bad.write_text(text)
+        assert rt.skel_load_plan(str(bad).encode()) == E_INVAL, text
+
+
+PLAN = os.path.join(ROOT, "paper_1405_2915_amd", "plans", "gfx950.plan")
+
+
+def test_default_plan_applies_to_its_stencil_class_only(rt):
+    """The shipped plan's MapOverlap entries were tuned on the 9 x 9 separable
+    Gaussian and the 5-point 1D binomial; calls of any other class take the
+    static rules (e.g. a separable 3 x 3 on 2^24 pixels: the marching
+    window)."""
+    assert rt.skel_load_plan(PLAN.encode()) == OK
+    sel = lambda sk, n, aux, rows=4096: name_of(
+        rt, sk, rt.skel_select_variant(sk, F32, n, rows, n // rows, aux))
+    assert sel(SK_OV2, 1 << 24, 1 + 2 * 1) == "O2e_march"           # separable 3 x 3
+    assert sel(SK_OV2, 1 << 24, 1 + 2 * 4) == "O2d_separable_l1"    # the tuned 9 x 9
+    assert sel(SK_OV2, 1 << 22, 1 + 2 * 4, 2048) == "O2c_lds_separable"
+    assert sel(SK_OV2, 1 << 24, 2 * 1) == "O2e_march"               # dense 5-point
+    assert sel(SK_OV2, 1 << 24, 2 * 4) == "O2b_lds_tile"            # dense 9 x 9
+    assert sel(SK_OV1, 1 << 24, 2) == "O1c_shuffle"                 # the tuned radius
+    assert sel(SK_OV1, 1 << 24, 7) == "O1b_lds_tile"                # static: radius > 4
+    # the forward and the flipped transpose of a separable 3 x 3 agree
+    assert sel(SK_OV2B, 1 << 24, 1 + 2 * 1) == "A1_flipped_forward"
 
 
 def test_environment_override(rt, monkeypatch):

@@ -119,8 +119,8 @@ def test_variant_names_and_plan(skel):
     names = {sk: [skel.skel_variant_name(sk, v) for v in range(skel.skel_variant_count(sk))]
              for sk in range(6)}
     assert names[skel.SK_REDUCE] == ["R0_single_wg", "R1_two_pass", "R2_ticket", "R3_atomic",
-                                     "R4_compensated"]
-    assert names[skel.SK_MAPREDUCE][4] == "MR4_compensated"
+                                     "R4_compensated", "R5_pairwise"]
+    assert names[skel.SK_MAPREDUCE][4:] == ["MR4_compensated", "MR5_pairwise"]
     assert names[skel.SK_SCAN][2:] == ["S2_decoupled_lookback", "S3_persistent_lookback"]
     # the tuned plan picks one of the single-pass variants for a large scan
     assert skel.skel_select_variant(skel.SK_SCAN, skel.I32, 1 << 27) in (2, 3)
@@ -157,3 +157,42 @@ def test_range_granular_coherence(skel, oracle_mod):
     assert y.stats()["d2h"] == 3 and y.stats()["d2h_bytes"] == 4 * n
     assert np.all(np.abs(full - oracle_mod.map_f32("affine", [2.0, 1.0], xh))
                   <= 1e-6 * (2 * np.abs(xh) + 1))
+
+
+def test_failed_call_keeps_coherence_state(skel):
+    """A call that fails after its operands were acquired -- here a first,
+    larger unfused MapReduce inside a graph capture, whose scratch memory (the
+    stored products) cannot grow there -- returns SKEL_E_STATE and leaves its
+    output's validity as it was: both copies still current, nothing counted."""
+    import torch
+    mr0 = skel.variant_index(skel.SK_MAPREDUCE, "MR0_unfused")
+    s = torch.cuda.Stream()
+    small = skel.Container.from_numpy(si.uniform_f32(1000, -1.0, 1.0, 3, 90))
+    r = skel.Container.empty(skel.F32, 1)
+    with torch.cuda.stream(s):  # the stream's workspace, sized for the small call
+        skel.skel_mapreduce(skel.MAP_MUL, None, [small, small], skel.SUM, r, variant=mr0)
+    n = 1 << 20  # 4 MiB of products: more scratch than the small call made
+    x = skel.Container.from_numpy(si.uniform_f32(n, -1.0, 1.0, 3, 91))
+    out = skel.Container.from_numpy(np.array([42.0], np.float32))
+    with torch.cuda.stream(s):  # device copies current before the capture
+        for c in (x, out):
+            skel.skel_container_acquire(c, skel.DEVICE, skel.READ)
+            skel.skel_container_release(c, skel.DEVICE)
+    skel.skel_sync(s)
+    before = (out.valid_ranges(skel.HOST), out.valid_ranges(skel.DEVICE), out.stats())
+    assert before[0] == before[1] == [(0, 1)]
+    g = torch.cuda.CUDAGraph()
+    status = None
+    try:
+        with torch.cuda.graph(g, stream=s):
+            try:
+                skel.skel_mapreduce(skel.MAP_MUL, None, [x, x], skel.SUM, out, variant=mr0)
+            except skel.SkelError as e:
+                status = e.status
+    except RuntimeError:
+        pass  # torch may refuse an empty capture; the call's own status is what counts
+    assert status == skel.E_STATE
+    assert out.valid_ranges(skel.HOST) == before[0]
+    assert out.valid_ranges(skel.DEVICE) == before[1]
+    assert out.stats()["eager_equiv"] == before[2]["eager_equiv"]
+    assert out.to_numpy()[0] == 42.0

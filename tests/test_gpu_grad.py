@@ -344,3 +344,10 @@ def test_wrap_tensor_round_trip(skel, oracle_mod):
     with pytest.raises(skel.SkelError) as e:  # a view at a 4-byte offset
         skel.wrap_tensor(x[1:5])
     assert e.value.status == skel.E_INVAL
+    # an empty tensor of any shape is an empty container (Reduce: the identity)
+    ce = skel.wrap_tensor(torch.empty((0, 5), device=dev))
+    assert ce.shape == (1, 0)
+    out = skel.Container.empty(skel.F32, 1)
+    skel.skel_reduce(skel.SUM, ce, out)
+    assert out.to_numpy()[0] == 0.0
+    ce.destroy()

@@ -102,7 +102,7 @@ def test_reduce_f32(skel, oracle_mod, op):
         ref = oracle_mod.reduce(op, x)
         mag = oracle_mod.abs_sum(x)
         for v in variants(skel, skel.SK_REDUCE):
-            if v in (3, 4) and op != "sum":  # atomic and compensated finish: sums only
+            if v in (3, 4, 5) and op != "sum":  # atomic, compensated, pairwise: sums only
                 with pytest.raises(skel.SkelError) as e:
                     skel.skel_reduce(RED_OPS[op], cont(skel, x), scalar_out(skel, skel.F32),
                                      variant=v)
@@ -123,7 +123,7 @@ def test_reduce_sum_of_indices(skel, n):
     exact = n * (n - 1) // 2
     xi = np.arange(n, dtype=np.int32)
     for v in variants(skel, skel.SK_REDUCE):
-        if v != 4:  # the compensated variant is floating point only
+        if v not in (4, 5):  # compensated and pairwise: floating point only
             o32, o64 = scalar_out(skel, skel.I32), scalar_out(skel, skel.I64)
             skel.skel_reduce(skel.SUM, cont(skel, xi), o32, variant=v)
             skel.skel_reduce(skel.SUM, cont(skel, xi), o64, variant=v)
@@ -148,7 +148,7 @@ def test_reduce_int_bit_exact(skel, oracle_mod, pair, op):
         ref = oracle_mod.reduce(op, x, np.int64 if dout == skel.I64 else np.int32)
         for v in variants(skel, skel.SK_REDUCE):
             out = scalar_out(skel, dout)
-            if v == 4:
+            if v in (4, 5):
                 with pytest.raises(skel.SkelError) as e:
                     skel.skel_reduce(RED_OPS[op], cont(skel, x), out, variant=v)
                 assert e.value.status == skel.E_UNSUPPORTED
@@ -159,7 +159,7 @@ def test_reduce_int_bit_exact(skel, oracle_mod, pair, op):
 
 def test_reduce_deterministic_variants(skel):
     x = si.normal_f32((1 << 22) + 11, 1, 9)
-    for v in (0, 1, 2, 4):
+    for v in (0, 1, 2, 4, 5):
         vals = set()
         for _ in range(3):
             out = scalar_out(skel, skel.F32)
@@ -185,7 +185,7 @@ def test_mapreduce_f32(skel, oracle_mod, mop, op):
         for v in variants(skel, skel.SK_MAPREDUCE):
             out = scalar_out(skel, skel.F32)
             ins = [cont(skel, x), cont(skel, y)] if two else [cont(skel, x)]
-            if v == 4 and op != "sum":  # compensated summation: sums only
+            if v in (4, 5) and op != "sum":  # compensated, pairwise: sums only
                 with pytest.raises(skel.SkelError) as e:
                     skel.skel_mapreduce(MAP_OPS[mop], params, ins, RED_OPS[op], out,
                                         variant=v)
@@ -209,7 +209,7 @@ def test_mapreduce_bf16_inputs(skel, oracle_mod):
         ref, mag = oracle_mod.mapreduce("mul", None, xf, yf)
         rsum = oracle_mod.reduce("sum", xf)
         asum = oracle_mod.abs_sum(xf)
-        for v in (1, 2, 3, 4):
+        for v in (1, 2, 3, 4, 5):
             out = scalar_out(skel, skel.F32)
             skel.skel_mapreduce(skel.MAP_MUL, None, [cont(skel, xb, skel.BF16),
                                                      cont(skel, yb, skel.BF16)],

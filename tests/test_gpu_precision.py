@@ -10,6 +10,13 @@ and depth the longest chain of dependent additions (a few hundred at the
 launch shapes used here).  The bar written below, u*2|s| + 2^-36 sum|x|, sits
 between that worst case and the typical error; the plain variants are held to
 the general floating-point reduction bar 1e-5 sum|x|.
+
+The pairwise variants (R5, MR5) add every value along a balanced tree: each
+lane's chunk as a tree, the chunk sums by a binary counter of partial sums,
+then the cross-lane and cross-workgroup trees, at most 64 additions deep at
+these sizes (about 54 at 2^28), so |r - s| <= 64 u sum|x| (recursive summation
+bound of depth 64; one more u per product for the dot).  The sizes run up to
+2^28, the precision workload itself.
 """
 import numpy as np
 import pytest
@@ -19,8 +26,9 @@ import synth_inputs as si
 pytestmark = pytest.mark.gpu
 
 U = 2.0 ** -24
-R2, R4 = 2, 4
-MR2, MR4 = 2, 4
+R2, R4, R5 = 2, 4, 5
+MR2, MR4, MR5 = 2, 4, 5
+PAIR_DEPTH = 64
 
 
 def comp_bar(exact, mag):
@@ -43,34 +51,46 @@ def run_dot(skel, a, b, dtype, v, mop=None):
     return float(out.to_numpy()[0])
 
 
-@pytest.mark.parametrize("n", [0, 1, 7, 4097, (1 << 20) + 3, 1 << 24])
+@pytest.mark.parametrize("n", [0, 1, 7, 4097, (1 << 20) + 3, 1 << 24, 1 << 26, 1 << 28])
 def test_compensated_bf16_sum(skel, oracle_mod, n):
+    print(f"bf16 sum n={n}", flush=True)
     xb = si.log_uniform_signed_bf16(n, config=4, index=11)
     xf = si.bf16_bits_to_f32(xb)
     exact = oracle_mod.sum_bf16_exact(xb)
     mag = oracle_mod.abs_sum(xf)
+    del xf
     plain = run_reduce(skel, xb, skel.BF16, R2)
     comp = run_reduce(skel, xb, skel.BF16, R4)
-    ep, ec = abs(plain - exact), abs(comp - exact)
+    pair = run_reduce(skel, xb, skel.BF16, R5)
+    ep, ec, ew = abs(plain - exact), abs(comp - exact), abs(pair - exact)
     print(f"bf16 sum n={n}: exact={exact:.9g} plain_err={ep:.3g} comp_err={ec:.3g} "
-          f"sum|x|={mag:.3g}")
+          f"pair_err={ew:.3g} sum|x|={mag:.3g}")
     assert ep <= 1e-5 * mag + 1e-30
     assert ec <= comp_bar(exact, mag) + 1e-30, (ec, exact, mag)
+    assert ew <= PAIR_DEPTH * U * mag + 1e-30, (ew, exact, mag)
 
 
-@pytest.mark.parametrize("n", [4097, (1 << 22) + 1])
+@pytest.mark.parametrize("n", [4097, (1 << 22) + 1, 1 << 26, 1 << 28])
 def test_compensated_bf16_dot(skel, oracle_mod, n):
+    print(f"bf16 dot n={n}", flush=True)
     xb = si.log_uniform_signed_bf16(n, config=4, index=12)
     yb = si.log_uniform_signed_bf16(n, config=4, index=13)
     exact = oracle_mod.dot_bf16_exact(xb, yb)
     xf, yf = si.bf16_bits_to_f32(xb), si.bf16_bits_to_f32(yb)
-    mag = oracle_mod.fsum(np.abs(xf.astype(np.float64) * yf.astype(np.float64)))
+    # bf16 x bf16 products are exact in binary32 (8 + 8 significand bits), so
+    # the binary64 sum of their absolute values in index order is sum|x y|
+    # to within 2^-53 n
+    mag = oracle_mod.abs_sum(xf * yf)
+    del xf, yf
     plain = run_dot(skel, xb, yb, skel.BF16, MR2)
     comp = run_dot(skel, xb, yb, skel.BF16, MR4)
-    ep, ec = abs(plain - exact), abs(comp - exact)
-    print(f"bf16 dot n={n}: exact={exact:.9g} plain_err={ep:.3g} comp_err={ec:.3g}")
+    pair = run_dot(skel, xb, yb, skel.BF16, MR5)
+    ep, ec, ew = abs(plain - exact), abs(comp - exact), abs(pair - exact)
+    print(f"bf16 dot n={n}: exact={exact:.9g} plain_err={ep:.3g} comp_err={ec:.3g} "
+          f"pair_err={ew:.3g} sum|xy|={mag:.3g}")
     assert ep <= 1e-5 * mag + 1e-30
     assert ec <= comp_bar(exact, mag) + 1e-30, (ec, exact, mag)
+    assert ew <= (PAIR_DEPTH + 1) * U * mag + 1e-30, (ew, exact, mag)
 
 
 def test_compensated_f32_products(skel, oracle_mod):
