@@ -65,14 +65,21 @@ def build_hip(verbose: bool = False, jobs: int = 8) -> str:
     return LIB
 
 
-def build_hosttest(verbose: bool = False) -> str:
+HOSTTEST_SAN_LIB = os.path.join(PKG, "libskel_hosttest_san.so")
+# AddressSanitizer and UndefinedBehaviorSanitizer for the host-only builds
+SANITIZE = ["-fsanitize=address,undefined", "-fno-omit-frame-pointer",
+            "-fno-sanitize-recover=undefined"]
+
+
+def build_hosttest(verbose: bool = False, sanitize: bool = False) -> str:
     srcs = [os.path.join(CSRC, s) for s in HOST_SOURCES]
     srcs.append(os.path.join(ROOT, "tests", "host", "fake_backend.cpp"))
-    tmp = HOSTTEST_LIB + ".tmp"
-    _run(["g++", "-std=c++17", "-O1", "-g", "-fPIC", "-shared", "-Wall",
-          f"-I{INC}", f"-I{CSRC}", "-o", tmp] + srcs, verbose)
-    os.replace(tmp, HOSTTEST_LIB)
-    return HOSTTEST_LIB
+    out = HOSTTEST_SAN_LIB if sanitize else HOSTTEST_LIB
+    tmp = out + ".tmp"
+    _run(["g++", "-std=c++17", "-O1", "-g", "-fPIC", "-shared", "-Wall"] +
+         (SANITIZE if sanitize else []) + [f"-I{INC}", f"-I{CSRC}", "-o", tmp] + srcs, verbose)
+    os.replace(tmp, out)
+    return out
 
 
 def build(verbose: bool = False) -> None:
@@ -81,5 +88,13 @@ def build(verbose: bool = False) -> None:
 
 
 if __name__ == "__main__":
-    build(verbose="-v" in sys.argv)
-    print(LIB)
+    if "--sanitize" in sys.argv:
+        # the container protocol, plan and chain table (and the oracle) built
+        # with the sanitizers; see sanitize_env() for running the CPU tests
+        print(build_hosttest("-v" in sys.argv, sanitize=True))
+        sys.path.insert(0, ROOT)
+        from oracle import build as oracle_build
+        print(oracle_build.build("-v" in sys.argv, sanitize=True))
+    else:
+        build(verbose="-v" in sys.argv)
+        print(LIB)

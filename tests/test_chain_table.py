@@ -13,7 +13,9 @@ import pytest
 import synth_inputs as si
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-LIB = os.path.join(ROOT, "paper_1405_2915_amd", "libskel_hosttest.so")
+# SKEL_HOSTTEST_LIB selects another build (the sanitizer build, for one)
+LIB = os.environ.get("SKEL_HOSTTEST_LIB") or os.path.join(ROOT, "paper_1405_2915_amd",
+                                                          "libskel_hosttest.so")
 
 
 @pytest.fixture(scope="module")

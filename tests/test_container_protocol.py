@@ -15,7 +15,9 @@ import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-LIB = os.path.join(ROOT, "paper_1405_2915_amd", "libskel_hosttest.so")
+# SKEL_HOSTTEST_LIB selects another build (the sanitizer build, for one)
+LIB = os.environ.get("SKEL_HOSTTEST_LIB") or os.path.join(ROOT, "paper_1405_2915_amd",
+                                                          "libskel_hosttest.so")
 
 OK, E_INVAL, E_DTYPE, E_SHAPE, E_NOMEM, E_STATE, E_UNSUP, E_HIP = range(8)
 F32, BF16, I32, I64 = range(4)
@@ -139,7 +141,8 @@ def test_lazy_copies_and_data_flow(rt):
     # a "kernel" writes the device copy in place
     st, dp = acquire(rt, h, DEVICE, RW)
     assert st == OK
-    C.memmove(dp, (np.full(16, 7.0, np.float32)).ctypes.data, 64)
+    src = np.full(16, 7.0, np.float32)  # held while its address is in use
+    C.memmove(dp, src.ctypes.data, 64)
     assert rt.skel_container_release(h, DEVICE, C.c_void_p(1)) == OK
     # host read sees the device write: exactly one D2H, and it waited first
     before = counts(rt)["event_syncs"]
@@ -541,7 +544,8 @@ def test_partial_host_write_sends_only_that_range(rt):
     assert s0["h2d"] == 1 and s0["h2d_bytes"] == 4 * n
     st, p = _acq_range(rt, h, HOST, WRITE, 100, 50)
     assert st == OK
-    C.memmove(p, np.full(50, -1.0, np.float32).ctypes.data, 200)
+    src = np.full(50, -1.0, np.float32)  # held while its address is in use
+    C.memmove(p, src.ctypes.data, 200)
     assert rt.skel_container_release(h, HOST, None) == OK
     assert _ranges(rt, h, DEVICE) == [(0, 100), (150, n)]
     assert _ranges(rt, h, HOST) == [(0, n)]
@@ -560,7 +564,8 @@ def test_partial_host_read_copies_only_the_range(rt):
     n = 512
     h = create(rt, n, np.zeros(n, np.float32))
     st, dp = acquire(rt, h, DEVICE, WRITE)        # a kernel rewrites everything
-    C.memmove(dp, np.arange(n, dtype=np.float32).ctypes.data, 4 * n)
+    src = np.arange(n, dtype=np.float32)  # held while its address is in use
+    C.memmove(dp, src.ctypes.data, 4 * n)
     assert rt.skel_container_release(h, DEVICE, C.c_void_p(1)) == OK
     assert _ranges(rt, h, HOST) == []
     st, p = _acq_range(rt, h, HOST, READ, 10, 20)
