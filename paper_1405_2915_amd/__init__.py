@@ -31,7 +31,9 @@ except ImportError:
     torch = None
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libskel.so")
+# SKEL_LIBRARY selects another build of the library (the shrunk-tile scan
+# build of the stress test, for one)
+LIB_PATH = os.environ.get("SKEL_LIBRARY") or os.path.join(_HERE, "libskel.so")
 
 # ------------------------------------------------------------- skel.h enums
 OK, E_INVAL, E_DTYPE, E_SHAPE, E_NOMEM, E_STATE, E_UNSUPPORTED, E_HIP, E_NOINIT, \

@@ -82,8 +82,27 @@ def build_hosttest(verbose: bool = False, sanitize: bool = False) -> str:
     return out
 
 
+SCAN_STRESS_LIB = os.path.join(PKG, "libskel_scan_w2.so")
+
+
+def build_scan_stress(verbose: bool = False) -> str:
+    """libskel_scan_w2.so: the library with the scan tiles shrunk to two
+    wavefronts (4096 elements for 4-byte inputs instead of 32768), eight times
+    as many tiles and a deeper decoupled look-back, for the look-back stress
+    test.  The other objects are those of the product build."""
+    obj = os.path.join(BUILD, "k_scan.hip.w2.o")
+    _run([HIPCC] + HIP_FLAGS + ["-DSKEL_SCAN_WAVES=2", "-x", "hip", "-c",
+                                os.path.join(CSRC, "k_scan.hip"), "-o", obj], verbose)
+    objs = [os.path.join(BUILD, s + ".o") for s in HIP_SOURCES if s != "k_scan.hip"] + [obj]
+    tmp = SCAN_STRESS_LIB + ".tmp"
+    _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs, verbose)
+    os.replace(tmp, SCAN_STRESS_LIB)
+    return SCAN_STRESS_LIB
+
+
 def build(verbose: bool = False) -> None:
     build_hip(verbose)
+    build_scan_stress(verbose)
     build_hosttest(verbose)
 
 

@@ -88,3 +88,23 @@ def test_persistent_segments_repeated(skel, oracle_mod):
     skel.skel_sync()
     for c in (cx, co, cout):
         c.destroy()
+
+
+def test_shrunk_tile_lookback_stress(skel):
+    """The look-back with tiles shrunk to two wavefronts (the library built
+    with SKEL_SCAN_WAVES=2: 32768 tiles for 2^27 elements instead of 4096, so
+    each tile looks back over many more unfinished predecessors), in a child
+    process that loads that build: 20 repeats of each single-pass variant,
+    bit-identical to the oracle."""
+    import os
+    import subprocess
+    import sys
+    from paper_1405_2915_amd import build_lib
+    if not os.path.exists(build_lib.SCAN_STRESS_LIB):
+        pytest.fail("libskel_scan_w2.so not built (paper_1405_2915_amd/build_lib.py)")
+    child = os.path.join(os.path.dirname(os.path.abspath(__file__)), "scan_stress_child.py")
+    env = dict(os.environ, SKEL_LIBRARY=build_lib.SCAN_STRESS_LIB)
+    res = subprocess.run([sys.executable, "-u", child], env=env, capture_output=True,
+                         text=True, timeout=240)
+    print(res.stdout[-2000:], res.stderr[-2000:])
+    assert res.returncode == 0 and res.stdout.strip().endswith("ok")
