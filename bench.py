@@ -56,6 +56,19 @@ PLAIN = {"map_saxpy": "M0_scalar", "mapoverlap1d_5pt": "O1a_direct",
          "scan_excl_i32_i64": "S1_reduce_then_scan", "mapreduce_dot": "MR0_unfused",
          "mapoverlap2d_9x9": "O2a_direct", "reduce_sum": "R1_two_pass"}
 DOMINANT = "scan_excl_i32_i64"
+# variants bulk selection may give each call of the step (the single-workgroup
+# forms, which would take one CU at these sizes, the order-dependent atomic
+# Reduce and the slow direct 2D stencils are left out)
+STEP_SITES = {
+    "map_saxpy": ["M0_scalar", "M1_vec4", "M2_vec4x4_nt"],
+    "mapoverlap1d_5pt": ["O1a_direct", "O1b_lds_tile", "O1c_shuffle"],
+    "scan_excl_i32_i64": ["S1_reduce_then_scan", "S2_decoupled_lookback",
+                          "S3_persistent_lookback"],
+    "mapreduce_dot": ["MR1_fused_two_pass", "MR2_fused_ticket", "MR4_compensated",
+                      "MR5_pairwise"],
+    "mapoverlap2d_9x9": ["O2c_lds_separable", "O2d_separable_l1", "O2e_march"],
+    "reduce_sum": ["R1_two_pass", "R2_ticket", "R4_compensated", "R5_pairwise"],
+}
 # kernels of each Scan variant (int32 -> int64, exclusive sum)
 SCAN_KERNELS = {
     "S0_single_wg": "scan_single<int32 -> int64, exclusive sum>",
@@ -186,6 +199,40 @@ def copy_ceiling(skel, torch, reps=10):
     a.destroy()
     b.destroy()
     return 8 * n / (ms * 1e-3) / 1e9, ms
+
+
+def isolated(skel, torch, wl, name, reps, before):
+    """One skeleton of the step alone, `reps` times, each call preceded by a
+    pass over a separate 1 GiB buffer that replaces the Infinity Cache's
+    contents: `before` = "read" (a Reduce: the cache holds clean lines) or
+    "write" (a Map writing it with plain stores: the cache holds dirty
+    lines, as after the step's scan).  Kernel time from HIP events around
+    the call on the launch stream."""
+    n = 1 << 28
+    buf = skel.Container.from_numpy(np.zeros(n, np.float32))
+    dst = skel.Container.empty(skel.F32, n) if before == "write" else None
+    r = skel.Container.empty(skel.F32, 1)
+    m1 = skel.variant_index(skel.SK_MAP, "M1_vec4")  # plain 16-byte stores
+    r1 = skel.variant_index(skel.SK_REDUCE, "R1_two_pass")
+    call = dict(wl.calls())[name]
+    st = torch.cuda.current_stream()
+    evs = []
+    for _ in range(reps + 1):
+        if before == "write":
+            skel.skel_map(skel.MAP_IDENTITY, None, [buf], dst, variant=m1)
+        else:
+            skel.skel_reduce(skel.SUM, buf, r, variant=r1)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        call()
+        e1.record(st)
+        evs.append((e0, e1))
+    torch.cuda.synchronize()
+    us = float(np.median([a.elapsed_time(b) for a, b in evs[1:]])) * 1e3
+    for c in (buf, dst, r):
+        if c is not None:
+            c.destroy()
+    return us
 
 
 def traffic_from_profile(name, per_launch_bytes, variant):
@@ -629,6 +676,14 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-variant pass")
     ap.add_argument("--no-next", action="store_true",
                     help="skip the batched, bf16 and graph-replay measurements")
+    ap.add_argument("--no-bulk", action="store_true",
+                    help="time the step with the per-call plan's variants only (no bulk "
+                         "selection over the whole step)")
+    ap.add_argument("--isolate", choices=ORDER, default=None,
+                    help="time this one skeleton of the step alone (--steps calls) and exit")
+    ap.add_argument("--before", choices=["read", "write"], default="read",
+                    help="with --isolate: a 1 GiB read (clean cache) or plain write (dirty "
+                         "cache) before every call")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: the skeletons run on one GPU; --gpus {args.gpus} is not supported "
@@ -639,10 +694,54 @@ def main():
 
     skel.skel_init(0, "torch")
     wl = Workload(skel)
+    if args.isolate:
+        name = args.isolate
+        us = isolated(skel, torch, wl, name, max(args.steps, 3), args.before)
+        sk_id = {"map_saxpy": skel.SK_MAP, "mapoverlap1d_5pt": skel.SK_MAPOVERLAP1D,
+                 "scan_excl_i32_i64": skel.SK_SCAN, "mapreduce_dot": skel.SK_MAPREDUCE,
+                 "mapoverlap2d_9x9": skel.SK_MAPOVERLAP2D, "reduce_sum": skel.SK_REDUCE}[name]
+        env_key = {skel.SK_MAP: "MAP", skel.SK_MAPOVERLAP1D: "MAPOVERLAP1D",
+                   skel.SK_SCAN: "SCAN", skel.SK_MAPREDUCE: "MAPREDUCE",
+                   skel.SK_MAPOVERLAP2D: "MAPOVERLAP2D", skel.SK_REDUCE: "REDUCE"}[sk_id]
+        var = os.environ.get("SKEL_VARIANT_" + env_key)
+        gbs = BYTES[name] / (us * 1e-6) / 1e9
+        print(json.dumps({"isolated": name, "before": args.before,
+                          "variant": var or skel.skel_variant_name(sk_id, wl.selected()[name]),
+                          "us": round(us, 2), "GBps": round(gbs, 1),
+                          "frac_hbm": round(gbs / HBM_PEAK_GBS, 4), "calls": args.steps}),
+              flush=True)
+        return
     calls = wl.calls()
     log(f"warmup {args.warmup} (first call copies every operand to HBM once)")
     run_steps(torch, calls, max(args.warmup, 1), with_events=False)
     skel.skel_sync()
+    ids = {"map_saxpy": skel.SK_MAP, "mapoverlap1d_5pt": skel.SK_MAPOVERLAP1D,
+           "scan_excl_i32_i64": skel.SK_SCAN, "mapreduce_dot": skel.SK_MAPREDUCE,
+           "mapoverlap2d_9x9": skel.SK_MAPOVERLAP2D, "reduce_sum": skel.SK_REDUCE}
+    plan_sel = wl.selected()
+    names = lambda a: {k: skel.skel_variant_name(ids[k], v) for k, v in a.items()}
+
+    def time_chain(assign, steps=8, samples=3):
+        cl = wl.calls(assign)
+        run_steps(torch, cl, 2, with_events=False)
+        return float(np.median([run_steps(torch, cl, steps, with_events=False)[0] / steps * 1e3
+                                for _ in range(samples)]))
+    selection = {"per_call_plan": names(plan_sel)}
+    sel = plan_sel
+    if not args.no_bulk:
+        # global composition over the step (Section V): the variants of all six
+        # calls chosen together by whole-step time, from the plan's choices
+        from paper_1405_2915_amd import compose
+        log("bulk selection of the step's variants (whole-step timings)")
+        sites = {k: [skel.variant_index(ids[k], nm) for nm in v] for k, v in STEP_SITES.items()}
+        sel, rep = compose.bulk_select(time_chain, sites, plan_sel)
+        skel.skel_sync()
+        selection.update({"bulk": names(sel), "per_call_plan_ms_per_step": round(rep["start_ms"], 4),
+                          "bulk_ms_per_step": round(rep["final_ms"], 4),
+                          "whole_step_trials": len(rep["trials"])})
+        calls = wl.calls(sel)
+        run_steps(torch, calls, 2, with_events=False)
+        skel.skel_sync()
     xfer_before = {k: getattr(wl, k).stats() for k in ("x", "y", "z", "s", "img")}
     log(f"timing {args.steps} steps")
     el, ms_dom = run_steps(torch, calls, args.steps, with_events={DOMINANT})
@@ -657,7 +756,6 @@ def main():
     _, ms = run_steps(torch, calls, max(5, args.steps // 2), with_events=True)
     skel.skel_sync()
 
-    sel = wl.selected()
     per = {}
     for name in ORDER:
         avg = float(np.mean(ms[name]))
@@ -713,6 +811,7 @@ def main():
         "copy_ceiling_GBps": round(ceil_gbs, 1),
         "per_skeleton": per,
         "speedup_vs_plain": speedup,
+        "selection": selection,
     }
     if not args.no_next:
         log("graph replay of one step")
