@@ -308,8 +308,9 @@ skel_status skel_mapoverlap2d_fields(skel_container *in, skel_container *out,
  * out[i] = in[i] op ... op in[n-1]; reverse exclusive out[n-1] = identity,
  * out[i] = in[i+1] op ... op in[n-1].  Type pairs: I32 -> I32 (wraps), I32 ->
  * I64, I64 -> I64 (exact, wrapping), F32 -> F32.  out may equal in when the
- * types agree.  The reverse kinds run in the single-pass variants only (S2
- * and S3; a forced S0 or S1 gives SKEL_E_UNSUPPORTED). */
+ * types agree.  The reverse kinds run in the single-pass variants only (S2,
+ * S3 and S4, the single pass with small tiles; a forced S0 or S1 gives
+ * SKEL_E_UNSUPPORTED). */
 skel_status skel_scan(skel_container *in, skel_container *out,
                       skel_scan_kind kind, skel_reduce_op op, int variant,
                       void *stream);

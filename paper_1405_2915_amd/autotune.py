@@ -11,9 +11,15 @@ target system.  This module is that off-line step for one GPU:
 
 For each tuned skeleton (sum Reduce, dot MapReduce, inclusive int32 Scan,
 saxpy Map, 5-point MapOverlap1D, 9x9 separable MapOverlap2D on a near-square
-image) and each size n = 2^k it times every selectable variant (forced), as the median of `reps` runs measured with HIP events on the
-launch stream, with the 256 MiB Infinity Cache evicted before every timed call
-(by reading a 512 MiB buffer); it writes the fastest variant per
+image) and each size n = 2^k it times every selectable variant (forced) with
+HIP events on the launch stream.  Above 2^22 elements: the median of `reps`
+single calls, each after the 256 MiB Infinity Cache was evicted (by reading a
+512 MiB buffer).  Up to 2^22 elements, where one call lasts a few
+microseconds: after one eviction, `burst` calls back to back between one
+event pair, the time per call being their span divided by `burst` (median of
+`reps` bursts) -- so the figure is the kernels' time on the device, not the
+host's issue time of one call, and later calls of a burst find their operands
+in the caches, as calls of that size do in a loop.  It writes the fastest variant per
 (skeleton, dtype, log2 n) as a plan table (the text format of skel_load_plan)
 and a JSON report of every timing.  Single-workgroup variants are not timed
 above 2^22 elements (they use one CU of 256).  The atomic-finish Reduce (R3),
@@ -38,18 +44,26 @@ DEFAULT_PLAN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "plans",
 SINGLE_WG_MAX_LOG2 = 22
 
 
-def _timed(torch, fn, evict, reps):
+BURST_MAX_LOG2 = 22  # sizes timed as bursts of back-to-back calls
+BURST = 20
+
+
+def _timed(torch, fn, evict, reps, burst=1):
+    """Median over `reps` of (event span around `burst` back-to-back calls) /
+    burst, in microseconds, the Infinity Cache evicted before each span."""
     st = torch.cuda.current_stream()
+    fn()  # sizes the stream's workspace; first-use costs stay out of the timing
     times = []
     for _ in range(reps):
         evict()
         a = torch.cuda.Event(enable_timing=True)
         b = torch.cuda.Event(enable_timing=True)
         a.record(st)
-        fn()
+        for _ in range(burst):
+            fn()
         b.record(st)
         b.synchronize()
-        times.append(a.elapsed_time(b) * 1e3)
+        times.append(a.elapsed_time(b) * 1e3 / burst)
     return float(np.median(times))
 
 
@@ -111,13 +125,15 @@ def tune(lo=10, hi=28, reps=7, log=print, allow_order_dependent=False):
                 vname = skel.skel_variant_name(sk, v)
                 if vname == single.get(sk) and k > SINGLE_WG_MAX_LOG2:
                     continue
-                res[vname] = round(_timed(torch, lambda: call(v), evict, reps), 3)
+                burst = BURST if k <= BURST_MAX_LOG2 else 1
+                res[vname] = round(_timed(torch, lambda: call(v), evict, reps, burst), 3)
             report["results"].setdefault(name, {})[str(k)] = res
             log(f"{name:10s} 2^{k:2d}: " + "  ".join(f"{a}={b:.1f}" for a, b in res.items()))
         for c in (x, y, s, so, out1, o1, img, imo):
             c.destroy()
     report["dtypes"] = {"REDUCE": "f32", "MAPREDUCE": "f32", "SCAN": "i32", "MAP": "f32",
                         "MAPOVERLAP1D": "f32", "MAPOVERLAP2D": "f32"}
+    report["timing"] = {"burst_max_log2": BURST_MAX_LOG2, "burst": BURST}
     # the stencil class each MapOverlap entry was tuned on: radius 2 (the
     # 5-point binomial) in 1D, separable 9 x 9 (1 + 2 * 4) in 2D
     report["classes"] = {"MAPOVERLAP1D": 2, "MAPOVERLAP2D": 1 + 2 * 4}
@@ -147,6 +163,38 @@ def plan_from_report(report, tol=0.05, allow_order_dependent=False):
     return table
 
 
+# the single fixed plain form each plan choice is compared with
+PLAIN = {"REDUCE": "R1_two_pass", "MAPREDUCE": "MR0_unfused", "SCAN": "S1_reduce_then_scan",
+         "MAP": "M0_scalar", "MAPOVERLAP1D": "O1a_direct", "MAPOVERLAP2D": "O2a_direct"}
+
+
+def write_summary(report, table, path, header):
+    """Markdown: for every skeleton and size, every variant's time, the
+    plan's choice and its speedup over the fixed plain form."""
+    choice = {(name, k): v for name, _dt, k, v, _c in table}
+    with open(path, "w") as f:
+        f.write("# Off-line tuning sweep: every variant at every size (us per call)\n\n")
+        for line in header:
+            f.write(f"{line}\n\n")
+        f.write("Command: `python -m paper_1405_2915_amd.autotune --report FILE.json "
+                "--summary FILE.md` (writes the plan to plans/gfx950.plan).\n\n")
+        for name, per_k in report["results"].items():
+            variants = sorted({v for r in per_k.values() for v in r})
+            plain = PLAIN.get(name)
+            f.write(f"## {name} ({report['dtypes'].get(name, 'f32')})\n\n")
+            f.write("| log2 n | " + " | ".join(variants) + " | plan | speedup vs "
+                    f"{plain} |\n")
+            f.write("|---:|" + "---:|" * len(variants) + "---|---:|\n")
+            for k in sorted(per_k, key=int):
+                r = per_k[k]
+                pick = choice.get((name, int(k)))
+                cells = [f"{r[v]:.2f}" if v in r else "-" for v in variants]
+                sp = (f"{r[plain] / r[pick]:.2f}" if plain in r and pick in r and r[pick] > 0
+                      else "-")
+                f.write(f"| {k} | " + " | ".join(cells) + f" | {pick} | {sp} |\n")
+            f.write("\n")
+
+
 def write_plan(table, path, header):
     os.makedirs(os.path.dirname(path), exist_ok=True)
     with open(path, "w") as f:
@@ -166,6 +214,9 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=DEFAULT_PLAN)
     ap.add_argument("--report", default=None)
+    ap.add_argument("--summary", default=None,
+                    help="also write a markdown table of every timing and the speedup over "
+                         "the fixed plain form")
     ap.add_argument("--min", type=int, default=10)
     ap.add_argument("--max", type=int, default=28)
     ap.add_argument("--reps", type=int, default=7)
@@ -179,6 +230,8 @@ def main():
             report = json.load(f)
         table = plan_from_report(report, allow_order_dependent=args.allow_order_dependent)
         write_plan(table, args.out, report.get("header", []))
+        if args.summary:
+            write_summary(report, table, args.summary, report.get("header", []))
         print(json.dumps({"plan": args.out, "entries": len(table)}))
         return
     log = lambda m: print(f"[autotune] {m}", file=sys.stderr, flush=True)
@@ -190,10 +243,14 @@ def main():
                         f"sizes 2^{args.min}..2^{args.max}, median of {args.reps}, "
                         "Infinity Cache evicted before each timed call; a choice is kept "
                         "while within 5% of the fastest"]
+    report["header"].append(f"sizes up to 2^{BURST_MAX_LOG2}: bursts of {BURST} back-to-back "
+                            "calls per event pair")
     write_plan(table, args.out, report["header"])
     if args.report:
         with open(args.report, "w") as f:
             json.dump(report, f, indent=1)
+    if args.summary:
+        write_summary(report, table, args.summary, report["header"])
     print(json.dumps({"plan": args.out, "entries": len(table)}))
 
 

@@ -29,7 +29,8 @@ const char* const kOverlap1D[] = {"O1a_direct", "O1b_lds_tile", "O1c_shuffle"};
 const char* const kOverlap2D[] = {"O2a_direct", "O2b_lds_tile", "O2c_lds_separable",
                                   "O2d_separable_l1", "O2e_march"};
 const char* const kScan[] = {"S0_single_wg", "S1_reduce_then_scan",
-                             "S2_decoupled_lookback", "S3_persistent_lookback"};
+                             "S2_decoupled_lookback", "S3_persistent_lookback",
+                             "S4_small_tile_lookback"};
 
 const char* const kSegments[] = {"B0_per_segment", "B1_persistent"};
 const char* const kScanRows[] = {"SR0_per_row", "SR1_wave_per_row"};
@@ -238,7 +239,8 @@ bool selectable(int v, const CallContext& c, const char** why) {
         }
         return true;
     case SKEL_SK_SCAN:
-        if (c.reverse && v != S2_LOOKBACK && v != S3_PERSISTENT_LOOKBACK) {
+        if (c.reverse && v != S2_LOOKBACK && v != S3_PERSISTENT_LOOKBACK &&
+            v != S4_SMALL_TILE_LOOKBACK) {
             *why = "reverse scans run in the single-pass variants only";
             return false;
         }

@@ -23,7 +23,7 @@ enum Overlap1DVariant { O1A_DIRECT = 0, O1B_LDS_TILE = 1, O1C_SHUFFLE = 2, OVERL
 enum Overlap2DVariant { O2A_DIRECT = 0, O2B_LDS_TILE = 1, O2C_LDS_SEPARABLE = 2,
                         O2D_SEPARABLE_L1 = 3, O2E_MARCH = 4, OVERLAP2D_NVAR };
 enum ScanVariant { S0_SINGLE_WG = 0, S1_REDUCE_THEN_SCAN = 1, S2_LOOKBACK = 2,
-                   S3_PERSISTENT_LOOKBACK = 3, SCAN_NVAR };
+                   S3_PERSISTENT_LOOKBACK = 3, S4_SMALL_TILE_LOOKBACK = 4, SCAN_NVAR };
 enum SegmentsVariant { B0_PER_SEGMENT = 0, B1_PERSISTENT = 1, SEGMENTS_NVAR };
 enum ScanRowsVariant { SR0_PER_ROW = 0, SR1_WAVE_PER_ROW = 1, SCANROWS_NVAR };
 // the call chain Map -> MapOverlap 2D -> Reduce SUM (forward and backward)

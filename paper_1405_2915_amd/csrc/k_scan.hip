@@ -27,6 +27,10 @@
 //       on a retry only the descriptors that were not yet valid are re-read.
 //       Tiles are numbered by an atomic counter in start order, so every tile
 //       waited on is already resident: the wait always ends.
+//   S4  S2 with tiles of two wavefronts (4096 elements for 4-byte inputs,
+//       2048 for 8-byte): for arrays of a few million elements, whose 32768-
+//       element tiles would leave most CUs idle (2^20 elements: 256 tiles
+//       instead of 32)
 //   S3  S2's tile step run by persistent workgroups (one per resident slot)
 //       that loop over tile ids; a workgroup takes its next id once its
 //       stores are issued, so no workgroup launch sits between one tile's
@@ -58,7 +62,7 @@ using namespace dev;
 
 constexpr uint32_t kSpinLimit = 1u << 22;
 
-template <int DIN, int DOUT, int OP>
+template <int DIN, int DOUT, int OP, int WAVES = SKEL_SCAN_WAVES>
 struct SP {
     using in_t = typename Stored<DIN>::type;
     using out_t = typename Stored<DOUT>::type;
@@ -69,7 +73,7 @@ struct SP {
     static constexpr int kWaveElems = kWave * E * R;      // 2048
     // wavefronts per workgroup: 16 for 4-byte inputs; 8 for 8-byte inputs,
     // whose raw rows need twice the registers
-    static constexpr int NW = sizeof(in_t) == 4 ? SKEL_SCAN_WAVES : SKEL_SCAN_WAVES / 2;
+    static constexpr int NW = sizeof(in_t) == 4 ? WAVES : (WAVES > 1 ? WAVES / 2 : 1);
     static constexpr int kBlock = NW * kWave;
     static constexpr int64_t kTile = (int64_t)NW * kWaveElems;
 };
@@ -577,8 +581,22 @@ skel_status scan_typed(int v, int kind, const void* x, void* y, int64_t n, Launc
     const bool rev = kind == SKEL_REVERSE_INCLUSIVE || kind == SKEL_REVERSE_EXCLUSIVE;
     const int excl = (kind == SKEL_EXCLUSIVE || kind == SKEL_REVERSE_EXCLUSIVE) ? 1 : 0;
     hipStream_t st = lc.stream;
-    if (rev && v != S2_LOOKBACK && v != S3_PERSISTENT_LOOKBACK)
+    if (rev && v != S2_LOOKBACK && v != S3_PERSISTENT_LOOKBACK && v != S4_SMALL_TILE_LOOKBACK)
         return fail(SKEL_E_UNSUPPORTED, "reverse scans run in the single-pass variants only");
+    if (v == S4_SMALL_TILE_LOOKBACK) {
+        using PS = SP<DIN, DOUT, OP, 2>;
+        const int64_t nts = (n + PS::kTile - 1) / PS::kTile;
+        void* status = nullptr;
+        skel_status e = ws_status(lc, (size_t)nts * 16, &status);
+        if (e != SKEL_OK) return e;
+        if (rev)
+            scan_lookback<PS, true><<<(unsigned)nts, PS::kBlock, 0, st>>>(
+                in, out, n, nts, excl, static_cast<u64*>(status), lc.ws->sync);
+        else
+            scan_lookback<PS, false><<<(unsigned)nts, PS::kBlock, 0, st>>>(
+                in, out, n, nts, excl, static_cast<u64*>(status), lc.ws->sync);
+        return launch_check("scan_lookback_small");
+    }
     switch (v) {
     case S0_SINGLE_WG:
         scan_single<P><<<1, P::kBlock, 0, st>>>(in, out, n, ntiles, excl);

@@ -317,7 +317,7 @@ def name_of(lib, sk, v):
 
 
 def test_variant_registry(rt):
-    want = {SK_MAP: 3, SK_REDUCE: 6, SK_MAPREDUCE: 6, SK_OV1: 3, SK_OV2: 5, SK_SCAN: 4,
+    want = {SK_MAP: 3, SK_REDUCE: 6, SK_MAPREDUCE: 6, SK_OV1: 3, SK_OV2: 5, SK_SCAN: 5,
             SK_SEG: 2, SK_OV1B: 2, SK_OV2B: 2, SK_SCANROWS: 2, SK_CHAIN: 2}
     for sk, k in want.items():
         assert rt.skel_variant_count(sk) == k

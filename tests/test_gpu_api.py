@@ -121,7 +121,8 @@ def test_variant_names_and_plan(skel):
     assert names[skel.SK_REDUCE] == ["R0_single_wg", "R1_two_pass", "R2_ticket", "R3_atomic",
                                      "R4_compensated", "R5_pairwise"]
     assert names[skel.SK_MAPREDUCE][4:] == ["MR4_compensated", "MR5_pairwise"]
-    assert names[skel.SK_SCAN][2:] == ["S2_decoupled_lookback", "S3_persistent_lookback"]
+    assert names[skel.SK_SCAN][2:] == ["S2_decoupled_lookback", "S3_persistent_lookback",
+                                       "S4_small_tile_lookback"]
     # the tuned plan picks one of the single-pass variants for a large scan
     assert skel.skel_select_variant(skel.SK_SCAN, skel.I32, 1 << 27) in (2, 3)
 

@@ -28,7 +28,7 @@ def cont(skel, a, dtype=None):
 
 
 # ------------------------------------------------------------ reverse scans
-SINGLE_PASS = (2, 3)  # S2 decoupled look-back, S3 its persistent form
+SINGLE_PASS = (2, 3, 4)  # S2 decoupled look-back, S3 its persistent form, S4 small tiles
 
 
 @pytest.mark.parametrize("pair", ["i32_i32", "i32_i64", "i64_i64"])

@@ -15,7 +15,7 @@ import synth_inputs as si
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("variant", [2, 3])
+@pytest.mark.parametrize("variant", [2, 3, 4])
 def test_lookback_scan_repeated(skel, oracle_mod, variant):
     import torch
     n = 1 << 27
