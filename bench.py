@@ -65,9 +65,9 @@ STEP_SITES = {
     "scan_excl_i32_i64": ["S1_reduce_then_scan", "S2_decoupled_lookback",
                           "S3_persistent_lookback"],
     "mapreduce_dot": ["MR1_fused_two_pass", "MR2_fused_ticket", "MR4_compensated",
-                      "MR5_pairwise"],
+                      "MR5_pairwise", "MR6_fused_gather"],
     "mapoverlap2d_9x9": ["O2c_lds_separable", "O2d_separable_l1", "O2e_march"],
-    "reduce_sum": ["R1_two_pass", "R2_ticket", "R4_compensated", "R5_pairwise"],
+    "reduce_sum": ["R1_two_pass", "R2_ticket", "R4_compensated", "R5_pairwise", "R6_gather"],
 }
 # kernels of each Scan variant (int32 -> int64, exclusive sum)
 SCAN_KERNELS = {
@@ -612,7 +612,11 @@ def cpu_baseline(wl):
 
 def small_config(skel, torch):
     """The small configuration (2^20 elements, resident in the 256 MiB
-    Infinity Cache, launch-bound): median kernel time per call."""
+    Infinity Cache, latency-bound): device time per call from bursts of 50
+    back-to-back calls between one event pair, enqueued behind a spin kernel
+    so that host issue gaps stay out (the plan's variant for each call), every
+    Reduce and single-pass Scan variant on its own, and the four calls as one
+    step issued call by call and replayed as a captured graph."""
     import synth_inputs as si
     n = 1 << 20
     x = skel.Container.from_numpy(si.uniform_f32(n, -1.0, 1.0, 0, 0))
@@ -624,42 +628,57 @@ def small_config(skel, torch):
     r = skel.Container.empty(skel.F32, 1)
     w5 = si.binomial5_weights()
     calls = {
-        "map_saxpy": (12 * n, lambda: skel.skel_map(skel.MAP_AXPY, [2.5], [x, y], y)),
-        "reduce_sum": (4 * n, lambda: skel.skel_reduce(skel.SUM, x, r)),
-        "scan_incl_i32": (8 * n, lambda: skel.skel_scan(s, so, skel.INCLUSIVE, skel.SUM)),
-        "mapoverlap1d_5pt": (8 * n, lambda: skel.skel_mapoverlap1d(z, o, w5, 2,
-                                                                   skel.EDGE_CLAMP)),
+        "map_saxpy": (12 * n, skel.SK_MAP, skel.F32,
+                      lambda v=-1: skel.skel_map(skel.MAP_AXPY, [2.5], [x, y], y, variant=v)),
+        "reduce_sum": (4 * n, skel.SK_REDUCE, skel.F32,
+                       lambda v=-1: skel.skel_reduce(skel.SUM, x, r, variant=v)),
+        "scan_incl_i32": (8 * n, skel.SK_SCAN, skel.I32,
+                          lambda v=-1: skel.skel_scan(s, so, skel.INCLUSIVE, skel.SUM,
+                                                      variant=v)),
+        "mapoverlap1d_5pt": (8 * n, skel.SK_MAPOVERLAP1D, skel.F32,
+                             lambda v=-1: skel.skel_mapoverlap1d(z, o, w5, 2, skel.EDGE_CLAMP,
+                                                                 variant=v)),
     }
-    res = {"elements": n}
-    for name, (nbytes, fn) in calls.items():
-        ms = time_call(torch, fn, 50)
-        res[name] = {"us": round(ms * 1e3, 2), "GBps": round(nbytes / (ms * 1e-3) / 1e9, 1)}
-    # the four calls as one step, issued call by call and replayed as a
-    # captured HIP graph (launch-bound work is where the graph pays)
+    from paper_1405_2915_amd.autotune import SpinCalibration, burst_us
+    burst = 50
     stream = torch.cuda.Stream()
-    reps = 200
+
+    def per_call_us(body, reps=burst):
+        body()
+        return burst_us(torch, body, reps, spin)
+
+    res = {"elements": n,
+           "timing": f"bursts of {burst} back-to-back calls per event pair, enqueued behind "
+                     "a spin kernel (device time, no host issue gaps)"}
     with torch.cuda.stream(stream):
-        for _, fn in calls.values():  # sizes this stream's workspace outside the capture
+        spin = SpinCalibration(torch)
+        for name, (nbytes, sk, dt, fn) in calls.items():
+            us = per_call_us(fn)
+            v = skel.skel_select_variant(sk, dt, n, aux=2 if sk == skel.SK_MAPOVERLAP1D else 0)
+            res[name] = {"variant": skel.skel_variant_name(sk, v), "us": round(us, 2),
+                         "GBps": round(nbytes / (us * 1e-6) / 1e9, 1)}
+        # the latency-bound variants one by one (the single-workgroup forms
+        # and the order-dependent atomic finish left out)
+        for name, sk, keep in (("reduce_sum", skel.SK_REDUCE,
+                                ("R1_two_pass", "R2_ticket", "R6_gather")),
+                               ("scan_incl_i32", skel.SK_SCAN,
+                                ("S1_reduce_then_scan", "S2_decoupled_lookback",
+                                 "S3_persistent_lookback", "S4_small_tile_lookback",
+                                 "S5_flat_lookback"))):
+            fn = calls[name][3]
+            res[name]["variants_us"] = {
+                vn: round(per_call_us(lambda: fn(skel.variant_index(sk, vn))), 2) for vn in keep}
+        # the four calls as one step (launch-bound work is where the graph pays)
+        for _, _, _, fn in calls.values():  # sizes this stream's workspace outside the capture
             fn()
         torch.cuda.synchronize()
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g, stream=stream):
-            for _, fn in calls.values():
+            for _, _, _, fn in calls.values():
                 fn()
         torch.cuda.synchronize()
-
-        def per_step(body):
-            body()
-            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            a.record(stream)
-            for _ in range(reps):
-                body()
-            b.record(stream)
-            b.synchronize()
-            return a.elapsed_time(b) / reps * 1e3
-
-        eager = per_step(lambda: [fn() for _, fn in calls.values()])
-        graph = per_step(g.replay)
+        eager = per_call_us(lambda: [fn() for _, _, _, fn in calls.values()], 25)
+        graph = per_call_us(g.replay, 25)
     skel.skel_sync(stream)
     res["step_of_four"] = {"eager_us": round(eager, 2), "graph_us": round(graph, 2)}
     for c in (x, y, s, so, z, o, r):
@@ -679,6 +698,9 @@ def main():
     ap.add_argument("--no-bulk", action="store_true",
                     help="time the step with the per-call plan's variants only (no bulk "
                          "selection over the whole step)")
+    ap.add_argument("--small", action="store_true",
+                    help="time only the small configuration (2^20 elements) and print its "
+                         "JSON")
     ap.add_argument("--isolate", choices=ORDER, default=None,
                     help="time this one skeleton of the step alone (--steps calls) and exit")
     ap.add_argument("--before", choices=["read", "write"], default="read",
@@ -693,6 +715,11 @@ def main():
     import paper_1405_2915_amd as skel
 
     skel.skel_init(0, "torch")
+    if args.small:
+        res = small_config(skel, torch)
+        res["dispatch"] = dispatch_overhead(skel, torch)
+        print(json.dumps({"small_config": res}), flush=True)
+        return
     wl = Workload(skel)
     if args.isolate:
         name = args.isolate

@@ -309,8 +309,10 @@ skel_status skel_mapoverlap2d_fields(skel_container *in, skel_container *out,
  * out[i] = in[i+1] op ... op in[n-1].  Type pairs: I32 -> I32 (wraps), I32 ->
  * I64, I64 -> I64 (exact, wrapping), F32 -> F32.  out may equal in when the
  * types agree.  The reverse kinds run in the single-pass variants only (S2,
- * S3 and S4, the single pass with small tiles; a forced S0 or S1 gives
- * SKEL_E_UNSUPPORTED). */
+ * S3, S4 -- the single pass with small tiles -- and S5, the flat look-back
+ * over those tiles; a forced S0 or S1 gives SKEL_E_UNSUPPORTED).  S5 takes at
+ * most 1024 tiles: 2^22 elements, 2^21 for I64 inputs (SKEL_E_UNSUPPORTED
+ * beyond). */
 skel_status skel_scan(skel_container *in, skel_container *out,
                       skel_scan_kind kind, skel_reduce_op op, int variant,
                       void *stream);

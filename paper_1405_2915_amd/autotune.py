@@ -17,9 +17,12 @@ single calls, each after the 256 MiB Infinity Cache was evicted (by reading a
 512 MiB buffer).  Up to 2^22 elements, where one call lasts a few
 microseconds: after one eviction, `burst` calls back to back between one
 event pair, the time per call being their span divided by `burst` (median of
-`reps` bursts) -- so the figure is the kernels' time on the device, not the
-host's issue time of one call, and later calls of a burst find their operands
-in the caches, as calls of that size do in a loop.  It writes the fastest variant per
+`reps` bursts).  A spin kernel ahead of the pair holds the stream until the
+host has enqueued the whole burst, so the calls run back to back at the
+device's pace: the figure is the kernels' time on the device, not the host's
+issue time of a call (a few microseconds through Python and the C ABI, as
+long as a small kernel), and later calls of a burst find their operands in
+the caches, as calls of that size do in a loop.  It writes the fastest variant per
 (skeleton, dtype, log2 n) as a plan table (the text format of skel_load_plan)
 and a JSON report of every timing.  Single-workgroup variants are not timed
 above 2^22 elements (they use one CU of 256).  The atomic-finish Reduce (R3),
@@ -48,22 +51,70 @@ BURST_MAX_LOG2 = 22  # sizes timed as bursts of back-to-back calls
 BURST = 20
 
 
-def _timed(torch, fn, evict, reps, burst=1):
-    """Median over `reps` of (event span around `burst` back-to-back calls) /
-    burst, in microseconds, the Infinity Cache evicted before each span."""
+class SpinCalibration:
+    """Cycles of torch.cuda._sleep (a spin kernel) per microsecond, measured
+    once with events."""
+
+    def __init__(self, torch):
+        st = torch.cuda.current_stream()
+        torch.cuda._sleep(1000)
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        cycles = 1 << 22
+        a.record(st)
+        torch.cuda._sleep(cycles)
+        b.record(st)
+        b.synchronize()
+        self.cycles_per_us = cycles / max(a.elapsed_time(b) * 1e3, 1e-3)
+
+
+def burst_us(torch, fn, burst, spin, before=None):
+    """Device time per call (us) of `burst` back-to-back calls of fn.  A spin
+    kernel holds the stream while the host enqueues the burst (it spins for
+    three times the host's measured issue time of one burst, plus 100 us), so
+    the calls then run back to back at the device's pace and the event pair
+    around them sees no host issue gaps: small calls are timed by the GPU, not
+    by the Python and C-ABI cost of issuing them.  `before` (e.g. a cache
+    eviction pass) runs ahead of the spin."""
+    import time
+    st = torch.cuda.current_stream()
+    t0 = time.perf_counter()
+    for _ in range(burst):
+        fn()
+    host_us = (time.perf_counter() - t0) * 1e6
+    torch.cuda.synchronize()
+    if before is not None:
+        before()
+    torch.cuda._sleep(int(spin.cycles_per_us * (3.0 * host_us + 100.0)))
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(st)
+    for _ in range(burst):
+        fn()
+    b.record(st)
+    b.synchronize()
+    return a.elapsed_time(b) * 1e3 / burst
+
+
+def _timed(torch, fn, evict, reps, burst=1, spin=None):
+    """Median over `reps` of the device time per call in microseconds, the
+    Infinity Cache evicted before each timing: one call per event pair, or
+    (burst > 1) a burst of back-to-back calls behind a spin kernel."""
     st = torch.cuda.current_stream()
     fn()  # sizes the stream's workspace; first-use costs stay out of the timing
     times = []
     for _ in range(reps):
+        if burst > 1:
+            times.append(burst_us(torch, fn, burst, spin, before=evict))
+            continue
         evict()
         a = torch.cuda.Event(enable_timing=True)
         b = torch.cuda.Event(enable_timing=True)
         a.record(st)
-        for _ in range(burst):
-            fn()
+        fn()
         b.record(st)
         b.synchronize()
-        times.append(a.elapsed_time(b) * 1e3 / burst)
+        times.append(a.elapsed_time(b) * 1e3)
     return float(np.median(times))
 
 
@@ -86,6 +137,7 @@ def tune(lo=10, hi=28, reps=7, log=print, allow_order_dependent=False):
 
     evict()
     torch.cuda.synchronize()
+    spin = SpinCalibration(torch)
     report = {"lo": lo, "hi": hi, "reps": reps, "unit": "us", "results": {}}
     single = {skel.SK_REDUCE: "R0_single_wg", skel.SK_MAPREDUCE: "MR3_fused_single_wg",
               skel.SK_SCAN: "S0_single_wg"}
@@ -126,14 +178,21 @@ def tune(lo=10, hi=28, reps=7, log=print, allow_order_dependent=False):
                 if vname == single.get(sk) and k > SINGLE_WG_MAX_LOG2:
                     continue
                 burst = BURST if k <= BURST_MAX_LOG2 else 1
-                res[vname] = round(_timed(torch, lambda: call(v), evict, reps, burst), 3)
+                try:
+                    res[vname] = round(_timed(torch, lambda: call(v), evict, reps, burst,
+                                                   spin), 3)
+                except skel.SkelError as err:
+                    if err.status != skel.E_UNSUPPORTED:
+                        raise
+                    # not selectable at this size (e.g. S5 beyond 1024 tiles)
             report["results"].setdefault(name, {})[str(k)] = res
             log(f"{name:10s} 2^{k:2d}: " + "  ".join(f"{a}={b:.1f}" for a, b in res.items()))
         for c in (x, y, s, so, out1, o1, img, imo):
             c.destroy()
     report["dtypes"] = {"REDUCE": "f32", "MAPREDUCE": "f32", "SCAN": "i32", "MAP": "f32",
                         "MAPOVERLAP1D": "f32", "MAPOVERLAP2D": "f32"}
-    report["timing"] = {"burst_max_log2": BURST_MAX_LOG2, "burst": BURST}
+    report["timing"] = {"burst_max_log2": BURST_MAX_LOG2, "burst": BURST,
+                        "spin_cycles_per_us": round(spin.cycles_per_us, 1)}
     # the stencil class each MapOverlap entry was tuned on: radius 2 (the
     # 5-point binomial) in 1D, separable 9 x 9 (1 + 2 * 4) in 2D
     report["classes"] = {"MAPOVERLAP1D": 2, "MAPOVERLAP2D": 1 + 2 * 4}
@@ -244,7 +303,8 @@ def main():
                         "Infinity Cache evicted before each timed call; a choice is kept "
                         "while within 5% of the fastest"]
     report["header"].append(f"sizes up to 2^{BURST_MAX_LOG2}: bursts of {BURST} back-to-back "
-                            "calls per event pair")
+                            "calls per event pair, enqueued behind a spin kernel (device "
+                            "time)")
     write_plan(table, args.out, report["header"])
     if args.report:
         with open(args.report, "w") as f:

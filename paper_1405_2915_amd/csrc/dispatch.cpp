@@ -21,16 +21,18 @@ namespace {
 
 const char* const kMap[] = {"M0_scalar", "M1_vec4", "M2_vec4x4_nt"};
 const char* const kReduce[] = {"R0_single_wg", "R1_two_pass", "R2_ticket",
-                               "R3_atomic", "R4_compensated", "R5_pairwise"};
+                               "R3_atomic", "R4_compensated", "R5_pairwise",
+                               "R6_gather"};
 const char* const kMapReduce[] = {"MR0_unfused", "MR1_fused_two_pass",
                                   "MR2_fused_ticket", "MR3_fused_single_wg",
-                                  "MR4_compensated", "MR5_pairwise"};
+                                  "MR4_compensated", "MR5_pairwise",
+                                  "MR6_fused_gather"};
 const char* const kOverlap1D[] = {"O1a_direct", "O1b_lds_tile", "O1c_shuffle"};
 const char* const kOverlap2D[] = {"O2a_direct", "O2b_lds_tile", "O2c_lds_separable",
                                   "O2d_separable_l1", "O2e_march"};
 const char* const kScan[] = {"S0_single_wg", "S1_reduce_then_scan",
                              "S2_decoupled_lookback", "S3_persistent_lookback",
-                             "S4_small_tile_lookback"};
+                             "S4_small_tile_lookback", "S5_flat_lookback"};
 
 const char* const kSegments[] = {"B0_per_segment", "B1_persistent"};
 const char* const kScanRows[] = {"SR0_per_row", "SR1_wave_per_row"};
@@ -240,8 +242,12 @@ bool selectable(int v, const CallContext& c, const char** why) {
         return true;
     case SKEL_SK_SCAN:
         if (c.reverse && v != S2_LOOKBACK && v != S3_PERSISTENT_LOOKBACK &&
-            v != S4_SMALL_TILE_LOOKBACK) {
+            v != S4_SMALL_TILE_LOOKBACK && v != S5_FLAT_LOOKBACK) {
             *why = "reverse scans run in the single-pass variants only";
+            return false;
+        }
+        if (v == S5_FLAT_LOOKBACK && c.n > kFlatMaxTiles * scan_flat_tile(c.din)) {
+            *why = "flat look-back takes at most 1024 tiles (2^22 elements, 2^21 for I64)";
             return false;
         }
         return true;

@@ -15,15 +15,20 @@ namespace skel {
 // variant indices (stable: they are the values of the `variant` argument)
 enum MapVariant { M0_SCALAR = 0, M1_VEC4 = 1, M2_VEC4X4_NT = 2, MAP_NVAR };
 enum ReduceVariant { R0_SINGLE_WG = 0, R1_TWO_PASS = 1, R2_TICKET = 2, R3_ATOMIC = 3,
-                     R4_COMPENSATED = 4, R5_PAIRWISE = 5, REDUCE_NVAR };
+                     R4_COMPENSATED = 4, R5_PAIRWISE = 5, R6_GATHER = 6, REDUCE_NVAR };
 enum MapReduceVariant { MR0_UNFUSED = 0, MR1_FUSED_TWO_PASS = 1, MR2_FUSED_TICKET = 2,
                         MR3_FUSED_SINGLE_WG = 3, MR4_COMPENSATED = 4, MR5_PAIRWISE = 5,
-                        MAPREDUCE_NVAR };
+                        MR6_FUSED_GATHER = 6, MAPREDUCE_NVAR };
 enum Overlap1DVariant { O1A_DIRECT = 0, O1B_LDS_TILE = 1, O1C_SHUFFLE = 2, OVERLAP1D_NVAR };
 enum Overlap2DVariant { O2A_DIRECT = 0, O2B_LDS_TILE = 1, O2C_LDS_SEPARABLE = 2,
                         O2D_SEPARABLE_L1 = 3, O2E_MARCH = 4, OVERLAP2D_NVAR };
 enum ScanVariant { S0_SINGLE_WG = 0, S1_REDUCE_THEN_SCAN = 1, S2_LOOKBACK = 2,
-                   S3_PERSISTENT_LOOKBACK = 3, S4_SMALL_TILE_LOOKBACK = 4, SCAN_NVAR };
+                   S3_PERSISTENT_LOOKBACK = 3, S4_SMALL_TILE_LOOKBACK = 4, S5_FLAT_LOOKBACK = 5,
+                   SCAN_NVAR };
+// S5 (flat look-back): elements per tile for an input type, and the most tiles
+// one call may have (every tile reads all its predecessors' totals)
+constexpr int64_t scan_flat_tile(int din) { return din == SKEL_I64 ? 2048 : 4096; }
+constexpr int64_t kFlatMaxTiles = 1024;
 enum SegmentsVariant { B0_PER_SEGMENT = 0, B1_PERSISTENT = 1, SEGMENTS_NVAR };
 enum ScanRowsVariant { SR0_PER_ROW = 0, SR1_WAVE_PER_ROW = 1, SCANROWS_NVAR };
 // the call chain Map -> MapOverlap 2D -> Reduce SUM (forward and backward)

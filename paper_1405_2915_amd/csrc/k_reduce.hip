@@ -20,6 +20,11 @@
 //             lane's additions form a balanced tree over its whole share
 //             (error growing with log n instead of n per lane), for the same
 //             HBM traffic
+//   R6 / MR6  one pass without tickets: every workgroup but the last
+//             publishes its partial; the last workgroup by index gathers all
+//             of them in index order (deterministic), skipping R2's two
+//             serialised atomics -- the latency that dominates arrays of a few
+//             million elements
 //   MR0       the composed plain form: Map into a temporary, then R1
 // Every lane streams 16-byte vectors with four loads in flight and keeps four
 // independent accumulators; partials are combined by 64-lane butterflies and
@@ -470,6 +475,74 @@ __global__ __launch_bounds__(kBlock) void k_ticket(Src s, int64_t n, u64* slots,
     }
 }
 
+// Single pass without tickets (R6 / MR6): every workgroup but the last
+// publishes its partial as a tagged word and exits; the last workgroup by
+// index -- the last to start, so every other one has started and none of them
+// waits on anything -- reads all partials with every lane at once (a retry
+// re-reads only the slots not yet valid), combines them in a fixed order
+// (deterministic) with its own, and advances the epoch: every other workgroup
+// read the epoch before it published.  This saves the two serialised
+// device-scope ticket atomics of R2 (a few microseconds on arrays of a few
+// million elements, where the whole reduction takes about as long).
+template <class P, class Src>
+__global__ __launch_bounds__(kBlock) void k_gather(Src s, int64_t n, u64* slots, u64* sync,
+                                                   typename P::out_t* out) {
+    using acc_t = typename P::acc_t;
+    using C = typename P::C;
+    __shared__ acc_t lds[kBlock / kWave];
+    __shared__ acc_t s_own;
+    __shared__ uint32_t s_epoch;
+    uint32_t ep = 0;
+    if (threadIdx.x == 0) ep = epoch_of_call(sync);  // in flight with the first loads
+    acc_t a = thread_acc<P, kBlock>(s, n, blockIdx.x, gridDim.x);
+    a = block_reduce<C>(a, lds);
+    const unsigned last = gridDim.x - 1;
+    if (blockIdx.x != last) {
+        if (threadIdx.x == 0) tagged_put(slots + 2 * blockIdx.x, kSlotReady, ep, a);
+        return;
+    }
+    if (threadIdx.x == 0) {
+        s_own = a;
+        s_epoch = ep;
+    }
+    __syncthreads();  // also ends block_reduce's reads of lds before its reuse
+    const uint32_t epoch = s_epoch;
+    acc_t b = C::id();
+    for (unsigned base = 0; base < last; base += 4 * kBlock) {
+        acc_t v[4];
+        bool ready[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            v[k] = C::id();
+            ready[k] = base + k * kBlock + threadIdx.x >= last;
+        }
+        uint32_t spins = 0;
+        while (true) {
+            bool all = true;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (ready[k]) continue;
+                const unsigned i = base + k * kBlock + threadIdx.x;
+                ready[k] = tagged_get(slots + 2 * i, epoch, v[k]) == kSlotReady;
+                all = all && ready[k];
+            }
+            if (all) break;
+            if (++spins > kSpinLimit) {  // bounded: flag it and finish
+                atomicOr(sync + SYNC_ERROR, 2ull);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) b = C::op(b, ready[k] ? v[k] : C::id());
+    }
+    b = block_reduce<C>(b, lds);
+    if (threadIdx.x == 0) {
+        *out = (typename P::out_t)C::op(b, s_own);
+        epoch_advance(sync);
+    }
+}
+
 template <class P>
 __global__ void k_set_identity(typename P::out_t* out) {
     *out = (typename P::out_t)P::C::id();
@@ -521,6 +594,18 @@ int grid_for(int64_t n, const DevInfo& d) {
 // accumulators, rounded to 256 bytes
 size_t partial_bytes(const DevInfo& d) { return ((size_t)d.cus * 8 * 8 + 255) & ~size_t(255); }
 
+// single-pass launch without tickets (R6, MR6)
+template <class P, class Src>
+skel_status launch_gather(const Src& s, int64_t n, typename P::out_t* out, LaunchCtx& lc) {
+    int g = grid_for<P>(n, *lc.dev);
+    void* slots = nullptr;
+    skel_status e = ws_status(lc, (size_t)g * 16, &slots);
+    if (e != SKEL_OK) return e;
+    k_gather<P, Src><<<(unsigned)g, kBlock, 0, lc.stream>>>(s, n, static_cast<u64*>(slots),
+                                                            lc.ws->sync, out);
+    return launch_check("reduce_gather");
+}
+
 // single-pass ticket launch (R2, MR2 and the compensated forms R4, MR4)
 template <class P, class Src>
 skel_status launch_ticket(const Src& s, int64_t n, typename P::out_t* out, LaunchCtx& lc) {
@@ -555,6 +640,7 @@ skel_status run_variant(int v, const Src& s, int64_t n, typename P::out_t* out,
         return launch_check("reduce_finish");
     }
     case R2_TICKET: return launch_ticket<P>(s, n, out, lc);
+    case R6_GATHER: return launch_gather<P>(s, n, out, lc);
     case R3_ATOMIC: {
         int g = grid_for<P>(n, *lc.dev);
         k_set_identity<P><<<1, 1, 0, st>>>(out);
@@ -639,6 +725,7 @@ skel_status mapreduce_typed(int v, float p0, float p1, const void* x, const void
     int rv = v == MR1_FUSED_TWO_PASS ? R1_TWO_PASS
              : v == MR2_FUSED_TICKET ? R2_TICKET
              : v == MR3_FUSED_SINGLE_WG ? R0_SINGLE_WG
+             : v == MR6_FUSED_GATHER    ? R6_GATHER
                                         : -1;
     if (rv < 0) return fail(SKEL_E_UNSUPPORTED, "mapreduce variant %d", v);
     return run_variant<P>(rv, s, n, out, lc, part);

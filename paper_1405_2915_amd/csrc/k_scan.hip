@@ -31,6 +31,10 @@
 //       2048 for 8-byte): for arrays of a few million elements, whose 32768-
 //       element tiles would leave most CUs idle (2^20 elements: 256 tiles
 //       instead of 32)
+//   S5  flat look-back over S4's tiles for arrays of at most 1024 of them:
+//       tiles numbered by workgroup index, and each tile reads the totals of
+//       all its predecessors in one round of parallel loads (no prefix chain,
+//       no atomic counter)
 //   S3  S2's tile step run by persistent workgroups (one per resident slot)
 //       that loop over tile ids; a workgroup takes its next id once its
 //       stores are issued, so no workgroup launch sits between one tile's
@@ -61,6 +65,7 @@ namespace {
 using namespace dev;
 
 constexpr uint32_t kSpinLimit = 1u << 22;
+constexpr int kFlatPerLane = 8;  // S5: descriptors each lane reads per round
 
 template <int DIN, int DOUT, int OP, int WAVES = SKEL_SCAN_WAVES>
 struct SP {
@@ -384,6 +389,98 @@ __global__ __launch_bounds__(P::kBlock) void scan_lookback_persist(
     }
 }
 
+// S5: flat look-back.  The tile is the workgroup index: workgroups start in
+// index order, so every tile waited on has already started (and with at most
+// kFlatMaxTiles small tiles all of them are resident at once).  Each tile
+// publishes its total, then every lane of the workgroup reads its share of the
+// totals of all preceding tiles -- one round of parallel loads, re-reading only
+// those not yet valid -- and the workgroup combines them.  A tile so waits for
+// one publish-to-read latency, not for a chain of prefixes, and takes no
+// ticket from an atomic counter (device-scope atomics on one word serialise).
+// The last tile in scan order advances the epoch once it has seen every other
+// tile's total: by then every tile has read this call's epoch.
+template <class P>
+__device__ __forceinline__ typename P::acc_t flat_prefix(u64* status, int64_t seq,
+                                                         uint32_t epoch, u64* err) {
+    using acc_t = typename P::acc_t;
+    using C = typename P::C;
+    acc_t a = C::id();
+    for (int64_t base = 0; base < seq; base += (int64_t)kFlatPerLane * P::kBlock) {
+        acc_t v[kFlatPerLane];
+        bool ready[kFlatPerLane];
+#pragma unroll
+        for (int k = 0; k < kFlatPerLane; ++k) {
+            v[k] = C::id();
+            ready[k] = base + k * P::kBlock + (int64_t)threadIdx.x >= seq;
+        }
+        uint32_t spins = 0;
+        while (true) {
+            bool all = true;
+#pragma unroll
+            for (int k = 0; k < kFlatPerLane; ++k) {
+                if (ready[k]) continue;
+                const int64_t j = base + k * P::kBlock + threadIdx.x;
+                ready[k] = tagged_get(status + 2 * j, epoch, v[k]) != ST_INVALID;
+                all = all && ready[k];
+            }
+            if (all) break;
+            if (++spins > kSpinLimit) {  // bounded: flag it and finish
+                atomicOr(err, 1ull);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+#pragma unroll
+        for (int k = 0; k < kFlatPerLane; ++k) a = C::op(a, ready[k] ? v[k] : C::id());
+    }
+    return a;
+}
+
+template <class P, bool FULL, bool REV>
+__device__ __forceinline__ void flat_tile(const typename P::in_t* in, typename P::out_t* out,
+                                          int64_t n, int64_t seq, int64_t tile, int64_t ntiles,
+                                          int exclusive, u64* status, u64* sync) {
+    using acc_t = typename P::acc_t;
+    using C = typename P::C;
+    __shared__ acc_t s_wtot[P::NW];
+    __shared__ acc_t s_red[P::NW];
+    __shared__ acc_t s_prefix;
+    __shared__ uint32_t s_epoch;
+    uint32_t ep = 0;
+    if (threadIdx.x == 0) ep = epoch_of_call(sync);  // in flight with the tile's loads
+    Raw<P> raw;
+    tile_load<P, FULL, true>(in, n, tile, raw);
+    acc_t wex, agg;
+    tile_totals<P, REV>(lane_total<P, FULL>(n, tile, raw), s_wtot, &wex, &agg);
+    if (threadIdx.x == 0) {
+        s_epoch = ep;
+        if (seq + 1 < ntiles) publish(status, seq, ST_AGG, agg, ep);
+    }
+    __syncthreads();
+    const acc_t part = flat_prefix<P>(status, seq, s_epoch, sync + SYNC_ERROR);
+    const acc_t pre = block_reduce<C>(part, s_red);
+    if (threadIdx.x == 0) {
+        s_prefix = pre;
+        if (seq == ntiles - 1) epoch_advance(sync);
+    }
+    __syncthreads();
+    keep_raw_only<P>(raw);
+    tile_scan_store<P, FULL, REV>(out, n, tile, raw, C::op(s_prefix, wex), exclusive != 0);
+}
+
+template <class P, bool REV>
+__global__ __launch_bounds__(P::kBlock) void scan_flat(const typename P::in_t* in,
+                                                       typename P::out_t* out, int64_t n,
+                                                       int64_t ntiles, int exclusive,
+                                                       u64* status, u64* sync) {
+    const int64_t seq = blockIdx.x;
+    const int64_t tile = REV ? ntiles - 1 - seq : seq;  // data tile in scan order
+    if ((tile + 1) * P::kTile <= n)
+        flat_tile<P, true, REV>(in, out, n, seq, tile, ntiles, exclusive, status, sync);
+    else
+        flat_tile<P, false, REV>(in, out, n, seq, tile, ntiles, exclusive, status, sync);
+}
+
 // S1 pass 1: tile totals
 template <class P, bool FULL>
 __device__ __forceinline__ typename P::acc_t tile_sum(const typename P::in_t* in, int64_t n,
@@ -581,8 +678,27 @@ skel_status scan_typed(int v, int kind, const void* x, void* y, int64_t n, Launc
     const bool rev = kind == SKEL_REVERSE_INCLUSIVE || kind == SKEL_REVERSE_EXCLUSIVE;
     const int excl = (kind == SKEL_EXCLUSIVE || kind == SKEL_REVERSE_EXCLUSIVE) ? 1 : 0;
     hipStream_t st = lc.stream;
-    if (rev && v != S2_LOOKBACK && v != S3_PERSISTENT_LOOKBACK && v != S4_SMALL_TILE_LOOKBACK)
+    if (rev && v != S2_LOOKBACK && v != S3_PERSISTENT_LOOKBACK && v != S4_SMALL_TILE_LOOKBACK &&
+        v != S5_FLAT_LOOKBACK)
         return fail(SKEL_E_UNSUPPORTED, "reverse scans run in the single-pass variants only");
+    if (v == S5_FLAT_LOOKBACK) {
+        using PS = SP<DIN, DOUT, OP, 2>;
+        static_assert(PS::kTile == scan_flat_tile(DIN), "S5 tile size known to the plan");
+        const int64_t nts = (n + PS::kTile - 1) / PS::kTile;
+        if (nts > kFlatMaxTiles)
+            return fail(SKEL_E_UNSUPPORTED, "S5 takes at most %lld elements of this type",
+                        (long long)(kFlatMaxTiles * PS::kTile));
+        void* status = nullptr;
+        skel_status e = ws_status(lc, (size_t)nts * 16, &status);
+        if (e != SKEL_OK) return e;
+        if (rev)
+            scan_flat<PS, true><<<(unsigned)nts, PS::kBlock, 0, st>>>(
+                in, out, n, nts, excl, static_cast<u64*>(status), lc.ws->sync);
+        else
+            scan_flat<PS, false><<<(unsigned)nts, PS::kBlock, 0, st>>>(
+                in, out, n, nts, excl, static_cast<u64*>(status), lc.ws->sync);
+        return launch_check("scan_flat");
+    }
     if (v == S4_SMALL_TILE_LOOKBACK) {
         using PS = SP<DIN, DOUT, OP, 2>;
         const int64_t nts = (n + PS::kTile - 1) / PS::kTile;

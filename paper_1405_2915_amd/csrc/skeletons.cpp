@@ -505,7 +505,7 @@ skel_status skel_scan_rows(skel_container* in, skel_container* out, skel_scan_ki
         // before it enqueues anything; that no later row has to reset it
         // inside a capture is checked here, before the first row
         if (flat == S2_LOOKBACK || flat == S3_PERSISTENT_LOOKBACK ||
-            flat == S4_SMALL_TILE_LOOKBACK) {
+            flat == S4_SMALL_TILE_LOOKBACK || flat == S5_FLAT_LOOKBACK) {
             const skel_status ready = ws_status_ready(lc, 0, in->rows);
             if (ready != SKEL_OK) return ready;
         }

@@ -317,7 +317,7 @@ def name_of(lib, sk, v):
 
 
 def test_variant_registry(rt):
-    want = {SK_MAP: 3, SK_REDUCE: 6, SK_MAPREDUCE: 6, SK_OV1: 3, SK_OV2: 5, SK_SCAN: 5,
+    want = {SK_MAP: 3, SK_REDUCE: 7, SK_MAPREDUCE: 7, SK_OV1: 3, SK_OV2: 5, SK_SCAN: 6,
             SK_SEG: 2, SK_OV1B: 2, SK_OV2B: 2, SK_SCANROWS: 2, SK_CHAIN: 2}
     for sk, k in want.items():
         assert rt.skel_variant_count(sk) == k
@@ -484,6 +484,21 @@ def test_scan_rows_plan(rt):
     assert sel(4, (1 << 24) + 2, I64) == "SR0_per_row"      # 8-byte elements: aligned
     assert sel(4, 1 << 24, I32, 1) == "SR0_per_row"         # reverse kinds too
     assert rt.skel_variant_name(SK_SCANROWS, 2) is None
+
+
+def test_flat_scan_size_limit(rt, tmp_path):
+    """S5 (flat look-back) takes at most 1024 tiles: 2^22 elements of 4 bytes,
+    2^21 of 8; beyond that a table entry naming it falls back to the static
+    rule, and a forced S5 is refused."""
+    p = tmp_path / "plan.txt"
+    p.write_text("SCAN i32 20 S5_flat_lookback\nSCAN i64 20 S5_flat_lookback\n")
+    assert rt.skel_load_plan(str(p).encode()) == OK
+    sel = lambda n, dt: name_of(rt, SK_SCAN, rt.skel_select_variant(SK_SCAN, dt, n, 1, n, 0))
+    assert sel(1 << 22, I32) == "S5_flat_lookback"
+    assert sel((1 << 22) + 1, I32) == "S3_persistent_lookback"
+    assert sel(1 << 21, I64) == "S5_flat_lookback"
+    assert sel((1 << 21) + 1, I64) == "S3_persistent_lookback"
+    assert rt.skel_clear_plan() == OK
 
 
 def test_reverse_scan_plan(rt):

@@ -119,10 +119,11 @@ def test_variant_names_and_plan(skel):
     names = {sk: [skel.skel_variant_name(sk, v) for v in range(skel.skel_variant_count(sk))]
              for sk in range(6)}
     assert names[skel.SK_REDUCE] == ["R0_single_wg", "R1_two_pass", "R2_ticket", "R3_atomic",
-                                     "R4_compensated", "R5_pairwise"]
-    assert names[skel.SK_MAPREDUCE][4:] == ["MR4_compensated", "MR5_pairwise"]
+                                     "R4_compensated", "R5_pairwise", "R6_gather"]
+    assert names[skel.SK_MAPREDUCE][4:] == ["MR4_compensated", "MR5_pairwise",
+                                            "MR6_fused_gather"]
     assert names[skel.SK_SCAN][2:] == ["S2_decoupled_lookback", "S3_persistent_lookback",
-                                       "S4_small_tile_lookback"]
+                                       "S4_small_tile_lookback", "S5_flat_lookback"]
     # the tuned plan picks one of the single-pass variants for a large scan
     assert skel.skel_select_variant(skel.SK_SCAN, skel.I32, 1 << 27) in (2, 3)
 

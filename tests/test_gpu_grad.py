@@ -28,7 +28,8 @@ def cont(skel, a, dtype=None):
 
 
 # ------------------------------------------------------------ reverse scans
-SINGLE_PASS = (2, 3, 4)  # S2 decoupled look-back, S3 its persistent form, S4 small tiles
+SINGLE_PASS = (2, 3, 4, 5)  # S2 decoupled look-back, S3 its persistent form, S4 small
+# tiles, S5 flat look-back
 
 
 @pytest.mark.parametrize("pair", ["i32_i32", "i32_i64", "i64_i64"])

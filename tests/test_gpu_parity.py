@@ -407,13 +407,13 @@ def test_scan_in_place_and_closed_forms(skel, oracle_mod):
 
 def test_scan_repeated_calls_reuse_descriptors(skel, oracle_mod):
     # the look-back descriptors and counters are reused across calls (a fresh
-    # epoch each call): alternate sizes and the three single-pass variants
+    # epoch each call): alternate sizes and the four single-pass variants
     # without clearing anything
-    for k in range(18):
+    for k in range(24):
         n = [(1 << 20) + 1, 9000, (1 << 18) + 77][k % 3]
         x = si.int_uniform_i32(n, 1000, 5, k)
         out = skel.Container.empty(skel.I64, n)
-        skel.skel_scan(cont(skel, x), out, skel.EXCLUSIVE, skel.SUM, variant=2 + (k // 3) % 3)
+        skel.skel_scan(cont(skel, x), out, skel.EXCLUSIVE, skel.SUM, variant=2 + (k // 3) % 4)
         assert np.array_equal(out.to_numpy(), oracle_mod.scan(x, "exclusive", "sum",
                                                               np.int64)), k
     skel.skel_sync()
