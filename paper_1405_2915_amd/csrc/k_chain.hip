@@ -76,6 +76,10 @@ template <class T>
 struct ChainGeom {
     T rows, cols;
     DivU<T> by_cols, by_rows;  // element index -> row; row -> field
+    // a lane's position moves by kBlock * 4 elements from one vector of a
+    // chunk to the next, and by the grid's stride from one chunk to the next:
+    // each step as (columns mod cols, rows mod rows) -- see advance()
+    T vec_c, vec_r, chunk_c, chunk_r;
     int ry, rx;
     int inner_ok;              // the field has interior rows and columns
     int small_r, small_c;      // fewer than 2r + 1 rows / columns
@@ -97,16 +101,35 @@ __device__ __forceinline__ int col_class(const ChainGeom<T>& g, T c) {
     return g.rx;
 }
 
-// (A^T 1) of the four consecutive elements from flat index e0.  Inside a
-// field (the common case) all four take the interior entry; a vector that
-// touches a border band, or straddles a row or field end, looks each element
-// up in the workgroup's LDS copy of the table.
+// (row within its field, column) of flat element index e: two divisions by
+// invariant integers (each a multiply-high, a quarter-rate instruction)
+template <class T>
+__device__ __forceinline__ void locate(const ChainGeom<T>& g, T e, T& rl, T& col) {
+    const T row = g.by_cols.div(e);
+    col = e - row * g.cols;
+    rl = row - g.by_rows.div(row) * g.rows;
+}
+
+// Move (rl, col) forward by a fixed number of elements given as (dc, dr) =
+// (that number mod cols, (that number div cols) mod rows).  col + dc < 2 cols
+// and rl + dr + 1 < 2 rows, so one conditional subtraction wraps each: adds,
+// compares and selects instead of the divisions of locate().
+template <class T>
+__device__ __forceinline__ void advance(const ChainGeom<T>& g, T dc, T dr, T& rl, T& col) {
+    col += dc;
+    const bool wrap = col >= g.cols;
+    col = wrap ? col - g.cols : col;
+    rl += dr + (wrap ? (T)1 : (T)0);
+    rl = rl >= g.rows ? rl - g.rows : rl;
+}
+
+// (A^T 1) of the four consecutive elements from (rl, col).  Inside a field
+// (the common case) all four take the interior entry; a vector that touches a
+// border band, or straddles a row or field end, looks each element up in the
+// workgroup's LDS copy of the table.
 template <class T>
 __device__ __forceinline__ void coef4(const ChainGeom<T>& g, const float (&tab)[kMaxClasses * kMaxClasses],
-                                      T e0, float (&c)[4]) {
-    const T row = g.by_cols.div(e0);
-    T col = e0 - row * g.cols;
-    T rl = row - g.by_rows.div(row) * g.rows;
+                                      T rl, T col, float (&c)[4]) {
     const bool inner = g.inner_ok && rl >= (T)g.ry && rl < g.rows - g.ry && col >= (T)g.rx &&
                        col + 3 + g.rx < g.cols;
     if (inner) {
@@ -203,27 +226,36 @@ __global__ __launch_bounds__(kBlock) void chain_fwd(const float* x, T n, ChainGe
     // the memory system stays busy while the lanes compute
     f32x4 v[kUnroll];
     load_chunk(xv, nv, (T)blockIdx.x * CH, v);
+    // the lane's position at its first vector of each chunk
+    T rl0 = 0, col0 = 0;
+    if ((T)blockIdx.x * CH + threadIdx.x < nv)
+        locate(g, 4 * ((T)blockIdx.x * CH + threadIdx.x), rl0, col0);
     for (T base = (T)blockIdx.x * CH; base < nv; base += stride) {
         f32x4 cur[kUnroll];
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) cur[u] = v[u];
         if (base + stride < nv) load_chunk(xv, nv, base + stride, v);
+        T rl = rl0, col = col0;
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
             const T i = base + u * kBlock + threadIdx.x;
             if (i >= nv) break;
             float c[4];
-            coef4(g, tab, 4 * i, c);
+            coef4(g, tab, rl, col, c);
 #pragma unroll
             for (int e = 0; e < 4; ++e)
                 acc[u] = __builtin_fmaf(chain_f<MOP>(cur[u][e], p0, p1), c[e], acc[u]);
+            advance(g, g.vec_c, g.vec_r, rl, col);
         }
+        advance(g, g.chunk_c, g.chunk_r, rl0, col0);
     }
     // the n % 4 tail: one element per low lane of workgroup 0
     const T t = nv * 4 + threadIdx.x;
     if (blockIdx.x == 0 && t < n) {
         float c[4];
-        coef4(g, tab, t, c);
+        T rl, col;
+        locate(g, t, rl, col);
+        coef4(g, tab, rl, col, c);
         acc[0] = __builtin_fmaf(chain_f<MOP>(x[t], p0, p1), c[0], acc[0]);
     }
     float a = 0.0f;
@@ -266,17 +298,22 @@ __global__ __launch_bounds__(kBlock) void chain_bwd(const float* x, T n, ChainGe
     const T stride = (T)gridDim.x * CH;
     f32x4 v[kUnroll];
     load_chunk(xv, nv, (T)blockIdx.x * CH, v);
+    T rl0 = 0, col0 = 0;
+    if ((T)blockIdx.x * CH + threadIdx.x < nv)
+        locate(g, 4 * ((T)blockIdx.x * CH + threadIdx.x), rl0, col0);
     for (T base = (T)blockIdx.x * CH; base < nv; base += stride) {
         f32x4 cur[kUnroll];
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) cur[u] = v[u];
         if (base + stride < nv) load_chunk(xv, nv, base + stride, v);
+        T rl = rl0, col = col0;
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
             const T i = base + u * kBlock + threadIdx.x;
             if (i >= nv) break;
             float c[4];
-            coef4(g, tab, 4 * i, c);
+            coef4(g, tab, rl, col, c);
+            advance(g, g.vec_c, g.vec_r, rl, col);
             f32x4 o;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
@@ -292,7 +329,9 @@ __global__ __launch_bounds__(kBlock) void chain_bwd(const float* x, T n, ChainGe
     const T t = nv * 4 + threadIdx.x;
     if (blockIdx.x == 0 && t < n) {
         float c[4];
-        coef4(g, tab, t, c);
+        T rl, col;
+        locate(g, t, rl, col);
+        coef4(g, tab, rl, col, c);
         float o, s0, s1;
         chain_grad<MOP>(x[t], gv * c[0], p0, p1, o, s0, s1);
         dx[t] = o;
@@ -325,10 +364,18 @@ int grid_for(int64_t n, const DevInfo& d) {
 }
 
 template <class T>
-ChainGeom<T> geometry(const ChainTable& t) {
+ChainGeom<T> geometry(const ChainTable& t, int groups) {
     ChainGeom<T> g;
     g.rows = (T)t.rows;
     g.cols = (T)t.cols;
+    // element steps between a lane's vectors (kBlock vectors of 4) and
+    // between its chunks (the grid's stride), as (mod cols, div cols mod rows)
+    const uint64_t vstep = (uint64_t)kBlock * 4;
+    const uint64_t cstep = (uint64_t)groups * kBlock * kUnroll * 4;
+    g.vec_c = (T)(vstep % t.cols);
+    g.vec_r = (T)((vstep / t.cols) % t.rows);
+    g.chunk_c = (T)(cstep % t.cols);
+    g.chunk_r = (T)((cstep / t.cols) % t.rows);
     g.by_cols = make_div<T>((uint64_t)t.cols);
     g.by_rows = make_div<T>((uint64_t)t.rows);
     g.ry = t.ry;
@@ -350,7 +397,8 @@ skel_status fused_forward(const float* x, int64_t n, const ChainTable& tb, float
     skel_status e = ws_scratch(lc, (size_t)groups * sizeof(float), &mem);
     if (e != SKEL_OK) return e;
     float* part = static_cast<float*>(mem);
-    chain_fwd<MOP, T><<<groups, kBlock, 0, lc.stream>>>(x, (T)n, geometry<T>(tb), p0, p1, part);
+    chain_fwd<MOP, T><<<groups, kBlock, 0, lc.stream>>>(x, (T)n, geometry<T>(tb, groups), p0, p1,
+                                                       part);
     if ((e = launch_check("chain_fwd")) != SKEL_OK) return e;
     chain_finish<<<1, kBlock, 0, lc.stream>>>(part, groups, 1, (float)tb.pad_total, out);
     return launch_check("chain_finish");
@@ -365,8 +413,8 @@ skel_status fused_backward(const float* x, int64_t n, const ChainTable& tb, floa
     skel_status e = ws_scratch(lc, (size_t)groups * 2 * sizeof(float), &mem);
     if (e != SKEL_OK) return e;
     float* part = static_cast<float*>(mem);
-    chain_bwd<MOP, T><<<groups, kBlock, 0, lc.stream>>>(x, (T)n, geometry<T>(tb), p0, p1, g1, dx,
-                                                       part);
+    chain_bwd<MOP, T><<<groups, kBlock, 0, lc.stream>>>(x, (T)n, geometry<T>(tb, groups), p0, p1,
+                                                       g1, dx, part);
     if ((e = launch_check("chain_bwd")) != SKEL_OK) return e;
     if (NP == 0 || !dparams) return SKEL_OK;
     chain_finish<<<1, kBlock, 0, lc.stream>>>(part, groups, NP, 0.0f, dparams);
