@@ -2,7 +2,9 @@
 5-point stencil on every field, then prefix sums along every field row, and the
 backward pass (reverse row-wise scan of the upstream gradient, then the
 stencil's transpose on every field), run through the C ABI exactly as the
-benchmark runs it (one batched-field stencil call per pass).  Sampled rows are checked against the oracle: a row of the
+benchmark runs it (one batched-field stencil call per pass).  Two whole fields
+(the first and the last: 8.4 million outputs per pass) are checked against the
+oracle element by element, and sampled rows of other fields: a row of the
 stencil (or of its transpose) depends only on the three field rows around it,
 so the oracle runs on those three rows and the scan on the whole row.
 
@@ -17,7 +19,8 @@ import synth_inputs as si
 pytestmark = pytest.mark.gpu
 
 F, H, W = 64, 2048, 2048
-SAMPLES = [(0, 0), (0, 1), (0, 1000), (63, 2047), (31, 2046), (17, 555)]
+FULL_FIELDS = (0, F - 1)
+SAMPLES = [(1, 0), (5, 1), (9, 1000), (62, 2047), (31, 2046), (17, 555)]
 
 
 def block(a, r):
@@ -47,6 +50,22 @@ def test_field_layer_full_size(skel, oracle_mod):
     skel.skel_scan_rows(cgz, cgy, skel.REVERSE_INCLUSIVE, skel.SUM)
     skel.skel_mapoverlap2d_fields_backward(cgy, cgx, F, w2d=w5, edge=skel.EDGE_CLAMP)
     skel.skel_sync()
+    for f in FULL_FIELDS:
+        xf, gzf = x[f].cpu().numpy(), gz[f].cpu().numpy()
+        yref, mag = oracle_mod.mapoverlap2d(xf, 1, 1, w2d=w5, edge="clamp")
+        zref, _ = oracle_mod.scan_rows(yref.astype(np.float32), "inclusive")
+        bound = 1e-5 * oracle_mod.scan_rows(mag.astype(np.float32), "inclusive")[0] + 1e-30
+        err = np.abs(z[f].cpu().numpy().astype(np.float64) - zref)
+        assert np.all(err <= bound), ("forward", f, np.unravel_index(np.argmax(err - bound),
+                                                                     err.shape))
+        gyf, gmag = oracle_mod.scan_rows(gzf, "reverse_inclusive")
+        assert np.all(np.abs(gy[f].cpu().numpy() - gyf) <= 1e-5 * gmag + 1e-30), ("rev", f)
+        dref, _ = oracle_mod.mapoverlap2d_adjoint(gyf.astype(np.float32), 1, 1, w2d=w5,
+                                                  edge="clamp")
+        _, dmag = oracle_mod.mapoverlap2d_adjoint(gmag.astype(np.float32), 1, 1,
+                                                  w2d=np.abs(w5), edge="clamp")
+        err = np.abs(gx[f].cpu().numpy().astype(np.float64) - dref)
+        assert np.all(err <= 1e-5 * dmag + 1e-30), ("backward", f)
     for f, r in SAMPLES:
         xb, k = block(x[f].cpu().numpy(), r)
         yb, mag = oracle_mod.mapoverlap2d(xb, 1, 1, w2d=w5, edge="clamp")
