@@ -87,7 +87,7 @@ def test_reverse_scan_variants_and_full_size(skel, oracle_mod):
     out = skel.Container.empty(skel.I64, n)
     skel.skel_scan(cont(skel, xs), out, skel.REVERSE_EXCLUSIVE, skel.SUM)
     got = out.to_numpy()
-    suffix = np.cumsum(xs[::-1].astype(np.int64))[::-1]  # inclusive suffix sums
+    suffix = oracle_mod.scan(xs, "reverse_inclusive", "sum", out_dtype=np.int64)
     assert got[-1] == 0
     idx = np.concatenate([np.arange(40000), np.arange(n - 40000, n - 1),
                           si.rng(8, 3).integers(0, n - 1, 4000)])
