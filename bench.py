@@ -214,7 +214,10 @@ def isolated(skel, torch, wl, name, reps, before):
     r = skel.Container.empty(skel.F32, 1)
     m1 = skel.variant_index(skel.SK_MAP, "M1_vec4")  # plain 16-byte stores
     r1 = skel.variant_index(skel.SK_REDUCE, "R1_two_pass")
-    call = dict(wl.calls())[name]
+    calls = wl.calls()
+    for _, c in calls:  # one whole step first: every operand then holds valid data
+        c()
+    call = dict(calls)[name]
     st = torch.cuda.current_stream()
     evs = []
     for _ in range(reps + 1):
