@@ -204,16 +204,16 @@ def copy_ceiling(skel, torch, reps=10):
 def isolated(skel, torch, wl, name, reps, before):
     """One skeleton of the step alone, `reps` times, each call preceded by a
     pass over a separate 1 GiB buffer that replaces the Infinity Cache's
-    contents: `before` = "read" (a Reduce: the cache holds clean lines) or
-    "write" (a Map writing it with plain stores: the cache holds dirty
-    lines, as after the step's scan).  Kernel time from HIP events around
-    the call on the launch stream."""
+    contents: `before` = "read" (plain loads, torch's sum: the cache holds
+    clean lines; the library's Reduce kernels load non-temporally and leave
+    most of the cache in place) or "write" (a Map writing it with plain
+    stores: the cache holds dirty lines, as after the step's scan).  Kernel
+    time from HIP events around the call on the launch stream."""
     n = 1 << 28
-    buf = skel.Container.from_numpy(np.zeros(n, np.float32))
+    buf = skel.Container.from_numpy(np.zeros(n, np.float32)) if before == "write" else None
+    flush = torch.zeros(n, dtype=torch.float32, device="cuda") if before == "read" else None
     dst = skel.Container.empty(skel.F32, n) if before == "write" else None
-    r = skel.Container.empty(skel.F32, 1)
     m1 = skel.variant_index(skel.SK_MAP, "M1_vec4")  # plain 16-byte stores
-    r1 = skel.variant_index(skel.SK_REDUCE, "R1_two_pass")
     calls = wl.calls()
     for _, c in calls:  # one whole step first: every operand then holds valid data
         c()
@@ -224,7 +224,7 @@ def isolated(skel, torch, wl, name, reps, before):
         if before == "write":
             skel.skel_map(skel.MAP_IDENTITY, None, [buf], dst, variant=m1)
         else:
-            skel.skel_reduce(skel.SUM, buf, r, variant=r1)
+            flush.sum()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(st)
         call()
@@ -232,7 +232,7 @@ def isolated(skel, torch, wl, name, reps, before):
         evs.append((e0, e1))
     torch.cuda.synchronize()
     us = float(np.median([a.elapsed_time(b) for a, b in evs[1:]])) * 1e3
-    for c in (buf, dst, r):
+    for c in (buf, dst):
         if c is not None:
             c.destroy()
     return us

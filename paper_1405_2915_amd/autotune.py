@@ -13,8 +13,10 @@ For each tuned skeleton (sum Reduce, dot MapReduce, inclusive int32 Scan,
 saxpy Map, 5-point MapOverlap1D, 9x9 separable MapOverlap2D on a near-square
 image) and each size n = 2^k it times every selectable variant (forced) with
 HIP events on the launch stream.  Above 2^22 elements: the median of `reps`
-single calls, each after the 256 MiB Infinity Cache was evicted (by reading a
-512 MiB buffer).  Up to 2^22 elements, where one call lasts a few
+single calls, each after the 256 MiB Infinity Cache was evicted by a pass of
+plain loads over a 1 GiB buffer (non-temporal loads, which the Reduce kernels
+use, leave most of the cache's contents in place: a 2^24-element copy takes
+the same time after such a pass as back to back).  Up to 2^22 elements, where one call lasts a few
 microseconds: after one eviction, `burst` calls back to back between one
 event pair, the time per call being their span divided by `burst` (median of
 `reps` bursts).  A spin kernel ahead of the pair holds the stream until the
@@ -29,6 +31,16 @@ above 2^22 elements (they use one CU of 256).  The atomic-finish Reduce (R3),
 whose floating-point result depends on the order the workgroups finish in, is
 left out of the plan unless --allow-order-dependent is given: a tuned plan
 keeps every automatic call deterministic.
+
+--adaptive samples sizes adaptively instead of all of them (adaptive
+sampling, cited in Section II as a way to spend fewer off-line sample
+executions at a small loss of precision): per skeleton, both ends of the
+range are timed first, and a size interval is bisected only while the
+variant chosen at its lower end is more than the tolerance slower than the
+fastest variant at its upper end.  Unsampled sizes take the choice of the
+nearest sampled size below, as the plan table does.  --compare FULL.json
+states, for every size of a full sweep, how much slower the adaptive plan's
+choice is than that sweep's fastest variant.
 """
 from __future__ import annotations
 
@@ -121,29 +133,74 @@ def _timed(torch, fn, evict, reps, burst=1, spin=None):
 ORDER_DEPENDENT = {"R3_atomic"}
 
 
-def tune(lo=10, hi=28, reps=7, log=print, allow_order_dependent=False):
-    import torch
+class Bisection:
+    """Adaptive choice of the sizes (log2 n) to sample for one skeleton.
 
-    import paper_1405_2915_amd as skel
-    import synth_inputs as si
+    Starts from both ends of [lo, hi]; after each round of measurements an
+    open interval [a, b] is settled when the fastest variant at a is within
+    `tol` of the fastest at b (the plan then keeps it across the interval),
+    and is otherwise split at its midpoint, until intervals are one size
+    wide.  `res` maps every sampled size to its {variant: us}."""
 
-    skel.skel_init(0, "torch", plan=None)  # time the variants, not a previous plan
-    flush = skel.Container.from_numpy(np.zeros(1 << 27, np.float32))
-    fl_out = skel.Container.empty(skel.F32, 1)
-    r1 = skel.variant_index(skel.SK_REDUCE, "R1_two_pass")
+    def __init__(self, lo, hi, tol=0.05, exclude=()):
+        self.tol = tol
+        self.exclude = set(exclude)
+        self.res = {}
+        self.pending = {lo, hi}
+        self.open = [(lo, hi)] if hi > lo else []
 
-    def evict():
-        skel.skel_reduce(skel.SUM, flush, fl_out, variant=r1)
+    def _best(self, k):
+        r = {a: b for a, b in self.res[k].items() if a not in self.exclude}
+        return min(r, key=r.get), r
 
-    evict()
-    torch.cuda.synchronize()
-    spin = SpinCalibration(torch)
-    report = {"lo": lo, "hi": hi, "reps": reps, "unit": "us", "results": {}}
-    single = {skel.SK_REDUCE: "R0_single_wg", skel.SK_MAPREDUCE: "MR3_fused_single_wg",
-              skel.SK_SCAN: "S0_single_wg"}
-    w5 = si.binomial5_weights()
-    g9 = si.gaussian_weights(4, 2.0)
-    for k in range(lo, hi + 1):
+    def settled(self, a, b):
+        wa, _ = self._best(a)
+        _, rb = self._best(b)
+        return wa in rb and rb[wa] <= (1 + self.tol) * min(rb.values())
+
+    def wanted(self):
+        return sorted(self.pending - set(self.res))
+
+    def add(self, k, res):
+        self.res[k] = res
+
+    def step(self):
+        """Split the unsettled intervals; True while sizes remain to sample."""
+        nxt = []
+        for a, b in self.open:
+            if b - a <= 1 or self.settled(a, b):
+                continue
+            m = (a + b) // 2
+            self.pending.add(m)
+            nxt += [(a, m), (m, b)]
+        self.open = nxt
+        return bool(self.wanted())
+
+
+class _Timer:
+    """Containers of one size and the timed calls of every tuned skeleton."""
+
+    CASES = ("REDUCE", "MAPREDUCE", "SCAN", "MAP", "MAPOVERLAP1D", "MAPOVERLAP2D")
+
+    def __init__(self, torch, skel, si, reps, log):
+        self.torch, self.skel, self.si, self.reps, self.log = torch, skel, si, reps, log
+        # plain-load read of 1 GiB: replaces the Infinity Cache's contents with
+        # clean lines of another buffer
+        self.flush = torch.zeros(1 << 28, dtype=torch.float32, device="cuda")
+        self.evict()
+        torch.cuda.synchronize()
+        self.spin = SpinCalibration(torch)
+        self.single = {skel.SK_REDUCE: "R0_single_wg", skel.SK_MAPREDUCE: "MR3_fused_single_wg",
+                       skel.SK_SCAN: "S0_single_wg"}
+        self.w5 = si.binomial5_weights()
+        self.g9 = si.gaussian_weights(4, 2.0)
+
+    def evict(self):
+        self.flush.sum()
+
+    def time_size(self, k, names):
+        """{name: {variant: us}} for the named skeletons at n = 2^k."""
+        skel, si = self.skel, self.si
         n = 1 << k
         x = skel.Container.from_numpy(si.normal_f32(n, 2, 0))
         y = skel.Container.from_numpy(si.normal_f32(n, 2, 1))
@@ -155,48 +212,124 @@ def tune(lo=10, hi=28, reps=7, log=print, allow_order_dependent=False):
         img = skel.Container.from_numpy(si.uniform_f32(n, 0.0, 1.0, 2, 3).reshape(rows,
                                                                                    n // rows))
         imo = skel.Container.empty(skel.F32, rows, n // rows)
+        w5, g9 = self.w5, self.g9
         cases = {
-            ("REDUCE", "f32", skel.SK_REDUCE):
-                lambda v: skel.skel_reduce(skel.SUM, x, out1, variant=v),
-            ("MAPREDUCE", "f32", skel.SK_MAPREDUCE):
-                lambda v: skel.skel_mapreduce(skel.MAP_MUL, None, [x, y], skel.SUM, out1,
-                                              variant=v),
-            ("SCAN", "i32", skel.SK_SCAN):
-                lambda v: skel.skel_scan(s, so, skel.INCLUSIVE, skel.SUM, variant=v),
-            ("MAP", "f32", skel.SK_MAP):
-                lambda v: skel.skel_map(skel.MAP_AXPY, [2.5], [x, y], y, variant=v),
-            ("MAPOVERLAP1D", "f32", skel.SK_MAPOVERLAP1D):
-                lambda v: skel.skel_mapoverlap1d(x, o1, w5, 2, skel.EDGE_CLAMP, variant=v),
-            ("MAPOVERLAP2D", "f32", skel.SK_MAPOVERLAP2D):
-                lambda v: skel.skel_mapoverlap2d(img, imo, wy=g9, wx=g9, edge=skel.EDGE_CLAMP,
-                                                 variant=v),
+            "REDUCE": (skel.SK_REDUCE,
+                       lambda v: skel.skel_reduce(skel.SUM, x, out1, variant=v)),
+            "MAPREDUCE": (skel.SK_MAPREDUCE,
+                          lambda v: skel.skel_mapreduce(skel.MAP_MUL, None, [x, y], skel.SUM,
+                                                        out1, variant=v)),
+            "SCAN": (skel.SK_SCAN,
+                     lambda v: skel.skel_scan(s, so, skel.INCLUSIVE, skel.SUM, variant=v)),
+            "MAP": (skel.SK_MAP,
+                    lambda v: skel.skel_map(skel.MAP_AXPY, [2.5], [x, y], y, variant=v)),
+            "MAPOVERLAP1D": (skel.SK_MAPOVERLAP1D,
+                             lambda v: skel.skel_mapoverlap1d(x, o1, w5, 2, skel.EDGE_CLAMP,
+                                                              variant=v)),
+            "MAPOVERLAP2D": (skel.SK_MAPOVERLAP2D,
+                             lambda v: skel.skel_mapoverlap2d(img, imo, wy=g9, wx=g9,
+                                                              edge=skel.EDGE_CLAMP, variant=v)),
         }
-        for (name, _dt, sk), call in cases.items():
+        out = {}
+        for name in names:
+            sk, call = cases[name]
             res = {}
             for v in range(skel.skel_variant_count(sk)):
                 vname = skel.skel_variant_name(sk, v)
-                if vname == single.get(sk) and k > SINGLE_WG_MAX_LOG2:
+                if vname == self.single.get(sk) and k > SINGLE_WG_MAX_LOG2:
                     continue
                 burst = BURST if k <= BURST_MAX_LOG2 else 1
                 try:
-                    res[vname] = round(_timed(torch, lambda: call(v), evict, reps, burst,
-                                                   spin), 3)
+                    res[vname] = round(_timed(self.torch, lambda: call(v), self.evict,
+                                              self.reps, burst, self.spin), 3)
                 except skel.SkelError as err:
                     if err.status != skel.E_UNSUPPORTED:
                         raise
                     # not selectable at this size (e.g. S5 beyond 1024 tiles)
-            report["results"].setdefault(name, {})[str(k)] = res
-            log(f"{name:10s} 2^{k:2d}: " + "  ".join(f"{a}={b:.1f}" for a, b in res.items()))
+            out[name] = res
+            self.log(f"{name:12s} 2^{k:2d}: " + "  ".join(f"{a}={b:.1f}" for a, b in res.items()))
         for c in (x, y, s, so, out1, o1, img, imo):
             c.destroy()
+        return out
+
+
+def tune(lo=10, hi=28, reps=7, log=print, allow_order_dependent=False, adaptive=False,
+         tol=0.05):
+    import torch
+
+    import paper_1405_2915_amd as skel
+    import synth_inputs as si
+
+    skel.skel_init(0, "torch", plan=None)  # time the variants, not a previous plan
+    timer = _Timer(torch, skel, si, reps, log)
+    report = {"lo": lo, "hi": hi, "reps": reps, "unit": "us", "results": {},
+              "mode": "adaptive" if adaptive else "full"}
+    if not adaptive:
+        for k in range(lo, hi + 1):
+            for name, res in timer.time_size(k, _Timer.CASES).items():
+                report["results"].setdefault(name, {})[str(k)] = res
+    else:
+        excl = () if allow_order_dependent else ORDER_DEPENDENT
+        bis = {name: Bisection(lo, hi, tol, excl) for name in _Timer.CASES}
+        rounds = 0
+        while True:
+            want = {}
+            for name, b in bis.items():
+                for k in b.wanted():
+                    want.setdefault(k, []).append(name)
+            if not want:
+                break
+            rounds += 1
+            for k in sorted(want):
+                for name, res in timer.time_size(k, want[k]).items():
+                    bis[name].add(k, res)
+            for b in bis.values():
+                b.step()
+        for name, b in bis.items():
+            report["results"][name] = {str(k): b.res[k] for k in sorted(b.res)}
+        report["rounds"] = rounds
+        report["sampled"] = {name: sorted(b.res) for name, b in bis.items()}
     report["dtypes"] = {"REDUCE": "f32", "MAPREDUCE": "f32", "SCAN": "i32", "MAP": "f32",
                         "MAPOVERLAP1D": "f32", "MAPOVERLAP2D": "f32"}
     report["timing"] = {"burst_max_log2": BURST_MAX_LOG2, "burst": BURST,
-                        "spin_cycles_per_us": round(spin.cycles_per_us, 1)}
+                        "spin_cycles_per_us": round(timer.spin.cycles_per_us, 1)}
     # the stencil class each MapOverlap entry was tuned on: radius 2 (the
     # 5-point binomial) in 1D, separable 9 x 9 (1 + 2 * 4) in 2D
     report["classes"] = {"MAPOVERLAP1D": 2, "MAPOVERLAP2D": 1 + 2 * 4}
-    return plan_from_report(report, allow_order_dependent=allow_order_dependent), report
+    return plan_from_report(report, tol=tol, allow_order_dependent=allow_order_dependent), report
+
+
+def plan_choice(table, name, k):
+    """The plan's variant for skeleton `name` at log2 n = k: the entry of the
+    nearest sampled size at or below k (None below the first)."""
+    best = None
+    for nm, _dt, kk, v, _c in sorted(table, key=lambda e: e[2]):
+        if nm == name and kk <= k:
+            best = v
+    return best
+
+
+def compare_with_full(table, full_report, allow_order_dependent=False):
+    """For every skeleton and size of a full sweep: the chosen variant's time
+    over the fastest there.  Returns {name: {"sizes": N, "worst": x,
+    "mean": x, "over_tol": count}} and the per-size ratios."""
+    out, ratios = {}, {}
+    for name, per_k in full_report["results"].items():
+        rs = []
+        for k, res in per_k.items():
+            res = {a: b for a, b in res.items()
+                   if allow_order_dependent or a not in ORDER_DEPENDENT}
+            pick = plan_choice(table, name, int(k))
+            if pick is None or pick not in res:
+                continue
+            r = res[pick] / min(res.values())
+            rs.append(r)
+            ratios[(name, int(k))] = r
+        if rs:
+            out[name] = {"sizes": len(rs), "worst": round(max(rs), 3),
+                         "mean": round(float(np.mean(rs)), 4),
+                         "over_tol": sum(r > 1.05 for r in rs)}
+    return out, ratios
 
 
 def plan_from_report(report, tol=0.05, allow_order_dependent=False):
@@ -283,6 +416,11 @@ def main():
                     help="let the plan pick the atomic-finish Reduce")
     ap.add_argument("--from-report", default=None,
                     help="write the plan from a saved JSON report, without timing")
+    ap.add_argument("--adaptive", action="store_true",
+                    help="sample sizes adaptively (bisect only where the choice changes)")
+    ap.add_argument("--compare", default=None,
+                    help="a full sweep's JSON report: state how far the written plan's "
+                         "choices are from that sweep's fastest variants")
     args = ap.parse_args()
     if args.from_report:
         with open(args.from_report) as f:
@@ -291,17 +429,26 @@ def main():
         write_plan(table, args.out, report.get("header", []))
         if args.summary:
             write_summary(report, table, args.summary, report.get("header", []))
-        print(json.dumps({"plan": args.out, "entries": len(table)}))
+        res = {"plan": args.out, "entries": len(table)}
+        if args.compare:
+            with open(args.compare) as f:
+                full = json.load(f)
+            res["against_full_sweep"], _ = compare_with_full(table, full,
+                                                             args.allow_order_dependent)
+        print(json.dumps(res))
         return
     log = lambda m: print(f"[autotune] {m}", file=sys.stderr, flush=True)
-    table, report = tune(args.min, args.max, args.reps, log, args.allow_order_dependent)
+    table, report = tune(args.min, args.max, args.reps, log, args.allow_order_dependent,
+                         adaptive=args.adaptive)
     import torch
     dev = torch.cuda.get_device_properties(0)
     report["header"] = [f"device: {dev.name} ({dev.gcnArchName}), "
                         f"{dev.multi_processor_count} CUs",
-                        f"sizes 2^{args.min}..2^{args.max}, median of {args.reps}, "
-                        "Infinity Cache evicted before each timed call; a choice is kept "
-                        "while within 5% of the fastest"]
+                        f"sizes 2^{args.min}..2^{args.max}"
+                        + (" sampled adaptively" if args.adaptive else "")
+                        + f", median of {args.reps}, Infinity Cache evicted (plain-load read "
+                        "of 1 GiB) before each timed call; a choice is kept while within 5% "
+                        "of the fastest"]
     report["header"].append(f"sizes up to 2^{BURST_MAX_LOG2}: bursts of {BURST} back-to-back "
                             "calls per event pair, enqueued behind a spin kernel (device "
                             "time)")
@@ -311,7 +458,16 @@ def main():
             json.dump(report, f, indent=1)
     if args.summary:
         write_summary(report, table, args.summary, report["header"])
-    print(json.dumps({"plan": args.out, "entries": len(table)}))
+    res = {"plan": args.out, "entries": len(table)}
+    if args.adaptive:
+        res["samples"] = {name: len(ks) for name, ks in report["sampled"].items()}
+        res["rounds"] = report["rounds"]
+    if args.compare:
+        with open(args.compare) as f:
+            full = json.load(f)
+        res["against_full_sweep"], _ = compare_with_full(table, full,
+                                                         args.allow_order_dependent)
+    print(json.dumps(res))
 
 
 if __name__ == "__main__":

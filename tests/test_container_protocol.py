@@ -397,8 +397,8 @@ def test_default_plan_applies_to_its_stencil_class_only(rt):
     assert rt.skel_load_plan(PLAN.encode()) == OK
     sel = lambda sk, n, aux, rows=4096: name_of(
         rt, sk, rt.skel_select_variant(sk, F32, n, rows, n // rows, aux))
-    assert sel(SK_OV2, 1 << 24, 1 + 2 * 1) == "O2e_march"           # separable 3 x 3
-    assert sel(SK_OV2, 1 << 24, 1 + 2 * 4) == "O2d_separable_l1"    # the tuned 9 x 9
+    assert sel(SK_OV2, 1 << 26, 1 + 2 * 1, 8192) == "O2e_march"     # separable 3 x 3
+    assert sel(SK_OV2, 1 << 26, 1 + 2 * 4, 8192) == "O2d_separable_l1"  # the tuned 9 x 9
     assert sel(SK_OV2, 1 << 22, 1 + 2 * 4, 2048) == "O2c_lds_separable"
     assert sel(SK_OV2, 1 << 24, 2 * 1) == "O2e_march"               # dense 5-point
     assert sel(SK_OV2, 1 << 24, 2 * 4) == "O2b_lds_tile"            # dense 9 x 9
