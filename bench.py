@@ -76,7 +76,18 @@ SCAN_KERNELS = {
     "S2_decoupled_lookback": "scan_lookback<int32 -> int64, exclusive sum>",
     "S3_persistent_lookback": "scan_lookback_persist<int32 -> int64, exclusive sum>",
 }
-KERNEL_SRC = {"scan_excl_i32_i64": "k_scan.hip"}
+# device sources of the dominant kernel: its traffic figure holds only while
+# their combined hash is the one the counters were taken on
+KERNEL_SRC = {"scan_excl_i32_i64": ("k_scan.hip", "kcommon.hpp", "kepoch.hpp")}
+
+
+def source_hash(name):
+    """sha256 over the named kernel's device sources, in the listed order."""
+    h = hashlib.sha256()
+    for src in KERNEL_SRC[name]:
+        with open(os.path.join(ROOT, "paper_1405_2915_amd", "csrc", src), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def log(msg):
@@ -252,9 +263,7 @@ def traffic_from_profile(name, per_launch_bytes, variant):
     m_var = re.search(r"variant:\s*(\S+)", text)
     if not m_hash or not m_bytes or not m_var or m_var.group(1) != variant:
         return None
-    cur = hashlib.sha256(open(os.path.join(ROOT, "paper_1405_2915_amd", "csrc", src),
-                              "rb").read()).hexdigest()
-    if cur != m_hash.group(1):
+    if source_hash(name) != m_hash.group(1):
         return None
     return float(m_bytes.group(1))
 

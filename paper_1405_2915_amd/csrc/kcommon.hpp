@@ -261,20 +261,29 @@ __device__ __forceinline__ void tagged_put(u64* w2, int state, uint32_t epoch, A
 
 // Returns the state (0 when the word is stale, i.e. of another epoch, or when
 // the two halves of a 64-bit payload carry different tags) and the payload.
+//
+// Both words of a 64-bit payload are loaded before either is examined, so a
+// read costs one round trip to the device-coherent level, not two (a load
+// issued only after the first word's tag checked out waits for that word).
+// Which order the two words are observed in does not matter: a pair is taken
+// only when both carry the same state and epoch, and a writer publishes each
+// state's pair with one tag.
 template <class A>
 __device__ __forceinline__ int tagged_get(u64* w2, uint32_t epoch, A& v) {
-    const u64 lo = tag_load(w2);
-    if (((lo >> 32) & 0x3fffffffull) != epoch) return 0;
     if constexpr (sizeof(A) == 4) {
+        const u64 lo = tag_load(w2);
+        if (((lo >> 32) & 0x3fffffffull) != epoch) return 0;
         const uint32_t b = (uint32_t)lo;
         __builtin_memcpy(&v, &b, 4);
+        return (int)(lo >> 62);
     } else {
+        const u64 lo = tag_load(w2);
         const u64 hi = tag_load(w2 + 1);
-        if ((hi >> 32) != (lo >> 32)) return 0;
+        if (((lo >> 32) & 0x3fffffffull) != epoch || (hi >> 32) != (lo >> 32)) return 0;
         const u64 b = (lo & 0xffffffffull) | (hi << 32);
         __builtin_memcpy(&v, &b, 8);
+        return (int)(lo >> 62);
     }
-    return (int)(lo >> 62);
 }
 
 // ---------------------------------------------------------- vector access --
