@@ -628,7 +628,8 @@ def small_config(skel, torch):
     back-to-back calls between one event pair, enqueued behind a spin kernel
     so that host issue gaps stay out (the plan's variant for each call), every
     Reduce and single-pass Scan variant on its own, and the four calls as one
-    step issued call by call and replayed as a captured graph."""
+    step: issued call by call, replayed as a captured graph, and forked onto
+    four streams (eagerly and as a graph with four branches)."""
     import synth_inputs as si
     n = 1 << 20
     x = skel.Container.from_numpy(si.uniform_f32(n, -1.0, 1.0, 0, 0))
@@ -691,8 +692,35 @@ def small_config(skel, torch):
         torch.cuda.synchronize()
         eager = per_call_us(lambda: [fn() for _, _, _, fn in calls.values()], 25)
         graph = per_call_us(g.replay, 25)
+        # The four calls are independent, and the containers order only
+        # conflicting accesses (the Map and the Reduce both only read x): the
+        # same step with three calls forked onto their own streams and the
+        # fourth on this one, joined again, eagerly and as one captured graph
+        # with four branches.
+        fns = [fn for _, _, _, fn in calls.values()]
+        side = [torch.cuda.Stream() for _ in fns[1:]]
+
+        def fork():
+            for st, fn in zip(side, fns[1:]):
+                st.wait_stream(stream)
+                with torch.cuda.stream(st):
+                    fn()
+            fns[0]()
+            for st in side:
+                stream.wait_stream(st)
+
+        fork()  # outside capture: sizes every stream's workspace
+        torch.cuda.synchronize()
+        g4 = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g4, stream=stream):
+            fork()
+        torch.cuda.synchronize()
+        eager4 = per_call_us(fork, 25)
+        graph4 = per_call_us(g4.replay, 25)
     skel.skel_sync(stream)
-    res["step_of_four"] = {"eager_us": round(eager, 2), "graph_us": round(graph, 2)}
+    res["step_of_four"] = {"eager_us": round(eager, 2), "graph_us": round(graph, 2),
+                           "four_streams_eager_us": round(eager4, 2),
+                           "four_streams_graph_us": round(graph4, 2)}
     for c in (x, y, s, so, z, o, r):
         c.destroy()
     return res

@@ -204,9 +204,12 @@ skel_status skel_container_destroy(skel_container *c);
  *   READ  copies from the other place iff this copy is stale;
  *   WRITE copies nothing and invalidates the other copy (whole overwrite);
  *   RW    both.
- * A device acquire enqueues its copy on `stream` and orders it after the
- * container's last device access on any other stream.  A host acquire waits
- * for the container's device work to finish.  Errors: SKEL_E_STATE when a
+ * A device acquire enqueues its copy on `stream` and orders the access after
+ * the conflicting device accesses on other streams (Section V dependences): a
+ * WRITE/RW acquire, or a READ that copies stale data, after every other
+ * stream's last access; a READ only after other streams' writes, so reads of
+ * one container on several streams may run concurrently.  A host acquire
+ * waits for the container's device work to finish.  Errors: SKEL_E_STATE when a
  * WRITE/RW acquire is outstanding, when WRITE/RW meets outstanding readers,
  * or when READ/RW finds no valid copy. */
 skel_status skel_container_acquire(skel_container *c, skel_place place,

@@ -25,7 +25,7 @@ skel_container::StreamEvent* event_for(skel_container* c, void* stream,
     void* ev = nullptr;
     *st = rt().backend->event_create(&ev);
     if (*st != SKEL_OK) return nullptr;
-    c->events.push_back({stream, ev, false, false, 0, {}});
+    c->events.push_back({stream, ev, false, false, 0, false, 0, {}});
     return &c->events.back();
 }
 
@@ -37,26 +37,39 @@ skel_status flush_pending(skel_container::StreamEvent& e) {
     e.recorded = true;
     e.pending = false;
     e.gen += 1;
+    if (e.pending_write) {
+        e.wgen = e.gen;
+        e.pending_write = false;
+    }
     return SKEL_OK;
 }
 
-// Make `stream` wait for the last device access of every other stream,
-// skipping events whose current generation it already waited on.
-skel_status order_after_other_streams(skel_container* c, void* stream) {
+// Make `stream` wait for the device accesses of other streams that conflict
+// with an access of kind `writing` (Section V: the dependences of a call are
+// found from its operands).  A writer waits for every other stream's last
+// access (reads and writes); a reader only for other streams' writes, which
+// include the copies of stale ranges that a reader's acquire enqueued: reads
+// on different streams run concurrently.  Events whose generation this stream
+// already waited on are skipped.
+skel_status order_after_other_streams(skel_container* c, void* stream, bool writing) {
     skel_status st = SKEL_OK;
     if (!event_for(c, stream, &st)) return st;  // entry for `stream` exists now
     size_t me = 0;
     while (c->events[me].stream != stream) ++me;
     for (size_t k = 0; k < c->events.size(); ++k) {
         if (k == me) continue;
+        auto& seen = c->events[me].seen;
+        auto it = seen.begin();
+        while (it != seen.end() && it->first != c->events[k].stream) ++it;
+        const uint64_t waited = it != seen.end() ? it->second : 0;
+        if (!writing && !c->events[k].pending_write &&
+            (c->events[k].wgen == 0 || waited >= c->events[k].wgen))
+            continue;  // no write of stream k this one is not yet ordered after
         st = flush_pending(c->events[k]);
         if (st != SKEL_OK) return st;
         const auto& e = c->events[k];
         if (!e.recorded) continue;
-        auto& seen = c->events[me].seen;
-        auto it = seen.begin();
-        while (it != seen.end() && it->first != e.stream) ++it;
-        if (it != seen.end() && it->second == e.gen) continue;
+        if (waited == e.gen) continue;
         st = rt().backend->stream_wait_event(stream, e.event);
         if (st != SKEL_OK) return st;
         if (it != seen.end()) it->second = e.gen;
@@ -176,11 +189,21 @@ skel_status acquire(skel_container* c, skel_place place, skel_access access, int
                 if (st != SKEL_OK) return st;
             }
             // order after device work on other streams (Section V dependences)
-            st = order_after_other_streams(c, stream);
+            const auto missing = has_read(access) ? ranges_missing(c->valid_dev, lo, hi)
+                                                  : std::vector<std::pair<int64_t, int64_t>>{};
+            st = order_after_other_streams(c, stream, has_write(access) || !missing.empty());
             if (st != SKEL_OK) return st;
+            if (!missing.empty()) {
+                // this stream now writes the device copy: later readers on
+                // other streams order after it
+                skel_container::StreamEvent* me = event_for(c, stream, &st);
+                if (!me) return st;
+                me->pending = true;
+                me->pending_write = true;
+            }
             if (has_read(access)) {
                 // copy only the stale parts of the range (partial copies)
-                for (const auto& m : ranges_missing(c->valid_dev, lo, hi)) {
+                for (const auto& m : missing) {
                     const size_t off = (size_t)m.first * es, len = (size_t)(m.second - m.first) * es;
                     st = be->copy_h2d(static_cast<char*>(c->dev) + off,
                                       static_cast<const char*>(c->host) + off, len, stream);
@@ -249,6 +272,7 @@ skel_status release(skel_container* c, skel_place place, void* stream) {
             skel_container::StreamEvent* e = event_for(c, stream, &st);
             if (!e) return st;
             e->pending = true;  // recorded lazily, when someone must order after it
+            if (c->writer == SKEL_DEVICE) e->pending_write = true;
             c->last_stream = stream;
         }
         if (c->writer == SKEL_DEVICE) c->writer = -1;
@@ -340,6 +364,7 @@ skel_status skel_container_wrap_device(skel_dtype dtype, int64_t rows, int64_t c
             return st;
         }
         e->pending = true;
+        e->pending_write = true;
         c->last_stream = stream;
     }
     *out = c;

@@ -40,6 +40,8 @@ struct skel_container {
         bool recorded;  // the event holds a record
         bool pending;   // work enqueued on the stream since the last record
         uint64_t gen;   // number of records so far
+        bool pending_write;  // that work writes the device copy
+        uint64_t wgen;       // first record that follows the stream's last write (0: none)
         // (other stream, generation of its event this stream already waited on)
         std::vector<std::pair<void*, uint64_t>> seen;
     };

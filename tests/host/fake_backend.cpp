@@ -6,6 +6,7 @@
 // allocation and of copies can be injected.
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <vector>
 
 #include "chain_table.hpp"
@@ -22,6 +23,38 @@ int g_fail_dev_alloc = 0;
 int g_fail_copy = 0;
 // (stream, event) of every stream_wait_event, for ordering checks
 std::vector<std::pair<void*, void*>> g_waits;
+
+// Ordering model: every operation enqueued on a stream (copies, and the test's
+// stand-ins for kernels) gets the stream's next position; a vector clock per
+// stream holds, for every other stream, the last position known to complete
+// before the stream's next operation.  An event record snapshots the
+// recording stream's clock and position, a stream wait merges a snapshot into
+// the waiting stream's clock, and an event (or stream) sync merges it into the
+// host's.
+using Clock = std::map<void*, long>;
+struct Op {
+    void* stream;
+    long pos;
+    Clock clock;  // the stream's clock when the operation was enqueued
+};
+std::map<void*, long> g_pos;
+std::map<void*, Clock> g_clock;
+std::map<void*, Clock> g_snap;  // event -> snapshot of its last record
+Clock g_host;
+std::vector<Op> g_ops;
+
+void merge(Clock& into, const Clock& from) {
+    for (const auto& kv : from)
+        if (into[kv.first] < kv.second) into[kv.first] = kv.second;
+}
+
+// the host issues an operation after everything it has seen complete
+int enqueue(void* s) {
+    merge(g_clock[s], g_host);
+    const long p = ++g_pos[s];
+    g_ops.push_back({s, p, g_clock[s]});
+    return (int)g_ops.size() - 1;
+}
 
 class FakeBackend final : public skel::Backend {
   public:
@@ -48,22 +81,24 @@ class FakeBackend final : public skel::Backend {
         g_counts.dev_frees++;
         std::free(p);
     }
-    skel_status copy_h2d(void* dst, const void* src, size_t bytes, void*) override {
+    skel_status copy_h2d(void* dst, const void* src, size_t bytes, void* s) override {
         if (g_fail_copy > 0) {
             g_fail_copy--;
             return skel::fail(SKEL_E_HIP, "injected copy failure");
         }
         std::memcpy(dst, src, bytes);
         g_counts.h2d++;
+        enqueue(s);
         return SKEL_OK;
     }
-    skel_status copy_d2h(void* dst, const void* src, size_t bytes, void*) override {
+    skel_status copy_d2h(void* dst, const void* src, size_t bytes, void* s) override {
         if (g_fail_copy > 0) {
             g_fail_copy--;
             return skel::fail(SKEL_E_HIP, "injected copy failure");
         }
         std::memcpy(dst, src, bytes);
         g_counts.d2h++;
+        enqueue(s);
         return SKEL_OK;
     }
     skel_status event_create(void** ev) override {
@@ -72,22 +107,29 @@ class FakeBackend final : public skel::Backend {
         return SKEL_OK;
     }
     void event_destroy(void* ev) override { delete static_cast<int*>(ev); }
-    skel_status event_record(void* ev, void*) override {
+    skel_status event_record(void* ev, void* s) override {
         ++*static_cast<int*>(ev);
         g_counts.event_records++;
+        Clock snap = g_clock[s];
+        snap[s] = g_pos[s];
+        g_snap[ev] = snap;
         return SKEL_OK;
     }
     skel_status stream_wait_event(void* s, void* ev) override {
         g_counts.stream_waits++;
         g_waits.emplace_back(s, ev);
+        merge(g_clock[s], g_snap[ev]);
         return SKEL_OK;
     }
-    skel_status event_sync(void*) override {
+    skel_status event_sync(void* ev) override {
         g_counts.event_syncs++;
+        merge(g_host, g_snap[ev]);
         return SKEL_OK;
     }
-    skel_status stream_sync(void*) override {
+    skel_status stream_sync(void* s) override {
         g_counts.stream_syncs++;
+        merge(g_host, g_clock[s]);
+        if (g_host[s] < g_pos[s]) g_host[s] = g_pos[s];
         return SKEL_OK;
     }
 };
@@ -105,6 +147,11 @@ skel_status skel_hosttest_init(void) {
     std::memset(&g_counts, 0, sizeof g_counts);
     g_fail_dev_alloc = g_fail_copy = 0;
     g_waits.clear();
+    g_pos.clear();
+    g_clock.clear();
+    g_snap.clear();
+    g_host.clear();
+    g_ops.clear();
     return SKEL_OK;
 }
 
@@ -137,6 +184,29 @@ int skel_hosttest_wait_count_on(void* stream) {
     for (auto& w : g_waits)
         if (w.first == stream) ++k;
     return k;
+}
+
+// Stand-in for a kernel enqueued on `stream`: returns its operation index.
+int skel_hosttest_enqueue(void* stream) { return enqueue(stream); }
+
+// Operations enqueued so far (copies included).
+int skel_hosttest_op_count(void) { return (int)g_ops.size(); }
+
+// 1 if operation i completes before operation j starts (same stream: stream
+// order; otherwise j's stream had waited on an event recorded after i).
+int skel_hosttest_op_before(int i, int j) {
+    const Op& a = g_ops.at((size_t)i);
+    const Op& b = g_ops.at((size_t)j);
+    if (a.stream == b.stream) return a.pos < b.pos ? 1 : 0;
+    const auto it = b.clock.find(a.stream);
+    return it != b.clock.end() && it->second >= a.pos ? 1 : 0;
+}
+
+// 1 if operation i is known complete on the host (an event or stream sync).
+int skel_hosttest_op_before_host(int i) {
+    const Op& a = g_ops.at((size_t)i);
+    const auto it = g_host.find(a.stream);
+    return it != g_host.end() && it->second >= a.pos ? 1 : 0;
 }
 
 }  // extern "C"

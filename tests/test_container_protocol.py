@@ -244,6 +244,75 @@ def test_cross_stream_dependence(rt):
     assert rt.skel_container_destroy(h) == OK
 
 
+def test_reads_on_other_streams_are_not_ordered(rt):
+    # only conflicting accesses are ordered: reads of one operand on different
+    # streams run concurrently, writes (a reader's copy of stale data included)
+    # are ordered against everything
+    h = create(rt, 32, np.zeros(32, np.float32))
+    waits = lambda s: rt.skel_hosttest_wait_count_on(C.c_void_p(s))
+    for s in (11, 22, 11, 33):  # 11 copies the host data: a write
+        st, _ = acquire(rt, h, DEVICE, READ, stream=s)
+        assert st == OK and rt.skel_container_release(h, DEVICE, C.c_void_p(s)) == OK
+    assert (waits(11), waits(22), waits(33)) == (0, 1, 1)  # 22 and 33 after 11's copy only
+    st, _ = acquire(rt, h, DEVICE, WRITE, stream=44)  # a writer waits for every reader
+    assert st == OK and rt.skel_container_release(h, DEVICE, C.c_void_p(44)) == OK
+    assert waits(44) == 3
+    st, _ = acquire(rt, h, DEVICE, READ, stream=22)  # and a reader for the writer
+    assert st == OK and rt.skel_container_release(h, DEVICE, C.c_void_p(22)) == OK
+    assert waits(22) == 2
+    assert rt.skel_container_destroy(h) == OK
+
+
+def _device_access(rt, h, stream, access):
+    """acquire on the device, one stand-in kernel, release; returns the
+    (operation, writes) pairs of the access: its copies, then the kernel"""
+    first = rt.skel_hosttest_op_count()
+    st, _ = acquire(rt, h, DEVICE, access, stream=stream)
+    if st != OK:
+        return st, []
+    copies = [(i, True) for i in range(first, rt.skel_hosttest_op_count())]
+    k = rt.skel_hosttest_enqueue(C.c_void_p(stream))
+    assert rt.skel_container_release(h, DEVICE, C.c_void_p(stream)) == OK
+    return st, copies + [(k, access != READ)]
+
+
+@pytest.mark.parametrize("seed", range(16))
+def test_random_stream_traces_order_every_conflict(rt, seed):
+    """Random device and host accesses on four streams, checked against a
+    vector-clock model of the fake runtime: every pair of operations that
+    touch the device copy from different streams, one of them a write, is
+    ordered (the earlier completes before the later starts); every host access
+    comes after all earlier device operations."""
+    rt.skel_hosttest_enqueue.argtypes = [C.c_void_p]
+    rnd = random.Random(seed)
+    h = create(rt, 16, np.zeros(16, np.float32))
+    ops = []  # (operation, writes) of every device access so far
+    unordered_reads = 0
+    for _ in range(200):
+        if rnd.random() < 0.15:
+            access = rnd.choice((READ, WRITE, RW))
+            first = rt.skel_hosttest_op_count()
+            st, _ = acquire(rt, h, HOST, access)
+            assert st == OK
+            for i, _w in ops:
+                assert rt.skel_hosttest_op_before_host(i), (seed, i)
+            ops += [(i, False) for i in range(first, rt.skel_hosttest_op_count())]  # D2H
+            assert rt.skel_container_release(h, HOST, None) == OK
+            continue
+        stream = rnd.choice((11, 22, 33, 44))
+        st, mine = _device_access(rt, h, stream, rnd.choice((READ, READ, WRITE, RW)))
+        assert st == OK
+        for j, wj in mine:
+            for i, wi in ops:
+                if wi or wj:
+                    assert rt.skel_hosttest_op_before(i, j), (seed, i, j)
+                elif not rt.skel_hosttest_op_before(i, j):
+                    unordered_reads += 1
+        ops += mine
+    assert rt.skel_container_destroy(h) == OK
+    assert unordered_reads > 0  # reads on different streams did overlap
+
+
 def test_injected_failures_leave_state_unchanged(rt):
     x = np.arange(8, dtype=np.float32)
     h = create(rt, 8, x)

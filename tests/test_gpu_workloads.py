@@ -43,6 +43,77 @@ def test_small_plain_skeletons(skel, oracle_mod):
     skel.skel_sync()
 
 
+def test_small_step_on_four_streams(skel, oracle_mod):
+    """The small configuration's four calls are independent (the Map and the
+    Reduce both only read x), and the containers order only conflicting
+    accesses (Section V), so the four calls may run on four streams at once:
+    eagerly, and as one captured graph whose four branches fork from one
+    stream and join it again.  New inputs before every round, eager rounds
+    between the replays; every result of every round matches the oracle."""
+    import torch
+    n = (1 << 20) + 3
+    w = si.binomial5_weights()
+    cx, cy, cz = (skel.Container.empty(skel.F32, n) for _ in range(3))
+    cs = skel.Container.empty(skel.I32, n)
+    cm, co = skel.Container.empty(skel.F32, n), skel.Container.empty(skel.F32, n)
+    cr, cso = skel.Container.empty(skel.F32, 1), skel.Container.empty(skel.I32, n)
+    main = torch.cuda.Stream()
+    side = [torch.cuda.Stream() for _ in range(4)]
+    calls = (lambda st: skel.skel_map(skel.MAP_AXPY, [2.5], [cx, cy], cm, stream=st),
+             lambda st: skel.skel_reduce(skel.SUM, cx, cr, stream=st),
+             lambda st: skel.skel_scan(cs, cso, skel.INCLUSIVE, skel.SUM, stream=st),
+             lambda st: skel.skel_mapoverlap1d(cz, co, w, 2, skel.EDGE_CLAMP, stream=st))
+
+    def put(rep):
+        arrs = (si.uniform_f32(n, -1.0, 1.0, 9, 4 * rep), si.uniform_f32(n, -1.0, 1.0, 9, 4 * rep + 1),
+                si.int_uniform_i32(n, 100, 9, 4 * rep + 2),
+                si.uniform_f32(n, -1.0, 1.0, 9, 4 * rep + 3))
+        for c, a in zip((cx, cy, cs, cz), arrs):
+            c.write_numpy(a)
+            skel.skel_container_acquire(c, skel.DEVICE, skel.READ, main)  # resident
+            skel.skel_container_release(c, skel.DEVICE, main)
+        return arrs
+
+    def fork():
+        for st, fn in zip(side, calls):
+            st.wait_stream(main)
+            fn(st)
+        for st in side:
+            main.wait_stream(st)
+
+    def check(arrs, what):
+        x, y, s, z = arrs
+        assert np.array_equal(cm.to_numpy(), oracle_mod.map_f32("axpy", [2.5], x, y)
+                              .astype(np.float32)), what
+        got = float(cr.to_numpy()[0])
+        assert abs(got - oracle_mod.reduce("sum", x)) <= 1e-5 * oracle_mod.abs_sum(x), what
+        assert np.array_equal(cso.to_numpy(), oracle_mod.scan(s, "inclusive", "sum")), what
+        ref, mag = oracle_mod.mapoverlap1d(z, w, 2)
+        assert np.all(np.abs(co.to_numpy().astype(np.float64) - ref) <= 1e-6 * mag + 1e-30), what
+
+    arrs = put(0)
+    with torch.cuda.stream(main):
+        fork()  # eager; also sizes every stream's workspace outside the capture
+    check(arrs, "eager")
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=main):
+        fork()
+    torch.cuda.synchronize()
+    for rep in range(1, 4):
+        arrs = put(2 * rep)
+        with torch.cuda.stream(main):
+            fork()
+        check(arrs, f"eager round {rep}")
+        arrs = put(2 * rep + 1)
+        with torch.cuda.stream(main):
+            g.replay()
+        for c in (cm, cr, cso, co):
+            c.mark_device_written(main)
+        check(arrs, f"replay {rep}")
+    skel.skel_sync()
+
+
 def test_gaussian_stencil_4096(skel, oracle_mod):
     H = W = 4096
     x = si.uniform_f32(H * W, 0.0, 1.0, 1, 0).reshape(H, W)
