@@ -692,6 +692,14 @@ def small_config(skel, torch):
         torch.cuda.synchronize()
         eager = per_call_us(lambda: [fn() for _, _, _, fn in calls.values()], 25)
         graph = per_call_us(g.replay, 25)
+        # ten steps in one graph: what a replay costs beyond its kernels
+        g10 = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g10, stream=stream):
+            for _ in range(10):
+                for _, _, _, fn in calls.values():
+                    fn()
+        torch.cuda.synchronize()
+        graph10 = per_call_us(g10.replay, 10) / 10
         # The four calls are independent, and the containers order only
         # conflicting accesses (the Map and the Reduce both only read x): the
         # same step with three calls forked onto their own streams and the
@@ -719,6 +727,7 @@ def small_config(skel, torch):
         graph4 = per_call_us(g4.replay, 25)
     skel.skel_sync(stream)
     res["step_of_four"] = {"eager_us": round(eager, 2), "graph_us": round(graph, 2),
+                           "graph_of_ten_steps_us_per_step": round(graph10, 2),
                            "four_streams_eager_us": round(eager4, 2),
                            "four_streams_graph_us": round(graph4, 2)}
     for c in (x, y, s, so, z, o, r):
