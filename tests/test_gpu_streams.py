@@ -1,14 +1,16 @@
 """Cross-stream ordering on the device (Section V: the containers find each
 call's dependences from its operands).  A seeded random sequence of skeleton
 calls over four shared containers -- Map saxpy (in place or not), 5-point
-MapOverlap 1D, sum Reduce, host reads and host rewrites -- runs once with
-every call on one stream and once with each call on one of three streams, a
+MapOverlap 1D, inclusive Scan (in place or not; the flat look-back S5, whose
+binary32 combination order is fixed, where S2/S3 combine in timing-dependent
+order), sum Reduce, dot MapReduce, host reads and host rewrites -- runs once
+with every call on one stream and once with each call on one of three streams, a
 spin kernel delaying some calls' streams so that later calls on other streams
 would overtake them unless ordered.  Both runs launch the same kernels on the
 same data in the same program order, so any missed dependence (a read before
 another stream's write has finished, a write over data another stream is
-still reading) shows as a difference: every container, every Reduce result
-and every host read must be bitwise equal."""
+still reading) shows as a difference: every container, every Reduce and
+MapReduce result and every host read must be bitwise equal."""
 import random
 
 import numpy as np
@@ -26,8 +28,8 @@ def make_ops(seed, count=60):
     rnd = random.Random(seed)
     ops = []
     for i in range(count):
-        kind = rnd.choices(("axpy", "stencil", "reduce", "read", "write"),
-                           weights=(35, 25, 25, 8, 7))[0]
+        kind = rnd.choices(("axpy", "stencil", "scan", "reduce", "dot", "read", "write"),
+                           weights=(25, 20, 15, 15, 10, 8, 7))[0]
         a, b, c = (rnd.randrange(NCONT) for _ in range(3))
         if kind == "stencil" and c == a:
             c = (a + 1) % NCONT
@@ -51,9 +53,16 @@ def run_trace(skel, torch, ops, streams):
             skel.skel_map(skel.MAP_AXPY, [op["alpha"]], [a, b], c, stream=s)
         elif op["kind"] == "stencil":
             skel.skel_mapoverlap1d(a, c, w5, 2, skel.EDGE_CLAMP, stream=s)
+        elif op["kind"] == "scan":
+            skel.skel_scan(a, c, skel.INCLUSIVE, skel.SUM,
+                           variant=skel.variant_index(skel.SK_SCAN, "S5_flat_lookback"), stream=s)
         elif op["kind"] == "reduce":
             r = skel.Container.empty(skel.F32, 1)
             skel.skel_reduce(skel.SUM, a, r, stream=s)
+            sums.append(r)
+        elif op["kind"] == "dot":
+            r = skel.Container.empty(skel.F32, 1)
+            skel.skel_mapreduce(skel.MAP_MUL, None, [a, b], skel.SUM, r, stream=s)
             sums.append(r)
         elif op["kind"] == "read":
             seen.append(a.to_numpy().copy())
@@ -78,7 +87,7 @@ def test_random_calls_on_three_streams_match_one_stream(skel, seed):
     got = run_trace(skel, torch, ops, three)
     for k, (x, y) in enumerate(zip(ref[0], got[0])):
         assert np.array_equal(x.view(np.uint32), y.view(np.uint32)), (seed, "container", k)
-    assert ref[1] == got[1], (seed, "reduce results")
+    assert ref[1] == got[1], (seed, "Reduce and MapReduce results")
     assert len(ref[2]) == len(got[2])
     for k, (x, y) in enumerate(zip(ref[2], got[2])):
         assert np.array_equal(x.view(np.uint32), y.view(np.uint32)), (seed, "host read", k)
