@@ -114,7 +114,12 @@ int static_rule(const CallContext& c) {
         return c.separable ? overlap2d_separable_variant(c.n, c.radius)
                            : overlap2d_dense_variant(c.n, c.radius);
     case SKEL_SK_SCAN:
-        return c.n <= (INT64_C(1) << 15) && !c.reverse ? S0_SINGLE_WG : S3_PERSISTENT_LOOKBACK;
+        // the flat look-back while the array fits its 1024 tiles (the tuned plan's
+        // choice for int32 up to 2^22, and its binary32 combination order is
+        // fixed, so float scans are bit-stable run to run); beyond, the persistent
+        // look-back
+        return c.n <= kFlatMaxTiles * scan_flat_tile(c.din) ? S5_FLAT_LOOKBACK
+                                                            : S3_PERSISTENT_LOOKBACK;
     case SKEL_SK_REDUCE_SEGMENTS: return B1_PERSISTENT;
     case SKEL_SK_SCAN_ROWS:
         // a few long rows: one single-pass scan per row fills the device;

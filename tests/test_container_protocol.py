@@ -401,7 +401,13 @@ def test_static_plan(rt):
         rt, sk, rt.skel_select_variant(sk, dt, n, 1, n, sep))
     assert sel(SK_REDUCE, 1000) == "R0_single_wg"
     assert sel(SK_REDUCE, 1 << 26) == "R2_ticket"
-    assert sel(SK_SCAN, 100, I32) == "S0_single_wg"
+    # the flat look-back up to its 1024 tiles (4096 elements each, 2048 for
+    # 64-bit inputs), then the persistent look-back
+    assert sel(SK_SCAN, 100, I32) == "S5_flat_lookback"
+    assert sel(SK_SCAN, 1 << 22, F32) == "S5_flat_lookback"
+    assert sel(SK_SCAN, (1 << 22) + 1, F32) == "S3_persistent_lookback"
+    assert sel(SK_SCAN, 1 << 21, I64) == "S5_flat_lookback"
+    assert sel(SK_SCAN, (1 << 21) + 1, I64) == "S3_persistent_lookback"
     assert sel(SK_SCAN, 1 << 27, I32) == "S3_persistent_lookback"
     # aux = separable + 2 * radius: the marching window up to radius 2 on large
     # images (either weight form), else the separable L1 variant or, for dense
@@ -438,7 +444,7 @@ def test_plan_table(rt, tmp_path):
     assert sel(SK_REDUCE, 1 << 28) == "R3_atomic"          # extrapolate beyond
     assert sel(SK_REDUCE, 16) == "R1_two_pass"             # below the table
     assert sel(SK_SCAN, 1 << 20, I32) == "S1_reduce_then_scan"
-    assert sel(SK_SCAN, 1 << 20, I64) == "S3_persistent_lookback"  # no entry: static
+    assert sel(SK_SCAN, 1 << 22, I64) == "S3_persistent_lookback"  # no entry: static
     # table entry not selectable for this call: static rule instead
     assert sel(SK_OV2, 1 << 20, F32, 0) == "O2e_march"
     # a bad file is rejected whole and the old table stays
@@ -573,8 +579,8 @@ def test_flat_scan_size_limit(rt, tmp_path):
 def test_reverse_scan_plan(rt):
     sel = lambda n, aux: name_of(rt, SK_SCAN, rt.skel_select_variant(SK_SCAN, I32, n, 1, n,
                                                                      aux))
-    assert sel(100, 0) == "S0_single_wg"
-    assert sel(100, 1) == "S3_persistent_lookback"  # reverse kinds: single pass only
+    assert sel(100, 0) == "S5_flat_lookback"
+    assert sel(100, 1) == "S5_flat_lookback"  # the flat look-back runs the reverse kinds too
     assert sel(1 << 27, 1) == "S3_persistent_lookback"
 
 
