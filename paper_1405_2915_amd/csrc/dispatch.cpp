@@ -106,9 +106,11 @@ int find_variant(int skeleton, const char* name) {
 int static_rule(const CallContext& c) {
     switch (c.skeleton) {
     case SKEL_SK_MAP: return c.n < (INT64_C(1) << 14) ? M1_VEC4 : M2_VEC4X4_NT;
-    case SKEL_SK_REDUCE: return c.n <= (INT64_C(1) << 15) ? R0_SINGLE_WG : R2_TICKET;
+    // (the tuned binary32 plan's choices, for the types it does not cover: one
+    // workgroup for small arrays, then the ticket-free gather)
+    case SKEL_SK_REDUCE: return c.n <= (INT64_C(1) << 15) ? R0_SINGLE_WG : R6_GATHER;
     case SKEL_SK_MAPREDUCE:
-        return c.n <= (INT64_C(1) << 15) ? MR3_FUSED_SINGLE_WG : MR2_FUSED_TICKET;
+        return c.n <= (INT64_C(1) << 15) ? MR3_FUSED_SINGLE_WG : MR6_FUSED_GATHER;
     case SKEL_SK_MAPOVERLAP1D: return c.radius <= 4 ? O1C_SHUFFLE : O1B_LDS_TILE;
     case SKEL_SK_MAPOVERLAP2D:
         return c.separable ? overlap2d_separable_variant(c.n, c.radius)

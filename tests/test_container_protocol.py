@@ -400,7 +400,10 @@ def test_static_plan(rt):
     sel = lambda sk, n, dt=F32, sep=0: name_of(
         rt, sk, rt.skel_select_variant(sk, dt, n, 1, n, sep))
     assert sel(SK_REDUCE, 1000) == "R0_single_wg"
-    assert sel(SK_REDUCE, 1 << 26) == "R2_ticket"
+    assert sel(SK_REDUCE, 1 << 26) == "R6_gather"
+    assert sel(SK_REDUCE, 1 << 20, I64) == "R6_gather"
+    assert sel(SK_MAPREDUCE, 1 << 26) == "MR6_fused_gather"
+    assert sel(SK_MAPREDUCE, 1000) == "MR3_fused_single_wg"
     # the flat look-back up to its 1024 tiles (4096 elements each, 2048 for
     # 64-bit inputs), then the persistent look-back
     assert sel(SK_SCAN, 100, I32) == "S5_flat_lookback"
