@@ -111,7 +111,11 @@ int static_rule(const CallContext& c) {
     case SKEL_SK_REDUCE: return c.n <= (INT64_C(1) << 15) ? R0_SINGLE_WG : R6_GATHER;
     case SKEL_SK_MAPREDUCE:
         return c.n <= (INT64_C(1) << 15) ? MR3_FUSED_SINGLE_WG : MR6_FUSED_GATHER;
-    case SKEL_SK_MAPOVERLAP1D: return c.radius <= 4 ? O1C_SHUFFLE : O1B_LDS_TILE;
+    case SKEL_SK_MAPOVERLAP1D:
+        // up to 2^20 elements the direct form (its loads hit the cache; as the
+        // tuned plan has it for radius 2), beyond that the cross-lane form
+        if (c.radius > 4) return O1B_LDS_TILE;
+        return c.n <= (INT64_C(1) << 20) ? O1A_DIRECT : O1C_SHUFFLE;
     case SKEL_SK_MAPOVERLAP2D:
         return c.separable ? overlap2d_separable_variant(c.n, c.radius)
                            : overlap2d_dense_variant(c.n, c.radius);

@@ -427,7 +427,8 @@ def test_static_plan(rt):
     assert sel(SK_OV2, 1 << 18, F32, 2 * 1) == "O2b_lds_tile"
     assert sel(SK_OV2, 1 << 24, F32, 1 + 2 * 4) == "O2d_separable_l1"
     assert sel(SK_OV2, 1 << 24, F32, 1 + 2 * 2) == "O2e_march"
-    assert sel(SK_OV1, 1 << 20, F32, 2) == "O1c_shuffle"   # aux = radius
+    assert sel(SK_OV1, 1 << 21, F32, 2) == "O1c_shuffle"   # aux = radius
+    assert sel(SK_OV1, 1 << 20, F32, 3) == "O1a_direct"    # small arrays: direct
     assert sel(SK_OV1, 1 << 20, F32, 7) == "O1b_lds_tile"  # beyond 4 neighbours
     assert sel(SK_MAP, 1 << 20) == "M2_vec4x4_nt"
     assert sel(SK_OV1B, 1 << 20, F32, 2) == "A1_flipped_forward"
